@@ -1,0 +1,161 @@
+"""Benchmark of the sparse SCF hot path on one MI355X.
+
+A step is one SCF iteration of the library (Fock build, C^T H C, rotation
+selection and application, re-orthonormalization, charges, energy) on the
+12,288-atom synthetic water box (4096 molecules, 24,576 AOs, 16,384 occupied
+MOs), inputs resident in HBM.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--config water4096] [--precision fp64]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SCF steps/sec + HBM GB/s at 12k atoms; FP32 vs FP64 form at 1e-6 Ha"
+PEAK = {"hbm": 8000.0, "fp64": 78.6, "fp32": 157.3}   # GB/s, TFLOP/s (MI355X, dense)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(system, budget_s: float, eps: float, e_conv: float):
+    """The FP64 oracle on the host cores: set-up untimed, then SCF steps until the budget."""
+    from oracle.oracle import Oracle
+    threads = os.cpu_count() or 1
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp and omp.isdigit():
+        threads = min(threads, int(omp))
+    o = Oracle(system, eps=eps, e_conv=e_conv, n_threads=threads)
+    n, t_sum = 0, 0.0
+    while t_sum < budget_s and n < 20:
+        t = time.time()
+        o.step()
+        t_sum += time.time() - t
+        n += 1
+    return dict(value=n / t_sum, unit="SCF steps/s", cores=threads, kind="oracle",
+                sample=f"oracle SCF steps 1..{n} of the same {system.name} system (set-up not timed), "
+                       f"{t_sum:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=18)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="water4096")
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--eps", type=float, default=1e-5)
+    ap.add_argument("--e-conv", type=float, default=1e-6)
+    ap.add_argument("--cpu-budget", type=float, default=25.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="time without per-kernel HIP events")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs the sparse SCF path on one GPU only; "
+              "--gpus N with N > 1 is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1402_2880_amd import synth
+    from paper_1402_2880_amd.sscf import FP32_MIXED, FP64, SparseSCF
+
+    torch.cuda.set_device(0)
+    t = time.time()
+    system = synth.make_config(args.config, args.seed)
+    log(f"[bench] {args.config}: {system.n_atoms} atoms, {system.n_ao} AOs, {system.n_mo} MOs "
+        f"(generated in {time.time() - t:.1f} s)")
+    prec = FP64 if args.precision == "fp64" else FP32_MIXED
+    t = time.time()
+    g = SparseSCF(system, eps=args.eps, e_conv=args.e_conv, precision=prec, profile=not args.no_profile)
+    log(f"[bench] set-up + initial orthonormalization {time.time() - t:.1f} s "
+        f"({g.init_info()['n_ortho_sweeps']} sweeps)")
+    for k in range(args.warmup):
+        si = g.step()
+        log(f"[bench] warmup {k + 1}: E {si['energy']:.10f} rot {si['n_rotations']} "
+            f"{si['ms_total']:.1f} ms")
+    if not args.no_profile:
+        g.reset_kernel_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for k in range(args.steps):
+        infos.append(g.step())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for k, si in enumerate(infos):
+        log(f"[bench] step {args.warmup + k + 1}: E {si['energy']:.10f} dE {si['delta_e']:.2e} "
+            f"rot {si['n_rotations']} sweeps {si['n_ortho_sweeps']} {si['ms_total']:.1f} ms "
+            f"(fock {si['ms_fock']:.2f} cfc {si['ms_cfc']:.2f} sel {si['ms_select']:.2f} "
+            f"rot {si['ms_rot']:.2f} ortho {si['ms_ortho']:.2f} sums {si['ms_sums']:.2f})")
+    value = args.steps / elapsed
+    roofline = None
+    kstats = None
+    if not args.no_profile:
+        kstats = g.kernel_stats()
+        for name, st in kstats.items():
+            if st["launches"]:
+                log(f"[bench] kernel {name}: {st['launches']} launches, {st['ms']:.2f} ms, "
+                    f"{st['flops'] / max(st['ms'], 1e-9) / 1e9:.1f} TFLOP/s, "
+                    f"{st['bytes'] / max(st['ms'], 1e-9) / 1e6:.1f} GB/s")
+        # the dominant kernel by time
+        name, st = max(kstats.items(), key=lambda kv: kv[1]["ms"])
+        per_launch_ms = st["ms"] / max(st["launches"], 1)
+        if st["flops"] > 0:
+            achieved = st["flops"] / st["launches"] / (per_launch_ms * 1e-3) / 1e12
+            peak = PEAK["fp64"] if args.precision == "fp64" else PEAK["fp32"]
+            roofline = dict(kernel=name, bound="mfma", achieved=round(achieved, 3), peak=peak,
+                            unit="TFLOP/s", frac=round(achieved / peak, 4), traffic=None,
+                            avg_launch_ms=round(per_launch_ms, 4), launches=st["launches"])
+        else:
+            achieved = st["bytes"] / st["launches"] / (per_launch_ms * 1e-3) / 1e9
+            roofline = dict(kernel=name, bound="hbm", achieved=round(achieved, 1), peak=PEAK["hbm"],
+                            unit="GB/s", frac=round(achieved / PEAK["hbm"], 4), traffic=None,
+                            avg_launch_ms=round(per_launch_ms, 4), launches=st["launches"])
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] CPU baseline (oracle) ...")
+        cpu = cpu_baseline(system, args.cpu_budget, args.eps, args.e_conv)
+        log(f"[bench] CPU baseline {cpu}")
+    last = infos[-1]
+    out = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "SCF steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config} seed {args.seed}: {system.n_atoms} atoms, {system.n_ao} AOs, "
+                               f"{system.n_mo} MOs ({system.n_occ} occupied), {system.n_groups} MO groups; "
+                               f"eps {args.eps}, e_conv {args.e_conv}; SCF steps "
+                               f"{args.warmup + 1}..{args.warmup + args.steps}",
+                   "precision": args.precision, "energy_last": last["energy"],
+                   "converged_last": bool(last["converged"])},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    if kstats is not None:
+        out["kernels"] = {k: dict(launches=v["launches"], ms=round(v["ms"], 3),
+                                  tflops=round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 3),
+                                  gbs=round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1))
+                          for k, v in kstats.items() if v["launches"]}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/* sscf.h -- C ABI of the MI355X (gfx950) sparse SCF library.
+ *
+ * Method: A. Scemama, N. Renon, M. Rapacioli, "A Sparse SCF algorithm and its
+ * parallel implementation: Application to DFTB" (arXiv:1402.2880).
+ *
+ * The problem (paper, section 2): given the AO overlap S and the reference
+ * Kohn-Sham matrix H0 on the atom-neighbour pattern (section 3.2), the DFTB
+ * charge term (section 3.7), an initial guess of local MOs (section 3.3) and
+ * the sparse threshold eps (section 4.1), iterate the Fock build (step IV) and
+ * the partial diagonalization by occupied-virtual rotations (step V, section
+ * 3.5), each step followed by re-orthonormalization of the MOs (step III,
+ * section 3.4), to self-consistent local MOs, the total energy and the density.
+ *
+ * Conventions for every call:
+ *  - The return value is an sscf_status: SSCF_OK (0) or a negative error code.
+ *    sscf_last_error(ctx) gives a human-readable message.  No C++ exception
+ *    crosses this interface.
+ *  - Array arguments are HOST pointers unless stated otherwise; the library
+ *    copies what it needs and never keeps a caller pointer after returning.
+ *  - A context is used by one host thread at a time; calls on different
+ *    contexts are independent.  All device work of a context runs in order on
+ *    the stream given at initialization.
+ *  - Every number is FP64 unless stated otherwise; indices are 0-based.
+ */
+#ifndef SSCF_H
+#define SSCF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sscf_status;
+
+enum {
+  SSCF_OK = 0,
+  SSCF_E_INVALID_ARG = -1, /* bad shape, index, pattern, NaN/Inf, NULL pointer      */
+  SSCF_E_NOT_SPD = -2,     /* a diagonal element of C^T S C is not positive           */
+  SSCF_E_ORTHO = -3,       /* initial orthonormalization did not reach eps/100        */
+  SSCF_E_HIP = -4,         /* a HIP runtime call failed (message holds its string)    */
+  SSCF_E_STATE = -5,       /* call out of order (e.g. on a failed context)            */
+  SSCF_E_CAPACITY = -6,    /* a fixed capacity was exceeded (message names it)        */
+  SSCF_E_NOMEM = -7        /* device or host allocation failed                        */
+};
+
+enum { SSCF_FP64 = 0, SSCF_FP32_MIXED = 1 };
+
+enum { SSCF_FOCK_H0 = 0, SSCF_FOCK_FULL = 1 };
+
+/* bits of sscf_system_desc.flags */
+enum { SSCF_FLAG_PROFILE = 1 };  /* time kernel classes with HIP events; count their work */
+
+#define SSCF_N_KERNEL_CLASSES 7
+
+typedef struct sscf_ctx sscf_ctx; /* opaque, owned by the library */
+
+/* Optional device allocator (for example a framework's caching allocator).
+ * alloc returns device memory of at least `bytes` bytes usable on `stream`, or
+ * NULL; free releases it.  When alloc is NULL the library uses hipMalloc/hipFree. */
+typedef struct {
+  void* self;
+  void* (*alloc)(void* self, size_t bytes, void* stream);
+  void (*free)(void* self, void* ptr, void* stream);
+} sscf_allocator;
+
+/* Problem description.  All arrays are host memory owned by the caller. */
+typedef struct {
+  /* atoms (section 3.7: minimal valence basis, 1 or 4 AOs per atom) */
+  int32_t n_atoms;
+  const int32_t* atom_nao;     /* [n_atoms] AOs per atom, 1..4; AOs are numbered atom by atom   */
+  const double* xyz_bohr;      /* [n_atoms][3] positions (bohr)                                 */
+  const double* hubbard_u;     /* [n_atoms] U (Ha) > 0: gamma_aa = U_a,
+                                  gamma_ab = 1/sqrt(r^2 + ((1/U_a + 1/U_b)/2)^2)                */
+  const double* q0;            /* [n_atoms] reference valence populations                       */
+  const int32_t* atom_group;   /* [n_atoms] MO group of the atom, 0..n_groups-1 (section 3.2)   */
+  int32_t n_groups;
+  /* atom-neighbour pattern (section 3.2): atom-block CSR, symmetric, self block present,
+     columns strictly increasing in each row; block k = (a, blk_col[k]) is the row-major
+     atom_nao[a] x atom_nao[b] sub-matrix starting at blk_off[k] of S_val / H0_val */
+  const int64_t* blk_rowptr;   /* [n_atoms + 1]                                                 */
+  const int32_t* blk_col;      /* [blk_rowptr[n_atoms]]                                          */
+  const int64_t* blk_off;      /* [blk_rowptr[n_atoms]]                                          */
+  const double* S_val;         /* overlap, symmetric                                            */
+  const double* H0_val;        /* reference Kohn-Sham matrix, symmetric (Ha)                    */
+  int64_t n_val;               /* length of S_val / H0_val                                      */
+  /* molecular orbitals: MO j < n_occ is doubly occupied (closed shell) */
+  int32_t n_mo;
+  int32_t n_occ;
+  const int32_t* mo_group;     /* [n_mo] group of each MO; MOs keep it for the whole SCF        */
+  /* initial guess C0 (section 3.3), CSC: column j has rows c0_row[c0_colptr[j] ..
+     c0_colptr[j+1]-1], strictly increasing, values c0_val */
+  const int64_t* c0_colptr;    /* [n_mo + 1]                                                     */
+  const int32_t* c0_row;
+  const double* c0_val;
+  /* thresholds (section 4.1; section 3.2; section 3.5) */
+  double eps;                  /* sparse threshold epsilon, e.g. 1e-5                           */
+  double e_conv;               /* SCF converged when |E(n) - E(n-1)| < e_conv (Ha)              */
+  double group_nbr_bohr;       /* MO groups are neighbours below this atom-atom distance (20)    */
+  double rot_cap_factor;       /* at most rot_cap_factor * n_occ rotations per step (10)        */
+  int32_t max_sweeps_init;     /* orthonormalization sweeps allowed at initialization (200)     */
+  int32_t max_sweeps_step;     /* orthonormalization sweeps allowed per SCF step (50)           */
+  int32_t scc;                 /* 1: add the DFTB charge term of section 3.7; 0: gamma = 0      */
+  int32_t precision;           /* SSCF_FP64, or SSCF_FP32_MIXED: C^T H C and the rotation angles
+                                  in FP32, everything else in FP64                              */
+  void* hip_stream;            /* hipStream_t for all device work; NULL = default stream        */
+  sscf_allocator alloc;        /* zero-filled = hipMalloc / hipFree                             */
+  uint64_t flags;              /* 0, or SSCF_FLAG_PROFILE                                       */
+} sscf_system_desc;
+
+/* Per-step report.  Times are device time (HIP events) in milliseconds. */
+typedef struct {
+  double energy;               /* total energy after the step (Ha)                              */
+  double delta_e;              /* energy(n) - energy(n-1)                                       */
+  double dq_max;               /* max_a |q_a(n) - q_a(n-1)| (section 4.1)                       */
+  double max_abs_fov;          /* largest |F_ia| before the rotations                           */
+  double ortho_eta;            /* largest off-diagonal of the normalized C^T S C at exit        */
+  double e_band;               /* sum_uv P_uv H0_uv                                             */
+  double e_coul;               /* 1/2 sum_ab dq_a gamma_ab dq_b                                 */
+  int32_t n_candidates;        /* pairs with |F_ia| >= eps                                      */
+  int32_t n_rotations;         /* rotations applied                                             */
+  int32_t n_ortho_sweeps;      /* pair-combination sweeps applied                               */
+  int32_t converged;           /* |delta_e| < e_conv                                            */
+  int32_t ortho_converged;     /* eta < eps/100 was reached                                     */
+  int32_t post_ortho;          /* occupied-only orthonormalization was run (once converged)     */
+  int64_t nnz_tiles;           /* active 16-row tiles of C                                      */
+  float ms_fock, ms_cfc, ms_select, ms_rot, ms_ortho, ms_sums, ms_total;
+} sscf_step_info;
+
+/* Copy the problem to the device, check it, build the neighbour maps and the
+ * rotation schedule, and orthonormalize C0 (section 3.4) until the largest
+ * off-diagonal of the normalized C^T S C is below eps/100.  On success *out is a
+ * new context; on failure *out is NULL and the status tells why
+ * (SSCF_E_INVALID_ARG, SSCF_E_NOT_SPD, SSCF_E_ORTHO, SSCF_E_HIP, SSCF_E_NOMEM,
+ * SSCF_E_CAPACITY).  The failure message is available from sscf_last_error(NULL). */
+sscf_status sscf_init_system(const sscf_system_desc* desc, sscf_ctx** out);
+
+/* Replace the Fock input for the following steps (section 2, step IV).
+ * f_val has the layout of S_val (n_val values, host memory).
+ * mode SSCF_FOCK_H0:   f_val is a new H0; the charge term is still added each step.
+ * mode SSCF_FOCK_FULL: f_val is the complete Fock matrix; no charge term is added
+ *                      and the energy becomes sum_uv P_uv F_uv.
+ * Errors: SSCF_E_INVALID_ARG (NULL, bad mode, NaN/Inf, not symmetric). */
+sscf_status sscf_set_fock(sscf_ctx* ctx, const double* f_val, int32_t mode);
+
+/* One SCF step (section 2, steps IV and V, then step III): Fock build with the
+ * charges of the previous step, C^T H C on neighbouring groups, selection and
+ * application of the occupied-virtual rotations, re-orthonormalization, Mulliken
+ * charges, energy and convergence test; once converged, the occupied MOs are
+ * orthonormalized among themselves (section 4.1) and the energy recomputed.
+ * `info` may be NULL.  Non-convergence is not an error. */
+sscf_status sscf_scf_step(sscf_ctx* ctx, sscf_step_info* info);
+
+/* Total energy (Ha) of the current MOs. */
+sscf_status sscf_get_energy(const sscf_ctx* ctx, double* e_total);
+
+/* Density P = 2 C_occ C_occ^T on the atom-block pattern of S, written to the
+ * caller's host buffer p_val of n_val >= desc.n_val doubles (layout of S_val). */
+sscf_status sscf_get_density(const sscf_ctx* ctx, double* p_val, size_t n_val);
+
+/* Mulliken populations q_a (section 3.7, eq. pop) into q[n_atoms] (host). */
+sscf_status sscf_get_charges(const sscf_ctx* ctx, double* q, size_t n);
+
+/* The MOs as CSC (rows increasing).  Call with row == NULL to get *nnz; then
+ * with arrays colptr[n_mo + 1], row[*nnz], val[*nnz] (host).  Entries are the
+ * nonzero coefficients. */
+sscf_status sscf_get_mo_coefficients(const sscf_ctx* ctx, int64_t* colptr, int32_t* row,
+                                     double* val, int64_t* nnz);
+
+/* The report of the initialization (orthonormalization sweeps, eta, energy). */
+sscf_status sscf_init_info(const sscf_ctx* ctx, sscf_step_info* info);
+
+/* Jacobi blocks (occupied group g, virtual group h) and their rounds, in the
+ * order they are applied: g[n], h[n], round[n] with n = *n_blocks.  Call with
+ * g == NULL to get *n_blocks. */
+sscf_status sscf_get_schedule(const sscf_ctx* ctx, int32_t* g, int32_t* h, int32_t* round,
+                              int32_t* n_blocks);
+
+/* Work and time of the main kernel classes, accumulated over the calls since
+ * initialization (or the last reset) when the context was created with
+ * SSCF_FLAG_PROFILE.  Classes: spmm_tiles (S C, H C, H0 C), pair_overlap
+ * (C^T S C), pair_fock (occupied-virtual C^T H C), ortho_update (C - 1/2 C D),
+ * givens_round (one launch per round of rotation blocks), select, fock.  `flops`
+ * counts the FP64 MFMA tile products of the class (2048 flops each) and `bytes`
+ * the algorithmic traffic of the rotation pass (each rotated element of an active
+ * row read and written once).  Call with out == NULL to get *n. */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double ms;                   /* summed HIP-event time of the launches                         */
+  double flops;
+  double bytes;
+} sscf_kernel_stat;
+
+sscf_status sscf_get_kernel_stats(const sscf_ctx* ctx, sscf_kernel_stat* out, int32_t* n);
+sscf_status sscf_reset_kernel_stats(sscf_ctx* ctx);
+
+/* Release the context and all its device memory. */
+void sscf_destroy(sscf_ctx* ctx);
+
+/* Last error message of ctx (or of the last failed sscf_init_system if ctx is NULL). */
+const char* sscf_last_error(const sscf_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1015 @@
+// Host side of the gfx950 sparse SCF library: the C ABI of include/sscf.h,
+// set-up of the patterns and schedules, and the per-step driver.
+//
+// Paper: A. Scemama, N. Renon, M. Rapacioli, "A Sparse SCF algorithm and its
+// parallel implementation: Application to DFTB", arXiv:1402.2880.
+//
+// Readings of points the paper leaves open (the same ones the test oracle uses):
+//  * orthonormalization (section 3.4): each sweep recomputes C^T S C, normalizes,
+//    tests max |D_ij| < eps/100 on the normalized matrix D, and otherwise
+//    combines every pair with |D_ij| >= 1e-3 max|D| at once, C <- C - 1/2 C D_sel,
+//    then zeroes |C| < 1e-3 eps in the combined columns (section 4.1);
+//  * partial diagonalization (section 3.5): at most rot_cap_factor * n_occ
+//    rotations per step, chosen by decreasing |F_ia| >= eps (ties by (i, a)),
+//    applied block round by block round with angles from the F of the start of
+//    the step; the rotation is C'_i = c C_i + s C_a, C'_a = -s C_i + c C_a; after
+//    each block the rotated columns lose |C| < eps (section 4.1);
+//  * each step ends with a full re-orthonormalization; once |dE| < e_conv the
+//    occupied MOs are orthonormalized among themselves (section 4.1);
+//  * E = sum_uv P_uv H0_uv + 1/2 dq^T gamma dq, P = 2 C_occ C_occ^T.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/sscf.h"
+#include "sscf_internal.h"
+
+using namespace sscf;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+struct Fail {
+  sscf_status code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(sscf_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  throw Fail{code, buf};
+}
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) fail(SSCF_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+#define HIPC(x) hip_check((x), #x)
+
+int round16(int x) { return ((x + 15) / 16) * 16; }
+
+// kernel classes reported by sscf_get_kernel_stats
+enum { KC_SPMM, KC_PAIR_O, KC_PAIR_F, KC_UPDATE, KC_GIVENS, KC_SELECT, KC_FOCK };
+const char* const KC_NAME[SSCF_N_KERNEL_CLASSES] = {
+    "spmm_tiles", "pair_overlap", "pair_fock", "ortho_update", "givens_round", "select", "fock"};
+// MFMA tile products count 16 x 16 x 4 multiply-adds; the Givens counter holds bytes
+const double KC_FLOP_PER_UNIT[SSCF_N_KERNEL_CLASSES] = {2048.0, 2048.0, 2048.0, 2048.0, 0.0, 0.0, 0.0};
+const double KC_BYTE_PER_UNIT[SSCF_N_KERNEL_CLASSES] = {0.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0};
+
+}  // namespace
+
+struct sscf_ctx {
+  // parameters
+  double eps = 0, e_conv = 0, r_nbr = 0, rot_cap = 0;
+  int max_sweeps_init = 0, max_sweeps_step = 0, scc = 1, precision = 0;
+  int fock_full = 0;
+  hipStream_t stream = nullptr;
+  sscf_allocator alloc{};
+  std::vector<void*> owned;
+  std::string err;
+  bool failed = false;
+
+  // sizes
+  View v{};
+  int64_t n_val = 0;
+  int n_pairs = 0, n_blocks = 0, n_rounds = 0;
+
+  // host copies needed after set-up
+  std::vector<int64_t> h_blk_rowptr, h_blk_off;
+  std::vector<int32_t> h_blk_col, h_atom_nao;
+  std::vector<int32_t> h_mo_of;      // [G * W] MO index of a panel column, -1 if none
+  std::vector<int32_t> h_pnocc, h_pnvirt;
+  std::vector<int32_t> h_jb_g, h_jb_h, h_jb_round;
+  std::vector<int32_t> h_round_ptr;  // blocks of round r: round_list[round_ptr[r] .. round_ptr[r+1])
+  std::vector<int64_t> h_ao_off;
+
+  // device arrays
+  double *xyz = nullptr, *U = nullptr, *q0 = nullptr;
+  int* ao_atom = nullptr;
+  int64_t* ao_off = nullptr;
+  int *xs_ptr = nullptr, *xs_col = nullptr, *xs_row = nullptr;
+  int64_t* val_map = nullptr;        // atom-block value index -> row-block element index
+  double *S = nullptr, *H0 = nullptr, *H = nullptr, *Hfull = nullptr;
+  double* C[2] = {nullptr, nullptr};
+  uint8_t* actC[2] = {nullptr, nullptr};
+  int* listC[2] = {nullptr, nullptr};
+  int* cntC[2] = {nullptr, nullptr};
+  int cur = 0;                        // C[cur] is the current MO matrix
+  double* Y = nullptr;
+  uint8_t* actY = nullptr;
+  int *listY = nullptr, *cntY = nullptr;
+  uint8_t* act_tmp = nullptr;
+  int *list_tmp = nullptr, *cnt_tmp = nullptr;
+  int *pnocc = nullptr, *pnvirt = nullptr, *mo_of = nullptr;
+  int *gn_ptr = nullptr, *gn = nullptr, *pair_of = nullptr, *pg = nullptr, *ph = nullptr, *self_pair = nullptr;
+  double* O = nullptr;
+  double* sc = nullptr;
+  uint8_t *upd = nullptr, *pair_sel = nullptr;
+  int *jb_g = nullptr, *jb_h = nullptr, *jb_nocc = nullptr, *jb_nvirt = nullptr, *round_list = nullptr;
+  double *F = nullptr, *Fdiag = nullptr, *dvec = nullptr;
+  int *rot_cnt = nullptr, *tcnt = nullptr, *tcol = nullptr;
+  int2* rot_col = nullptr;
+  double2* rot_cs = nullptr;
+  unsigned int* hist = nullptr;
+  long long* ties = nullptr;
+  double *q = nullptr, *q_prev = nullptr, *dq = nullptr, *Q = nullptr, *rowq = nullptr, *pblk = nullptr,
+         *pval = nullptr;
+  Scalars* sd = nullptr;
+  hipEvent_t ev[8] = {};
+
+  // state
+  double E = 0.0;
+  sscf_step_info init_info{};
+
+  // optional profiling (SSCF_FLAG_PROFILE): HIP events around the launches of each
+  // kernel class, device counters of MFMA tile products / algorithmic bytes
+  bool prof = false;
+  std::vector<hipEvent_t> pev;
+  std::vector<int> pcls;
+  int pused = 0;
+  double pms[SSCF_N_KERNEL_CLASSES] = {};
+  long long plaunch[SSCF_N_KERNEL_CLASSES] = {};
+  unsigned long long* pctr = nullptr;
+
+  int pbegin(int c) {
+    if (!prof) return -1;
+    if ((size_t)(2 * pused + 2) > pev.size()) {
+      for (int k = 0; k < 64; ++k) {
+        hipEvent_t e;
+        HIPC(hipEventCreate(&e));
+        pev.push_back(e);
+      }
+    }
+    if ((size_t)pused >= pcls.size()) pcls.resize(pused + 32);
+    HIPC(hipEventRecord(pev[2 * pused], stream));
+    pcls[pused] = c;
+    return pused++;
+  }
+  void pend(int i) {
+    if (i >= 0) HIPC(hipEventRecord(pev[2 * i + 1], stream));
+  }
+  unsigned long long* ctr(int c) { return prof ? pctr + c : nullptr; }
+  void pcollect() {
+    if (!prof) return;
+    sync();
+    for (int i = 0; i < pused; ++i) {
+      float ms = 0.f;
+      HIPC(hipEventElapsedTime(&ms, pev[2 * i], pev[2 * i + 1]));
+      pms[pcls[i]] += ms;
+      plaunch[pcls[i]] += 1;
+    }
+    pused = 0;
+  }
+
+  template <class T>
+  T* dalloc(size_t n) {
+    const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    void* p = nullptr;
+    if (alloc.alloc) {
+      p = alloc.alloc(alloc.self, bytes, (void*)stream);
+      if (!p) fail(SSCF_E_NOMEM, "device allocation of %zu bytes failed", bytes);
+    } else {
+      const hipError_t e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) fail(SSCF_E_NOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    owned.push_back(p);
+    return static_cast<T*>(p);
+  }
+
+  void dfree(void* p) {
+    if (!p) return;
+    auto it = std::find(owned.begin(), owned.end(), p);
+    if (it == owned.end()) return;
+    if (stream) hipStreamSynchronize(stream);
+    if (alloc.free) alloc.free(alloc.self, p, (void*)stream);
+    else hipFree(p);
+    owned.erase(it);
+  }
+
+  template <class T>
+  T* upload(const T* src, size_t n) {
+    T* d = dalloc<T>(n);
+    if (n) HIPC(hipMemcpyAsync(d, src, n * sizeof(T), hipMemcpyHostToDevice, stream));
+    return d;
+  }
+
+  void release() {
+    if (stream) hipStreamSynchronize(stream);
+    for (void* p : owned) {
+      if (alloc.free) alloc.free(alloc.self, p, (void*)stream);
+      else hipFree(p);
+    }
+    owned.clear();
+    for (auto& e : ev)
+      if (e) { hipEventDestroy(e); e = nullptr; }
+    for (auto& e : pev) hipEventDestroy(e);
+    pev.clear();
+  }
+
+  void sync() { HIPC(hipStreamSynchronize(stream)); }
+
+  Scalars read_scalars() {
+    Scalars h{};
+    HIPC(hipMemcpyAsync(&h, sd, sizeof(Scalars), hipMemcpyDeviceToHost, stream));
+    sync();
+    return h;
+  }
+
+  // ---------------------------------------------------------------------------------------
+  void rebuild_list(int b) { launch_list(v, actC[b], listC[b], cntC[b], stream); }
+
+  // Y = X C on the dilated support of C
+  void product(const double* X, bool dilate) {
+    if (dilate) {
+      launch_dilate(v, actC[cur], actY, stream);
+      launch_list(v, actY, listY, cntY, stream);
+    }
+    const int pi = pbegin(KC_SPMM);
+    launch_spmm(v, X, C[cur], actC[cur], listY, cntY, Y, ctr(KC_SPMM), stream);
+    pend(pi);
+  }
+
+  // orthonormalization loop (section 3.4); returns the number of combination sweeps
+  int orthonormalize(int occ_only, int max_sweeps, double* eta_out, int* converged) {
+    const double tol = eps / 100.0, cut = 1e-3 * eps;
+    int sweeps = 0;
+    *converged = 0;
+    for (;;) {
+      product(S, true);
+      const int W = v.W;
+      const int pi = pbegin(KC_PAIR_O);
+      const int nt = (occ_only ? v.OW : W) / 16;
+      launch_pair(v, n_pairs, pg, ph, C[cur], listC[cur], cntC[cur], Y, actY, 0, nt, 0, nt, O, W, (size_t)W * W,
+                  ctr(KC_PAIR_O), stream);
+      pend(pi);
+      HIPC(hipMemsetAsync(&sd->eta_bits, 0, sizeof(unsigned long long), stream));
+      HIPC(hipMemsetAsync(&sd->err, 0, sizeof(int), stream));
+      launch_ortho_scale(v, v.G, self_pair, O, pnocc, pnvirt, occ_only, sc, sd, stream);
+      launch_normalize_d(v, n_pairs, pg, ph, O, sc, pnocc, pnvirt, occ_only, sd, stream);
+      launch_scale_c(v, C[cur], listC[cur], cntC[cur], sc, stream);
+      const Scalars h = read_scalars();
+      if (h.err & 1) fail(SSCF_E_NOT_SPD, "C^T S C has a non-positive diagonal element");
+      double eta;
+      std::memcpy(&eta, &h.eta_bits, sizeof(double));
+      *eta_out = eta;
+      if (eta < tol) { *converged = 1; break; }
+      if (sweeps >= max_sweeps) break;
+      // pair combinations C <- C - 1/2 C D_sel into the other buffer
+      const int nx = 1 - cur;
+      HIPC(hipMemsetAsync(upd, 0, (size_t)v.G * W, stream));
+      launch_mark_selected(v, n_pairs, pg, ph, O, sd, pair_sel, upd, stream);
+      launch_update_support(v, actC[cur], gn_ptr, gn, pair_of, pair_sel, act_tmp, stream);
+      launch_list(v, act_tmp, list_tmp, cnt_tmp, stream);
+      launch_clear_tiles(v, C[nx], actC[nx], listC[nx], cntC[nx], stream);
+      const int pu = pbegin(KC_UPDATE);
+      launch_ortho_update(v, C[cur], actC[cur], gn_ptr, gn, pair_of, pair_sel, O, sd, upd, cut, list_tmp, cnt_tmp,
+                          C[nx], actC[nx], ctr(KC_UPDATE), stream);
+      pend(pu);
+      rebuild_list(nx);
+      cur = nx;
+      ++sweeps;
+    }
+    return sweeps;
+  }
+
+  // Mulliken charges from C and Y = S C of the last orthonormalization pass
+  void charges(int shift_prev) {
+    launch_charges_rows(v, C[cur], actC[cur], Y, actY, sc, pnocc, rowq, stream);
+    HIPC(hipMemsetAsync(&sd->dq_bits, 0, sizeof(unsigned long long), stream));
+    launch_atom_charges(v, ao_off, rowq, q, q_prev, dq, sd, shift_prev, stream);
+  }
+
+  // Q = gamma dq (kept current in every mode, for the next Fock build), the Coulomb
+  // energy and the band energy sum P H0 (or P F with a complete Fock matrix)
+  void energy_terms() {
+    launch_coulomb(v, scc, dq, Q, stream);
+    launch_sum_coul(v, scc && !fock_full, dq, Q, sd, stream);
+    product(fock_full ? Hfull : H0, false);   // support of C unchanged since the last dilation
+    launch_coldot(v, C[cur], listC[cur], cntC[cur], Y, actY, dvec, stream);
+    launch_sum_band(v, dvec, pnocc, sd, stream);
+  }
+
+  int64_t active_tiles() {
+    std::vector<int> cnt(v.G);
+    HIPC(hipMemcpyAsync(cnt.data(), cntC[cur], sizeof(int) * v.G, hipMemcpyDeviceToHost, stream));
+    sync();
+    int64_t s = 0;
+    for (int c : cnt) s += c;
+    return s;
+  }
+};
+
+// =========================================================================================
+// set-up
+// =========================================================================================
+
+namespace {
+
+void validate(const sscf_system_desc* d) {
+  if (!d) fail(SSCF_E_INVALID_ARG, "desc is NULL");
+  if (d->n_atoms <= 0 || !d->atom_nao || !d->xyz_bohr || !d->hubbard_u || !d->q0 || !d->atom_group)
+    fail(SSCF_E_INVALID_ARG, "atom arrays missing or n_atoms <= 0");
+  if (d->n_groups <= 0) fail(SSCF_E_INVALID_ARG, "n_groups must be positive");
+  if (!d->blk_rowptr || !d->blk_col || !d->blk_off || !d->S_val || !d->H0_val || d->n_val <= 0)
+    fail(SSCF_E_INVALID_ARG, "atom-block pattern or values missing");
+  if (d->n_mo <= 0 || d->n_occ < 0 || d->n_occ > d->n_mo || !d->mo_group || !d->c0_colptr || !d->c0_row ||
+      !d->c0_val)
+    fail(SSCF_E_INVALID_ARG, "MO arrays missing or bad n_mo / n_occ");
+  if (!(d->eps >= 0.0) || !std::isfinite(d->eps) || !(d->e_conv >= 0.0) || !(d->group_nbr_bohr > 0.0) ||
+      !(d->rot_cap_factor >= 0.0) || d->max_sweeps_init < 0 || d->max_sweeps_step < 0)
+    fail(SSCF_E_INVALID_ARG, "bad thresholds");
+  if (d->precision != SSCF_FP64 && d->precision != SSCF_FP32_MIXED) fail(SSCF_E_INVALID_ARG, "bad precision");
+  if (d->precision == SSCF_FP32_MIXED) fail(SSCF_E_INVALID_ARG, "the FP32 form is not available in this build");
+  if (d->flags & ~(uint64_t)SSCF_FLAG_PROFILE) fail(SSCF_E_INVALID_ARG, "unknown bits in flags");
+  for (int a = 0; a < d->n_atoms; ++a) {
+    if (d->atom_nao[a] < 1 || d->atom_nao[a] > 4) fail(SSCF_E_INVALID_ARG, "atom %d: atom_nao must be 1..4", a);
+    if (d->atom_group[a] < 0 || d->atom_group[a] >= d->n_groups) fail(SSCF_E_INVALID_ARG, "atom %d: bad group", a);
+    if (!(d->hubbard_u[a] > 0.0) || !std::isfinite(d->hubbard_u[a])) fail(SSCF_E_INVALID_ARG, "atom %d: bad U", a);
+    if (!std::isfinite(d->q0[a])) fail(SSCF_E_INVALID_ARG, "atom %d: bad q0", a);
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(d->xyz_bohr[3 * a + k])) fail(SSCF_E_INVALID_ARG, "atom %d: bad position", a);
+  }
+}
+
+}  // namespace
+
+static void build(sscf_ctx* x, const sscf_system_desc* d) {
+  validate(d);
+  x->eps = d->eps;
+  x->e_conv = d->e_conv;
+  x->r_nbr = d->group_nbr_bohr;
+  x->rot_cap = d->rot_cap_factor;
+  x->max_sweeps_init = d->max_sweeps_init;
+  x->max_sweeps_step = d->max_sweeps_step;
+  x->scc = d->scc ? 1 : 0;
+  x->precision = d->precision;
+  x->stream = (hipStream_t)d->hip_stream;
+  x->alloc = d->alloc;
+  x->n_val = d->n_val;
+  x->prof = (d->flags & SSCF_FLAG_PROFILE) != 0;
+  View& v = x->v;
+  const int na = d->n_atoms;
+  v.n_atoms = na;
+  v.n_mo = d->n_mo;
+  v.n_occ = d->n_occ;
+  v.G = d->n_groups;
+  const int G = v.G;
+
+  // AOs, row blocks
+  std::vector<int64_t> ao_off(na + 1, 0);
+  for (int a = 0; a < na; ++a) ao_off[a + 1] = ao_off[a] + d->atom_nao[a];
+  if (ao_off[na] > (1LL << 30)) fail(SSCF_E_CAPACITY, "too many AOs");
+  v.n_ao = (int)ao_off[na];
+  v.n_rb = (v.n_ao + RB - 1) / RB;
+  std::vector<int> ao_atom(v.n_ao);
+  for (int a = 0; a < na; ++a)
+    for (int64_t mu = ao_off[a]; mu < ao_off[a + 1]; ++mu) ao_atom[mu] = a;
+  x->h_ao_off = ao_off;
+
+  // atom-block pattern: checks, symmetry, and the row-block pattern
+  const int64_t* rp = d->blk_rowptr;
+  if (rp[0] != 0) fail(SSCF_E_INVALID_ARG, "blk_rowptr[0] must be 0");
+  for (int a = 0; a < na; ++a) {
+    if (rp[a + 1] < rp[a]) fail(SSCF_E_INVALID_ARG, "blk_rowptr must not decrease");
+    bool self = false;
+    for (int64_t k = rp[a]; k < rp[a + 1]; ++k) {
+      const int b = d->blk_col[k];
+      if (b < 0 || b >= na || (k > rp[a] && d->blk_col[k - 1] >= b))
+        fail(SSCF_E_INVALID_ARG, "row %d of the atom-block pattern: columns must be in range and increasing", a);
+      if (b == a) self = true;
+      const int64_t end = d->blk_off[k] + (int64_t)d->atom_nao[a] * d->atom_nao[b];
+      if (d->blk_off[k] < 0 || end > d->n_val) fail(SSCF_E_INVALID_ARG, "block (%d, %d) outside the values", a, b);
+      for (int64_t t = d->blk_off[k]; t < end; ++t)
+        if (!std::isfinite(d->S_val[t]) || !std::isfinite(d->H0_val[t]))
+          fail(SSCF_E_INVALID_ARG, "non-finite S or H0 in block (%d, %d)", a, b);
+    }
+    if (!self) fail(SSCF_E_INVALID_ARG, "atom %d has no self block", a);
+  }
+  auto find_blk = [&](int a, int b) -> int64_t {
+    const int32_t* lo = d->blk_col + rp[a];
+    const int32_t* hi = d->blk_col + rp[a + 1];
+    const int32_t* it = std::lower_bound(lo, hi, b);
+    return (it != hi && *it == b) ? (int64_t)(it - d->blk_col) : -1;
+  };
+  for (int a = 0; a < na; ++a)
+    for (int64_t k = rp[a]; k < rp[a + 1]; ++k) {
+      const int b = d->blk_col[k];
+      const int64_t kt = find_blk(b, a);
+      if (kt < 0) fail(SSCF_E_INVALID_ARG, "atom-block pattern is not symmetric at (%d, %d)", a, b);
+      const int nA = d->atom_nao[a], nB = d->atom_nao[b];
+      for (int i = 0; i < nA; ++i)
+        for (int j = 0; j < nB; ++j) {
+          const int64_t s1 = d->blk_off[k] + (int64_t)i * nB + j, s2 = d->blk_off[kt] + (int64_t)j * nA + i;
+          if (d->S_val[s1] != d->S_val[s2] || d->H0_val[s1] != d->H0_val[s2])
+            fail(SSCF_E_INVALID_ARG, "S and H0 must be symmetric (atoms %d, %d)", a, b);
+        }
+    }
+  // row-block pattern (r, c) covered by any atom block
+  std::vector<std::vector<int>> rbcols(v.n_rb);
+  for (int a = 0; a < na; ++a)
+    for (int64_t k = rp[a]; k < rp[a + 1]; ++k) {
+      const int b = d->blk_col[k];
+      for (int64_t r = ao_off[a] / RB; r <= (ao_off[a + 1] - 1) / RB; ++r)
+        for (int64_t c = ao_off[b] / RB; c <= (ao_off[b + 1] - 1) / RB; ++c) rbcols[r].push_back((int)c);
+    }
+  std::vector<int> xs_ptr(v.n_rb + 1, 0), xs_col, xs_row;
+  for (int r = 0; r < v.n_rb; ++r) {
+    auto& cs = rbcols[r];
+    std::sort(cs.begin(), cs.end());
+    cs.erase(std::unique(cs.begin(), cs.end()), cs.end());
+    for (int c : cs) { xs_col.push_back(c); xs_row.push_back(r); }
+    xs_ptr[r + 1] = (int)xs_col.size();
+  }
+  v.nbx = (int)xs_col.size();
+  auto xs_find = [&](int r, int c) -> int64_t {
+    auto lo = xs_col.begin() + xs_ptr[r], hi = xs_col.begin() + xs_ptr[r + 1];
+    auto it = std::lower_bound(lo, hi, c);
+    return (int64_t)(it - xs_col.begin());
+  };
+  std::vector<int64_t> val_map(d->n_val, -1);
+  for (int a = 0; a < na; ++a)
+    for (int64_t k = rp[a]; k < rp[a + 1]; ++k) {
+      const int b = d->blk_col[k];
+      const int nA = d->atom_nao[a], nB = d->atom_nao[b];
+      for (int i = 0; i < nA; ++i)
+        for (int j = 0; j < nB; ++j) {
+          const int64_t mu = ao_off[a] + i, nu = ao_off[b] + j;
+          const int64_t bi = xs_find((int)(mu / RB), (int)(nu / RB));
+          val_map[d->blk_off[k] + (int64_t)i * nB + j] = bi * 256 + (mu % RB) * 16 + (nu % RB);
+        }
+    }
+  for (int64_t t = 0; t < d->n_val; ++t)
+    if (val_map[t] < 0) fail(SSCF_E_INVALID_ARG, "value %lld of S_val is not covered by any block", (long long)t);
+
+  // MO panels (section 3.2: MOs keep their group)
+  std::vector<int> nocc(G, 0), nvirt(G, 0), mo_col(v.n_mo);
+  for (int j = 0; j < v.n_mo; ++j) {
+    const int g = d->mo_group[j];
+    if (g < 0 || g >= G) fail(SSCF_E_INVALID_ARG, "MO %d: bad group", j);
+    mo_col[j] = (j < v.n_occ) ? nocc[g]++ : nvirt[g]++;
+  }
+  int mo_ = 0, mv_ = 0;
+  for (int g = 0; g < G; ++g) { mo_ = std::max(mo_, nocc[g]); mv_ = std::max(mv_, nvirt[g]); }
+  v.OW = std::max(16, round16(mo_));
+  v.VW = std::max(16, round16(mv_));
+  v.W = v.OW + v.VW;
+  if (v.W > MAX_W) fail(SSCF_E_CAPACITY, "MO group too large: %d + %d MOs (panel limit %d)", mo_, mv_, MAX_W);
+  std::vector<int> mo_panel(v.n_mo);
+  x->h_mo_of.assign((size_t)G * v.W, -1);
+  for (int j = 0; j < v.n_mo; ++j) {
+    mo_panel[j] = d->mo_group[j];
+    if (j >= v.n_occ) mo_col[j] += v.OW;
+    x->h_mo_of[(size_t)mo_panel[j] * v.W + mo_col[j]] = j;
+  }
+  x->h_pnocc = nocc;
+  x->h_pnvirt = nvirt;
+
+  // C0 checks
+  const int64_t* cp = d->c0_colptr;
+  if (cp[0] != 0) fail(SSCF_E_INVALID_ARG, "c0_colptr[0] must be 0");
+  for (int j = 0; j < v.n_mo; ++j) {
+    if (cp[j + 1] < cp[j]) fail(SSCF_E_INVALID_ARG, "c0_colptr must not decrease");
+    for (int64_t t = cp[j]; t < cp[j + 1]; ++t) {
+      if (d->c0_row[t] < 0 || d->c0_row[t] >= v.n_ao || (t > cp[j] && d->c0_row[t] <= d->c0_row[t - 1]))
+        fail(SSCF_E_INVALID_ARG, "C0 column %d: rows must be increasing and in range", j);
+      if (!std::isfinite(d->c0_val[t])) fail(SSCF_E_INVALID_ARG, "C0 column %d: non-finite value", j);
+    }
+  }
+  const int64_t nnz0 = cp[v.n_mo];
+  if (nnz0 > (1LL << 31) - 1) fail(SSCF_E_CAPACITY, "C0 too large");
+
+  // group neighbour map: some atom pair closer than r_nbr (section 3.2)
+  std::vector<uint8_t> gnbr((size_t)G * G, 0);
+  {
+    const double r2 = x->r_nbr * x->r_nbr;
+    for (int g = 0; g < G; ++g) gnbr[(size_t)g * G + g] = 1;
+    for (int a = 0; a < na; ++a) {
+      const double* pa = d->xyz_bohr + 3 * a;
+      const int ga = d->atom_group[a];
+      for (int b = a + 1; b < na; ++b) {
+        const int gb = d->atom_group[b];
+        if (gnbr[(size_t)ga * G + gb]) continue;
+        const double* pb = d->xyz_bohr + 3 * b;
+        const double dx = pa[0] - pb[0], dy = pa[1] - pb[1], dz = pa[2] - pb[2];
+        if (dx * dx + dy * dy + dz * dz < r2) { gnbr[(size_t)ga * G + gb] = 1; gnbr[(size_t)gb * G + ga] = 1; }
+      }
+    }
+  }
+  std::vector<int> gn_ptr(G + 1, 0), gn;
+  for (int g = 0; g < G; ++g) {
+    for (int h = 0; h < G; ++h)
+      if (gnbr[(size_t)g * G + h]) gn.push_back(h);
+    gn_ptr[g + 1] = (int)gn.size();
+  }
+  // unordered pairs g <= h
+  std::vector<int> pg, ph, pair_of((size_t)G * G, -1), self_pair(G, -1);
+  for (int g = 0; g < G; ++g)
+    for (int h = g; h < G; ++h)
+      if (gnbr[(size_t)g * G + h]) {
+        pair_of[(size_t)g * G + h] = pair_of[(size_t)h * G + g] = (int)pg.size();
+        if (g == h) self_pair[g] = (int)pg.size();
+        pg.push_back(g);
+        ph.push_back(h);
+      }
+  x->n_pairs = (int)pg.size();
+  // Jacobi blocks (g occupied, h virtual), greedy rounds in (g, h) order (section 3.5)
+  {
+    int maxdeg = 0;
+    for (int g = 0; g < G; ++g) maxdeg = std::max(maxdeg, gn_ptr[g + 1] - gn_ptr[g]);
+    const int RMAX = 2 * maxdeg + 2;
+    std::vector<uint8_t> used_o((size_t)G * RMAX, 0), used_v((size_t)G * RMAX, 0);
+    for (int g = 0; g < G; ++g) {
+      if (nocc[g] == 0) continue;
+      for (int k = gn_ptr[g]; k < gn_ptr[g + 1]; ++k) {
+        const int h = gn[k];
+        if (nvirt[h] == 0) continue;
+        int r = 0;
+        while (used_o[(size_t)g * RMAX + r] || used_v[(size_t)h * RMAX + r]) ++r;
+        used_o[(size_t)g * RMAX + r] = used_v[(size_t)h * RMAX + r] = 1;
+        x->h_jb_g.push_back(g);
+        x->h_jb_h.push_back(h);
+        x->h_jb_round.push_back(r);
+        x->n_rounds = std::max(x->n_rounds, r + 1);
+      }
+    }
+    x->n_blocks = (int)x->h_jb_g.size();
+    x->h_round_ptr.assign(x->n_rounds + 1, 0);
+    for (int r : x->h_jb_round) x->h_round_ptr[r + 1]++;
+    for (int r = 0; r < x->n_rounds; ++r) x->h_round_ptr[r + 1] += x->h_round_ptr[r];
+  }
+  std::vector<int> round_list(x->n_blocks), jb_nocc(x->n_blocks), jb_nvirt(x->n_blocks);
+  {
+    std::vector<int> fillp(x->h_round_ptr.begin(), x->h_round_ptr.end() - 1);
+    for (int b = 0; b < x->n_blocks; ++b) {
+      round_list[fillp[x->h_jb_round[b]]++] = b;
+      jb_nocc[b] = nocc[x->h_jb_g[b]];
+      jb_nvirt[b] = nvirt[x->h_jb_h[b]];
+    }
+  }
+
+  // ---- device memory -------------------------------------------------------------------
+  for (auto& e : x->ev) HIPC(hipEventCreate(&e));
+  hipStream_t s = x->stream;
+  x->xyz = x->upload(d->xyz_bohr, (size_t)3 * na);
+  x->U = x->upload(d->hubbard_u, na);
+  x->q0 = x->upload(d->q0, na);
+  x->ao_atom = x->upload(ao_atom.data(), ao_atom.size());
+  x->ao_off = x->upload(ao_off.data(), ao_off.size());
+  x->xs_ptr = x->upload(xs_ptr.data(), xs_ptr.size());
+  x->xs_col = x->upload(xs_col.data(), xs_col.size());
+  x->xs_row = x->upload(xs_row.data(), xs_row.size());
+  x->val_map = x->upload(val_map.data(), val_map.size());
+  v.xyz = x->xyz;
+  v.U = x->U;
+  v.q0 = x->q0;
+  v.ao_atom = x->ao_atom;
+  v.xs_ptr = x->xs_ptr;
+  v.xs_col = x->xs_col;
+  v.xs_row = x->xs_row;
+  const size_t nxe = (size_t)v.nbx * 256;
+  x->S = x->dalloc<double>(nxe);
+  x->H0 = x->dalloc<double>(nxe);
+  x->H = x->dalloc<double>(nxe);
+  HIPC(hipMemsetAsync(x->S, 0, nxe * sizeof(double), s));
+  HIPC(hipMemsetAsync(x->H0, 0, nxe * sizeof(double), s));
+  {
+    double* tmp = x->upload(d->S_val, d->n_val);
+    launch_scatter(x->val_map, d->n_val, tmp, x->S, s);
+    x->dfree(tmp);
+    tmp = x->upload(d->H0_val, d->n_val);
+    launch_scatter(x->val_map, d->n_val, tmp, x->H0, s);
+    x->dfree(tmp);
+  }
+  x->h_blk_rowptr.assign(rp, rp + na + 1);
+  x->h_blk_col.assign(d->blk_col, d->blk_col + rp[na]);
+  x->h_blk_off.assign(d->blk_off, d->blk_off + rp[na]);
+  x->h_atom_nao.assign(d->atom_nao, d->atom_nao + na);
+  const size_t ntiles = (size_t)G * v.n_rb;
+  const size_t tile_elems = (size_t)RB * v.W;
+  for (int b = 0; b < 2; ++b) {
+    x->C[b] = x->dalloc<double>(ntiles * tile_elems);
+    HIPC(hipMemsetAsync(x->C[b], 0, ntiles * tile_elems * sizeof(double), s));
+    x->actC[b] = x->dalloc<uint8_t>(ntiles);
+    HIPC(hipMemsetAsync(x->actC[b], 0, ntiles, s));
+    x->listC[b] = x->dalloc<int>(ntiles);
+    x->cntC[b] = x->dalloc<int>(G);
+    HIPC(hipMemsetAsync(x->cntC[b], 0, sizeof(int) * G, s));
+  }
+  x->Y = x->dalloc<double>(ntiles * tile_elems);
+  x->actY = x->dalloc<uint8_t>(ntiles);
+  x->listY = x->dalloc<int>(ntiles);
+  x->cntY = x->dalloc<int>(G);
+  x->act_tmp = x->dalloc<uint8_t>(ntiles);
+  x->list_tmp = x->dalloc<int>(ntiles);
+  x->cnt_tmp = x->dalloc<int>(G);
+  x->pnocc = x->upload(nocc.data(), G);
+  x->pnvirt = x->upload(nvirt.data(), G);
+  x->mo_of = x->upload(x->h_mo_of.data(), x->h_mo_of.size());
+  x->gn_ptr = x->upload(gn_ptr.data(), gn_ptr.size());
+  x->gn = x->upload(gn.data(), gn.size());
+  x->pair_of = x->upload(pair_of.data(), pair_of.size());
+  x->pg = x->upload(pg.data(), pg.size());
+  x->ph = x->upload(ph.data(), ph.size());
+  x->self_pair = x->upload(self_pair.data(), self_pair.size());
+  x->O = x->dalloc<double>((size_t)x->n_pairs * v.W * v.W);
+  x->sc = x->dalloc<double>((size_t)G * v.W);
+  x->upd = x->dalloc<uint8_t>((size_t)G * v.W);
+  x->pair_sel = x->dalloc<uint8_t>(x->n_pairs);
+  x->jb_g = x->upload(x->h_jb_g.data(), x->n_blocks);
+  x->jb_h = x->upload(x->h_jb_h.data(), x->n_blocks);
+  x->jb_nocc = x->upload(jb_nocc.data(), x->n_blocks);
+  x->jb_nvirt = x->upload(jb_nvirt.data(), x->n_blocks);
+  x->round_list = x->upload(round_list.data(), x->n_blocks);
+  const size_t per = (size_t)v.OW * v.VW;
+  x->F = x->dalloc<double>((size_t)x->n_blocks * per);
+  x->Fdiag = x->dalloc<double>((size_t)G * v.W);
+  x->dvec = x->dalloc<double>((size_t)G * v.W);
+  x->rot_cnt = x->dalloc<int>(x->n_blocks);
+  x->rot_col = x->dalloc<int2>((size_t)x->n_blocks * per);
+  x->rot_cs = x->dalloc<double2>((size_t)x->n_blocks * per);
+  x->tcnt = x->dalloc<int>(x->n_blocks);
+  x->tcol = x->dalloc<int>((size_t)x->n_blocks * v.W);
+  x->hist = x->dalloc<unsigned int>(256);
+  HIPC(hipMemsetAsync(x->hist, 0, 256 * sizeof(unsigned int), s));
+  x->ties = x->dalloc<long long>(MAX_TIES);
+  x->q = x->dalloc<double>(na);
+  x->q_prev = x->dalloc<double>(na);
+  x->dq = x->dalloc<double>(na);
+  x->Q = x->dalloc<double>(na);
+  HIPC(hipMemsetAsync(x->q, 0, sizeof(double) * na, s));
+  x->rowq = x->dalloc<double>(v.n_ao);
+  x->sd = x->dalloc<Scalars>(1);
+  HIPC(hipMemsetAsync(x->sd, 0, sizeof(Scalars), s));
+  x->pctr = x->dalloc<unsigned long long>(SSCF_N_KERNEL_CLASSES);
+  HIPC(hipMemsetAsync(x->pctr, 0, sizeof(unsigned long long) * SSCF_N_KERNEL_CLASSES, s));
+
+  // C0 into the tiles
+  {
+    std::vector<int64_t> col_of(nnz0);
+    for (int j = 0; j < v.n_mo; ++j)
+      for (int64_t t = cp[j]; t < cp[j + 1]; ++t) col_of[t] = j;
+    int64_t* dcol = x->upload(col_of.data(), nnz0);
+    int* drow = x->upload(d->c0_row, nnz0);
+    double* dval = x->upload(d->c0_val, nnz0);
+    int* dpanel = x->upload(mo_panel.data(), v.n_mo);
+    int* dcolm = x->upload(mo_col.data(), v.n_mo);
+    launch_scatter_c0(v, (int)nnz0, dcol, drow, dval, dpanel, dcolm, x->C[0], x->actC[0], s);
+    x->cur = 0;
+    x->rebuild_list(0);
+    x->dfree(dcol); x->dfree(drow); x->dfree(dval); x->dfree(dpanel); x->dfree(dcolm);
+  }
+  x->sync();
+
+  // initial orthonormalization (section 3.4), charges and energy
+  HIPC(hipEventRecord(x->ev[0], s));
+  double eta = 0.0;
+  int conv = 0;
+  const int sweeps = x->orthonormalize(0, x->max_sweeps_init, &eta, &conv);
+  if (!conv) fail(SSCF_E_ORTHO, "initial orthonormalization did not reach eps/100 in %d sweeps (eta %.3e)", sweeps, eta);
+  x->charges(0);
+  HIPC(hipMemcpyAsync(x->q_prev, x->q, sizeof(double) * na, hipMemcpyDeviceToDevice, s));
+  x->energy_terms();
+  HIPC(hipEventRecord(x->ev[1], s));
+  const Scalars h = x->read_scalars();
+  x->E = h.e_band + h.e_coul;
+  sscf_step_info& ii = x->init_info;
+  std::memset(&ii, 0, sizeof(ii));
+  ii.energy = x->E;
+  ii.e_band = h.e_band;
+  ii.e_coul = h.e_coul;
+  ii.ortho_eta = eta;
+  ii.n_ortho_sweeps = sweeps;
+  ii.ortho_converged = conv;
+  ii.nnz_tiles = x->active_tiles();
+  float ms = 0.f;
+  HIPC(hipEventElapsedTime(&ms, x->ev[0], x->ev[1]));
+  ii.ms_ortho = ms;
+  ii.ms_total = ms;
+  x->pcollect();
+}
+
+// one SCF step
+static void step(sscf_ctx* x, sscf_step_info* out) {
+  View& v = x->v;
+  hipStream_t s = x->stream;
+  sscf_step_info info;
+  std::memset(&info, 0, sizeof(info));
+  const double E_prev = x->E;
+  HIPC(hipMemsetAsync(x->sd, 0, offsetof(Scalars, e_band), s));
+  HIPC(hipEventRecord(x->ev[0], s));
+  // step IV: Fock matrix with the charges of the previous step (Q = gamma dq)
+  int pi = x->pbegin(KC_FOCK);
+  launch_fock(v, x->S, x->H0, x->fock_full ? x->Hfull : nullptr, x->Q, x->eps, x->H, s);
+  x->pend(pi);
+  HIPC(hipEventRecord(x->ev[1], s));
+  // C^T H C: occupied-virtual blocks and the diagonal
+  x->product(x->H, true);
+  pi = x->pbegin(KC_PAIR_F);
+  launch_pair(v, x->n_blocks, x->jb_g, x->jb_h, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur], x->Y, x->actY, 0,
+              v.OW / 16, v.OW, v.VW / 16, x->F, v.VW, (size_t)v.OW * v.VW, x->ctr(KC_PAIR_F), s);
+  x->pend(pi);
+  launch_coldot(v, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur], x->Y, x->actY, x->Fdiag, s);
+  HIPC(hipEventRecord(x->ev[2], s));
+  // step V: selection of the rotations
+  pi = x->pbegin(KC_SELECT);
+  launch_count_candidates(x->n_blocks, v.OW, v.VW, x->jb_nocc, x->jb_nvirt, x->F, x->eps, x->sd, s);
+  x->pend(pi);
+  int n_cand = 0;
+  HIPC(hipMemcpyAsync(&n_cand, &x->sd->n_cand, sizeof(int), hipMemcpyDeviceToHost, s));
+  x->sync();
+  const long long K = (long long)std::floor(x->rot_cap * v.n_occ);
+  pi = x->pbegin(KC_SELECT);
+  if (n_cand <= K) {
+    launch_sel_init(x->sd, K, 1, s);
+  } else {
+    launch_sel_init(x->sd, K, 0, s);
+    for (int shift = 56; shift >= 0; shift -= 8)
+      launch_radix_pass(x->n_blocks, v.OW, v.VW, x->jb_nocc, x->jb_nvirt, x->F, x->eps, shift, x->sd, x->hist, s);
+    launch_sel_finish(x->sd, s);
+    launch_tie_cut(x->n_blocks, v.OW, v.VW, x->jb_g, x->jb_h, x->jb_nocc, x->jb_nvirt, x->F, x->mo_of, v.W, v.n_mo,
+                   x->eps, x->sd, x->ties, s);
+  }
+  launch_block_select(v, x->n_blocks, x->jb_g, x->jb_h, x->jb_nocc, x->jb_nvirt, x->F, x->Fdiag, x->mo_of, x->eps,
+                      x->sd, x->rot_cnt, x->rot_col, x->rot_cs, x->tcnt, x->tcol, s);
+  x->pend(pi);
+  HIPC(hipEventRecord(x->ev[3], s));
+  // rotations, round by round
+  for (int r = 0; r < x->n_rounds; ++r) {
+    const int b0 = x->h_round_ptr[r], b1 = x->h_round_ptr[r + 1];
+    const int pg_ = x->pbegin(KC_GIVENS);
+    launch_givens_round(v, b1 - b0, x->round_list + b0, x->jb_g, x->jb_h, x->rot_cnt, x->rot_col, x->rot_cs, x->tcnt,
+                        x->tcol, x->eps, x->C[x->cur], x->actC[x->cur], x->ctr(KC_GIVENS), s);
+    x->pend(pg_);
+  }
+  x->rebuild_list(x->cur);
+  HIPC(hipEventRecord(x->ev[4], s));
+  // step III: re-orthonormalization
+  double eta = 0.0;
+  int conv = 0;
+  info.n_ortho_sweeps = x->orthonormalize(0, x->max_sweeps_step, &eta, &conv);
+  info.ortho_eta = eta;
+  info.ortho_converged = conv;
+  HIPC(hipEventRecord(x->ev[5], s));
+  // charges, Coulomb term, energy
+  x->charges(1);
+  x->energy_terms();
+  HIPC(hipEventRecord(x->ev[6], s));
+  Scalars h = x->read_scalars();
+  if (h.err & 2) fail(SSCF_E_CAPACITY, "more than %d rotation candidates share the cut-off |F|", MAX_TIES);
+  double E = h.e_band + h.e_coul;
+  std::memcpy(&info.dq_max, &h.dq_bits, sizeof(double));
+  std::memcpy(&info.max_abs_fov, &h.fov_bits, sizeof(double));
+  info.n_candidates = h.n_cand;
+  info.n_rotations = h.n_rot;
+  info.delta_e = E - E_prev;
+  info.converged = std::fabs(info.delta_e) < x->e_conv;
+  if (info.converged) {
+    // occupied-only orthonormalization after convergence (section 4.1)
+    double eta2 = 0.0;
+    int conv2 = 0;
+    x->orthonormalize(1, x->max_sweeps_step, &eta2, &conv2);
+    info.post_ortho = 1;
+    x->charges(0);
+    x->energy_terms();
+    h = x->read_scalars();
+    E = h.e_band + h.e_coul;
+  }
+  HIPC(hipEventRecord(x->ev[7], s));
+  x->sync();
+  info.energy = E;
+  info.e_band = h.e_band;
+  info.e_coul = h.e_coul;
+  info.nnz_tiles = x->active_tiles();
+  float t[7];
+  for (int i = 0; i < 7; ++i) HIPC(hipEventElapsedTime(&t[i], x->ev[i], x->ev[i + 1]));
+  info.ms_fock = t[0];
+  info.ms_cfc = t[1];
+  info.ms_select = t[2];
+  info.ms_rot = t[3];
+  info.ms_ortho = t[4];
+  info.ms_sums = t[5] + t[6];
+  HIPC(hipEventElapsedTime(&info.ms_total, x->ev[0], x->ev[7]));
+  x->E = E;
+  x->pcollect();
+  if (out) *out = info;
+}
+
+// =========================================================================================
+// C ABI
+// =========================================================================================
+
+template <class Fn>
+static sscf_status guarded(sscf_ctx* x, Fn&& fn) {
+  try {
+    fn();
+  } catch (const Fail& f) {
+    x->err = f.msg;
+    if (f.code == SSCF_E_HIP) x->failed = true;
+    return f.code;
+  } catch (const std::exception& e) {
+    x->err = e.what();
+    return SSCF_E_NOMEM;
+  }
+  return SSCF_OK;
+}
+
+extern "C" {
+
+sscf_status sscf_init_system(const sscf_system_desc* desc, sscf_ctx** out) {
+  if (!out) { g_init_error = "out is NULL"; return SSCF_E_INVALID_ARG; }
+  *out = nullptr;
+  sscf_ctx* x = nullptr;
+  try {
+    x = new sscf_ctx();
+    build(x, desc);
+  } catch (const Fail& f) {
+    g_init_error = f.msg;
+    if (x) { x->release(); delete x; }
+    return f.code;
+  } catch (const std::exception& e) {
+    g_init_error = e.what();
+    if (x) { x->release(); delete x; }
+    return SSCF_E_NOMEM;
+  }
+  g_init_error.clear();
+  *out = x;
+  return SSCF_OK;
+}
+
+sscf_status sscf_set_fock(sscf_ctx* x, const double* f_val, int32_t mode) {
+  if (!x) return SSCF_E_INVALID_ARG;
+  return guarded(x, [&] {
+    if (x->failed) fail(SSCF_E_STATE, "context failed earlier: %s", x->err.c_str());
+    if (!f_val || (mode != SSCF_FOCK_H0 && mode != SSCF_FOCK_FULL)) fail(SSCF_E_INVALID_ARG, "bad set_fock arguments");
+    for (int64_t t = 0; t < x->n_val; ++t)
+      if (!std::isfinite(f_val[t])) fail(SSCF_E_INVALID_ARG, "non-finite Fock value at %lld", (long long)t);
+    const auto& rp = x->h_blk_rowptr;
+    const auto& col = x->h_blk_col;
+    for (int a = 0; a < x->v.n_atoms; ++a)
+      for (int64_t k = rp[a]; k < rp[a + 1]; ++k) {
+        const int b = col[k];
+        const int64_t kt = std::lower_bound(col.begin() + rp[b], col.begin() + rp[b + 1], a) - col.begin();
+        const int nA = x->h_atom_nao[a], nB = x->h_atom_nao[b];
+        for (int i = 0; i < nA; ++i)
+          for (int j = 0; j < nB; ++j)
+            if (f_val[x->h_blk_off[k] + (int64_t)i * nB + j] != f_val[x->h_blk_off[kt] + (int64_t)j * nA + i])
+              fail(SSCF_E_INVALID_ARG, "Fock matrix is not symmetric (atoms %d, %d)", a, b);
+      }
+    const size_t nxe = (size_t)x->v.nbx * 256;
+    double* tmp = x->upload(f_val, x->n_val);
+    double* dst = (mode == SSCF_FOCK_H0) ? x->H0 : (x->Hfull ? x->Hfull : (x->Hfull = x->dalloc<double>(nxe)));
+    HIPC(hipMemsetAsync(dst, 0, nxe * sizeof(double), x->stream));
+    launch_scatter(x->val_map, x->n_val, tmp, dst, x->stream);
+    x->dfree(tmp);
+    x->fock_full = (mode == SSCF_FOCK_FULL);
+    x->sync();
+  });
+}
+
+sscf_status sscf_scf_step(sscf_ctx* x, sscf_step_info* info) {
+  if (!x) return SSCF_E_INVALID_ARG;
+  return guarded(x, [&] {
+    if (x->failed) fail(SSCF_E_STATE, "context failed earlier: %s", x->err.c_str());
+    step(x, info);
+  });
+}
+
+sscf_status sscf_get_energy(const sscf_ctx* x, double* e) {
+  if (!x || !e) return SSCF_E_INVALID_ARG;
+  *e = x->E;
+  return SSCF_OK;
+}
+
+sscf_status sscf_init_info(const sscf_ctx* x, sscf_step_info* info) {
+  if (!x || !info) return SSCF_E_INVALID_ARG;
+  *info = x->init_info;
+  return SSCF_OK;
+}
+
+sscf_status sscf_get_charges(const sscf_ctx* cx, double* q, size_t n) {
+  sscf_ctx* x = const_cast<sscf_ctx*>(cx);
+  if (!x || !q || n < (size_t)x->v.n_atoms) return SSCF_E_INVALID_ARG;
+  return guarded(x, [&] {
+    HIPC(hipMemcpyAsync(q, x->q, sizeof(double) * x->v.n_atoms, hipMemcpyDeviceToHost, x->stream));
+    x->sync();
+  });
+}
+
+sscf_status sscf_get_density(const sscf_ctx* cx, double* p_val, size_t n_val) {
+  sscf_ctx* x = const_cast<sscf_ctx*>(cx);
+  if (!x || !p_val || n_val < (size_t)x->n_val) return SSCF_E_INVALID_ARG;
+  return guarded(x, [&] {
+    if (!x->pblk) x->pblk = x->dalloc<double>((size_t)x->v.nbx * 256);
+    if (!x->pval) x->pval = x->dalloc<double>(x->n_val);
+    launch_density_blocks(x->v, x->C[x->cur], x->actC[x->cur], x->pnocc, x->pblk, x->stream);
+    launch_gather(x->val_map, x->n_val, x->pblk, x->pval, x->stream);
+    HIPC(hipMemcpyAsync(p_val, x->pval, sizeof(double) * x->n_val, hipMemcpyDeviceToHost, x->stream));
+    x->sync();
+  });
+}
+
+sscf_status sscf_get_mo_coefficients(const sscf_ctx* cx, int64_t* colptr, int32_t* row, double* val, int64_t* nnz) {
+  sscf_ctx* x = const_cast<sscf_ctx*>(cx);
+  if (!x || !nnz) return SSCF_E_INVALID_ARG;
+  return guarded(x, [&] {
+    const View& v = x->v;
+    const size_t ntiles = (size_t)v.G * v.n_rb;
+    std::vector<uint8_t> act(ntiles);
+    HIPC(hipMemcpyAsync(act.data(), x->actC[x->cur], ntiles, hipMemcpyDeviceToHost, x->stream));
+    x->sync();
+    std::vector<std::vector<std::pair<int32_t, double>>> cols(v.n_mo);
+    std::vector<double> tile((size_t)RB * v.W);
+    for (int g = 0; g < v.G; ++g)
+      for (int r = 0; r < v.n_rb; ++r) {
+        const size_t t = (size_t)g * v.n_rb + r;
+        if (!act[t]) continue;
+        HIPC(hipMemcpyAsync(tile.data(), x->C[x->cur] + t * RB * v.W, sizeof(double) * RB * v.W,
+                            hipMemcpyDeviceToHost, x->stream));
+        x->sync();
+        for (int k = 0; k < RB; ++k)
+          for (int c = 0; c < v.W; ++c) {
+            const double val_ = tile[(size_t)k * v.W + c];
+            const int j = x->h_mo_of[(size_t)g * v.W + c];
+            if (val_ != 0.0 && j >= 0) cols[j].push_back({r * RB + k, val_});
+          }
+      }
+    int64_t total = 0;
+    for (auto& c : cols) total += (int64_t)c.size();
+    if (row && val && colptr) {
+      if (*nnz < total) fail(SSCF_E_INVALID_ARG, "buffers too small: %lld entries needed", (long long)total);
+      int64_t p = 0;
+      colptr[0] = 0;
+      for (int j = 0; j < v.n_mo; ++j) {
+        for (auto& e : cols[j]) { row[p] = e.first; val[p] = e.second; ++p; }
+        colptr[j + 1] = p;
+      }
+    }
+    *nnz = total;
+  });
+}
+
+sscf_status sscf_get_schedule(const sscf_ctx* x, int32_t* g, int32_t* h, int32_t* round, int32_t* n_blocks) {
+  if (!x || !n_blocks) return SSCF_E_INVALID_ARG;
+  if (g && h && round) {
+    if (*n_blocks < x->n_blocks) return SSCF_E_INVALID_ARG;
+    for (int b = 0; b < x->n_blocks; ++b) { g[b] = x->h_jb_g[b]; h[b] = x->h_jb_h[b]; round[b] = x->h_jb_round[b]; }
+  }
+  *n_blocks = x->n_blocks;
+  return SSCF_OK;
+}
+
+sscf_status sscf_get_kernel_stats(const sscf_ctx* cx, sscf_kernel_stat* out, int32_t* n) {
+  sscf_ctx* x = const_cast<sscf_ctx*>(cx);
+  if (!x || !n) return SSCF_E_INVALID_ARG;
+  if (!out) { *n = SSCF_N_KERNEL_CLASSES; return SSCF_OK; }
+  if (*n < SSCF_N_KERNEL_CLASSES) return SSCF_E_INVALID_ARG;
+  return guarded(x, [&] {
+    if (!x->prof) fail(SSCF_E_STATE, "profiling was not requested (SSCF_FLAG_PROFILE)");
+    unsigned long long c[SSCF_N_KERNEL_CLASSES];
+    HIPC(hipMemcpyAsync(c, x->pctr, sizeof(c), hipMemcpyDeviceToHost, x->stream));
+    x->sync();
+    for (int k = 0; k < SSCF_N_KERNEL_CLASSES; ++k) {
+      std::memset(out[k].name, 0, sizeof(out[k].name));
+      std::strncpy(out[k].name, KC_NAME[k], sizeof(out[k].name) - 1);
+      out[k].launches = x->plaunch[k];
+      out[k].ms = x->pms[k];
+      out[k].flops = KC_FLOP_PER_UNIT[k] * (double)c[k];
+      out[k].bytes = KC_BYTE_PER_UNIT[k] * (double)c[k];
+    }
+    *n = SSCF_N_KERNEL_CLASSES;
+  });
+}
+
+sscf_status sscf_reset_kernel_stats(sscf_ctx* x) {
+  if (!x) return SSCF_E_INVALID_ARG;
+  return guarded(x, [&] {
+    if (!x->prof) fail(SSCF_E_STATE, "profiling was not requested (SSCF_FLAG_PROFILE)");
+    x->pcollect();
+    for (int k = 0; k < SSCF_N_KERNEL_CLASSES; ++k) { x->pms[k] = 0.0; x->plaunch[k] = 0; }
+    HIPC(hipMemsetAsync(x->pctr, 0, sizeof(unsigned long long) * SSCF_N_KERNEL_CLASSES, x->stream));
+    x->sync();
+  });
+}
+
+void sscf_destroy(sscf_ctx* x) {
+  if (!x) return;
+  x->release();
+  delete x;
+}
+
+const char* sscf_last_error(const sscf_ctx* x) {
+  if (!x) return g_init_error.c_str();
+  return x->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,135 @@
+// Internal declarations of the gfx950 sparse SCF library: data layout and
+// kernel launchers.  Not part of the public C ABI (include/sscf.h).
+//
+// Layout in HBM (MI355X, 288 GB per GPU):
+//  * AOs are grouped in row blocks of RB = 16 consecutive AOs (n_rb blocks).
+//  * The MOs of MO group g (section 3.2) form panel g of W columns: occupied
+//    MOs in columns [0, OW), virtual MOs in [OW, OW + VW) = [OW, W); unused
+//    columns are zero.  W, OW, VW are multiples of 16.
+//  * C is stored with dense capacity: tile (g, r) holds rows 16 r .. 16 r + 15
+//    of panel g as a row-major 16 x W block at C + (g * n_rb + r) * 16 W.
+//    act[g * n_rb + r] tells whether the tile may hold nonzeros; an inactive C
+//    tile is all zeros.  list[g * n_rb + t], t < cnt[g], are the active row
+//    blocks of panel g in increasing order.
+//  * S, H0 and H are stored as 16 x 16 row-major blocks on the row-block
+//    pattern of the atom-neighbour map (block-CSR: xs_ptr, xs_col, xs_row).
+//  * C^T S C is kept as W x W blocks for the unordered neighbour pairs
+//    (g <= h); the occupied-virtual part of C^T H C as OW x VW blocks for the
+//    Jacobi blocks (g occupied, h virtual).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace sscf {
+
+constexpr int RB = 16;           // AOs per row block
+constexpr int MAX_W = 128;       // widest panel supported
+constexpr int MAX_TIES = 4096;   // candidates sharing the cut-off |F| that can be ordered
+
+// scalars shared between kernels and the host (one device copy per context)
+struct Scalars {
+  unsigned long long eta_bits;      // max |D_ij| (bits of a non-negative double)
+  unsigned long long fov_bits;      // max |F_ia|
+  unsigned long long dq_bits;       // max |q_a - q_prev_a|
+  unsigned long long cut_key;       // |F| key of the last selected rotation
+  long long tie_cut;                // largest (i * n_mo + a) taken among ties at cut_key
+  long long remaining;              // radix selection state
+  unsigned long long prefix, mask;
+  int n_cand;
+  int n_rot;
+  int err;                          // 1: non-positive diagonal of C^T S C
+  int tie_count;                    // keys equal to cut_key (from the last radix pass)
+  int tie_n;                        // tie keys collected
+  double e_band, e_coul;
+  double eta;
+};
+
+struct View {
+  // sizes
+  int n_atoms, n_ao, n_rb, n_mo, n_occ, G, W, OW, VW;
+  // geometry
+  const double* xyz;
+  const double* U;
+  const double* q0;
+  const int* ao_atom;
+  // row-block pattern
+  int nbx;
+  const int* xs_ptr;
+  const int* xs_col;
+  const int* xs_row;
+};
+
+// ---- launchers (sscf_kernels.hip) ------------------------------------------------------
+void launch_fill(double* p, size_t n, double v, hipStream_t s);
+void launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t s);
+void launch_fill_i32(int* p, size_t n, int v, hipStream_t s);
+void launch_scatter_c0(const View& v, int nnz, const int64_t* colptr_expanded_col, const int* row,
+                       const double* val, const int* mo_panel, const int* mo_col, double* C,
+                       uint8_t* act, hipStream_t s);
+void launch_dilate(const View& v, const uint8_t* actC, uint8_t* actY, hipStream_t s);
+void launch_list(const View& v, const uint8_t* act, int* list, int* cnt, hipStream_t s);
+void launch_spmm(const View& v, const double* X, const double* C, const uint8_t* actC,
+                 const int* listY, const int* cntY, double* Y, unsigned long long* ctr, hipStream_t s);
+void launch_pair(const View& v, int n_pairs, const int* pg, const int* ph, const double* C,
+                 const int* listC, const int* cntC, const double* Y, const uint8_t* actY,
+                 int row_off, int MT, int col_off, int NT, double* out, int ld, size_t out_stride,
+                 unsigned long long* ctr, hipStream_t s);
+void launch_coldot(const View& v, const double* C, const int* listC, const int* cntC,
+                   const double* Y, const uint8_t* actY, double* out, hipStream_t s);
+void launch_ortho_scale(const View& v, int n_pairs_self, const int* self_pair, const double* O,
+                        const int* pnocc, const int* pnvirt, int occ_only, double* sc,
+                        Scalars* sd, hipStream_t s);
+void launch_normalize_d(const View& v, int n_pairs, const int* pg, const int* ph, double* O,
+                        const double* sc, const int* pnocc, const int* pnvirt, int occ_only,
+                        Scalars* sd, hipStream_t s);
+void launch_scale_c(const View& v, double* C, const int* listC, const int* cntC, const double* sc,
+                    hipStream_t s);
+void launch_mark_selected(const View& v, int n_pairs, const int* pg, const int* ph, const double* D,
+                          const Scalars* sd, uint8_t* pair_sel, uint8_t* upd, hipStream_t s);
+void launch_update_support(const View& v, const uint8_t* actC, const int* gn_ptr, const int* gn,
+                           const int* pair_of, const uint8_t* pair_sel, uint8_t* act_new,
+                           hipStream_t s);
+void launch_clear_tiles(const View& v, double* C, uint8_t* act, const int* list, const int* cnt,
+                        hipStream_t s);
+void launch_ortho_update(const View& v, const double* C, const uint8_t* actC, const int* gn_ptr,
+                         const int* gn, const int* pair_of, const uint8_t* pair_sel, const double* D,
+                         const Scalars* sd, const uint8_t* upd, double cut, const int* listN,
+                         const int* cntN, double* Cn, uint8_t* actN, unsigned long long* ctr,
+                         hipStream_t s);
+void launch_coulomb(const View& v, int scc, const double* dq, double* Q, hipStream_t s);
+void launch_fock(const View& v, const double* S, const double* H0, const double* Hfull,
+                 const double* Q, double eps, double* H, hipStream_t s);
+void launch_count_candidates(int nb, int OW, int VW, const int* jb_nocc, const int* jb_nvirt,
+                             const double* F, double tau, Scalars* sd, hipStream_t s);
+void launch_radix_pass(int nb, int OW, int VW, const int* jb_nocc, const int* jb_nvirt,
+                       const double* F, double tau, int shift, Scalars* sd, unsigned int* hist,
+                       hipStream_t s);
+void launch_sel_init(Scalars* sd, long long K, int select_all, hipStream_t s);
+void launch_sel_finish(Scalars* sd, hipStream_t s);
+void launch_tie_cut(int nb, int OW, int VW, const int* jb_g, const int* jb_h, const int* jb_nocc,
+                    const int* jb_nvirt, const double* F, const int* mo_of, int W, long long n_mo,
+                    double tau, Scalars* sd, long long* ties, hipStream_t s);
+void launch_block_select(const View& v, int nb, const int* jb_g, const int* jb_h, const int* jb_nocc,
+                         const int* jb_nvirt, const double* F, const double* Fdiag, const int* mo_of,
+                         double tau, Scalars* sd, int* rot_cnt, int2* rot_col, double2* rot_cs,
+                         int* tcnt, int* tcol, hipStream_t s);
+void launch_givens_round(const View& v, int n_round_blocks, const int* round_blocks,
+                         const int* jb_g, const int* jb_h, const int* rot_cnt, const int2* rot_col,
+                         const double2* rot_cs, const int* tcnt, const int* tcol, double eps,
+                         double* C, uint8_t* actC, unsigned long long* ctr, hipStream_t s);
+void launch_charges_rows(const View& v, const double* C, const uint8_t* actC, const double* Y,
+                         const uint8_t* actY, const double* sc, const int* pnocc, double* rowq,
+                         hipStream_t s);
+void launch_atom_charges(const View& v, const int64_t* ao_off, const double* rowq, double* q,
+                         double* q_prev, double* dq, Scalars* sd, int shift_prev, hipStream_t s);
+void launch_sum_band(const View& v, const double* d, const int* pnocc, Scalars* sd, hipStream_t s);
+void launch_sum_coul(const View& v, int scc, const double* dq, const double* Q, Scalars* sd,
+                     hipStream_t s);
+void launch_density_blocks(const View& v, const double* C, const uint8_t* actC, const int* pnocc,
+                           double* P, hipStream_t s);
+void launch_gather(const int64_t* map, int64_t n, const double* src, double* dst, hipStream_t s);
+void launch_scatter(const int64_t* map, int64_t n, const double* src, double* dst, hipStream_t s);
+
+}  // namespace sscf

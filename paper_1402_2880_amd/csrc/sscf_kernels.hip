@@ -1,0 +1,1046 @@
+// HIP kernels of the sparse SCF hot path for gfx950 (MI355X, wave64).
+//
+// Paper: A. Scemama, N. Renon, M. Rapacioli, "A Sparse SCF algorithm and its
+// parallel implementation: Application to DFTB", arXiv:1402.2880.
+//
+// The C^T X C products of section 3.6 (X = S for the orthonormalization,
+// X = H for the partial diagonalization) run as block-sparse products of dense
+// 16-row tiles on the FP64 matrix cores (v_mfma_f64_16x16x4f64).  The pair
+// combinations of section 3.4 are the product C D_sel on the same tiles.  The
+// Jacobi rotations of section 3.5 are applied round by round, one thread per
+// AO row, since rows of C are independent under right multiplication.
+//
+// FP64 16x16x4 MFMA operand layout (lane l of the wave): A[l % 16][l / 16],
+// B[l / 16][l % 16]; result register r holds D[l / 16 + 4 r][l % 16].
+#include "sscf_internal.h"
+
+#include <math.h>
+
+namespace sscf {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ unsigned long long dbits(double x) {
+  return (unsigned long long)__double_as_longlong(x);
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+__device__ __forceinline__ int wave_sum_i(int v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// block-wide max of a non-negative double, folded into *bits with atomicMax
+__device__ void block_max_to(double v, unsigned long long* bits) {
+  __shared__ double red[16];
+  v = wave_max(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) m = fmax(m, red[i]);
+    atomicMax(bits, dbits(m));
+  }
+}
+
+static inline unsigned int nblk(size_t n, int t) { return (unsigned int)((n + t - 1) / t); }
+
+// ---------------------------------------------------------------------------------------
+// small utilities
+// ---------------------------------------------------------------------------------------
+
+__global__ void k_fill(double* p, size_t n, double v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_u8(uint8_t* p, size_t n, uint8_t v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_i32(int* p, size_t n, int v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+void launch_fill(double* p, size_t n, double v, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_fill, dim3(nblk(n, 256) < 65536 ? nblk(n, 256) : 65536), dim3(256), 0, s, p, n, v);
+}
+void launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_fill_u8, dim3(nblk(n, 256) < 65536 ? nblk(n, 256) : 65536), dim3(256), 0, s, p, n, v);
+}
+void launch_fill_i32(int* p, size_t n, int v, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_fill_i32, dim3(nblk(n, 256) < 65536 ? nblk(n, 256) : 65536), dim3(256), 0, s, p, n, v);
+}
+
+__global__ void k_gather(const int64_t* map, int64_t n, const double* src, double* dst) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[map[i]];
+}
+__global__ void k_scatter(const int64_t* map, int64_t n, const double* src, double* dst) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) dst[map[i]] = src[i];
+}
+void launch_gather(const int64_t* map, int64_t n, const double* src, double* dst, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_gather, dim3(nblk(n, 256)), dim3(256), 0, s, map, n, src, dst);
+}
+void launch_scatter(const int64_t* map, int64_t n, const double* src, double* dst, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_scatter, dim3(nblk(n, 256)), dim3(256), 0, s, map, n, src, dst);
+}
+
+// C0 (one entry per thread) into the tiles
+__global__ void k_scatter_c0(int nnz, const int64_t* col_of, const int* row, const double* val,
+                             const int* mo_panel, const int* mo_col, int n_rb, int W, double* C,
+                             uint8_t* act) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  const int j = (int)col_of[e];
+  const int mu = row[e];
+  const int g = mo_panel[j];
+  const size_t tile = (size_t)g * n_rb + mu / RB;
+  C[(tile * RB + (mu % RB)) * W + mo_col[j]] = val[e];
+  act[tile] = 1;
+}
+void launch_scatter_c0(const View& v, int nnz, const int64_t* col_of, const int* row, const double* val,
+                       const int* mo_panel, const int* mo_col, double* C, uint8_t* act, hipStream_t s) {
+  if (nnz) hipLaunchKernelGGL(k_scatter_c0, dim3(nblk(nnz, 256)), dim3(256), 0, s, nnz, col_of, row, val,
+                              mo_panel, mo_col, v.n_rb, v.W, C, act);
+}
+
+// ---------------------------------------------------------------------------------------
+// supports: dilation of a panel's active row blocks through the pattern of S/H, and the
+// sorted lists of active row blocks
+// ---------------------------------------------------------------------------------------
+
+__global__ void k_dilate(int G, int n_rb, const int* xs_ptr, const int* xs_col, const uint8_t* actC,
+                         uint8_t* actY) {
+  const size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (idx >= (size_t)G * n_rb) return;
+  const int g = (int)(idx / n_rb), r = (int)(idx % n_rb);
+  const uint8_t* a = actC + (size_t)g * n_rb;
+  uint8_t any = 0;
+  for (int k = xs_ptr[r]; k < xs_ptr[r + 1]; ++k)
+    if (a[xs_col[k]]) { any = 1; break; }
+  actY[idx] = any;
+}
+void launch_dilate(const View& v, const uint8_t* actC, uint8_t* actY, hipStream_t s) {
+  const size_t n = (size_t)v.G * v.n_rb;
+  hipLaunchKernelGGL(k_dilate, dim3(nblk(n, 256)), dim3(256), 0, s, v.G, v.n_rb, v.xs_ptr, v.xs_col, actC, actY);
+}
+
+__global__ void __launch_bounds__(256) k_list(int n_rb, const uint8_t* act, int* list, int* cnt) {
+  const int g = blockIdx.x;
+  __shared__ int wsum[4];
+  const uint8_t* a = act + (size_t)g * n_rb;
+  int* L = list + (size_t)g * n_rb;
+  int base_out = 0;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int base = 0; base < n_rb; base += 256) {
+    const int r = base + threadIdx.x;
+    const bool f = r < n_rb && a[r];
+    const unsigned long long m = __ballot(f);
+    const int pre = __popcll(m & ((1ULL << lane) - 1ULL));
+    if (lane == 0) wsum[w] = __popcll(m);
+    __syncthreads();
+    int off = base_out;
+    for (int i = 0; i < w; ++i) off += wsum[i];
+    if (f) L[off + pre] = r;
+    const int tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+    base_out += tot;
+  }
+  if (threadIdx.x == 0) cnt[g] = base_out;
+}
+void launch_list(const View& v, const uint8_t* act, int* list, int* cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_list, dim3(v.G), dim3(256), 0, s, v.n_rb, act, list, cnt);
+}
+
+// ---------------------------------------------------------------------------------------
+// Y = X C on the tiles (X = S, H or H0 as 16 x 16 blocks).  One wave per output tile.
+// ---------------------------------------------------------------------------------------
+
+template <int NT>
+__global__ void __launch_bounds__(256) k_spmm(int n_rb, const int* __restrict__ xs_ptr,
+                                              const int* __restrict__ xs_col, const double* __restrict__ X,
+                                              const double* __restrict__ C, const uint8_t* __restrict__ actC,
+                                              const int* __restrict__ listY, const int* __restrict__ cntY,
+                                              double* __restrict__ Y, unsigned long long* ctr) {
+  constexpr int W = NT * 16;
+  const int g = blockIdx.y;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= cntY[g]) return;
+  unsigned int n_mfma = 0;
+  const int lane = threadIdx.x & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+  const size_t pb = (size_t)g * n_rb;
+  const int r = listY[pb + t];
+  d4 acc[NT];
+#pragma unroll
+  for (int n = 0; n < NT; ++n) acc[n] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int kb = xs_ptr[r]; kb < xs_ptr[r + 1]; ++kb) {
+    const int c = xs_col[kb];
+    if (!actC[pb + c]) continue;
+    n_mfma += 4 * NT;
+    const double* Xb = X + (size_t)kb * 256;
+    const double* Ct = C + (pb + c) * (RB * W);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const double a = Xb[lr * 16 + 4 * s + lk];
+#pragma unroll
+      for (int n = 0; n < NT; ++n) acc[n] = mfma64(a, Ct[(4 * s + lk) * W + n * 16 + lr], acc[n]);
+    }
+  }
+  double* Yt = Y + (pb + r) * (RB * W);
+#pragma unroll
+  for (int n = 0; n < NT; ++n)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Yt[(lk + 4 * q) * W + n * 16 + lr] = acc[n][q];
+  if (ctr && lane == 0) atomicAdd(ctr, (unsigned long long)n_mfma);
+}
+
+void launch_spmm(const View& v, const double* X, const double* C, const uint8_t* actC, const int* listY,
+                 const int* cntY, double* Y, unsigned long long* ctr, hipStream_t s) {
+  dim3 grid((v.n_rb + 3) / 4, v.G), blk(256);
+  switch (v.W / 16) {
+#define SSCF_SPMM(NT) case NT: hipLaunchKernelGGL(k_spmm<NT>, grid, blk, 0, s, v.n_rb, v.xs_ptr, v.xs_col, X, C, actC, listY, cntY, Y, ctr); break;
+    SSCF_SPMM(1) SSCF_SPMM(2) SSCF_SPMM(3) SSCF_SPMM(4) SSCF_SPMM(5) SSCF_SPMM(6) SSCF_SPMM(7) SSCF_SPMM(8)
+#undef SSCF_SPMM
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// out_p = C_g[:, row_off : row_off + 16 MT]^T Y_h[:, col_off : col_off + 16 NT] for pair p = (g, h),
+// summed over the row blocks active in both.  Four waves split the MT x NT output tiles 2 x 2.
+// ---------------------------------------------------------------------------------------
+
+template <int MW, int NW>
+__global__ void __launch_bounds__(256) k_pair(int n_rb, int W, const int* __restrict__ pg,
+                                              const int* __restrict__ ph, const double* __restrict__ C,
+                                              const int* __restrict__ listC, const int* __restrict__ cntC,
+                                              const double* __restrict__ Y, const uint8_t* __restrict__ actY,
+                                              int row_off, int MT, int col_off, int NT,
+                                              double* __restrict__ out, int ld, size_t out_stride,
+                                              unsigned long long* ctr) {
+  const int p = blockIdx.x;
+  const int g = pg[p], h = ph[p];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int MH = (MT + 1) / 2, NH = (NT + 1) / 2;
+  const int mt0 = (w >> 1) * MH, nt0 = (w & 1) * NH;
+  const int mc = min(MH, MT - mt0), nc = min(NH, NT - nt0);
+  d4 acc[MW][NW];
+#pragma unroll
+  for (int i = 0; i < MW; ++i)
+#pragma unroll
+    for (int j = 0; j < NW; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  const size_t gb = (size_t)g * n_rb, hb = (size_t)h * n_rb;
+  const int cnt = cntC[g];
+  unsigned int n_mfma = 0;
+  if (mc > 0 && nc > 0) {
+    for (int t = 0; t < cnt; ++t) {
+      const int r = listC[gb + t];
+      if (!actY[hb + r]) continue;
+      n_mfma += 4 * mc * nc;
+      const double* Ct = C + (gb + r) * (size_t)(RB * W) + row_off + mt0 * 16 + lr;
+      const double* Yt = Y + (hb + r) * (size_t)(RB * W) + col_off + nt0 * 16 + lr;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        double a[MW], b[NW];
+        const int ro = (4 * s + lk) * W;
+#pragma unroll
+        for (int i = 0; i < MW; ++i) a[i] = (i < mc) ? Ct[ro + i * 16] : 0.0;
+#pragma unroll
+        for (int j = 0; j < NW; ++j) b[j] = (j < nc) ? Yt[ro + j * 16] : 0.0;
+#pragma unroll
+        for (int i = 0; i < MW; ++i)
+#pragma unroll
+          for (int j = 0; j < NW; ++j)
+            if (i < mc && j < nc) acc[i][j] = mfma64(a[i], b[j], acc[i][j]);
+      }
+    }
+  }
+  double* o = out + (size_t)p * out_stride;
+#pragma unroll
+  for (int i = 0; i < MW; ++i)
+#pragma unroll
+    for (int j = 0; j < NW; ++j)
+      if (i < mc && j < nc)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          o[(size_t)((mt0 + i) * 16 + lk + 4 * q) * ld + (nt0 + j) * 16 + lr] = acc[i][j][q];
+  if (ctr && lane == 0 && n_mfma) atomicAdd(ctr, (unsigned long long)n_mfma);
+}
+
+void launch_pair(const View& v, int n_pairs, const int* pg, const int* ph, const double* C, const int* listC,
+                 const int* cntC, const double* Y, const uint8_t* actY, int row_off, int MT, int col_off,
+                 int NT, double* out, int ld, size_t out_stride, unsigned long long* ctr, hipStream_t s) {
+  if (n_pairs <= 0) return;
+  const int mw = (MT + 1) / 2, nw = (NT + 1) / 2;
+  const int m = mw > nw ? mw : nw;
+  dim3 grid(n_pairs), blk(256);
+  if (m <= 1)
+    hipLaunchKernelGGL((k_pair<1, 1>), grid, blk, 0, s, v.n_rb, v.W, pg, ph, C, listC, cntC, Y, actY, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+  else if (m <= 2)
+    hipLaunchKernelGGL((k_pair<2, 2>), grid, blk, 0, s, v.n_rb, v.W, pg, ph, C, listC, cntC, Y, actY, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+  else if (m <= 3)
+    hipLaunchKernelGGL((k_pair<3, 3>), grid, blk, 0, s, v.n_rb, v.W, pg, ph, C, listC, cntC, Y, actY, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+  else
+    hipLaunchKernelGGL((k_pair<4, 4>), grid, blk, 0, s, v.n_rb, v.W, pg, ph, C, listC, cntC, Y, actY, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+}
+
+// per-column dot products d[g][c] = sum_r sum_k C[g][r][k][c] Y[g][r][k][c]
+__global__ void k_coldot(int n_rb, int W, const double* C, const int* listC, const int* cntC, const double* Y,
+                         const uint8_t* actY, double* out) {
+  const int g = blockIdx.x, c = threadIdx.x;
+  if (c >= W) return;
+  const size_t gb = (size_t)g * n_rb;
+  double s = 0.0;
+  for (int t = 0; t < cntC[g]; ++t) {
+    const int r = listC[gb + t];
+    if (!actY[gb + r]) continue;
+    const double* Ct = C + (gb + r) * (size_t)(RB * W) + c;
+    const double* Yt = Y + (gb + r) * (size_t)(RB * W) + c;
+#pragma unroll
+    for (int k = 0; k < RB; ++k) s += Ct[k * W] * Yt[k * W];
+  }
+  out[(size_t)g * W + c] = s;
+}
+void launch_coldot(const View& v, const double* C, const int* listC, const int* cntC, const double* Y,
+                   const uint8_t* actY, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_coldot, dim3(v.G), dim3(v.W <= 64 ? 64 : (v.W <= 128 ? 128 : 256)), 0, s, v.n_rb, v.W, C,
+                     listC, cntC, Y, actY, out);
+}
+
+// ---------------------------------------------------------------------------------------
+// orthonormalization (section 3.4): scales, normalized overlaps D and eta, normalization
+// of C, selection of the pairs, the combination C <- C - 1/2 C D_sel with truncation
+// ---------------------------------------------------------------------------------------
+
+__device__ __forceinline__ bool col_in_scope(int c, int OW, int nocc, int nvirt, int occ_only) {
+  if (c < OW) return c < nocc;
+  if (occ_only) return false;
+  return c - OW < nvirt;
+}
+
+__global__ void k_ortho_scale(int G, int W, int OW, const int* self_pair, const double* O, const int* pnocc,
+                              const int* pnvirt, int occ_only, double* sc, Scalars* sd) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= G * W) return;
+  const int g = idx / W, c = idx % W;
+  double v = 1.0;
+  if (col_in_scope(c, OW, pnocc[g], pnvirt[g], occ_only)) {
+    const double d = O[(size_t)self_pair[g] * W * W + (size_t)c * W + c];
+    if (!(d > 0.0)) sd->err = 1;
+    else v = sqrt(d);
+  }
+  sc[idx] = v;
+}
+void launch_ortho_scale(const View& v, int, const int* self_pair, const double* O, const int* pnocc,
+                        const int* pnvirt, int occ_only, double* sc, Scalars* sd, hipStream_t s) {
+  const int n = v.G * v.W;
+  hipLaunchKernelGGL(k_ortho_scale, dim3(nblk(n, 256)), dim3(256), 0, s, v.G, v.W, v.OW, self_pair, O, pnocc,
+                     pnvirt, occ_only, sc, sd);
+}
+
+__global__ void __launch_bounds__(256) k_normalize_d(int W, int OW, const int* pg, const int* ph, double* O,
+                                                     const double* sc, const int* pnocc, const int* pnvirt,
+                                                     int occ_only, Scalars* sd) {
+  const int p = blockIdx.x;
+  const int g = pg[p], h = ph[p];
+  const int nog = pnocc[g], nvg = pnvirt[g], noh = pnocc[h], nvh = pnvirt[h];
+  double* Op = O + (size_t)p * W * W;
+  double m = 0.0;
+  for (int e = threadIdx.x; e < W * W; e += 256) {
+    const int i = e / W, j = e % W;
+    double d = 0.0;
+    if (col_in_scope(i, OW, nog, nvg, occ_only) && col_in_scope(j, OW, noh, nvh, occ_only) &&
+        !(g == h && i == j)) {
+      d = Op[e] / (sc[(size_t)g * W + i] * sc[(size_t)h * W + j]);
+      m = fmax(m, fabs(d));
+    }
+    Op[e] = d;
+  }
+  block_max_to(m, &sd->eta_bits);
+}
+void launch_normalize_d(const View& v, int n_pairs, const int* pg, const int* ph, double* O, const double* sc,
+                        const int* pnocc, const int* pnvirt, int occ_only, Scalars* sd, hipStream_t s) {
+  if (n_pairs > 0)
+    hipLaunchKernelGGL(k_normalize_d, dim3(n_pairs), dim3(256), 0, s, v.W, v.OW, pg, ph, O, sc, pnocc, pnvirt,
+                       occ_only, sd);
+}
+
+__global__ void __launch_bounds__(256) k_scale_c(int n_rb, int W, double* C, const int* listC, const int* cntC,
+                                                 const double* sc) {
+  const int g = blockIdx.y, t = blockIdx.x;
+  if (t >= cntC[g]) return;
+  const size_t tile = (size_t)g * n_rb + listC[(size_t)g * n_rb + t];
+  double* Ct = C + tile * (size_t)(RB * W);
+  const double* s = sc + (size_t)g * W;
+  for (int e = threadIdx.x; e < RB * W; e += 256) Ct[e] = Ct[e] / s[e % W];
+}
+void launch_scale_c(const View& v, double* C, const int* listC, const int* cntC, const double* sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_c, dim3(v.n_rb, v.G), dim3(256), 0, s, v.n_rb, v.W, C, listC, cntC, sc);
+}
+
+__global__ void __launch_bounds__(256) k_mark_selected(int W, const int* pg, const int* ph, const double* D,
+                                                       const Scalars* sd, uint8_t* pair_sel, uint8_t* upd) {
+  const int p = blockIdx.x;
+  const int g = pg[p], h = ph[p];
+  const double thr = 1e-3 * __longlong_as_double((long long)sd->eta_bits);
+  const double* Dp = D + (size_t)p * W * W;
+  int any = 0;
+  for (int e = threadIdx.x; e < W * W; e += 256) {
+    if (fabs(Dp[e]) >= thr && Dp[e] != 0.0) {
+      any = 1;
+      upd[(size_t)g * W + e / W] = 1;
+      upd[(size_t)h * W + e % W] = 1;
+    }
+  }
+  any = __syncthreads_or(any);
+  if (threadIdx.x == 0) pair_sel[p] = (uint8_t)(any ? 1 : 0);
+}
+void launch_mark_selected(const View& v, int n_pairs, const int* pg, const int* ph, const double* D,
+                          const Scalars* sd, uint8_t* pair_sel, uint8_t* upd, hipStream_t s) {
+  if (n_pairs > 0) hipLaunchKernelGGL(k_mark_selected, dim3(n_pairs), dim3(256), 0, s, v.W, pg, ph, D, sd, pair_sel, upd);
+}
+
+__global__ void k_update_support(int G, int n_rb, const uint8_t* actC, const int* gn_ptr, const int* gn,
+                                 const int* pair_of, const uint8_t* pair_sel, uint8_t* act_new) {
+  const size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (idx >= (size_t)G * n_rb) return;
+  const int g = (int)(idx / n_rb), r = (int)(idx % n_rb);
+  uint8_t a = actC[idx];
+  for (int k = gn_ptr[g]; k < gn_ptr[g + 1] && !a; ++k) {
+    const int h = gn[k];
+    if (pair_sel[pair_of[(size_t)g * G + h]] && actC[(size_t)h * n_rb + r]) a = 1;
+  }
+  act_new[idx] = a;
+}
+void launch_update_support(const View& v, const uint8_t* actC, const int* gn_ptr, const int* gn, const int* pair_of,
+                           const uint8_t* pair_sel, uint8_t* act_new, hipStream_t s) {
+  const size_t n = (size_t)v.G * v.n_rb;
+  hipLaunchKernelGGL(k_update_support, dim3(nblk(n, 256)), dim3(256), 0, s, v.G, v.n_rb, actC, gn_ptr, gn, pair_of,
+                     pair_sel, act_new);
+}
+
+__global__ void __launch_bounds__(256) k_clear_tiles(int n_rb, int W, double* C, uint8_t* act, const int* list,
+                                                     const int* cnt) {
+  const int g = blockIdx.y, t = blockIdx.x;
+  if (t >= cnt[g]) return;
+  const size_t tile = (size_t)g * n_rb + list[(size_t)g * n_rb + t];
+  double* Ct = C + tile * (size_t)(RB * W);
+  for (int e = threadIdx.x; e < RB * W; e += 256) Ct[e] = 0.0;
+  if (threadIdx.x == 0) act[tile] = 0;
+}
+void launch_clear_tiles(const View& v, double* C, uint8_t* act, const int* list, const int* cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_clear_tiles, dim3(v.n_rb, v.G), dim3(256), 0, s, v.n_rb, v.W, C, act, list, cnt);
+}
+
+// Cn[g][r] = C[g][r] - 1/2 sum_{h ~ g} C[h][r] D_sel(h, g), then |v| < cut -> 0 in the
+// columns that took part in a combination.  D is stored per unordered pair (a <= b) with
+// rows = MOs of a, columns = MOs of b.
+template <int NT>
+__global__ void __launch_bounds__(256) k_ortho_update(int G, int n_rb, const double* __restrict__ C,
+                                                      const uint8_t* __restrict__ actC, const int* __restrict__ gn_ptr,
+                                                      const int* __restrict__ gn, const int* __restrict__ pair_of,
+                                                      const uint8_t* __restrict__ pair_sel,
+                                                      const double* __restrict__ D, const Scalars* __restrict__ sd,
+                                                      const uint8_t* __restrict__ upd, double cut,
+                                                      const int* __restrict__ listN, const int* __restrict__ cntN,
+                                                      double* __restrict__ Cn, uint8_t* __restrict__ actN,
+                                                      unsigned long long* ctr) {
+  constexpr int W = NT * 16;
+  const int g = blockIdx.y;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= cntN[g]) return;
+  unsigned int n_mfma = 0;
+  const int lane = threadIdx.x & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int r = listN[(size_t)g * n_rb + t];
+  const double thr = 1e-3 * __longlong_as_double((long long)sd->eta_bits);
+  d4 acc[NT];
+#pragma unroll
+  for (int n = 0; n < NT; ++n) acc[n] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int k = gn_ptr[g]; k < gn_ptr[g + 1]; ++k) {
+    const int h = gn[k];
+    const int p = pair_of[(size_t)g * G + h];
+    if (!pair_sel[p] || !actC[(size_t)h * n_rb + r]) continue;
+    n_mfma += (W / 4) * NT;
+    const double* Ch = C + ((size_t)h * n_rb + r) * (RB * W);
+    const double* Dp = D + (size_t)p * W * W;
+    const bool tr = h > g;
+    for (int s = 0; s < W / 4; ++s) {
+      const double a = Ch[lr * W + 4 * s + lk];
+      const int kk = 4 * s + lk;
+#pragma unroll
+      for (int n = 0; n < NT; ++n) {
+        const int nn = n * 16 + lr;
+        double d = tr ? Dp[(size_t)nn * W + kk] : Dp[(size_t)kk * W + nn];
+        d = (fabs(d) >= thr) ? d : 0.0;
+        acc[n] = mfma64(a, d, acc[n]);
+      }
+    }
+  }
+  const size_t tile = (size_t)g * n_rb + r;
+  const bool own = actC[tile] != 0;
+  const double* Cg = C + tile * (RB * W);
+  double* Co = Cn + tile * (RB * W);
+  int any = 0;
+#pragma unroll
+  for (int n = 0; n < NT; ++n) {
+    const int j = n * 16 + lr;
+    const bool u = upd[(size_t)g * W + j] != 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = lk + 4 * q;
+      double v = (own ? Cg[i * W + j] : 0.0) - 0.5 * acc[n][q];
+      if (u && fabs(v) < cut) v = 0.0;
+      Co[i * W + j] = v;
+      any |= (v != 0.0);
+    }
+  }
+  const unsigned long long m = __ballot(any);
+  if (lane == 0) actN[tile] = (uint8_t)(m != 0ULL);
+  if (ctr && lane == 0) atomicAdd(ctr, (unsigned long long)n_mfma);
+}
+
+void launch_ortho_update(const View& v, const double* C, const uint8_t* actC, const int* gn_ptr, const int* gn,
+                         const int* pair_of, const uint8_t* pair_sel, const double* D, const Scalars* sd,
+                         const uint8_t* upd, double cut, const int* listN, const int* cntN, double* Cn,
+                         uint8_t* actN, unsigned long long* ctr, hipStream_t s) {
+  dim3 grid((v.n_rb + 3) / 4, v.G), blk(256);
+  switch (v.W / 16) {
+#define SSCF_UPD(NT) case NT: hipLaunchKernelGGL(k_ortho_update<NT>, grid, blk, 0, s, v.G, v.n_rb, C, actC, gn_ptr, gn, pair_of, pair_sel, D, sd, upd, cut, listN, cntN, Cn, actN, ctr); break;
+    SSCF_UPD(1) SSCF_UPD(2) SSCF_UPD(3) SSCF_UPD(4) SSCF_UPD(5) SSCF_UPD(6) SSCF_UPD(7) SSCF_UPD(8)
+#undef SSCF_UPD
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// DFTB Fock matrix (section 3.7): Q = gamma dq over all atom pairs, unscreened, then
+// H = H0 + 1/2 S (Q_a + Q_b) with |H| < eps -> 0 (section 4.1)
+// ---------------------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_coulomb(int n, int scc, const double* __restrict__ xyz,
+                                                 const double* __restrict__ U, const double* __restrict__ dq,
+                                                 double* __restrict__ Q) {
+  __shared__ double sx[256], sy[256], sz[256], su[256], sq[256];
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = a < n;
+  const double xa = live ? xyz[3 * a] : 0.0, ya = live ? xyz[3 * a + 1] : 0.0, za = live ? xyz[3 * a + 2] : 0.0;
+  const double ia = live ? 1.0 / U[a] : 0.0;
+  double s = 0.0;
+  for (int base = 0; base < n; base += 256) {
+    const int x = base + threadIdx.x;
+    __syncthreads();
+    if (x < n) {
+      sx[threadIdx.x] = xyz[3 * x]; sy[threadIdx.x] = xyz[3 * x + 1]; sz[threadIdx.x] = xyz[3 * x + 2];
+      su[threadIdx.x] = U[x]; sq[threadIdx.x] = dq[x];
+    }
+    __syncthreads();
+    const int m = min(256, n - base);
+    if (live && scc) {
+      for (int k = 0; k < m; ++k) {
+        double gam;
+        if (base + k == a) {
+          gam = su[k];
+        } else {
+          const double dx = xa - sx[k], dy = ya - sy[k], dz = za - sz[k];
+          const double u = 0.5 * (ia + 1.0 / su[k]);
+          gam = 1.0 / sqrt(dx * dx + dy * dy + dz * dz + u * u);
+        }
+        s += gam * sq[k];
+      }
+    }
+  }
+  if (live) Q[a] = s;
+}
+void launch_coulomb(const View& v, int scc, const double* dq, double* Q, hipStream_t s) {
+  hipLaunchKernelGGL(k_coulomb, dim3(nblk(v.n_atoms, 256)), dim3(256), 0, s, v.n_atoms, scc, v.xyz, v.U, dq, Q);
+}
+
+__global__ void k_fock(size_t n, int n_ao, const int* xs_row, const int* xs_col, const int* ao_atom,
+                       const double* S, const double* H0, const double* Hfull, const double* Q, double eps,
+                       double* H) {
+  const size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const size_t b = e >> 8;
+  const int i = (int)((e >> 4) & 15), j = (int)(e & 15);
+  const int mu = xs_row[b] * RB + i, nu = xs_col[b] * RB + j;
+  double h = 0.0;
+  if (mu < n_ao && nu < n_ao) {
+    if (Hfull) h = Hfull[e];
+    else h = H0[e] + 0.5 * S[e] * (Q[ao_atom[mu]] + Q[ao_atom[nu]]);
+  }
+  H[e] = (fabs(h) < eps) ? 0.0 : h;
+}
+void launch_fock(const View& v, const double* S, const double* H0, const double* Hfull, const double* Q, double eps,
+                 double* H, hipStream_t s) {
+  const size_t n = (size_t)v.nbx * 256;
+  hipLaunchKernelGGL(k_fock, dim3(nblk(n, 256)), dim3(256), 0, s, n, v.n_ao, v.xs_row, v.xs_col, v.ao_atom, S, H0,
+                     Hfull, Q, eps, H);
+}
+
+// ---------------------------------------------------------------------------------------
+// rotation selection (section 3.5): candidates |F_ia| >= eps (F != 0); at most K of them,
+// the largest |F| first with ties by (i, a); inside each Jacobi block ordered by
+// decreasing |F| then (i, a); angle from the F of the start of the step
+// ---------------------------------------------------------------------------------------
+
+__device__ __forceinline__ bool cand_of(const double* F, size_t e, int OW, int VW, const int* jb_nocc,
+                                        const int* jb_nvirt, double tau, double& f, int& b, int& i, int& a,
+                                        bool& valid) {
+  const size_t per = (size_t)OW * VW;
+  b = (int)(e / per);
+  const int rem = (int)(e % per);
+  i = rem / VW;
+  a = rem % VW;
+  valid = i < jb_nocc[b] && a < jb_nvirt[b];
+  f = F[e];
+  return valid && f != 0.0 && fabs(f) >= tau;
+}
+
+__global__ void __launch_bounds__(256) k_count_candidates(size_t n, int OW, int VW, const int* jb_nocc,
+                                                          const int* jb_nvirt, const double* F, double tau,
+                                                          Scalars* sd) {
+  __shared__ int cs[4];
+  int c = 0;
+  double m = 0.0;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    double f; int b, i, a; bool valid;
+    if (cand_of(F, e, OW, VW, jb_nocc, jb_nvirt, tau, f, b, i, a, valid)) ++c;
+    if (valid) m = fmax(m, fabs(f));
+  }
+  c = wave_sum_i(c);
+  if ((threadIdx.x & 63) == 0) cs[threadIdx.x >> 6] = c;
+  block_max_to(m, &sd->fov_bits);
+  if (threadIdx.x == 0) atomicAdd(&sd->n_cand, cs[0] + cs[1] + cs[2] + cs[3]);
+}
+void launch_count_candidates(int nb, int OW, int VW, const int* jb_nocc, const int* jb_nvirt, const double* F,
+                             double tau, Scalars* sd, hipStream_t s) {
+  const size_t n = (size_t)nb * OW * VW;
+  unsigned int g = nblk(n, 256);
+  if (g > 4096) g = 4096;
+  if (n) hipLaunchKernelGGL(k_count_candidates, dim3(g), dim3(256), 0, s, n, OW, VW, jb_nocc, jb_nvirt, F, tau, sd);
+}
+
+__global__ void __launch_bounds__(256) k_radix_hist(size_t n, int OW, int VW, const int* jb_nocc, const int* jb_nvirt,
+                                                    const double* F, double tau, int shift, const Scalars* sd,
+                                                    unsigned int* hist) {
+  __shared__ unsigned int lh[256];
+  lh[threadIdx.x] = 0;
+  __syncthreads();
+  const unsigned long long prefix = sd->prefix, mask = sd->mask;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    double f; int b, i, a; bool valid;
+    if (!cand_of(F, e, OW, VW, jb_nocc, jb_nvirt, tau, f, b, i, a, valid)) continue;
+    const unsigned long long key = dbits(fabs(f));
+    if ((key & mask) != prefix) continue;
+    atomicAdd(&lh[(key >> shift) & 0xFF], 1u);
+  }
+  __syncthreads();
+  if (lh[threadIdx.x]) atomicAdd(&hist[threadIdx.x], lh[threadIdx.x]);
+}
+
+// walk the histogram from the largest digit down and fix the digit of the K-th key
+__global__ void k_radix_pick(int shift, Scalars* sd, unsigned int* hist) {
+  if (threadIdx.x != 0) return;
+  long long acc = 0;
+  for (int bin = 255; bin >= 0; --bin) {
+    const long long c = hist[bin];
+    if (acc + c >= sd->remaining) {
+      sd->prefix |= ((unsigned long long)bin) << shift;
+      sd->mask |= 0xFFULL << shift;
+      sd->remaining -= acc;
+      sd->tie_count = (int)c;
+      break;
+    }
+    acc += c;
+  }
+  for (int bin = 0; bin < 256; ++bin) hist[bin] = 0;
+}
+
+void launch_radix_pass(int nb, int OW, int VW, const int* jb_nocc, const int* jb_nvirt, const double* F, double tau,
+                       int shift, Scalars* sd, unsigned int* hist, hipStream_t s) {
+  const size_t n = (size_t)nb * OW * VW;
+  unsigned int g = nblk(n, 256);
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_radix_hist, dim3(g), dim3(256), 0, s, n, OW, VW, jb_nocc, jb_nvirt, F, tau, shift, sd, hist);
+  hipLaunchKernelGGL(k_radix_pick, dim3(1), dim3(64), 0, s, shift, sd, hist);
+}
+
+__global__ void k_sel_init(Scalars* sd, long long K, int select_all) {
+  sd->prefix = 0ULL;
+  sd->mask = 0ULL;
+  sd->remaining = K;
+  sd->cut_key = 0ULL;                 // select_all: every candidate has a key > 0
+  sd->tie_cut = 0x7fffffffffffffffLL;
+  sd->tie_count = 0;
+  sd->tie_n = 0;
+  sd->n_rot = 0;
+  (void)select_all;
+}
+void launch_sel_init(Scalars* sd, long long K, int select_all, hipStream_t s) {
+  hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(1), 0, s, sd, K, select_all);
+}
+
+// after the radix passes: keys > prefix are all taken; `remaining` of the keys == prefix
+// are needed.  cut_key is the smallest key taken.  With select-all the cut stays at 0.
+__global__ void k_sel_finish(Scalars* sd) {
+  sd->cut_key = sd->prefix;
+  // keys == cut_key are all taken when no more of them exist than needed
+  if (sd->tie_count <= sd->remaining) sd->tie_cut = 0x7fffffffffffffffLL;
+  else sd->tie_cut = -1;              // resolved by launch_tie_cut
+}
+void launch_sel_finish(Scalars* sd, hipStream_t s) { hipLaunchKernelGGL(k_sel_finish, dim3(1), dim3(1), 0, s, sd); }
+
+// candidates with |F| == cut_key: collect their (i * n_mo + a) keys, sort them and keep
+// the `remaining` smallest (ties are taken by increasing (i, a))
+__global__ void k_tie_collect(size_t n, int OW, int VW, const int* jb_g, const int* jb_h, const int* jb_nocc,
+                              const int* jb_nvirt, const double* F, const int* mo_of, int W, long long n_mo,
+                              double tau, Scalars* sd, long long* ties) {
+  if (sd->tie_cut != -1) return;
+  const unsigned long long cut = sd->cut_key;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    double f; int b, i, a; bool valid;
+    if (!cand_of(F, e, OW, VW, jb_nocc, jb_nvirt, tau, f, b, i, a, valid)) continue;
+    if (dbits(fabs(f)) != cut) continue;
+    const long long ig = mo_of[(size_t)jb_g[b] * W + i], ag = mo_of[(size_t)jb_h[b] * W + OW + a];
+    const int pos = atomicAdd(&sd->tie_n, 1);
+    if (pos < MAX_TIES) ties[pos] = ig * n_mo + ag;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_tie_sort(Scalars* sd, const long long* ties) {
+  if (sd->tie_cut != -1) return;
+  __shared__ long long k[MAX_TIES];
+  const int n = sd->tie_n;
+  if (n > MAX_TIES) {
+    if (threadIdx.x == 0) { sd->err |= 2; sd->tie_cut = 0x7fffffffffffffffLL; }
+    return;
+  }
+  int N = 1;
+  while (N < n) N <<= 1;
+  for (int i = threadIdx.x; i < N; i += 256) k[i] = (i < n) ? ties[i] : 0x7fffffffffffffffLL;
+  __syncthreads();
+  for (int len = 2; len <= N; len <<= 1)
+    for (int j = len >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < N; i += 256) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const bool up = (i & len) == 0;
+          const long long x = k[i], y = k[ixj];
+          if ((x > y) == up) { k[i] = y; k[ixj] = x; }
+        }
+      }
+      __syncthreads();
+    }
+  if (threadIdx.x == 0) sd->tie_cut = k[sd->remaining - 1];
+}
+
+void launch_tie_cut(int nb, int OW, int VW, const int* jb_g, const int* jb_h, const int* jb_nocc, const int* jb_nvirt,
+                    const double* F, const int* mo_of, int W, long long n_mo, double tau, Scalars* sd,
+                    long long* ties, hipStream_t s) {
+  const size_t n = (size_t)nb * OW * VW;
+  unsigned int g = nblk(n, 256);
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_tie_collect, dim3(g), dim3(256), 0, s, n, OW, VW, jb_g, jb_h, jb_nocc, jb_nvirt, F, mo_of, W,
+                     n_mo, tau, sd, ties);
+  hipLaunchKernelGGL(k_tie_sort, dim3(1), dim3(256), 0, s, sd, ties);
+}
+
+// One workgroup per Jacobi block: the selected candidates of the block sorted by
+// (|F| descending, i, a), the angle of each pair from the stale F (section 3.5):
+// p = (F_ii - F_aa) / (2 F_ia), t = 1 / (p + sgn(p) sqrt(1 + p^2)), c = (1 + t^2)^(-1/2),
+// s = t c, sgn(0) = +1; and the sorted set of columns the block touches.
+constexpr int SEL_MAX = 4096;
+
+__global__ void __launch_bounds__(256) k_block_select(int W, int OW, int VW, const int* jb_g, const int* jb_h,
+                                                      const int* jb_nocc, const int* jb_nvirt, const double* F,
+                                                      const double* Fdiag, const int* mo_of, long long n_mo,
+                                                      double tau, Scalars* sd, int* rot_cnt, int2* rot_col,
+                                                      double2* rot_cs, int* tcnt, int* tcol) {
+  __shared__ unsigned long long khi[SEL_MAX];
+  __shared__ unsigned int klo[SEL_MAX];
+  __shared__ int n_sel;
+  __shared__ uint8_t used[MAX_W];
+  __shared__ int upos[MAX_W];
+  const int b = blockIdx.x;
+  const int g = jb_g[b], h = jb_h[b];
+  const int no = jb_nocc[b], nv = jb_nvirt[b];
+  const size_t per = (size_t)OW * VW;
+  const double* Fb = F + (size_t)b * per;
+  const unsigned long long cut = sd->cut_key;
+  const long long tie_cut = sd->tie_cut;
+  if (threadIdx.x == 0) n_sel = 0;
+  for (int c = threadIdx.x; c < MAX_W; c += 256) used[c] = 0;
+  __syncthreads();
+  for (int e = threadIdx.x; e < (int)per; e += 256) {
+    const int i = e / VW, a = e % VW;
+    if (i >= no || a >= nv) continue;
+    const double f = Fb[e];
+    if (f == 0.0 || fabs(f) < tau) continue;
+    const unsigned long long key = dbits(fabs(f));
+    bool sel = key > cut;
+    if (key == cut) {
+      const long long ia = (long long)mo_of[(size_t)g * W + i] * n_mo + mo_of[(size_t)h * W + OW + a];
+      sel = ia <= tie_cut;
+    }
+    if (!sel) continue;
+    const int pos = atomicAdd(&n_sel, 1);
+    khi[pos] = ~key;                       // ascending order = decreasing |F|
+    klo[pos] = ((unsigned)i << 16) | (unsigned)a;
+  }
+  __syncthreads();
+  const int n = n_sel;
+  int N = 1;
+  while (N < n) N <<= 1;
+  for (int i = n + threadIdx.x; i < N; i += 256) { khi[i] = ~0ULL; klo[i] = ~0u; }
+  __syncthreads();
+  for (int len = 2; len <= N; len <<= 1)
+    for (int j = len >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < N; i += 256) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const bool up = (i & len) == 0;
+          const unsigned long long x1 = khi[i], y1 = khi[ixj];
+          const unsigned int x2 = klo[i], y2 = klo[ixj];
+          const bool gt = (x1 > y1) || (x1 == y1 && x2 > y2);
+          if (gt == up) { khi[i] = y1; khi[ixj] = x1; klo[i] = y2; klo[ixj] = x2; }
+        }
+      }
+      __syncthreads();
+    }
+  const size_t rb0 = (size_t)b * per;
+  for (int q = threadIdx.x; q < n; q += 256) {
+    const int i = klo[q] >> 16, a = klo[q] & 0xFFFF;
+    const double f = Fb[(size_t)i * VW + a];
+    const double fii = Fdiag[(size_t)g * W + i], faa = Fdiag[(size_t)h * W + OW + a];
+    const double p = (fii - faa) / (2.0 * f);
+    const double sg = (p >= 0.0) ? 1.0 : -1.0;
+    const double t = 1.0 / (p + sg * sqrt(1.0 + p * p));
+    const double c = 1.0 / sqrt(1.0 + t * t);
+    rot_col[rb0 + q] = make_int2(i, OW + a);
+    rot_cs[rb0 + q] = make_double2(c, t * c);
+    used[i] = 1;
+    used[OW + a] = 1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int u = 0;
+    for (int c = 0; c < W; ++c)
+      if (used[c]) tcol[(size_t)b * W + u++] = c;
+    tcnt[b] = u;
+    rot_cnt[b] = n;
+    atomicAdd(&sd->n_rot, n);
+  }
+}
+
+void launch_block_select(const View& v, int nb, const int* jb_g, const int* jb_h, const int* jb_nocc, const int* jb_nvirt,
+                         const double* F, const double* Fdiag, const int* mo_of, double tau, Scalars* sd,
+                         int* rot_cnt, int2* rot_col, double2* rot_cs, int* tcnt, int* tcol, hipStream_t s) {
+  if (nb > 0)
+    hipLaunchKernelGGL(k_block_select, dim3(nb), dim3(256), 0, s, v.W, v.OW, v.VW, jb_g, jb_h, jb_nocc, jb_nvirt, F,
+                       Fdiag, mo_of, (long long)v.n_mo, tau, sd, rot_cnt, rot_col, rot_cs, tcnt, tcol);
+}
+
+// ---------------------------------------------------------------------------------------
+// rotation application, one round of Jacobi blocks per launch: one thread per AO row of
+// the row blocks where the occupied panel g or the virtual panel h is active.
+// C'_i = c C_i + s C_a, C'_a = -s C_i + c C_a in list order, then |C| < eps -> 0 in the
+// columns the block rotated.  Blocks of a round share no panel.
+// ---------------------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_givens_round(int n_rb, int W, int OW, const int* round_blocks,
+                                                      const int* jb_g, const int* jb_h, const int* rot_cnt,
+                                                      const int2* __restrict__ rot_col,
+                                                      const double2* __restrict__ rot_cs, const int* tcnt,
+                                                      const int* tcol, double eps, double* C, uint8_t* actC,
+                                                      unsigned long long* ctr) {
+  const int b = round_blocks[blockIdx.y];
+  const int n = rot_cnt[b];
+  if (n == 0) return;
+  const int g = jb_g[b], h = jb_h[b];
+  const int rb = blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int k = threadIdx.x & 15;
+  const bool in = rb < n_rb;
+  const size_t tg = (size_t)g * n_rb + (in ? rb : 0), th = (size_t)h * n_rb + (in ? rb : 0);
+  const bool ag = in && actC[tg], ah = in && actC[th];
+  const bool live = ag || ah;
+  int nzg = 0, nzh = 0;
+  if (live) {
+    double* rowg = C + (tg * RB + k) * W;
+    double* rowh = C + (th * RB + k) * W;
+    const size_t base = (size_t)b * OW * (W - OW);
+    for (int q = 0; q < n; ++q) {
+      const int2 cc = rot_col[base + q];
+      const double2 cs = rot_cs[base + q];
+      const double xi = rowg[cc.x], xa = rowh[cc.y];
+      rowg[cc.x] = cs.x * xi + cs.y * xa;
+      rowh[cc.y] = -cs.y * xi + cs.x * xa;
+    }
+    const int nt = tcnt[b];
+    for (int u = 0; u < nt; ++u) {
+      const int c = tcol[(size_t)b * W + u];
+      double* row = (c < OW) ? rowg : rowh;
+      double x = row[c];
+      if (fabs(x) < eps) { x = 0.0; row[c] = 0.0; }
+      if (x != 0.0) { if (c < OW) nzg = 1; else nzh = 1; }
+    }
+  }
+  // a tile that receives nonzeros becomes active (all 16 rows of a tile sit in one wave)
+  const unsigned long long mg = __ballot(nzg), mh = __ballot(nzh);
+  const int lane = threadIdx.x & 63;
+  const int sub = (lane >> 4) * 16;
+  if (in && k == 0) {
+    if (!ag && ((mg >> sub) & 0xFFFFULL)) actC[tg] = 1;
+    if (!ah && ((mh >> sub) & 0xFFFFULL)) actC[th] = 1;
+    // algorithmic traffic: each touched element of the 16 rows read and written once
+    if (ctr && live) atomicAdd(ctr, (unsigned long long)tcnt[b] * RB * 16ULL);
+  }
+}
+
+void launch_givens_round(const View& v, int n_round_blocks, const int* round_blocks, const int* jb_g, const int* jb_h,
+                         const int* rot_cnt, const int2* rot_col, const double2* rot_cs, const int* tcnt,
+                         const int* tcol, double eps, double* C, uint8_t* actC, unsigned long long* ctr,
+                         hipStream_t s) {
+  if (n_round_blocks <= 0) return;
+  dim3 grid((v.n_rb + 15) / 16, n_round_blocks), blk(256);
+  hipLaunchKernelGGL(k_givens_round, grid, blk, 0, s, v.n_rb, v.W, v.OW, round_blocks, jb_g, jb_h, rot_cnt, rot_col,
+                     rot_cs, tcnt, tcol, eps, C, actC, ctr);
+}
+
+// ---------------------------------------------------------------------------------------
+// Mulliken charges (section 3.7, eq. pop): q_a = sum_{u in a} 2 sum_{i occ} C_ui (S C)_ui.
+// Y holds S C of the C before its last normalization, so (S C)_ui = Y_ui / sc_i.
+// Row sums are formed panel by panel in increasing order (fixed order).
+// ---------------------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_charges_rows(int G, int n_rb, int n_ao, int W, const double* C,
+                                                      const uint8_t* actC, const double* Y, const uint8_t* actY,
+                                                      const double* sc, const int* pnocc, double* rowq) {
+  const int rb = blockIdx.x;
+  const int k = threadIdx.x >> 4, l = threadIdx.x & 15;
+  double acc = 0.0;
+  for (int g = 0; g < G; ++g) {
+    const size_t tile = (size_t)g * n_rb + rb;
+    if (!actC[tile] || !actY[tile]) continue;
+    const int no = pnocc[g];
+    const double* Cr = C + (tile * RB + k) * W;
+    const double* Yr = Y + (tile * RB + k) * W;
+    const double* s = sc + (size_t)g * W;
+    double part = 0.0;
+    for (int c = l; c < no; c += 16) part += Cr[c] * Yr[c] / s[c];
+    for (int o = 8; o > 0; o >>= 1) part += __shfl_xor(part, o, 16);
+    acc += part;
+  }
+  const int mu = rb * RB + k;
+  if (l == 0 && mu < n_ao) rowq[mu] = 2.0 * acc;
+}
+void launch_charges_rows(const View& v, const double* C, const uint8_t* actC, const double* Y, const uint8_t* actY,
+                         const double* sc, const int* pnocc, double* rowq, hipStream_t s) {
+  hipLaunchKernelGGL(k_charges_rows, dim3(v.n_rb), dim3(256), 0, s, v.G, v.n_rb, v.n_ao, v.W, C, actC, Y, actY, sc,
+                     pnocc, rowq);
+}
+
+__global__ void k_atom_charges(int n_atoms, const int64_t* ao_off, const double* rowq, const double* q0, double* q,
+                               double* q_prev, double* dq, Scalars* sd, int shift_prev) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  double d = 0.0;
+  if (a < n_atoms) {
+    double s = 0.0;
+    for (int64_t mu = ao_off[a]; mu < ao_off[a + 1]; ++mu) s += rowq[mu];
+    const double old = q[a];
+    if (shift_prev) { q_prev[a] = old; d = fabs(s - old); }
+    q[a] = s;
+    dq[a] = s - q0[a];
+  }
+  block_max_to(d, &sd->dq_bits);
+}
+void launch_atom_charges(const View& v, const int64_t* ao_off, const double* rowq, double* q, double* q_prev,
+                         double* dq, Scalars* sd, int shift_prev, hipStream_t s) {
+  hipLaunchKernelGGL(k_atom_charges, dim3(nblk(v.n_atoms, 256)), dim3(256), 0, s, v.n_atoms, ao_off, rowq, v.q0, q,
+                     q_prev, dq, sd, shift_prev);
+}
+
+// ---------------------------------------------------------------------------------------
+// energy sums (FP64, Neumaier compensation, fixed order)
+// ---------------------------------------------------------------------------------------
+
+__device__ __forceinline__ void nm_add(double& s, double& c, double x) {
+  const double t = s + x;
+  if (fabs(s) >= fabs(x)) c += (s - t) + x;
+  else c += (x - t) + s;
+  s = t;
+}
+
+// E_band = 2 sum_{i occ} C_i^T H0 C_i from the per-column dots d[g][c]
+__global__ void __launch_bounds__(256) k_sum_band(int G, int W, const double* d, const int* pnocc, Scalars* sd) {
+  __shared__ double ss[256], cc[256];
+  double s = 0.0, c = 0.0;
+  for (int g = threadIdx.x; g < G; g += 256)
+    for (int j = 0; j < pnocc[g]; ++j) nm_add(s, c, d[(size_t)g * W + j]);
+  ss[threadIdx.x] = s;
+  cc[threadIdx.x] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double S = 0.0, Cc = 0.0;
+    for (int i = 0; i < 256; ++i) { nm_add(S, Cc, ss[i]); nm_add(S, Cc, cc[i]); }
+    sd->e_band = 2.0 * (S + Cc);
+  }
+}
+void launch_sum_band(const View& v, const double* d, const int* pnocc, Scalars* sd, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_band, dim3(1), dim3(256), 0, s, v.G, v.W, d, pnocc, sd);
+}
+
+__global__ void __launch_bounds__(256) k_sum_coul(int n, int scc, const double* dq, const double* Q, Scalars* sd) {
+  __shared__ double ss[256], cc[256];
+  double s = 0.0, c = 0.0;
+  for (int a = threadIdx.x; a < n; a += 256) nm_add(s, c, 0.5 * dq[a] * Q[a]);
+  ss[threadIdx.x] = s;
+  cc[threadIdx.x] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double S = 0.0, Cc = 0.0;
+    for (int i = 0; i < 256; ++i) { nm_add(S, Cc, ss[i]); nm_add(S, Cc, cc[i]); }
+    sd->e_coul = scc ? (S + Cc) : 0.0;
+  }
+}
+void launch_sum_coul(const View& v, int scc, const double* dq, const double* Q, Scalars* sd, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_coul, dim3(1), dim3(256), 0, s, v.n_atoms, scc, dq, Q, sd);
+}
+
+// ---------------------------------------------------------------------------------------
+// density on the row-block pattern: P[r][c] = 2 sum_g C_g[r]_occ C_g[c]_occ^T (one wave
+// per 16 x 16 block; MFMA over the occupied columns)
+// ---------------------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_density_blocks(int nbx, int G, int n_rb, int W, int OW, const int* xs_row,
+                                                        const int* xs_col, const double* C, const uint8_t* actC,
+                                                        double* P) {
+  const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (b >= nbx) return;
+  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+  const int r = xs_row[b], c = xs_col[b];
+  d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+  for (int g = 0; g < G; ++g) {
+    const size_t tr = (size_t)g * n_rb + r, tc = (size_t)g * n_rb + c;
+    if (!actC[tr] || !actC[tc]) continue;
+    const double* A = C + tr * (RB * W);
+    const double* B = C + tc * (RB * W);
+    for (int s = 0; s < OW / 4; ++s) acc = mfma64(A[lr * W + 4 * s + lk], B[lr * W + 4 * s + lk], acc);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) P[(size_t)b * 256 + (lk + 4 * q) * 16 + lr] = 2.0 * acc[q];
+}
+void launch_density_blocks(const View& v, const double* C, const uint8_t* actC, const int*, double* P, hipStream_t s) {
+  hipLaunchKernelGGL(k_density_blocks, dim3((v.nbx + 3) / 4), dim3(256), 0, s, v.nbx, v.G, v.n_rb, v.W, v.OW,
+                     v.xs_row, v.xs_col, C, actC, P);
+}
+
+}  // namespace sscf

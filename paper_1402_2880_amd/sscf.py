@@ -1,0 +1,266 @@
+"""Python binding of the gfx950 sparse SCF library (include/sscf.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+libsscf.so.  PyTorch supplies the device memory (its caching allocator) and the
+stream.  There is no CPU fallback: if the library is missing, importing this
+module's entry points raises.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsscf.so")
+
+SSCF_OK = 0
+STATUS = {0: "SSCF_OK", -1: "SSCF_E_INVALID_ARG", -2: "SSCF_E_NOT_SPD", -3: "SSCF_E_ORTHO",
+          -4: "SSCF_E_HIP", -5: "SSCF_E_STATE", -6: "SSCF_E_CAPACITY", -7: "SSCF_E_NOMEM"}
+FP64, FP32_MIXED = 0, 1
+FOCK_H0, FOCK_FULL = 0, 1
+FLAG_PROFILE = 1
+N_KERNEL_CLASSES = 7
+
+ALLOC_FN = ct.CFUNCTYPE(ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p)
+FREE_FN = ct.CFUNCTYPE(None, ct.c_void_p, ct.c_void_p, ct.c_void_p)
+
+
+class Allocator(ct.Structure):
+    _fields_ = [("self", ct.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN)]
+
+
+class SystemDesc(ct.Structure):
+    _fields_ = [
+        ("n_atoms", ct.c_int32), ("atom_nao", ct.c_void_p), ("xyz_bohr", ct.c_void_p),
+        ("hubbard_u", ct.c_void_p), ("q0", ct.c_void_p), ("atom_group", ct.c_void_p),
+        ("n_groups", ct.c_int32), ("blk_rowptr", ct.c_void_p), ("blk_col", ct.c_void_p),
+        ("blk_off", ct.c_void_p), ("S_val", ct.c_void_p), ("H0_val", ct.c_void_p),
+        ("n_val", ct.c_int64), ("n_mo", ct.c_int32), ("n_occ", ct.c_int32),
+        ("mo_group", ct.c_void_p), ("c0_colptr", ct.c_void_p), ("c0_row", ct.c_void_p),
+        ("c0_val", ct.c_void_p), ("eps", ct.c_double), ("e_conv", ct.c_double),
+        ("group_nbr_bohr", ct.c_double), ("rot_cap_factor", ct.c_double),
+        ("max_sweeps_init", ct.c_int32), ("max_sweeps_step", ct.c_int32), ("scc", ct.c_int32),
+        ("precision", ct.c_int32), ("hip_stream", ct.c_void_p), ("alloc", Allocator),
+        ("flags", ct.c_uint64),
+    ]
+
+
+class StepInfo(ct.Structure):
+    _fields_ = [
+        ("energy", ct.c_double), ("delta_e", ct.c_double), ("dq_max", ct.c_double),
+        ("max_abs_fov", ct.c_double), ("ortho_eta", ct.c_double), ("e_band", ct.c_double),
+        ("e_coul", ct.c_double), ("n_candidates", ct.c_int32), ("n_rotations", ct.c_int32),
+        ("n_ortho_sweeps", ct.c_int32), ("converged", ct.c_int32), ("ortho_converged", ct.c_int32),
+        ("post_ortho", ct.c_int32), ("nnz_tiles", ct.c_int64), ("ms_fock", ct.c_float),
+        ("ms_cfc", ct.c_float), ("ms_select", ct.c_float), ("ms_rot", ct.c_float),
+        ("ms_ortho", ct.c_float), ("ms_sums", ct.c_float), ("ms_total", ct.c_float),
+    ]
+
+    def as_dict(self) -> Dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class KernelStat(ct.Structure):
+    _fields_ = [("name", ct.c_char * 32), ("launches", ct.c_int64), ("ms", ct.c_double),
+                ("flops", ct.c_double), ("bytes", ct.c_double)]
+
+
+EXPORTS = ["sscf_get_kernel_stats", "sscf_reset_kernel_stats", "sscf_init_system", "sscf_set_fock", "sscf_scf_step", "sscf_get_energy",
+           "sscf_get_density", "sscf_get_charges", "sscf_get_mo_coefficients", "sscf_init_info",
+           "sscf_get_schedule", "sscf_destroy", "sscf_last_error"]
+
+_lib = None
+
+
+def lib():
+    """The loaded libsscf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1402_2880_amd.build_lib` (no CPU fallback exists)")
+        L = ct.CDLL(LIB_PATH)
+        vp, i32, i64, sz = ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_size_t
+        L.sscf_init_system.argtypes = [ct.POINTER(SystemDesc), ct.POINTER(vp)]
+        L.sscf_set_fock.argtypes = [vp, vp, i32]
+        L.sscf_scf_step.argtypes = [vp, ct.POINTER(StepInfo)]
+        L.sscf_get_energy.argtypes = [vp, ct.POINTER(ct.c_double)]
+        L.sscf_get_density.argtypes = [vp, vp, sz]
+        L.sscf_get_charges.argtypes = [vp, vp, sz]
+        L.sscf_get_mo_coefficients.argtypes = [vp, vp, vp, vp, ct.POINTER(i64)]
+        L.sscf_init_info.argtypes = [vp, ct.POINTER(StepInfo)]
+        L.sscf_get_schedule.argtypes = [vp, vp, vp, vp, ct.POINTER(i32)]
+        L.sscf_get_kernel_stats.argtypes = [vp, vp, ct.POINTER(i32)]
+        L.sscf_reset_kernel_stats.argtypes = [vp]
+        L.sscf_destroy.argtypes = [vp]
+        L.sscf_destroy.restype = None
+        L.sscf_last_error.argtypes = [vp]
+        L.sscf_last_error.restype = ct.c_char_p
+        for f in EXPORTS[:-2]:
+            getattr(L, f).restype = ct.c_int32
+        _lib = L
+    return _lib
+
+
+class SSCFError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _p(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def _torch_allocator(device):
+    """Allocator callbacks that take device memory from torch's caching allocator."""
+    import torch
+
+    live = {}
+
+    def _alloc(_self, nbytes, stream):
+        ptr = torch.cuda.caching_allocator_alloc(int(nbytes), device)
+        live[ptr] = nbytes
+        return ptr
+
+    def _free(_self, ptr, stream):
+        if ptr in live:
+            del live[ptr]
+            torch.cuda.caching_allocator_delete(ptr)
+
+    return ALLOC_FN(_alloc), FREE_FN(_free)
+
+
+class SparseSCF:
+    """One sparse SCF problem on the GPU.  Construction copies the inputs to the device
+    and runs the initial orthonormalization."""
+
+    def __init__(self, system, eps: float = 1e-5, e_conv: float = 1e-6, group_nbr_bohr: float = 20.0,
+                 rot_cap_factor: float = 10.0, max_sweeps_init: int = 200, max_sweeps_step: int = 50,
+                 scc: bool = True, precision: int = FP64, stream=None, use_torch_allocator: bool = True,
+                 profile: bool = False):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the sparse SCF library needs a GPU")
+        self.system = s = system
+        self._device = torch.cuda.current_device()
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        k = self._keep = dict(
+            nao=np.ascontiguousarray(s.atom_nao, dtype=np.int32),
+            xyz=np.ascontiguousarray(s.xyz_bohr, dtype=np.float64),
+            U=np.ascontiguousarray(s.hubbard_u, dtype=np.float64),
+            q0=np.ascontiguousarray(s.q0, dtype=np.float64),
+            ag=np.ascontiguousarray(s.atom_group, dtype=np.int32),
+            rp=np.ascontiguousarray(s.blk_rowptr, dtype=np.int64),
+            bc=np.ascontiguousarray(s.blk_col, dtype=np.int32),
+            bo=np.ascontiguousarray(s.blk_off, dtype=np.int64),
+            S=np.ascontiguousarray(s.S_val, dtype=np.float64),
+            H0=np.ascontiguousarray(s.H0_val, dtype=np.float64),
+            mg=np.ascontiguousarray(s.mo_group, dtype=np.int32),
+            cp=np.ascontiguousarray(s.c0_colptr, dtype=np.int64),
+            cr=np.ascontiguousarray(s.c0_row, dtype=np.int32),
+            cv=np.ascontiguousarray(s.c0_val, dtype=np.float64),
+        )
+        if use_torch_allocator:
+            self._cb = _torch_allocator(self._device)
+            alloc = Allocator(None, self._cb[0], self._cb[1])
+        else:
+            self._cb = None
+            alloc = Allocator(None, ALLOC_FN(), FREE_FN())
+        d = SystemDesc(
+            n_atoms=s.n_atoms, atom_nao=_p(k["nao"]), xyz_bohr=_p(k["xyz"]), hubbard_u=_p(k["U"]),
+            q0=_p(k["q0"]), atom_group=_p(k["ag"]), n_groups=s.n_groups, blk_rowptr=_p(k["rp"]),
+            blk_col=_p(k["bc"]), blk_off=_p(k["bo"]), S_val=_p(k["S"]), H0_val=_p(k["H0"]),
+            n_val=k["S"].shape[0], n_mo=s.n_mo, n_occ=s.n_occ, mo_group=_p(k["mg"]),
+            c0_colptr=_p(k["cp"]), c0_row=_p(k["cr"]), c0_val=_p(k["cv"]), eps=eps, e_conv=e_conv,
+            group_nbr_bohr=group_nbr_bohr, rot_cap_factor=rot_cap_factor,
+            max_sweeps_init=max_sweeps_init, max_sweeps_step=max_sweeps_step, scc=1 if scc else 0,
+            precision=precision, hip_stream=self._stream.cuda_stream, alloc=alloc,
+            flags=FLAG_PROFILE if profile else 0)
+        h = ct.c_void_p()
+        rc = lib().sscf_init_system(ct.byref(d), ct.byref(h))
+        if rc != SSCF_OK:
+            raise SSCFError(rc, lib().sscf_last_error(None).decode())
+        self._h = h
+
+    def _check(self, rc: int):
+        if rc != SSCF_OK:
+            raise SSCFError(rc, lib().sscf_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().sscf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_info(self) -> Dict:
+        si = StepInfo()
+        self._check(lib().sscf_init_info(self._h, ct.byref(si)))
+        return si.as_dict()
+
+    def step(self) -> Dict:
+        si = StepInfo()
+        self._check(lib().sscf_scf_step(self._h, ct.byref(si)))
+        return si.as_dict()
+
+    def set_fock(self, f_val: np.ndarray, mode: int) -> None:
+        f = np.ascontiguousarray(f_val, dtype=np.float64)
+        self._check(lib().sscf_set_fock(self._h, _p(f), mode))
+
+    def energy(self) -> float:
+        e = ct.c_double()
+        self._check(lib().sscf_get_energy(self._h, ct.byref(e)))
+        return e.value
+
+    def density(self) -> np.ndarray:
+        out = np.zeros(self.system.S_val.shape[0])
+        self._check(lib().sscf_get_density(self._h, _p(out), out.shape[0]))
+        return out
+
+    def charges(self) -> np.ndarray:
+        out = np.zeros(self.system.n_atoms)
+        self._check(lib().sscf_get_charges(self._h, _p(out), out.shape[0]))
+        return out
+
+    def mo_csc(self):
+        nnz = ct.c_int64(0)
+        self._check(lib().sscf_get_mo_coefficients(self._h, None, None, None, ct.byref(nnz)))
+        cp = np.zeros(self.system.n_mo + 1, dtype=np.int64)
+        r = np.zeros(max(nnz.value, 1), dtype=np.int32)
+        v = np.zeros(max(nnz.value, 1))
+        self._check(lib().sscf_get_mo_coefficients(self._h, _p(cp), _p(r), _p(v), ct.byref(nnz)))
+        return cp, r[:nnz.value], v[:nnz.value]
+
+    def mo_dense(self) -> np.ndarray:
+        cp, r, v = self.mo_csc()
+        out = np.zeros((self.system.n_ao, self.system.n_mo))
+        for j in range(self.system.n_mo):
+            out[r[cp[j]:cp[j + 1]], j] = v[cp[j]:cp[j + 1]]
+        return out
+
+    def kernel_stats(self) -> Dict[str, Dict]:
+        arr = (KernelStat * N_KERNEL_CLASSES)()
+        n = ct.c_int32(N_KERNEL_CLASSES)
+        self._check(lib().sscf_get_kernel_stats(self._h, arr, ct.byref(n)))
+        return {a.name.decode(): dict(launches=a.launches, ms=a.ms, flops=a.flops, bytes=a.bytes)
+                for a in arr[:n.value]}
+
+    def reset_kernel_stats(self) -> None:
+        self._check(lib().sscf_reset_kernel_stats(self._h))
+
+    def schedule(self):
+        n = ct.c_int32(0)
+        self._check(lib().sscf_get_schedule(self._h, None, None, None, ct.byref(n)))
+        g = np.zeros(max(n.value, 1), dtype=np.int32)
+        h = np.zeros_like(g)
+        r = np.zeros_like(g)
+        self._check(lib().sscf_get_schedule(self._h, _p(g), _p(h), _p(r), ct.byref(n)))
+        return g[:n.value], h[:n.value], r[:n.value]
