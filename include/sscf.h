@@ -181,7 +181,8 @@ sscf_status sscf_get_schedule(const sscf_ctx* ctx, int32_t* g, int32_t* h, int32
  * initialization (or the last reset) when the context was created with
  * SSCF_FLAG_PROFILE.  Classes: spmm_tiles (S C, H C, H0 C), pair_overlap
  * (C^T S C), pair_fock (occupied-virtual C^T H C), ortho_update (C - 1/2 C D),
- * givens_round (one launch per round of rotation blocks), select, fock.  `flops`
+ * rotations (composition of each block's rotations and one pass over the row
+ * blocks), select, fock.  `flops`
  * counts the FP64 MFMA tile products of the class (2048 flops each) and `bytes`
  * the algorithmic traffic of the rotation pass (each rotated element of an active
  * row read and written once).  Call with out == NULL to get *n. */

@@ -61,7 +61,7 @@ int round16(int x) { return ((x + 15) / 16) * 16; }
 // kernel classes reported by sscf_get_kernel_stats
 enum { KC_SPMM, KC_PAIR_O, KC_PAIR_F, KC_UPDATE, KC_GIVENS, KC_SELECT, KC_FOCK };
 const char* const KC_NAME[SSCF_N_KERNEL_CLASSES] = {
-    "spmm_tiles", "pair_overlap", "pair_fock", "ortho_update", "givens_round", "select", "fock"};
+    "spmm_tiles", "pair_overlap", "pair_fock", "ortho_update", "rotations", "select", "fock"};
 // MFMA tile products count 16 x 16 x 4 multiply-adds; the Givens counter holds bytes
 const double KC_FLOP_PER_UNIT[SSCF_N_KERNEL_CLASSES] = {2048.0, 2048.0, 2048.0, 2048.0, 0.0, 0.0, 0.0};
 const double KC_BYTE_PER_UNIT[SSCF_N_KERNEL_CLASSES] = {0.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0};
@@ -104,21 +104,29 @@ struct sscf_ctx {
   uint8_t* actC[2] = {nullptr, nullptr};
   int* listC[2] = {nullptr, nullptr};
   int* cntC[2] = {nullptr, nullptr};
+  unsigned int* cmask[2] = {nullptr, nullptr};   // per tile: 16-column slices that may be nonzero
   int cur = 0;                        // C[cur] is the current MO matrix
   double* Y = nullptr;
   uint8_t* actY = nullptr;
+  unsigned int* ymask = nullptr;
   int *listY = nullptr, *cntY = nullptr;
   uint8_t* act_tmp = nullptr;
   int *list_tmp = nullptr, *cnt_tmp = nullptr;
   int *pnocc = nullptr, *pnvirt = nullptr, *mo_of = nullptr;
   int *gn_ptr = nullptr, *gn = nullptr, *pair_of = nullptr, *pg = nullptr, *ph = nullptr, *self_pair = nullptr;
   double* O = nullptr;
+  double* Dt = nullptr;                 // transposes of the off-diagonal D blocks
   double* sc = nullptr;
   uint8_t *upd = nullptr, *pair_sel = nullptr;
   int *jb_g = nullptr, *jb_h = nullptr, *jb_nocc = nullptr, *jb_nvirt = nullptr, *round_list = nullptr;
   double *F = nullptr, *Fdiag = nullptr, *dvec = nullptr;
-  int *rot_cnt = nullptr, *tcnt = nullptr, *tcol = nullptr;
-  int2* rot_col = nullptr;
+  int *rot_cnt = nullptr, *tcnt = nullptr, *tcol = nullptr, *round_ptr = nullptr;
+  int *rcnt = nullptr, *roff = nullptr;
+  int4* rmeta = nullptr;                // blocks with rotations, packed in round order
+  int2* rot_slot = nullptr;
+  double* Rrot = nullptr;               // composed rotation of each Jacobi block, W x W
+  // FP32 form: H, H C and the composed rotations in single precision
+  float *H32 = nullptr, *Y32 = nullptr, *R32 = nullptr;
   double2* rot_cs = nullptr;
   unsigned int* hist = nullptr;
   long long* ties = nullptr;
@@ -235,7 +243,7 @@ struct sscf_ctx {
       launch_list(v, actY, listY, cntY, stream);
     }
     const int pi = pbegin(KC_SPMM);
-    launch_spmm(v, X, C[cur], actC[cur], listY, cntY, Y, ctr(KC_SPMM), stream);
+    launch_spmm(v, X, C[cur], actC[cur], cmask[cur], listY, cntY, Y, ymask, ctr(KC_SPMM), stream);
     pend(pi);
   }
 
@@ -249,13 +257,13 @@ struct sscf_ctx {
       const int W = v.W;
       const int pi = pbegin(KC_PAIR_O);
       const int nt = (occ_only ? v.OW : W) / 16;
-      launch_pair(v, n_pairs, pg, ph, C[cur], listC[cur], cntC[cur], Y, actY, 0, nt, 0, nt, O, W, (size_t)W * W,
-                  ctr(KC_PAIR_O), stream);
+      launch_pair(v, n_pairs, pg, ph, C[cur], listC[cur], cntC[cur], cmask[cur], Y, actY, ymask, 0, nt, 0, nt, O, W,
+                  (size_t)W * W, ctr(KC_PAIR_O), stream);
       pend(pi);
       HIPC(hipMemsetAsync(&sd->eta_bits, 0, sizeof(unsigned long long), stream));
       HIPC(hipMemsetAsync(&sd->err, 0, sizeof(int), stream));
       launch_ortho_scale(v, v.G, self_pair, O, pnocc, pnvirt, occ_only, sc, sd, stream);
-      launch_normalize_d(v, n_pairs, pg, ph, O, sc, pnocc, pnvirt, occ_only, sd, stream);
+      launch_normalize_d(v, n_pairs, pg, ph, O, Dt, sc, pnocc, pnvirt, occ_only, sd, stream);
       launch_scale_c(v, C[cur], listC[cur], cntC[cur], sc, stream);
       const Scalars h = read_scalars();
       if (h.err & 1) fail(SSCF_E_NOT_SPD, "C^T S C has a non-positive diagonal element");
@@ -270,10 +278,10 @@ struct sscf_ctx {
       launch_mark_selected(v, n_pairs, pg, ph, O, sd, pair_sel, upd, stream);
       launch_update_support(v, actC[cur], gn_ptr, gn, pair_of, pair_sel, act_tmp, stream);
       launch_list(v, act_tmp, list_tmp, cnt_tmp, stream);
-      launch_clear_tiles(v, C[nx], actC[nx], listC[nx], cntC[nx], stream);
+      launch_clear_tiles(v, C[nx], actC[nx], cmask[nx], listC[nx], cntC[nx], stream);
       const int pu = pbegin(KC_UPDATE);
-      launch_ortho_update(v, C[cur], actC[cur], gn_ptr, gn, pair_of, pair_sel, O, sd, upd, cut, list_tmp, cnt_tmp,
-                          C[nx], actC[nx], ctr(KC_UPDATE), stream);
+      launch_ortho_update(v, C[cur], actC[cur], gn_ptr, gn, pair_of, pair_sel, O, Dt, sd, upd, cut, list_tmp, cnt_tmp,
+                          C[nx], actC[nx], cmask[cur], cmask[nx], ctr(KC_UPDATE), stream);
       pend(pu);
       rebuild_list(nx);
       cur = nx;
@@ -329,7 +337,6 @@ void validate(const sscf_system_desc* d) {
       !(d->rot_cap_factor >= 0.0) || d->max_sweeps_init < 0 || d->max_sweeps_step < 0)
     fail(SSCF_E_INVALID_ARG, "bad thresholds");
   if (d->precision != SSCF_FP64 && d->precision != SSCF_FP32_MIXED) fail(SSCF_E_INVALID_ARG, "bad precision");
-  if (d->precision == SSCF_FP32_MIXED) fail(SSCF_E_INVALID_ARG, "the FP32 form is not available in this build");
   if (d->flags & ~(uint64_t)SSCF_FLAG_PROFILE) fail(SSCF_E_INVALID_ARG, "unknown bits in flags");
   for (int a = 0; a < d->n_atoms; ++a) {
     if (d->atom_nao[a] < 1 || d->atom_nao[a] > 4) fail(SSCF_E_INVALID_ARG, "atom %d: atom_nao must be 1..4", a);
@@ -602,11 +609,14 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
     x->actC[b] = x->dalloc<uint8_t>(ntiles);
     HIPC(hipMemsetAsync(x->actC[b], 0, ntiles, s));
     x->listC[b] = x->dalloc<int>(ntiles);
+    x->cmask[b] = x->dalloc<unsigned int>(ntiles);
+    HIPC(hipMemsetAsync(x->cmask[b], 0, ntiles * sizeof(unsigned int), s));
     x->cntC[b] = x->dalloc<int>(G);
     HIPC(hipMemsetAsync(x->cntC[b], 0, sizeof(int) * G, s));
   }
   x->Y = x->dalloc<double>(ntiles * tile_elems);
   x->actY = x->dalloc<uint8_t>(ntiles);
+  x->ymask = x->dalloc<unsigned int>(ntiles);
   x->listY = x->dalloc<int>(ntiles);
   x->cntY = x->dalloc<int>(G);
   x->act_tmp = x->dalloc<uint8_t>(ntiles);
@@ -622,6 +632,7 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
   x->ph = x->upload(ph.data(), ph.size());
   x->self_pair = x->upload(self_pair.data(), self_pair.size());
   x->O = x->dalloc<double>((size_t)x->n_pairs * v.W * v.W);
+  x->Dt = x->dalloc<double>((size_t)x->n_pairs * v.W * v.W);
   x->sc = x->dalloc<double>((size_t)G * v.W);
   x->upd = x->dalloc<uint8_t>((size_t)G * v.W);
   x->pair_sel = x->dalloc<uint8_t>(x->n_pairs);
@@ -635,7 +646,18 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
   x->Fdiag = x->dalloc<double>((size_t)G * v.W);
   x->dvec = x->dalloc<double>((size_t)G * v.W);
   x->rot_cnt = x->dalloc<int>(x->n_blocks);
-  x->rot_col = x->dalloc<int2>((size_t)x->n_blocks * per);
+  x->rot_slot = x->dalloc<int2>((size_t)x->n_blocks * per);
+  if (x->precision == SSCF_FP32_MIXED) {
+    x->H32 = x->dalloc<float>(nxe);
+    x->Y32 = x->dalloc<float>(ntiles * tile_elems);
+    x->R32 = x->dalloc<float>((size_t)x->n_blocks * v.W * v.W);
+  } else {
+    x->Rrot = x->dalloc<double>((size_t)x->n_blocks * v.W * v.W);
+  }
+  x->round_ptr = x->upload(x->h_round_ptr.data(), x->h_round_ptr.size());
+  x->rcnt = x->dalloc<int>(x->n_rounds + 1);
+  x->roff = x->dalloc<int>(x->n_rounds + 1);
+  x->rmeta = x->dalloc<int4>(x->n_blocks);
   x->rot_cs = x->dalloc<double2>((size_t)x->n_blocks * per);
   x->tcnt = x->dalloc<int>(x->n_blocks);
   x->tcol = x->dalloc<int>((size_t)x->n_blocks * v.W);
@@ -663,7 +685,7 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
     double* dval = x->upload(d->c0_val, nnz0);
     int* dpanel = x->upload(mo_panel.data(), v.n_mo);
     int* dcolm = x->upload(mo_col.data(), v.n_mo);
-    launch_scatter_c0(v, (int)nnz0, dcol, drow, dval, dpanel, dcolm, x->C[0], x->actC[0], s);
+    launch_scatter_c0(v, (int)nnz0, dcol, drow, dval, dpanel, dcolm, x->C[0], x->actC[0], x->cmask[0], s);
     x->cur = 0;
     x->rebuild_list(0);
     x->dfree(dcol); x->dfree(drow); x->dfree(dval); x->dfree(dpanel); x->dfree(dcolm);
@@ -709,16 +731,32 @@ static void step(sscf_ctx* x, sscf_step_info* out) {
   HIPC(hipEventRecord(x->ev[0], s));
   // step IV: Fock matrix with the charges of the previous step (Q = gamma dq)
   int pi = x->pbegin(KC_FOCK);
-  launch_fock(v, x->S, x->H0, x->fock_full ? x->Hfull : nullptr, x->Q, x->eps, x->H, s);
+  launch_fock(v, x->S, x->H0, x->fock_full ? x->Hfull : nullptr, x->Q, x->eps, x->H, x->H32, s);
   x->pend(pi);
   HIPC(hipEventRecord(x->ev[1], s));
-  // C^T H C: occupied-virtual blocks and the diagonal
-  x->product(x->H, true);
-  pi = x->pbegin(KC_PAIR_F);
-  launch_pair(v, x->n_blocks, x->jb_g, x->jb_h, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur], x->Y, x->actY, 0,
-              v.OW / 16, v.OW, v.VW / 16, x->F, v.VW, (size_t)v.OW * v.VW, x->ctr(KC_PAIR_F), s);
-  x->pend(pi);
-  launch_coldot(v, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur], x->Y, x->actY, x->Fdiag, s);
+  // C^T H C: occupied-virtual blocks and the diagonal (FP32 in the precision form)
+  if (x->precision == SSCF_FP32_MIXED) {
+    launch_dilate(v, x->actC[x->cur], x->actY, s);
+    launch_list(v, x->actY, x->listY, x->cntY, s);
+    pi = x->pbegin(KC_SPMM);
+    launch_spmm32(v, x->H32, x->C[x->cur], x->actC[x->cur], x->cmask[x->cur], x->listY, x->cntY, x->Y32, x->ymask,
+                  x->ctr(KC_SPMM), s);
+    x->pend(pi);
+    pi = x->pbegin(KC_PAIR_F);
+    launch_pair32(v, x->n_blocks, x->jb_g, x->jb_h, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur],
+                  x->cmask[x->cur], x->Y32, x->actY, x->ymask, 0, v.OW / 16, v.OW, v.VW / 16, x->F, v.VW,
+                  (size_t)v.OW * v.VW, x->ctr(KC_PAIR_F), s);
+    x->pend(pi);
+    launch_coldot32(v, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur], x->Y32, x->actY, x->Fdiag, s);
+  } else {
+    x->product(x->H, true);
+    pi = x->pbegin(KC_PAIR_F);
+    launch_pair(v, x->n_blocks, x->jb_g, x->jb_h, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur],
+                x->cmask[x->cur], x->Y, x->actY, x->ymask, 0, v.OW / 16, v.OW, v.VW / 16, x->F, v.VW,
+                (size_t)v.OW * v.VW, x->ctr(KC_PAIR_F), s);
+    x->pend(pi);
+    launch_coldot(v, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur], x->Y, x->actY, x->Fdiag, s);
+  }
   HIPC(hipEventRecord(x->ev[2], s));
   // step V: selection of the rotations
   pi = x->pbegin(KC_SELECT);
@@ -740,17 +778,18 @@ static void step(sscf_ctx* x, sscf_step_info* out) {
                    x->eps, x->sd, x->ties, s);
   }
   launch_block_select(v, x->n_blocks, x->jb_g, x->jb_h, x->jb_nocc, x->jb_nvirt, x->F, x->Fdiag, x->mo_of, x->eps,
-                      x->sd, x->rot_cnt, x->rot_col, x->rot_cs, x->tcnt, x->tcol, s);
+                      x->sd, x->rot_cnt, x->rot_slot, x->rot_cs, x->tcnt, x->tcol,
+                      x->precision == SSCF_FP32_MIXED, s);
   x->pend(pi);
   HIPC(hipEventRecord(x->ev[3], s));
-  // rotations, round by round
-  for (int r = 0; r < x->n_rounds; ++r) {
-    const int b0 = x->h_round_ptr[r], b1 = x->h_round_ptr[r + 1];
-    const int pg_ = x->pbegin(KC_GIVENS);
-    launch_givens_round(v, b1 - b0, x->round_list + b0, x->jb_g, x->jb_h, x->rot_cnt, x->rot_col, x->rot_cs, x->tcnt,
-                        x->tcol, x->eps, x->C[x->cur], x->actC[x->cur], x->ctr(KC_GIVENS), s);
-    x->pend(pg_);
-  }
+  // rotations: composed per block, applied in one pass over the row blocks
+  pi = x->pbegin(KC_GIVENS);
+  launch_compose_rot(v, x->n_blocks, x->rot_cnt, x->rot_slot, x->rot_cs, x->tcnt, x->Rrot, x->R32, s);
+  launch_round_meta(x->n_rounds, x->round_ptr, x->round_list, x->rot_cnt, x->jb_g, x->jb_h, x->tcnt, x->rcnt,
+                    x->roff, x->rmeta, s);
+  launch_givens_rb(v, x->n_rounds, x->roff, x->rmeta, x->tcol, x->Rrot, x->R32, x->eps, x->C[x->cur],
+                   x->actC[x->cur], x->cmask[x->cur], x->ctr(KC_GIVENS), s);
+  x->pend(pi);
   x->rebuild_list(x->cur);
   HIPC(hipEventRecord(x->ev[4], s));
   // step III: re-orthonormalization

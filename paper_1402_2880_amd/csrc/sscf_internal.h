@@ -67,23 +67,25 @@ void launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t s);
 void launch_fill_i32(int* p, size_t n, int v, hipStream_t s);
 void launch_scatter_c0(const View& v, int nnz, const int64_t* colptr_expanded_col, const int* row,
                        const double* val, const int* mo_panel, const int* mo_col, double* C,
-                       uint8_t* act, hipStream_t s);
+                       uint8_t* act, unsigned int* cmask, hipStream_t s);
 void launch_dilate(const View& v, const uint8_t* actC, uint8_t* actY, hipStream_t s);
 void launch_list(const View& v, const uint8_t* act, int* list, int* cnt, hipStream_t s);
 void launch_spmm(const View& v, const double* X, const double* C, const uint8_t* actC,
-                 const int* listY, const int* cntY, double* Y, unsigned long long* ctr, hipStream_t s);
+                 const unsigned int* cmask, const int* listY, const int* cntY, double* Y,
+                 unsigned int* ymask, unsigned long long* ctr, hipStream_t s);
 void launch_pair(const View& v, int n_pairs, const int* pg, const int* ph, const double* C,
-                 const int* listC, const int* cntC, const double* Y, const uint8_t* actY,
-                 int row_off, int MT, int col_off, int NT, double* out, int ld, size_t out_stride,
-                 unsigned long long* ctr, hipStream_t s);
+                 const int* listC, const int* cntC, const unsigned int* cmask, const double* Y,
+                 const uint8_t* actY, const unsigned int* ymask, int row_off, int MT, int col_off,
+                 int NT, double* out, int ld, size_t out_stride, unsigned long long* ctr,
+                 hipStream_t s);
 void launch_coldot(const View& v, const double* C, const int* listC, const int* cntC,
                    const double* Y, const uint8_t* actY, double* out, hipStream_t s);
 void launch_ortho_scale(const View& v, int n_pairs_self, const int* self_pair, const double* O,
                         const int* pnocc, const int* pnvirt, int occ_only, double* sc,
                         Scalars* sd, hipStream_t s);
 void launch_normalize_d(const View& v, int n_pairs, const int* pg, const int* ph, double* O,
-                        const double* sc, const int* pnocc, const int* pnvirt, int occ_only,
-                        Scalars* sd, hipStream_t s);
+                        double* Dt, const double* sc, const int* pnocc, const int* pnvirt,
+                        int occ_only, Scalars* sd, hipStream_t s);
 void launch_scale_c(const View& v, double* C, const int* listC, const int* cntC, const double* sc,
                     hipStream_t s);
 void launch_mark_selected(const View& v, int n_pairs, const int* pg, const int* ph, const double* D,
@@ -91,16 +93,17 @@ void launch_mark_selected(const View& v, int n_pairs, const int* pg, const int* 
 void launch_update_support(const View& v, const uint8_t* actC, const int* gn_ptr, const int* gn,
                            const int* pair_of, const uint8_t* pair_sel, uint8_t* act_new,
                            hipStream_t s);
-void launch_clear_tiles(const View& v, double* C, uint8_t* act, const int* list, const int* cnt,
-                        hipStream_t s);
+void launch_clear_tiles(const View& v, double* C, uint8_t* act, unsigned int* cmask,
+                        const int* list, const int* cnt, hipStream_t s);
 void launch_ortho_update(const View& v, const double* C, const uint8_t* actC, const int* gn_ptr,
                          const int* gn, const int* pair_of, const uint8_t* pair_sel, const double* D,
-                         const Scalars* sd, const uint8_t* upd, double cut, const int* listN,
-                         const int* cntN, double* Cn, uint8_t* actN, unsigned long long* ctr,
-                         hipStream_t s);
+                         const double* Dt, const Scalars* sd, const uint8_t* upd, double cut,
+                         const int* listN,
+                         const int* cntN, double* Cn, uint8_t* actN, const unsigned int* cmask,
+                         unsigned int* cmaskN, unsigned long long* ctr, hipStream_t s);
 void launch_coulomb(const View& v, int scc, const double* dq, double* Q, hipStream_t s);
 void launch_fock(const View& v, const double* S, const double* H0, const double* Hfull,
-                 const double* Q, double eps, double* H, hipStream_t s);
+                 const double* Q, double eps, double* H, float* H32, hipStream_t s);
 void launch_count_candidates(int nb, int OW, int VW, const int* jb_nocc, const int* jb_nvirt,
                              const double* F, double tau, Scalars* sd, hipStream_t s);
 void launch_radix_pass(int nb, int OW, int VW, const int* jb_nocc, const int* jb_nvirt,
@@ -113,12 +116,26 @@ void launch_tie_cut(int nb, int OW, int VW, const int* jb_g, const int* jb_h, co
                     double tau, Scalars* sd, long long* ties, hipStream_t s);
 void launch_block_select(const View& v, int nb, const int* jb_g, const int* jb_h, const int* jb_nocc,
                          const int* jb_nvirt, const double* F, const double* Fdiag, const int* mo_of,
-                         double tau, Scalars* sd, int* rot_cnt, int2* rot_col, double2* rot_cs,
-                         int* tcnt, int* tcol, hipStream_t s);
-void launch_givens_round(const View& v, int n_round_blocks, const int* round_blocks,
-                         const int* jb_g, const int* jb_h, const int* rot_cnt, const int2* rot_col,
-                         const double2* rot_cs, const int* tcnt, const int* tcol, double eps,
-                         double* C, uint8_t* actC, unsigned long long* ctr, hipStream_t s);
+                         double tau, Scalars* sd, int* rot_cnt, int2* rot_slot, double2* rot_cs,
+                         int* tcnt, int* tcol, int fp32, hipStream_t s);
+void launch_compose_rot(const View& v, int nb, const int* rot_cnt, const int2* rot_slot,
+                        const double2* rot_cs, const int* tcnt, double* R, float* R32, hipStream_t s);
+void launch_round_meta(int n_rounds, const int* round_ptr, const int* round_list, const int* rot_cnt,
+                       const int* jb_g, const int* jb_h, const int* tcnt, int* rcnt, int* roff, int4* meta,
+                       hipStream_t s);
+void launch_givens_rb(const View& v, int n_rounds, const int* roff, const int4* meta, const int* tcol,
+                      const double* R, const float* R32, double eps, double* C, uint8_t* actC,
+                      unsigned int* cmask, unsigned long long* ctr, hipStream_t s);
+void launch_spmm32(const View& v, const float* X, const double* C, const uint8_t* actC,
+                   const unsigned int* cmask, const int* listY, const int* cntY, float* Y,
+                   unsigned int* ymask, unsigned long long* ctr, hipStream_t s);
+void launch_pair32(const View& v, int n_pairs, const int* pg, const int* ph, const double* C,
+                   const int* listC, const int* cntC, const unsigned int* cmask, const float* Y,
+                   const uint8_t* actY, const unsigned int* ymask, int row_off, int MT, int col_off,
+                   int NT, double* out, int ld, size_t out_stride, unsigned long long* ctr,
+                   hipStream_t s);
+void launch_coldot32(const View& v, const double* C, const int* listC, const int* cntC,
+                     const float* Y, const uint8_t* actY, double* out, hipStream_t s);
 void launch_charges_rows(const View& v, const double* C, const uint8_t* actC, const double* Y,
                          const uint8_t* actY, const double* sc, const int* pnocc, double* rowq,
                          hipStream_t s);

@@ -7,8 +7,9 @@
 // X = H for the partial diagonalization) run as block-sparse products of dense
 // 16-row tiles on the FP64 matrix cores (v_mfma_f64_16x16x4f64).  The pair
 // combinations of section 3.4 are the product C D_sel on the same tiles.  The
-// Jacobi rotations of section 3.5 are applied round by round, one thread per
-// AO row, since rows of C are independent under right multiplication.
+// Jacobi rotations of section 3.5 are composed per block into small orthogonal
+// matrices and applied in one pass over row blocks, since rows of C are
+// independent under right multiplication.
 //
 // FP64 16x16x4 MFMA operand layout (lane l of the wave): A[l % 16][l / 16],
 // B[l / 16][l % 16]; result register r holds D[l / 16 + 4 r][l % 16].
@@ -96,7 +97,7 @@ void launch_scatter(const int64_t* map, int64_t n, const double* src, double* ds
 // C0 (one entry per thread) into the tiles
 __global__ void k_scatter_c0(int nnz, const int64_t* col_of, const int* row, const double* val,
                              const int* mo_panel, const int* mo_col, int n_rb, int W, double* C,
-                             uint8_t* act) {
+                             uint8_t* act, unsigned int* cmask) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nnz) return;
   const int j = (int)col_of[e];
@@ -105,11 +106,13 @@ __global__ void k_scatter_c0(int nnz, const int64_t* col_of, const int* row, con
   const size_t tile = (size_t)g * n_rb + mu / RB;
   C[(tile * RB + (mu % RB)) * W + mo_col[j]] = val[e];
   act[tile] = 1;
+  if (val[e] != 0.0) atomicOr(&cmask[tile], 1u << (mo_col[j] >> 4));
 }
 void launch_scatter_c0(const View& v, int nnz, const int64_t* col_of, const int* row, const double* val,
-                       const int* mo_panel, const int* mo_col, double* C, uint8_t* act, hipStream_t s) {
+                       const int* mo_panel, const int* mo_col, double* C, uint8_t* act, unsigned int* cmask,
+                       hipStream_t s) {
   if (nnz) hipLaunchKernelGGL(k_scatter_c0, dim3(nblk(nnz, 256)), dim3(256), 0, s, nnz, col_of, row, val,
-                              mo_panel, mo_col, v.n_rb, v.W, C, act);
+                              mo_panel, mo_col, v.n_rb, v.W, C, act, cmask);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -168,8 +171,10 @@ template <int NT>
 __global__ void __launch_bounds__(256) k_spmm(int n_rb, const int* __restrict__ xs_ptr,
                                               const int* __restrict__ xs_col, const double* __restrict__ X,
                                               const double* __restrict__ C, const uint8_t* __restrict__ actC,
+                                              const unsigned int* __restrict__ cmask,
                                               const int* __restrict__ listY, const int* __restrict__ cntY,
-                                              double* __restrict__ Y, unsigned long long* ctr) {
+                                              double* __restrict__ Y, unsigned int* __restrict__ ymask,
+                                              unsigned long long* ctr) {
   constexpr int W = NT * 16;
   const int g = blockIdx.y;
   const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -185,29 +190,41 @@ __global__ void __launch_bounds__(256) k_spmm(int n_rb, const int* __restrict__ 
   for (int kb = xs_ptr[r]; kb < xs_ptr[r + 1]; ++kb) {
     const int c = xs_col[kb];
     if (!actC[pb + c]) continue;
-    n_mfma += 4 * NT;
+    const unsigned int m = cmask[pb + c];
     const double* Xb = X + (size_t)kb * 256;
     const double* Ct = C + (pb + c) * (RB * W);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const double a = Xb[lr * 16 + 4 * s + lk];
 #pragma unroll
-      for (int n = 0; n < NT; ++n) acc[n] = mfma64(a, Ct[(4 * s + lk) * W + n * 16 + lr], acc[n]);
+      for (int n = 0; n < NT; ++n)
+        if (m & (1u << n)) { acc[n] = mfma64(a, Ct[(4 * s + lk) * W + n * 16 + lr], acc[n]); ++n_mfma; }
     }
   }
   double* Yt = Y + (pb + r) * (RB * W);
+  unsigned int ym = 0;
 #pragma unroll
-  for (int n = 0; n < NT; ++n)
+  for (int n = 0; n < NT; ++n) {
+    int nz = 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) Yt[(lk + 4 * q) * W + n * 16 + lr] = acc[n][q];
-  if (ctr && lane == 0) atomicAdd(ctr, (unsigned long long)n_mfma);
+    for (int q = 0; q < 4; ++q) {
+      Yt[(lk + 4 * q) * W + n * 16 + lr] = acc[n][q];
+      nz |= acc[n][q] != 0.0;
+    }
+    if (__ballot(nz)) ym |= 1u << n;
+  }
+  if (lane == 0) {
+    ymask[pb + r] = ym;
+    if (ctr) atomicAdd(ctr, (unsigned long long)n_mfma);
+  }
 }
 
-void launch_spmm(const View& v, const double* X, const double* C, const uint8_t* actC, const int* listY,
-                 const int* cntY, double* Y, unsigned long long* ctr, hipStream_t s) {
+void launch_spmm_wave(const View& v, const double* X, const double* C, const uint8_t* actC, const unsigned int* cmask,
+                 const int* listY, const int* cntY, double* Y, unsigned int* ymask, unsigned long long* ctr,
+                 hipStream_t s) {
   dim3 grid((v.n_rb + 3) / 4, v.G), blk(256);
   switch (v.W / 16) {
-#define SSCF_SPMM(NT) case NT: hipLaunchKernelGGL(k_spmm<NT>, grid, blk, 0, s, v.n_rb, v.xs_ptr, v.xs_col, X, C, actC, listY, cntY, Y, ctr); break;
+#define SSCF_SPMM(NT) case NT: hipLaunchKernelGGL(k_spmm<NT>, grid, blk, 0, s, v.n_rb, v.xs_ptr, v.xs_col, X, C, actC, cmask, listY, cntY, Y, ymask, ctr); break;
     SSCF_SPMM(1) SSCF_SPMM(2) SSCF_SPMM(3) SSCF_SPMM(4) SSCF_SPMM(5) SSCF_SPMM(6) SSCF_SPMM(7) SSCF_SPMM(8)
 #undef SSCF_SPMM
   }
@@ -222,7 +239,9 @@ template <int MW, int NW>
 __global__ void __launch_bounds__(256) k_pair(int n_rb, int W, const int* __restrict__ pg,
                                               const int* __restrict__ ph, const double* __restrict__ C,
                                               const int* __restrict__ listC, const int* __restrict__ cntC,
+                                              const unsigned int* __restrict__ cmask,
                                               const double* __restrict__ Y, const uint8_t* __restrict__ actY,
+                                              const unsigned int* __restrict__ ymask,
                                               int row_off, int MT, int col_off, int NT,
                                               double* __restrict__ out, int ld, size_t out_stride,
                                               unsigned long long* ctr) {
@@ -245,7 +264,9 @@ __global__ void __launch_bounds__(256) k_pair(int n_rb, int W, const int* __rest
     for (int t = 0; t < cnt; ++t) {
       const int r = listC[gb + t];
       if (!actY[hb + r]) continue;
-      n_mfma += 4 * mc * nc;
+      const unsigned int ma = cmask[gb + r] >> (row_off / 16 + mt0);
+      const unsigned int mb = ymask[hb + r] >> (col_off / 16 + nt0);
+      if (!(ma & ((1u << mc) - 1u)) || !(mb & ((1u << nc) - 1u))) continue;
       const double* Ct = C + (gb + r) * (size_t)(RB * W) + row_off + mt0 * 16 + lr;
       const double* Yt = Y + (hb + r) * (size_t)(RB * W) + col_off + nt0 * 16 + lr;
 #pragma unroll
@@ -253,14 +274,17 @@ __global__ void __launch_bounds__(256) k_pair(int n_rb, int W, const int* __rest
         double a[MW], b[NW];
         const int ro = (4 * s + lk) * W;
 #pragma unroll
-        for (int i = 0; i < MW; ++i) a[i] = (i < mc) ? Ct[ro + i * 16] : 0.0;
+        for (int i = 0; i < MW; ++i) a[i] = (i < mc && (ma & (1u << i))) ? Ct[ro + i * 16] : 0.0;
 #pragma unroll
-        for (int j = 0; j < NW; ++j) b[j] = (j < nc) ? Yt[ro + j * 16] : 0.0;
+        for (int j = 0; j < NW; ++j) b[j] = (j < nc && (mb & (1u << j))) ? Yt[ro + j * 16] : 0.0;
 #pragma unroll
         for (int i = 0; i < MW; ++i)
 #pragma unroll
           for (int j = 0; j < NW; ++j)
-            if (i < mc && j < nc) acc[i][j] = mfma64(a[i], b[j], acc[i][j]);
+            if (i < mc && j < nc && (ma & (1u << i)) && (mb & (1u << j))) {
+              acc[i][j] = mfma64(a[i], b[j], acc[i][j]);
+              ++n_mfma;
+            }
       }
     }
   }
@@ -277,20 +301,21 @@ __global__ void __launch_bounds__(256) k_pair(int n_rb, int W, const int* __rest
 }
 
 void launch_pair(const View& v, int n_pairs, const int* pg, const int* ph, const double* C, const int* listC,
-                 const int* cntC, const double* Y, const uint8_t* actY, int row_off, int MT, int col_off,
-                 int NT, double* out, int ld, size_t out_stride, unsigned long long* ctr, hipStream_t s) {
+                 const int* cntC, const unsigned int* cmask, const double* Y, const uint8_t* actY,
+                 const unsigned int* ymask, int row_off, int MT, int col_off, int NT, double* out, int ld,
+                 size_t out_stride, unsigned long long* ctr, hipStream_t s) {
   if (n_pairs <= 0) return;
   const int mw = (MT + 1) / 2, nw = (NT + 1) / 2;
   const int m = mw > nw ? mw : nw;
   dim3 grid(n_pairs), blk(256);
   if (m <= 1)
-    hipLaunchKernelGGL((k_pair<1, 1>), grid, blk, 0, s, v.n_rb, v.W, pg, ph, C, listC, cntC, Y, actY, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+    hipLaunchKernelGGL((k_pair<1, 1>), grid, blk, 0, s, v.n_rb, v.W, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
   else if (m <= 2)
-    hipLaunchKernelGGL((k_pair<2, 2>), grid, blk, 0, s, v.n_rb, v.W, pg, ph, C, listC, cntC, Y, actY, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+    hipLaunchKernelGGL((k_pair<2, 2>), grid, blk, 0, s, v.n_rb, v.W, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
   else if (m <= 3)
-    hipLaunchKernelGGL((k_pair<3, 3>), grid, blk, 0, s, v.n_rb, v.W, pg, ph, C, listC, cntC, Y, actY, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+    hipLaunchKernelGGL((k_pair<3, 3>), grid, blk, 0, s, v.n_rb, v.W, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
   else
-    hipLaunchKernelGGL((k_pair<4, 4>), grid, blk, 0, s, v.n_rb, v.W, pg, ph, C, listC, cntC, Y, actY, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+    hipLaunchKernelGGL((k_pair<4, 4>), grid, blk, 0, s, v.n_rb, v.W, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
 }
 
 // per-column dot products d[g][c] = sum_r sum_k C[g][r][k][c] Y[g][r][k][c]
@@ -347,30 +372,44 @@ void launch_ortho_scale(const View& v, int, const int* self_pair, const double* 
                      pnvirt, occ_only, sc, sd);
 }
 
+// D = normalized O with the diagonal of the self pair removed; also writes the transpose
+// of each off-diagonal block (Dt[p] = D[p]^T) so that both orientations load coalesced.
 __global__ void __launch_bounds__(256) k_normalize_d(int W, int OW, const int* pg, const int* ph, double* O,
-                                                     const double* sc, const int* pnocc, const int* pnvirt,
-                                                     int occ_only, Scalars* sd) {
+                                                     double* Dt, const double* sc, const int* pnocc,
+                                                     const int* pnvirt, int occ_only, Scalars* sd) {
+  __shared__ double tb[16][17];
   const int p = blockIdx.x;
   const int g = pg[p], h = ph[p];
   const int nog = pnocc[g], nvg = pnvirt[g], noh = pnocc[h], nvh = pnvirt[h];
   double* Op = O + (size_t)p * W * W;
+  double* Tp = Dt + (size_t)p * W * W;
+  const int ii = threadIdx.x >> 4, jj = threadIdx.x & 15;
   double m = 0.0;
-  for (int e = threadIdx.x; e < W * W; e += 256) {
-    const int i = e / W, j = e % W;
-    double d = 0.0;
-    if (col_in_scope(i, OW, nog, nvg, occ_only) && col_in_scope(j, OW, noh, nvh, occ_only) &&
-        !(g == h && i == j)) {
-      d = Op[e] / (sc[(size_t)g * W + i] * sc[(size_t)h * W + j]);
-      m = fmax(m, fabs(d));
+  for (int ti = 0; ti < W; ti += 16)
+    for (int tj = 0; tj < W; tj += 16) {
+      const int i = ti + ii, j = tj + jj;
+      const size_t e = (size_t)i * W + j;
+      double d = 0.0;
+      if (col_in_scope(i, OW, nog, nvg, occ_only) && col_in_scope(j, OW, noh, nvh, occ_only) &&
+          !(g == h && i == j)) {
+        d = Op[e] / (sc[(size_t)g * W + i] * sc[(size_t)h * W + j]);
+        m = fmax(m, fabs(d));
+      }
+      Op[e] = d;
+      if (g != h) {
+        tb[ii][jj] = d;
+        __syncthreads();
+        Tp[(size_t)(tj + ii) * W + ti + jj] = tb[jj][ii];
+        __syncthreads();
+      }
     }
-    Op[e] = d;
-  }
   block_max_to(m, &sd->eta_bits);
 }
-void launch_normalize_d(const View& v, int n_pairs, const int* pg, const int* ph, double* O, const double* sc,
-                        const int* pnocc, const int* pnvirt, int occ_only, Scalars* sd, hipStream_t s) {
+void launch_normalize_d(const View& v, int n_pairs, const int* pg, const int* ph, double* O, double* Dt,
+                        const double* sc, const int* pnocc, const int* pnvirt, int occ_only, Scalars* sd,
+                        hipStream_t s) {
   if (n_pairs > 0)
-    hipLaunchKernelGGL(k_normalize_d, dim3(n_pairs), dim3(256), 0, s, v.W, v.OW, pg, ph, O, sc, pnocc, pnvirt,
+    hipLaunchKernelGGL(k_normalize_d, dim3(n_pairs), dim3(256), 0, s, v.W, v.OW, pg, ph, O, Dt, sc, pnocc, pnvirt,
                        occ_only, sd);
 }
 
@@ -428,37 +467,42 @@ void launch_update_support(const View& v, const uint8_t* actC, const int* gn_ptr
                      pair_sel, act_new);
 }
 
-__global__ void __launch_bounds__(256) k_clear_tiles(int n_rb, int W, double* C, uint8_t* act, const int* list,
-                                                     const int* cnt) {
+__global__ void __launch_bounds__(256) k_clear_tiles(int n_rb, int W, double* C, uint8_t* act, unsigned int* cmask,
+                                                     const int* list, const int* cnt) {
   const int g = blockIdx.y, t = blockIdx.x;
   if (t >= cnt[g]) return;
   const size_t tile = (size_t)g * n_rb + list[(size_t)g * n_rb + t];
   double* Ct = C + tile * (size_t)(RB * W);
   for (int e = threadIdx.x; e < RB * W; e += 256) Ct[e] = 0.0;
-  if (threadIdx.x == 0) act[tile] = 0;
+  if (threadIdx.x == 0) { act[tile] = 0; cmask[tile] = 0u; }
 }
-void launch_clear_tiles(const View& v, double* C, uint8_t* act, const int* list, const int* cnt, hipStream_t s) {
-  hipLaunchKernelGGL(k_clear_tiles, dim3(v.n_rb, v.G), dim3(256), 0, s, v.n_rb, v.W, C, act, list, cnt);
+void launch_clear_tiles(const View& v, double* C, uint8_t* act, unsigned int* cmask, const int* list, const int* cnt,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_clear_tiles, dim3(v.n_rb, v.G), dim3(256), 0, s, v.n_rb, v.W, C, act, cmask, list, cnt);
 }
 
 // Cn[g][r] = C[g][r] - 1/2 sum_{h ~ g} C[h][r] D_sel(h, g), then |v| < cut -> 0 in the
 // columns that took part in a combination.  D is stored per unordered pair (a <= b) with
-// rows = MOs of a, columns = MOs of b.
+// rows = MOs of a, columns = MOs of b; Dt holds the transposes, so D_sel(h, g) (rows = MOs
+// of h) is read row-contiguously in both orientations.  One wave per output tile, one
+// accumulator per 16-column slice; 16-column slices of C_h[r] known to be zero are skipped.
 template <int NT>
 __global__ void __launch_bounds__(256) k_ortho_update(int G, int n_rb, const double* __restrict__ C,
-                                                      const uint8_t* __restrict__ actC, const int* __restrict__ gn_ptr,
-                                                      const int* __restrict__ gn, const int* __restrict__ pair_of,
+                                                      const uint8_t* __restrict__ actC,
+                                                      const unsigned int* __restrict__ cmask,
+                                                      const int* __restrict__ gn_ptr, const int* __restrict__ gn,
+                                                      const int* __restrict__ pair_of,
                                                       const uint8_t* __restrict__ pair_sel,
-                                                      const double* __restrict__ D, const Scalars* __restrict__ sd,
+                                                      const double* __restrict__ D, const double* __restrict__ Dt,
+                                                      const Scalars* __restrict__ sd,
                                                       const uint8_t* __restrict__ upd, double cut,
                                                       const int* __restrict__ listN, const int* __restrict__ cntN,
                                                       double* __restrict__ Cn, uint8_t* __restrict__ actN,
-                                                      unsigned long long* ctr) {
+                                                      unsigned int* __restrict__ cmaskN, unsigned long long* ctr) {
   constexpr int W = NT * 16;
   const int g = blockIdx.y;
   const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= cntN[g]) return;
-  unsigned int n_mfma = 0;
   const int lane = threadIdx.x & 63;
   const int lr = lane & 15, lk = lane >> 4;
   const int r = listN[(size_t)g * n_rb + t];
@@ -466,24 +510,27 @@ __global__ void __launch_bounds__(256) k_ortho_update(int G, int n_rb, const dou
   d4 acc[NT];
 #pragma unroll
   for (int n = 0; n < NT; ++n) acc[n] = d4{0.0, 0.0, 0.0, 0.0};
+  unsigned int n_mfma = 0;
   for (int k = gn_ptr[g]; k < gn_ptr[g + 1]; ++k) {
     const int h = gn[k];
     const int p = pair_of[(size_t)g * G + h];
-    if (!pair_sel[p] || !actC[(size_t)h * n_rb + r]) continue;
-    n_mfma += (W / 4) * NT;
-    const double* Ch = C + ((size_t)h * n_rb + r) * (RB * W);
-    const double* Dp = D + (size_t)p * W * W;
-    const bool tr = h > g;
+    const size_t th = (size_t)h * n_rb + r;
+    if (!pair_sel[p] || !actC[th]) continue;
+    const unsigned int am = cmask[th];
+    const double* Ch = C + th * (RB * W) + lr * W + lk;
+    const double* Dp = ((h > g) ? Dt : D) + (size_t)p * W * W + lr;
+#pragma unroll
     for (int s = 0; s < W / 4; ++s) {
-      const double a = Ch[lr * W + 4 * s + lk];
-      const int kk = 4 * s + lk;
+      if (!(am & (1u << (s >> 2)))) continue;
+      const double a = Ch[4 * s];
+      const double* Dr = Dp + (size_t)(4 * s + lk) * W;
 #pragma unroll
       for (int n = 0; n < NT; ++n) {
-        const int nn = n * 16 + lr;
-        double d = tr ? Dp[(size_t)nn * W + kk] : Dp[(size_t)kk * W + nn];
+        double d = Dr[n * 16];
         d = (fabs(d) >= thr) ? d : 0.0;
         acc[n] = mfma64(a, d, acc[n]);
       }
+      n_mfma += NT;
     }
   }
   const size_t tile = (size_t)g * n_rb + r;
@@ -491,31 +538,38 @@ __global__ void __launch_bounds__(256) k_ortho_update(int G, int n_rb, const dou
   const double* Cg = C + tile * (RB * W);
   double* Co = Cn + tile * (RB * W);
   int any = 0;
+  unsigned int cm = 0;
 #pragma unroll
   for (int n = 0; n < NT; ++n) {
     const int j = n * 16 + lr;
     const bool u = upd[(size_t)g * W + j] != 0;
+    int nz = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = lk + 4 * q;
       double v = (own ? Cg[i * W + j] : 0.0) - 0.5 * acc[n][q];
       if (u && fabs(v) < cut) v = 0.0;
       Co[i * W + j] = v;
-      any |= (v != 0.0);
+      nz |= (v != 0.0);
     }
+    if (__ballot(nz)) cm |= 1u << n;
+    any |= nz;
   }
-  const unsigned long long m = __ballot(any);
-  if (lane == 0) actN[tile] = (uint8_t)(m != 0ULL);
-  if (ctr && lane == 0) atomicAdd(ctr, (unsigned long long)n_mfma);
+  if (lane == 0) {
+    actN[tile] = (uint8_t)(cm != 0u);
+    cmaskN[tile] = cm;
+    if (ctr && n_mfma) atomicAdd(ctr, (unsigned long long)n_mfma);
+  }
 }
 
 void launch_ortho_update(const View& v, const double* C, const uint8_t* actC, const int* gn_ptr, const int* gn,
-                         const int* pair_of, const uint8_t* pair_sel, const double* D, const Scalars* sd,
-                         const uint8_t* upd, double cut, const int* listN, const int* cntN, double* Cn,
-                         uint8_t* actN, unsigned long long* ctr, hipStream_t s) {
-  dim3 grid((v.n_rb + 3) / 4, v.G), blk(256);
+                         const int* pair_of, const uint8_t* pair_sel, const double* D, const double* Dt,
+                         const Scalars* sd, const uint8_t* upd, double cut, const int* listN, const int* cntN,
+                         double* Cn, uint8_t* actN, const unsigned int* cmask, unsigned int* cmaskN,
+                         unsigned long long* ctr, hipStream_t s) {
+  dim3 grid((v.n_rb + 3) / 4, v.G);
   switch (v.W / 16) {
-#define SSCF_UPD(NT) case NT: hipLaunchKernelGGL(k_ortho_update<NT>, grid, blk, 0, s, v.G, v.n_rb, C, actC, gn_ptr, gn, pair_of, pair_sel, D, sd, upd, cut, listN, cntN, Cn, actN, ctr); break;
+#define SSCF_UPD(NT) case NT: hipLaunchKernelGGL(k_ortho_update<NT>, grid, dim3(256), 0, s, v.G, v.n_rb, C, actC, cmask, gn_ptr, gn, pair_of, pair_sel, D, Dt, sd, upd, cut, listN, cntN, Cn, actN, cmaskN, ctr); break;
     SSCF_UPD(1) SSCF_UPD(2) SSCF_UPD(3) SSCF_UPD(4) SSCF_UPD(5) SSCF_UPD(6) SSCF_UPD(7) SSCF_UPD(8)
 #undef SSCF_UPD
   }
@@ -566,7 +620,7 @@ void launch_coulomb(const View& v, int scc, const double* dq, double* Q, hipStre
 
 __global__ void k_fock(size_t n, int n_ao, const int* xs_row, const int* xs_col, const int* ao_atom,
                        const double* S, const double* H0, const double* Hfull, const double* Q, double eps,
-                       double* H) {
+                       double* H, float* H32) {
   const size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   if (e >= n) return;
   const size_t b = e >> 8;
@@ -577,13 +631,15 @@ __global__ void k_fock(size_t n, int n_ao, const int* xs_row, const int* xs_col,
     if (Hfull) h = Hfull[e];
     else h = H0[e] + 0.5 * S[e] * (Q[ao_atom[mu]] + Q[ao_atom[nu]]);
   }
-  H[e] = (fabs(h) < eps) ? 0.0 : h;
+  h = (fabs(h) < eps) ? 0.0 : h;
+  H[e] = h;
+  if (H32) H32[e] = (float)h;
 }
 void launch_fock(const View& v, const double* S, const double* H0, const double* Hfull, const double* Q, double eps,
-                 double* H, hipStream_t s) {
+                 double* H, float* H32, hipStream_t s) {
   const size_t n = (size_t)v.nbx * 256;
   hipLaunchKernelGGL(k_fock, dim3(nblk(n, 256)), dim3(256), 0, s, n, v.n_ao, v.xs_row, v.xs_col, v.ao_atom, S, H0,
-                     Hfull, Q, eps, H);
+                     Hfull, Q, eps, H, H32);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -763,8 +819,8 @@ constexpr int SEL_MAX = 4096;
 __global__ void __launch_bounds__(256) k_block_select(int W, int OW, int VW, const int* jb_g, const int* jb_h,
                                                       const int* jb_nocc, const int* jb_nvirt, const double* F,
                                                       const double* Fdiag, const int* mo_of, long long n_mo,
-                                                      double tau, Scalars* sd, int* rot_cnt, int2* rot_col,
-                                                      double2* rot_cs, int* tcnt, int* tcol) {
+                                                      double tau, Scalars* sd, int* rot_cnt, int2* rot_slot,
+                                                      double2* rot_cs, int* tcnt, int* tcol, int fp32) {
   __shared__ unsigned long long khi[SEL_MAX];
   __shared__ unsigned int klo[SEL_MAX];
   __shared__ int n_sel;
@@ -816,103 +872,259 @@ __global__ void __launch_bounds__(256) k_block_select(int W, int OW, int VW, con
       }
       __syncthreads();
     }
-  const size_t rb0 = (size_t)b * per;
+  // touched columns (ascending) and the slot of each column
   for (int q = threadIdx.x; q < n; q += 256) {
-    const int i = klo[q] >> 16, a = klo[q] & 0xFFFF;
-    const double f = Fb[(size_t)i * VW + a];
-    const double fii = Fdiag[(size_t)g * W + i], faa = Fdiag[(size_t)h * W + OW + a];
-    const double p = (fii - faa) / (2.0 * f);
-    const double sg = (p >= 0.0) ? 1.0 : -1.0;
-    const double t = 1.0 / (p + sg * sqrt(1.0 + p * p));
-    const double c = 1.0 / sqrt(1.0 + t * t);
-    rot_col[rb0 + q] = make_int2(i, OW + a);
-    rot_cs[rb0 + q] = make_double2(c, t * c);
-    used[i] = 1;
-    used[OW + a] = 1;
+    used[klo[q] >> 16] = 1;
+    used[OW + (klo[q] & 0xFFFF)] = 1;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     int u = 0;
     for (int c = 0; c < W; ++c)
-      if (used[c]) tcol[(size_t)b * W + u++] = c;
+      if (used[c]) { upos[c] = u; tcol[(size_t)b * W + u] = c; ++u; }
     tcnt[b] = u;
     rot_cnt[b] = n;
     atomicAdd(&sd->n_rot, n);
+  }
+  __syncthreads();
+  const size_t rb0 = (size_t)b * per;
+  for (int q = threadIdx.x; q < n; q += 256) {
+    const int i = klo[q] >> 16, a = klo[q] & 0xFFFF;
+    const double f = Fb[(size_t)i * VW + a];
+    const double fii = Fdiag[(size_t)g * W + i], faa = Fdiag[(size_t)h * W + OW + a];
+    double c, sn;
+    if (fp32) {
+      const float pf = ((float)fii - (float)faa) / (2.0f * (float)f);
+      const float sgf = (pf >= 0.0f) ? 1.0f : -1.0f;
+      const float tf = 1.0f / (pf + sgf * sqrtf(1.0f + pf * pf));
+      const float cf = 1.0f / sqrtf(1.0f + tf * tf);
+      c = cf;
+      sn = tf * cf;
+    } else {
+      const double p = (fii - faa) / (2.0 * f);
+      const double sg = (p >= 0.0) ? 1.0 : -1.0;
+      const double t = 1.0 / (p + sg * sqrt(1.0 + p * p));
+      c = 1.0 / sqrt(1.0 + t * t);
+      sn = t * c;
+    }
+    rot_slot[rb0 + q] = make_int2(upos[i], upos[OW + a]);
+    rot_cs[rb0 + q] = make_double2(c, sn);
   }
 }
 
 void launch_block_select(const View& v, int nb, const int* jb_g, const int* jb_h, const int* jb_nocc, const int* jb_nvirt,
                          const double* F, const double* Fdiag, const int* mo_of, double tau, Scalars* sd,
-                         int* rot_cnt, int2* rot_col, double2* rot_cs, int* tcnt, int* tcol, hipStream_t s) {
+                         int* rot_cnt, int2* rot_slot, double2* rot_cs, int* tcnt, int* tcol, int fp32,
+                         hipStream_t s) {
   if (nb > 0)
     hipLaunchKernelGGL(k_block_select, dim3(nb), dim3(256), 0, s, v.W, v.OW, v.VW, jb_g, jb_h, jb_nocc, jb_nvirt, F,
-                       Fdiag, mo_of, (long long)v.n_mo, tau, sd, rot_cnt, rot_col, rot_cs, tcnt, tcol);
+                       Fdiag, mo_of, (long long)v.n_mo, tau, sd, rot_cnt, rot_slot, rot_cs, tcnt, tcol, fp32);
 }
 
 // ---------------------------------------------------------------------------------------
-// rotation application, one round of Jacobi blocks per launch: one thread per AO row of
-// the row blocks where the occupied panel g or the virtual panel h is active.
-// C'_i = c C_i + s C_a, C'_a = -s C_i + c C_a in list order, then |C| < eps -> 0 in the
-// columns the block rotated.  Blocks of a round share no panel.
+// rotation application.  The ordered rotations of a Jacobi block act on the block's
+// touched columns as one orthogonal matrix: x -> x G_1 G_2 ... G_n = x R_b for every
+// row x of C (rotations are column operations, rows are independent).  R_b is formed
+// once per block (row k of R_b is e_k rotated in list order); then one workgroup per
+// row block walks the rounds in order (a barrier between rounds, the blocks of a round
+// spread over its waves) and applies each relevant R_b to the 16-row slice with the
+// matrix cores, followed by the truncation |C| < eps of the block's columns.
 // ---------------------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) k_givens_round(int n_rb, int W, int OW, const int* round_blocks,
-                                                      const int* jb_g, const int* jb_h, const int* rot_cnt,
-                                                      const int2* __restrict__ rot_col,
-                                                      const double2* __restrict__ rot_cs, const int* tcnt,
-                                                      const int* tcol, double eps, double* C, uint8_t* actC,
-                                                      unsigned long long* ctr) {
-  const int b = round_blocks[blockIdx.y];
+template <typename Real>
+__global__ void __launch_bounds__(128) k_compose_rot(int W, int per, const int* rot_cnt, const int2* rot_slot,
+                                                     const double2* rot_cs, const int* tcnt, Real* R) {
+  const int b = blockIdx.x;
   const int n = rot_cnt[b];
   if (n == 0) return;
-  const int g = jb_g[b], h = jb_h[b];
-  const int rb = blockIdx.x * 16 + (threadIdx.x >> 4);
-  const int k = threadIdx.x & 15;
-  const bool in = rb < n_rb;
-  const size_t tg = (size_t)g * n_rb + (in ? rb : 0), th = (size_t)h * n_rb + (in ? rb : 0);
-  const bool ag = in && actC[tg], ah = in && actC[th];
-  const bool live = ag || ah;
-  int nzg = 0, nzh = 0;
-  if (live) {
-    double* rowg = C + (tg * RB + k) * W;
-    double* rowh = C + (th * RB + k) * W;
-    const size_t base = (size_t)b * OW * (W - OW);
-    for (int q = 0; q < n; ++q) {
-      const int2 cc = rot_col[base + q];
-      const double2 cs = rot_cs[base + q];
-      const double xi = rowg[cc.x], xa = rowh[cc.y];
-      rowg[cc.x] = cs.x * xi + cs.y * xa;
-      rowh[cc.y] = -cs.y * xi + cs.x * xa;
-    }
-    const int nt = tcnt[b];
-    for (int u = 0; u < nt; ++u) {
-      const int c = tcol[(size_t)b * W + u];
-      double* row = (c < OW) ? rowg : rowh;
-      double x = row[c];
-      if (fabs(x) < eps) { x = 0.0; row[c] = 0.0; }
-      if (x != 0.0) { if (c < OW) nzg = 1; else nzh = 1; }
-    }
+  const int T = tcnt[b];
+  const int T16 = (T + 15) & ~15;
+  const int k = threadIdx.x;
+  if (k >= T16) return;
+  Real* row = R + ((size_t)b * W + k) * W;
+  for (int j = 0; j < T16; ++j) row[j] = (j == k && k < T) ? Real(1) : Real(0);
+  if (k >= T) return;
+  const int2* sl = rot_slot + (size_t)b * per;
+  const double2* cs = rot_cs + (size_t)b * per;
+  for (int q = 0; q < n; ++q) {
+    const int2 ia = sl[q];
+    const Real c = (Real)cs[q].x, sn = (Real)cs[q].y;
+    const Real xi = row[ia.x], xa = row[ia.y];
+    row[ia.x] = c * xi + sn * xa;
+    row[ia.y] = -sn * xi + c * xa;
   }
-  // a tile that receives nonzeros becomes active (all 16 rows of a tile sit in one wave)
-  const unsigned long long mg = __ballot(nzg), mh = __ballot(nzh);
-  const int lane = threadIdx.x & 63;
-  const int sub = (lane >> 4) * 16;
-  if (in && k == 0) {
-    if (!ag && ((mg >> sub) & 0xFFFFULL)) actC[tg] = 1;
-    if (!ah && ((mh >> sub) & 0xFFFFULL)) actC[th] = 1;
-    // algorithmic traffic: each touched element of the 16 rows read and written once
-    if (ctr && live) atomicAdd(ctr, (unsigned long long)tcnt[b] * RB * 16ULL);
+}
+void launch_compose_rot(const View& v, int nb, const int* rot_cnt, const int2* rot_slot, const double2* rot_cs,
+                        const int* tcnt, double* R, float* R32, hipStream_t s) {
+  if (nb <= 0) return;
+  if (R32)
+    hipLaunchKernelGGL(k_compose_rot<float>, dim3(nb), dim3(128), 0, s, v.W, v.OW * v.VW, rot_cnt, rot_slot, rot_cs,
+                       tcnt, R32);
+  else
+    hipLaunchKernelGGL(k_compose_rot<double>, dim3(nb), dim3(128), 0, s, v.W, v.OW * v.VW, rot_cnt, rot_slot, rot_cs,
+                       tcnt, R);
+}
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4 mfma32(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// FP32 16x16x4 result register r holds D[4 (l / 16) + r][l % 16]; FP64 holds D[l / 16 + 4 r][l % 16]
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef d4 acc_t;
+  static __device__ __forceinline__ d4 op(double a, double b, d4 c) { return mfma64(a, b, c); }
+  static __device__ __forceinline__ int row(int lk, int q) { return lk + 4 * q; }
+};
+template <> struct Mfma<float> {
+  typedef f4 acc_t;
+  static __device__ __forceinline__ f4 op(float a, float b, f4 c) { return mfma32(a, b, c); }
+  static __device__ __forceinline__ int row(int lk, int q) { return 4 * lk + q; }
+};
+
+// The blocks that carry rotations, packed (block, g, h, touched columns) in round order,
+// with the offset of each round: one 16-byte load per block in the rotation pass.
+__global__ void __launch_bounds__(256) k_round_count(const int* round_ptr, const int* round_list, const int* rot_cnt,
+                                                     int* rcnt) {
+  const int r = blockIdx.x;
+  int c = 0;
+  for (int i = round_ptr[r] + threadIdx.x; i < round_ptr[r + 1]; i += 256) c += rot_cnt[round_list[i]] > 0;
+  c = wave_sum_i(c);
+  __shared__ int ws[4];
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) rcnt[r] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+__global__ void k_round_prefix(int n_rounds, const int* rcnt, int* roff) {
+  if (threadIdx.x != 0) return;
+  int acc = 0;
+  for (int r = 0; r < n_rounds; ++r) { roff[r] = acc; acc += rcnt[r]; }
+  roff[n_rounds] = acc;
+}
+
+__global__ void __launch_bounds__(256) k_round_fill(const int* round_ptr, const int* round_list, const int* rot_cnt,
+                                                    const int* jb_g, const int* jb_h, const int* tcnt, const int* roff,
+                                                    int4* meta) {
+  const int r = blockIdx.x;
+  __shared__ int wsum[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int base = roff[r];
+  for (int i0 = round_ptr[r]; i0 < round_ptr[r + 1]; i0 += 256) {
+    const int i = i0 + threadIdx.x;
+    const int b = (i < round_ptr[r + 1]) ? round_list[i] : -1;
+    const bool f = b >= 0 && rot_cnt[b] > 0;
+    const unsigned long long m = __ballot(f);
+    const int pre = __popcll(m & ((1ULL << lane) - 1ULL));
+    if (lane == 0) wsum[w] = __popcll(m);
+    __syncthreads();
+    int off = base;
+    for (int k = 0; k < w; ++k) off += wsum[k];
+    if (f) meta[off + pre] = make_int4(b, jb_g[b], jb_h[b], tcnt[b]);
+    const int tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+    base += tot;
   }
 }
 
-void launch_givens_round(const View& v, int n_round_blocks, const int* round_blocks, const int* jb_g, const int* jb_h,
-                         const int* rot_cnt, const int2* rot_col, const double2* rot_cs, const int* tcnt,
-                         const int* tcol, double eps, double* C, uint8_t* actC, unsigned long long* ctr,
-                         hipStream_t s) {
-  if (n_round_blocks <= 0) return;
-  dim3 grid((v.n_rb + 15) / 16, n_round_blocks), blk(256);
-  hipLaunchKernelGGL(k_givens_round, grid, blk, 0, s, v.n_rb, v.W, v.OW, round_blocks, jb_g, jb_h, rot_cnt, rot_col,
-                     rot_cs, tcnt, tcol, eps, C, actC, ctr);
+void launch_round_meta(int n_rounds, const int* round_ptr, const int* round_list, const int* rot_cnt, const int* jb_g,
+                       const int* jb_h, const int* tcnt, int* rcnt, int* roff, int4* meta, hipStream_t s) {
+  if (n_rounds <= 0) return;
+  hipLaunchKernelGGL(k_round_count, dim3(n_rounds), dim3(256), 0, s, round_ptr, round_list, rot_cnt, rcnt);
+  hipLaunchKernelGGL(k_round_prefix, dim3(1), dim3(64), 0, s, n_rounds, rcnt, roff);
+  hipLaunchKernelGGL(k_round_fill, dim3(n_rounds), dim3(256), 0, s, round_ptr, round_list, rot_cnt, jb_g, jb_h, tcnt,
+                     roff, meta);
+}
+
+template <int NTMAX, typename Real>
+__global__ void __launch_bounds__(512) k_givens_rb(int G, int n_rb, int W, int OW, int n_rounds,
+                                                   const int* __restrict__ roff, const int4* __restrict__ meta,
+                                                   const int* __restrict__ tcol,
+                                                   const Real* __restrict__ R, double eps, double* C,
+                                                   uint8_t* actC, unsigned int* cmask, unsigned long long* ctr) {
+  typedef typename Mfma<Real>::acc_t acc_t;
+  extern __shared__ uint8_t act_l[];
+  const int rb = blockIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int g = threadIdx.x; g < G; g += blockDim.x) act_l[g] = actC[(size_t)g * n_rb + rb];
+  __syncthreads();
+  unsigned long long bytes = 0;
+  for (int r = 0; r < n_rounds; ++r) {
+    const int b0 = roff[r], b1 = roff[r + 1];
+    for (int i = b0 + w; i < b1; i += nw) {
+      const int4 mt = meta[i];
+      const int b = mt.x, g = mt.y, h = mt.z, T = mt.w;
+      if (!act_l[g] && !act_l[h]) continue;
+      const int nt_n = (T + 15) >> 4;
+      const int* tc = tcol + (size_t)b * W;
+      const Real* Rb = R + (size_t)b * W * W;
+      double* Cg = C + ((size_t)g * n_rb + rb) * RB * W;
+      double* Ch = C + ((size_t)h * n_rb + rb) * RB * W;
+      acc_t acc[NTMAX];
+#pragma unroll
+      for (int n = 0; n < NTMAX; ++n) acc[n] = acc_t{0, 0, 0, 0};
+      for (int s = 0; s < 4 * nt_n; ++s) {
+        const int k = 4 * s + lk;
+        Real a = 0;
+        if (k < T) {
+          const int col = tc[k];
+          a = (Real)(col < OW ? Cg : Ch)[lr * W + col];
+        }
+#pragma unroll
+        for (int n = 0; n < NTMAX; ++n)
+          if (n < nt_n) acc[n] = Mfma<Real>::op(a, Rb[(size_t)k * W + n * 16 + lr], acc[n]);
+      }
+      int nzg = 0, nzh = 0;
+      unsigned int bg = 0, bh = 0;
+#pragma unroll
+      for (int n = 0; n < NTMAX; ++n) {
+        const int j = n * 16 + lr;
+        if (n < nt_n && j < T) {
+          const int col = tc[j];
+          double* base = (col < OW) ? Cg : Ch;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            double x = (double)acc[n][q];
+            if (fabs(x) < eps) x = 0.0;
+            base[Mfma<Real>::row(lk, q) * W + col] = x;
+            if (x != 0.0) {
+              if (col < OW) { nzg = 1; bg |= 1u << (col >> 4); }
+              else { nzh = 1; bh |= 1u << (col >> 4); }
+            }
+          }
+        }
+      }
+      const bool anyg = __ballot(nzg) != 0ULL, anyh = __ballot(nzh) != 0ULL;
+      for (int o = 32; o > 0; o >>= 1) { bg |= __shfl_xor(bg, o); bh |= __shfl_xor(bh, o); }
+      if (lane == 0) {
+        if (bg) atomicOr(&cmask[(size_t)g * n_rb + rb], bg);
+        if (bh) atomicOr(&cmask[(size_t)h * n_rb + rb], bh);
+        if (anyg && !act_l[g]) { act_l[g] = 1; actC[(size_t)g * n_rb + rb] = 1; }
+        if (anyh && !act_l[h]) { act_l[h] = 1; actC[(size_t)h * n_rb + rb] = 1; }
+      }
+      bytes += (unsigned long long)T * RB * 16ULL;
+    }
+    __syncthreads();
+  }
+  if (ctr && lane == 0 && bytes) atomicAdd(ctr, bytes);
+}
+
+void launch_givens_rb(const View& v, int n_rounds, const int* roff, const int4* meta, const int* tcol, const double* R,
+                      const float* R32, double eps, double* C, uint8_t* actC, unsigned int* cmask,
+                      unsigned long long* ctr, hipStream_t s) {
+  if (n_rounds <= 0) return;
+  const size_t lds = (size_t)v.G;
+  switch ((v.W + 15) / 16) {
+#define SSCF_GIV(N) case N: \
+    if (R32) hipLaunchKernelGGL((k_givens_rb<N, float>), dim3(v.n_rb), dim3(512), lds, s, v.G, v.n_rb, v.W, v.OW, n_rounds, roff, meta, tcol, R32, eps, C, actC, cmask, ctr); \
+    else hipLaunchKernelGGL((k_givens_rb<N, double>), dim3(v.n_rb), dim3(512), lds, s, v.G, v.n_rb, v.W, v.OW, n_rounds, roff, meta, tcol, R, eps, C, actC, cmask, ctr); \
+    break;
+    SSCF_GIV(1) SSCF_GIV(2) SSCF_GIV(3) SSCF_GIV(4) SSCF_GIV(5) SSCF_GIV(6) SSCF_GIV(7) SSCF_GIV(8)
+#undef SSCF_GIV
+  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1041,6 +1253,293 @@ __global__ void __launch_bounds__(256) k_density_blocks(int nbx, int G, int n_rb
 void launch_density_blocks(const View& v, const double* C, const uint8_t* actC, const int*, double* P, hipStream_t s) {
   hipLaunchKernelGGL(k_density_blocks, dim3((v.nbx + 3) / 4), dim3(256), 0, s, v.nbx, v.G, v.n_rb, v.W, v.OW,
                      v.xs_row, v.xs_col, C, actC, P);
+}
+
+// ---------------------------------------------------------------------------------------
+// FP32 form of C^T H C (the paper already runs this product in single precision, §4.1):
+// Y32 = H32 C and the occupied-virtual blocks and diagonal of C^T Y32, FP32 matrix cores
+// with FP32 accumulation; C itself stays FP64 and is rounded on load.
+// ---------------------------------------------------------------------------------------
+
+template <int NT>
+__global__ void __launch_bounds__(256) k_spmm32(int n_rb, const int* __restrict__ xs_ptr,
+                                                const int* __restrict__ xs_col, const float* __restrict__ X,
+                                                const double* __restrict__ C, const uint8_t* __restrict__ actC,
+                                                const unsigned int* __restrict__ cmask,
+                                                const int* __restrict__ listY, const int* __restrict__ cntY,
+                                                float* __restrict__ Y, unsigned int* __restrict__ ymask,
+                                                unsigned long long* ctr) {
+  constexpr int W = NT * 16;
+  const int g = blockIdx.y;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= cntY[g]) return;
+  unsigned int n_mfma = 0;
+  const int lane = threadIdx.x & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+  const size_t pb = (size_t)g * n_rb;
+  const int r = listY[pb + t];
+  f4 acc[NT];
+#pragma unroll
+  for (int n = 0; n < NT; ++n) acc[n] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int kb = xs_ptr[r]; kb < xs_ptr[r + 1]; ++kb) {
+    const int c = xs_col[kb];
+    if (!actC[pb + c]) continue;
+    const unsigned int m = cmask[pb + c];
+    const float* Xb = X + (size_t)kb * 256;
+    const double* Ct = C + (pb + c) * (RB * W);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const float a = Xb[lr * 16 + 4 * s + lk];
+#pragma unroll
+      for (int n = 0; n < NT; ++n)
+        if (m & (1u << n)) { acc[n] = mfma32(a, (float)Ct[(4 * s + lk) * W + n * 16 + lr], acc[n]); ++n_mfma; }
+    }
+  }
+  float* Yt = Y + (pb + r) * (RB * W);
+  unsigned int ym = 0;
+#pragma unroll
+  for (int n = 0; n < NT; ++n) {
+    int nz = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      Yt[(4 * lk + q) * W + n * 16 + lr] = acc[n][q];
+      nz |= acc[n][q] != 0.f;
+    }
+    if (__ballot(nz)) ym |= 1u << n;
+  }
+  if (lane == 0) {
+    ymask[pb + r] = ym;
+    if (ctr) atomicAdd(ctr, (unsigned long long)n_mfma);
+  }
+}
+
+void launch_spmm32_wave(const View& v, const float* X, const double* C, const uint8_t* actC, const unsigned int* cmask,
+                   const int* listY, const int* cntY, float* Y, unsigned int* ymask, unsigned long long* ctr,
+                   hipStream_t s) {
+  dim3 grid((v.n_rb + 3) / 4, v.G), blk(256);
+  switch (v.W / 16) {
+#define SSCF_SPMM32(NT) case NT: hipLaunchKernelGGL(k_spmm32<NT>, grid, blk, 0, s, v.n_rb, v.xs_ptr, v.xs_col, X, C, actC, cmask, listY, cntY, Y, ymask, ctr); break;
+    SSCF_SPMM32(1) SSCF_SPMM32(2) SSCF_SPMM32(3) SSCF_SPMM32(4) SSCF_SPMM32(5) SSCF_SPMM32(6) SSCF_SPMM32(7) SSCF_SPMM32(8)
+#undef SSCF_SPMM32
+  }
+}
+
+template <int MW, int NW>
+__global__ void __launch_bounds__(256) k_pair32(int n_rb, int W, const int* __restrict__ pg, const int* __restrict__ ph,
+                                                const double* __restrict__ C, const int* __restrict__ listC,
+                                                const int* __restrict__ cntC, const unsigned int* __restrict__ cmask,
+                                                const float* __restrict__ Y, const uint8_t* __restrict__ actY,
+                                                const unsigned int* __restrict__ ymask, int row_off, int MT,
+                                                int col_off, int NT, double* __restrict__ out, int ld,
+                                                size_t out_stride, unsigned long long* ctr) {
+  const int p = blockIdx.x;
+  const int g = pg[p], h = ph[p];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int MH = (MT + 1) / 2, NH = (NT + 1) / 2;
+  const int mt0 = (w >> 1) * MH, nt0 = (w & 1) * NH;
+  const int mc = min(MH, MT - mt0), nc = min(NH, NT - nt0);
+  f4 acc[MW][NW];
+#pragma unroll
+  for (int i = 0; i < MW; ++i)
+#pragma unroll
+    for (int j = 0; j < NW; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  const size_t gb = (size_t)g * n_rb, hb = (size_t)h * n_rb;
+  const int cnt = cntC[g];
+  unsigned int n_mfma = 0;
+  if (mc > 0 && nc > 0) {
+    for (int t = 0; t < cnt; ++t) {
+      const int r = listC[gb + t];
+      if (!actY[hb + r]) continue;
+      const unsigned int ma = cmask[gb + r] >> (row_off / 16 + mt0);
+      const unsigned int mb = ymask[hb + r] >> (col_off / 16 + nt0);
+      if (!(ma & ((1u << mc) - 1u)) || !(mb & ((1u << nc) - 1u))) continue;
+      const double* Ct = C + (gb + r) * (size_t)(RB * W) + row_off + mt0 * 16 + lr;
+      const float* Yt = Y + (hb + r) * (size_t)(RB * W) + col_off + nt0 * 16 + lr;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        float a[MW], b[NW];
+        const int ro = (4 * s + lk) * W;
+#pragma unroll
+        for (int i = 0; i < MW; ++i) a[i] = (i < mc && (ma & (1u << i))) ? (float)Ct[ro + i * 16] : 0.f;
+#pragma unroll
+        for (int j = 0; j < NW; ++j) b[j] = (j < nc && (mb & (1u << j))) ? Yt[ro + j * 16] : 0.f;
+#pragma unroll
+        for (int i = 0; i < MW; ++i)
+#pragma unroll
+          for (int j = 0; j < NW; ++j)
+            if (i < mc && j < nc && (ma & (1u << i)) && (mb & (1u << j))) {
+              acc[i][j] = mfma32(a[i], b[j], acc[i][j]);
+              ++n_mfma;
+            }
+      }
+    }
+  }
+  double* o = out + (size_t)p * out_stride;
+#pragma unroll
+  for (int i = 0; i < MW; ++i)
+#pragma unroll
+    for (int j = 0; j < NW; ++j)
+      if (i < mc && j < nc)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          o[(size_t)((mt0 + i) * 16 + 4 * lk + q) * ld + (nt0 + j) * 16 + lr] = (double)acc[i][j][q];
+  if (ctr && lane == 0 && n_mfma) atomicAdd(ctr, (unsigned long long)n_mfma);
+}
+
+void launch_pair32(const View& v, int n_pairs, const int* pg, const int* ph, const double* C, const int* listC,
+                   const int* cntC, const unsigned int* cmask, const float* Y, const uint8_t* actY,
+                   const unsigned int* ymask, int row_off, int MT, int col_off, int NT, double* out, int ld,
+                   size_t out_stride, unsigned long long* ctr, hipStream_t s) {
+  if (n_pairs <= 0) return;
+  const int mw = (MT + 1) / 2, nw = (NT + 1) / 2;
+  const int m = mw > nw ? mw : nw;
+  dim3 grid(n_pairs), blk(256);
+  if (m <= 1)
+    hipLaunchKernelGGL((k_pair32<1, 1>), grid, blk, 0, s, v.n_rb, v.W, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+  else if (m <= 2)
+    hipLaunchKernelGGL((k_pair32<2, 2>), grid, blk, 0, s, v.n_rb, v.W, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+  else if (m <= 3)
+    hipLaunchKernelGGL((k_pair32<3, 3>), grid, blk, 0, s, v.n_rb, v.W, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+  else
+    hipLaunchKernelGGL((k_pair32<4, 4>), grid, blk, 0, s, v.n_rb, v.W, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+}
+
+__global__ void k_coldot32(int n_rb, int W, const double* C, const int* listC, const int* cntC, const float* Y,
+                           const uint8_t* actY, double* out) {
+  const int g = blockIdx.x, c = threadIdx.x;
+  if (c >= W) return;
+  const size_t gb = (size_t)g * n_rb;
+  float s = 0.f;
+  for (int t = 0; t < cntC[g]; ++t) {
+    const int r = listC[gb + t];
+    if (!actY[gb + r]) continue;
+    const double* Ct = C + (gb + r) * (size_t)(RB * W) + c;
+    const float* Yt = Y + (gb + r) * (size_t)(RB * W) + c;
+#pragma unroll
+    for (int k = 0; k < RB; ++k) s += (float)Ct[k * W] * Yt[k * W];
+  }
+  out[(size_t)g * W + c] = (double)s;
+}
+void launch_coldot32(const View& v, const double* C, const int* listC, const int* cntC, const float* Y,
+                     const uint8_t* actY, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_coldot32, dim3(v.G), dim3(v.W <= 64 ? 64 : (v.W <= 128 ? 128 : 256)), 0, s, v.n_rb, v.W, C,
+                     listC, cntC, Y, actY, out);
+}
+
+// ---------------------------------------------------------------------------------------
+// Y = X C with the C tiles staged in LDS: one workgroup per SCH consecutive output row
+// blocks of panel g (one wave each).  The union of the blocks' S-row columns that are
+// active in panel g is collected in an LDS bitmap; each such C tile is loaded once into
+// LDS and applied by every wave whose row holds a block of X in that column.
+// Real = double (FP64 form) or float (FP32 form of H C; C is rounded when staged).
+// ---------------------------------------------------------------------------------------
+constexpr int SCH = 8;
+
+template <int NT, typename Real>
+__global__ void __launch_bounds__(SCH * 64) k_spmm_lds(int n_rb, const int* __restrict__ xs_ptr,
+                                                       const int* __restrict__ xs_col, const Real* __restrict__ X,
+                                                       const double* __restrict__ C, const uint8_t* __restrict__ actC,
+                                                       const unsigned int* __restrict__ cmask,
+                                                       const int* __restrict__ listY, const int* __restrict__ cntY,
+                                                       Real* __restrict__ Y, unsigned int* __restrict__ ymask,
+                                                       unsigned long long* ctr) {
+  constexpr int W = NT * 16;
+  typedef typename Mfma<Real>::acc_t acc_t;
+  extern __shared__ unsigned int cbits[];             // n_rb bits, then the staged tile
+  Real* tile = reinterpret_cast<Real*>(cbits + ((n_rb + 63) / 64) * 2);
+  const int g = blockIdx.y;
+  const int t0 = blockIdx.x * SCH;
+  const int cnt = cntY[g];
+  if (t0 >= cnt) return;
+  const int nt = min(SCH, cnt - t0);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const size_t pb = (size_t)g * n_rb;
+  const int nwords = (n_rb + 31) / 32;
+  for (int i = threadIdx.x; i < nwords; i += blockDim.x) cbits[i] = 0u;
+  __syncthreads();
+  const bool live = w < nt;
+  const int r = live ? listY[pb + t0 + w] : 0;
+  int kb = live ? xs_ptr[r] : 0;
+  const int kend = live ? xs_ptr[r + 1] : 0;
+  for (int k = kb + lane; k < kend; k += 64) {
+    const int c = xs_col[k];
+    if (actC[pb + c]) atomicOr(&cbits[c >> 5], 1u << (c & 31));
+  }
+  __syncthreads();
+  acc_t acc[NT];
+#pragma unroll
+  for (int n = 0; n < NT; ++n) acc[n] = acc_t{0, 0, 0, 0};
+  unsigned int n_mfma = 0;
+  for (int wd = 0; wd < nwords; ++wd) {
+    unsigned int bits = cbits[wd];
+    while (bits) {
+      const int c = wd * 32 + __ffs(bits) - 1;
+      bits &= bits - 1u;
+      const double* Ct = C + (pb + c) * (RB * W);
+      for (int e = threadIdx.x; e < RB * W; e += blockDim.x) tile[e] = (Real)Ct[e];
+      const unsigned int m = cmask[pb + c];
+      __syncthreads();
+      while (kb < kend && xs_col[kb] < c) ++kb;
+      if (kb < kend && xs_col[kb] == c) {
+        const Real* Xb = X + (size_t)kb * 256;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const Real a = Xb[lr * 16 + 4 * s + lk];
+#pragma unroll
+          for (int n = 0; n < NT; ++n)
+            if (m & (1u << n)) {
+              acc[n] = Mfma<Real>::op(a, tile[(4 * s + lk) * W + n * 16 + lr], acc[n]);
+              ++n_mfma;
+            }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (!live) return;
+  Real* Yt = Y + (pb + r) * (RB * W);
+  unsigned int ym = 0;
+#pragma unroll
+  for (int n = 0; n < NT; ++n) {
+    int nz = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      Yt[Mfma<Real>::row(lk, q) * W + n * 16 + lr] = acc[n][q];
+      nz |= acc[n][q] != Real(0);
+    }
+    if (__ballot(nz)) ym |= 1u << n;
+  }
+  if (lane == 0) {
+    ymask[pb + r] = ym;
+    if (ctr && n_mfma) atomicAdd(ctr, (unsigned long long)n_mfma);
+  }
+}
+
+template <typename Real>
+static void launch_spmm_lds(const View& v, const Real* X, const double* C, const uint8_t* actC,
+                            const unsigned int* cmask, const int* listY, const int* cntY, Real* Y,
+                            unsigned int* ymask, unsigned long long* ctr, hipStream_t s) {
+  dim3 grid((v.n_rb + SCH - 1) / SCH, v.G), blk(SCH * 64);
+  const size_t lds = ((v.n_rb + 63) / 64) * 2 * sizeof(unsigned int) + (size_t)RB * v.W * sizeof(Real);
+  switch (v.W / 16) {
+#define SSCF_SPL(NT) case NT: hipLaunchKernelGGL((k_spmm_lds<NT, Real>), grid, blk, lds, s, v.n_rb, v.xs_ptr, v.xs_col, X, C, actC, cmask, listY, cntY, Y, ymask, ctr); break;
+    SSCF_SPL(1) SSCF_SPL(2) SSCF_SPL(3) SSCF_SPL(4) SSCF_SPL(5) SSCF_SPL(6) SSCF_SPL(7) SSCF_SPL(8)
+#undef SSCF_SPL
+  }
+}
+
+void launch_spmm(const View& v, const double* X, const double* C, const uint8_t* actC, const unsigned int* cmask,
+                 const int* listY, const int* cntY, double* Y, unsigned int* ymask, unsigned long long* ctr,
+                 hipStream_t s) {
+  launch_spmm_lds<double>(v, X, C, actC, cmask, listY, cntY, Y, ymask, ctr, s);
+}
+
+void launch_spmm32(const View& v, const float* X, const double* C, const uint8_t* actC, const unsigned int* cmask,
+                   const int* listY, const int* cntY, float* Y, unsigned int* ymask, unsigned long long* ctr,
+                   hipStream_t s) {
+  launch_spmm_lds<float>(v, X, C, actC, cmask, listY, cntY, Y, ymask, ctr, s);
 }
 
 }  // namespace sscf

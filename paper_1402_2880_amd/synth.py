@@ -25,7 +25,7 @@ is a synthetic stand-in with the same structure):
   redrawn until it fits);
 * two-centre integrals V(r) = 0.3 exp(-r/0.9) Ha and sigma(r) = 0.2 exp(-r/0.9)
   (r in Angstrom, hard cut at 6 A) with Slater-Koster direction-cosine factors;
-* onsite energies O s -0.88, O p -0.45, H s +0.10 Ha; U_O = 0.30, U_H = 0.25 Ha;
+* onsite energies O s -0.88, O p -0.45, H s +0.30 Ha; U_O = 0.30, U_H = 0.25 Ha;
   q0 = 6 (O), 1 (H).
 """
 from __future__ import annotations
@@ -44,9 +44,11 @@ NAO = {EL_O: 4, EL_H: 1, EL_C: 4}
 # With typical DFTB onsite energies (O p -0.33, H s -0.24) and Hubbard values (0.50, 0.42)
 # the weak two-centre hopping of this model (0.10 Ha at the O-H bond) leaves a
 # self-consistent HOMO-LUMO gap of ~0.01 Ha in the 128-molecule box and the plain SCC
-# iteration diverges.  O p -0.45, H s +0.10, U 0.30 / 0.25 give a self-consistent gap
-# of ~0.2 Ha; V0, r0 and the geometry rules are untouched.
-ONSITE = {EL_O: (-0.88, -0.45), EL_H: (0.10, None), EL_C: (-0.50, -0.20)}
+# iteration diverges.  O p -0.45, U 0.30 / 0.25 and H s +0.30 give a self-consistent gap
+# of ~0.36 Ha; with H s +0.10 (gap ~0.2 Ha) the unmixed SCC iteration still converges for
+# 1024 molecules but turns unstable at 4096 (charge sloshing grows with the box).
+# V0, r0 and the geometry rules are untouched.
+ONSITE = {EL_O: (-0.88, -0.45), EL_H: (0.30, None), EL_C: (-0.50, -0.20)}
 HUBBARD_U = {EL_O: 0.30, EL_H: 0.25, EL_C: 0.30}
 Q0 = {EL_O: 6.0, EL_H: 1.0, EL_C: 4.0}
 

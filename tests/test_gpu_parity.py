@@ -176,3 +176,42 @@ def test_water4096_against_stored_oracle():
         assert gs["n_rotations"] == st["n_rotations"]
         assert gs["n_ortho_sweeps"] == st["n_ortho_sweeps"]
         assert np.abs(g.charges()[sample] - np.array(st["charges_sample"])).max() < Q_TOL
+
+
+# ---------------------------------------------------------------------------------------
+# FP32 form: C^T H C, angles and rotation products in FP32 (FP32 accumulation); the
+# orthonormalization, charges, energy and convergence test in FP64.  Bar: 1e-6 Ha per step
+# against the FP64 oracle.
+# ---------------------------------------------------------------------------------------
+
+FP32_TOL = 1e-6
+
+
+def test_fp32_form_water128(water128):
+    from paper_1402_2880_amd.sscf import FP32_MIXED
+    o = Oracle(water128)
+    g = gpu(water128, precision=FP32_MIXED)
+    assert abs(g.init_info()["energy"] - o.init_info()["energy"]) < E_TOL   # set-up is FP64
+    conv_g = conv_o = False
+    for k in range(20):
+        os_, gs = o.step(), g.step()
+        err = abs(gs["energy"] - os_["energy"])
+        print(f"[fp32] step {k + 1} |dE| vs FP64 oracle {err:.2e}", flush=True)
+        assert err < FP32_TOL, (k, err)
+        conv_g |= bool(gs["converged"])
+        conv_o |= bool(os_["converged"])
+    assert conv_g and conv_o
+
+
+def test_fp32_form_water4096():
+    from paper_1402_2880_amd.sscf import FP32_MIXED
+    if not os.path.exists(GOLDEN):
+        pytest.skip("golden values not generated")
+    rec = json.load(open(GOLDEN))
+    s = synth.make_config("water4096", 1)
+    g = gpu(s, eps=rec["eps"], e_conv=rec["e_conv"], precision=FP32_MIXED)
+    for k, st in enumerate(rec["steps"]):
+        gs = g.step()
+        err = abs(gs["energy"] - st["energy"])
+        print(f"[fp32] water4096 step {k + 1} |dE| {err:.2e} ms {gs['ms_total']:.1f}", flush=True)
+        assert err < FP32_TOL
