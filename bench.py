@@ -58,6 +58,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel HIP events")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="before the SCF, copy a buffer of this size three times: a kernel of known "
+                         "traffic against which hardware byte counters are scaled")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -70,6 +73,16 @@ def main():
     from paper_1402_2880_amd.sscf import FP32_MIXED, FP64, SparseSCF
 
     torch.cuda.set_device(0)
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 3 copies of {args.copy_calibration} MiB "
+            f"({args.copy_calibration * 1024} KiB read and written each)")
+        del src, dst
     t = time.time()
     system = synth.make_config(args.config, args.seed)
     log(f"[bench] {args.config}: {system.n_atoms} atoms, {system.n_ao} AOs, {system.n_mo} MOs "

@@ -83,6 +83,8 @@ struct sscf_ctx {
   View v{};
   int64_t n_val = 0;
   int n_pairs = 0, n_blocks = 0, n_rounds = 0;
+  int *pair_perm = nullptr, *jb_perm = nullptr;   // pairs / Jacobi blocks laid out per XCD
+  int pair_maxc = 0, jb_maxc = 0;
 
   // host copies needed after set-up
   std::vector<int64_t> h_blk_rowptr, h_blk_off;
@@ -118,6 +120,7 @@ struct sscf_ctx {
   double* Dt = nullptr;                 // transposes of the off-diagonal D blocks
   double* sc = nullptr;
   uint8_t *upd = nullptr, *pair_sel = nullptr;
+  unsigned int* fmask = nullptr;        // per pair: nonzero-fragment masks of D_sel and its transpose
   int *jb_g = nullptr, *jb_h = nullptr, *jb_nocc = nullptr, *jb_nvirt = nullptr, *round_list = nullptr;
   double *F = nullptr, *Fdiag = nullptr, *dvec = nullptr;
   int *rot_cnt = nullptr, *tcnt = nullptr, *tcol = nullptr, *round_ptr = nullptr;
@@ -257,7 +260,7 @@ struct sscf_ctx {
       const int W = v.W;
       const int pi = pbegin(KC_PAIR_O);
       const int nt = (occ_only ? v.OW : W) / 16;
-      launch_pair(v, n_pairs, pg, ph, C[cur], listC[cur], cntC[cur], cmask[cur], Y, actY, ymask, 0, nt, 0, nt, O, W,
+      launch_pair(v, n_pairs, pair_perm, pair_maxc, pg, ph, C[cur], listC[cur], cntC[cur], cmask[cur], Y, actY, ymask, 0, nt, 0, nt, O, W,
                   (size_t)W * W, ctr(KC_PAIR_O), stream);
       pend(pi);
       HIPC(hipMemsetAsync(&sd->eta_bits, 0, sizeof(unsigned long long), stream));
@@ -275,12 +278,12 @@ struct sscf_ctx {
       // pair combinations C <- C - 1/2 C D_sel into the other buffer
       const int nx = 1 - cur;
       HIPC(hipMemsetAsync(upd, 0, (size_t)v.G * W, stream));
-      launch_mark_selected(v, n_pairs, pg, ph, O, sd, pair_sel, upd, stream);
+      launch_mark_selected(v, n_pairs, pg, ph, O, sd, pair_sel, upd, fmask, stream);
       launch_update_support(v, actC[cur], gn_ptr, gn, pair_of, pair_sel, act_tmp, stream);
       launch_list(v, act_tmp, list_tmp, cnt_tmp, stream);
       launch_clear_tiles(v, C[nx], actC[nx], cmask[nx], listC[nx], cntC[nx], stream);
       const int pu = pbegin(KC_UPDATE);
-      launch_ortho_update(v, C[cur], actC[cur], gn_ptr, gn, pair_of, pair_sel, O, Dt, sd, upd, cut, list_tmp, cnt_tmp,
+      launch_ortho_update(v, C[cur], actC[cur], gn_ptr, gn, pair_of, pair_sel, O, Dt, fmask, sd, upd, cut, list_tmp, cnt_tmp,
                           C[nx], actC[nx], cmask[cur], cmask[nx], ctr(KC_UPDATE), stream);
       pend(pu);
       rebuild_list(nx);
@@ -322,6 +325,21 @@ struct sscf_ctx {
 // =========================================================================================
 
 namespace {
+
+// Items of a list sorted by group, laid out so that workgroup L (on XCD L % 8) takes item
+// perm[(L % 8) * maxc + L / 8]: every item of group g runs on XCD g % 8, in list order;
+// -1 pads the shorter XCD lists.
+std::vector<int> xcd_perm(const std::vector<int>& item_group, int* maxc) {
+  constexpr int NX = 8;
+  std::vector<std::vector<int>> lists(NX);
+  for (size_t i = 0; i < item_group.size(); ++i) lists[item_group[i] % NX].push_back((int)i);
+  int m = 1;
+  for (const auto& l : lists) m = std::max(m, (int)l.size());
+  std::vector<int> perm((size_t)NX * m, -1);
+  for (int x = 0; x < NX; ++x) std::copy(lists[x].begin(), lists[x].end(), perm.begin() + (size_t)x * m);
+  *maxc = m;
+  return perm;
+}
 
 void validate(const sscf_system_desc* d) {
   if (!d) fail(SSCF_E_INVALID_ARG, "desc is NULL");
@@ -629,6 +647,10 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
   x->gn = x->upload(gn.data(), gn.size());
   x->pair_of = x->upload(pair_of.data(), pair_of.size());
   x->pg = x->upload(pg.data(), pg.size());
+  {
+    std::vector<int> perm = xcd_perm(pg, &x->pair_maxc);
+    x->pair_perm = x->upload(perm.data(), perm.size());
+  }
   x->ph = x->upload(ph.data(), ph.size());
   x->self_pair = x->upload(self_pair.data(), self_pair.size());
   x->O = x->dalloc<double>((size_t)x->n_pairs * v.W * v.W);
@@ -636,7 +658,12 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
   x->sc = x->dalloc<double>((size_t)G * v.W);
   x->upd = x->dalloc<uint8_t>((size_t)G * v.W);
   x->pair_sel = x->dalloc<uint8_t>(x->n_pairs);
+  x->fmask = x->dalloc<unsigned int>((size_t)x->n_pairs * 16);
   x->jb_g = x->upload(x->h_jb_g.data(), x->n_blocks);
+  {
+    std::vector<int> perm = xcd_perm(x->h_jb_g, &x->jb_maxc);
+    x->jb_perm = x->upload(perm.data(), perm.size());
+  }
   x->jb_h = x->upload(x->h_jb_h.data(), x->n_blocks);
   x->jb_nocc = x->upload(jb_nocc.data(), x->n_blocks);
   x->jb_nvirt = x->upload(jb_nvirt.data(), x->n_blocks);
@@ -743,7 +770,7 @@ static void step(sscf_ctx* x, sscf_step_info* out) {
                   x->ctr(KC_SPMM), s);
     x->pend(pi);
     pi = x->pbegin(KC_PAIR_F);
-    launch_pair32(v, x->n_blocks, x->jb_g, x->jb_h, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur],
+    launch_pair32(v, x->n_blocks, x->jb_perm, x->jb_maxc, x->jb_g, x->jb_h, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur],
                   x->cmask[x->cur], x->Y32, x->actY, x->ymask, 0, v.OW / 16, v.OW, v.VW / 16, x->F, v.VW,
                   (size_t)v.OW * v.VW, x->ctr(KC_PAIR_F), s);
     x->pend(pi);
@@ -751,7 +778,7 @@ static void step(sscf_ctx* x, sscf_step_info* out) {
   } else {
     x->product(x->H, true);
     pi = x->pbegin(KC_PAIR_F);
-    launch_pair(v, x->n_blocks, x->jb_g, x->jb_h, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur],
+    launch_pair(v, x->n_blocks, x->jb_perm, x->jb_maxc, x->jb_g, x->jb_h, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur],
                 x->cmask[x->cur], x->Y, x->actY, x->ymask, 0, v.OW / 16, v.OW, v.VW / 16, x->F, v.VW,
                 (size_t)v.OW * v.VW, x->ctr(KC_PAIR_F), s);
     x->pend(pi);

@@ -73,7 +73,8 @@ void launch_list(const View& v, const uint8_t* act, int* list, int* cnt, hipStre
 void launch_spmm(const View& v, const double* X, const double* C, const uint8_t* actC,
                  const unsigned int* cmask, const int* listY, const int* cntY, double* Y,
                  unsigned int* ymask, unsigned long long* ctr, hipStream_t s);
-void launch_pair(const View& v, int n_pairs, const int* pg, const int* ph, const double* C,
+// perm / maxc: the items of a list sorted by group, laid out per XCD (see xcd_perm)
+void launch_pair(const View& v, int n_pairs, const int* perm, int maxc, const int* pg, const int* ph, const double* C,
                  const int* listC, const int* cntC, const unsigned int* cmask, const double* Y,
                  const uint8_t* actY, const unsigned int* ymask, int row_off, int MT, int col_off,
                  int NT, double* out, int ld, size_t out_stride, unsigned long long* ctr,
@@ -89,7 +90,7 @@ void launch_normalize_d(const View& v, int n_pairs, const int* pg, const int* ph
 void launch_scale_c(const View& v, double* C, const int* listC, const int* cntC, const double* sc,
                     hipStream_t s);
 void launch_mark_selected(const View& v, int n_pairs, const int* pg, const int* ph, const double* D,
-                          const Scalars* sd, uint8_t* pair_sel, uint8_t* upd, hipStream_t s);
+                          const Scalars* sd, uint8_t* pair_sel, uint8_t* upd, unsigned int* fmask, hipStream_t s);
 void launch_update_support(const View& v, const uint8_t* actC, const int* gn_ptr, const int* gn,
                            const int* pair_of, const uint8_t* pair_sel, uint8_t* act_new,
                            hipStream_t s);
@@ -97,10 +98,9 @@ void launch_clear_tiles(const View& v, double* C, uint8_t* act, unsigned int* cm
                         const int* list, const int* cnt, hipStream_t s);
 void launch_ortho_update(const View& v, const double* C, const uint8_t* actC, const int* gn_ptr,
                          const int* gn, const int* pair_of, const uint8_t* pair_sel, const double* D,
-                         const double* Dt, const Scalars* sd, const uint8_t* upd, double cut,
-                         const int* listN,
-                         const int* cntN, double* Cn, uint8_t* actN, const unsigned int* cmask,
-                         unsigned int* cmaskN, unsigned long long* ctr, hipStream_t s);
+                         const double* Dt, const unsigned int* fmask, const Scalars* sd, const uint8_t* upd,
+                         double cut, const int* listN, const int* cntN, double* Cn, uint8_t* actN,
+                         const unsigned int* cmask, unsigned int* cmaskN, unsigned long long* ctr, hipStream_t s);
 void launch_coulomb(const View& v, int scc, const double* dq, double* Q, hipStream_t s);
 void launch_fock(const View& v, const double* S, const double* H0, const double* Hfull,
                  const double* Q, double eps, double* H, float* H32, hipStream_t s);
@@ -129,7 +129,7 @@ void launch_givens_rb(const View& v, int n_rounds, const int* roff, const int4* 
 void launch_spmm32(const View& v, const float* X, const double* C, const uint8_t* actC,
                    const unsigned int* cmask, const int* listY, const int* cntY, float* Y,
                    unsigned int* ymask, unsigned long long* ctr, hipStream_t s);
-void launch_pair32(const View& v, int n_pairs, const int* pg, const int* ph, const double* C,
+void launch_pair32(const View& v, int n_pairs, const int* perm, int maxc, const int* pg, const int* ph, const double* C,
                    const int* listC, const int* cntC, const unsigned int* cmask, const float* Y,
                    const uint8_t* actY, const unsigned int* ymask, int row_off, int MT, int col_off,
                    int NT, double* out, int ld, size_t out_stride, unsigned long long* ctr,

@@ -164,70 +164,25 @@ void launch_list(const View& v, const uint8_t* act, int* list, int* cnt, hipStre
 }
 
 // ---------------------------------------------------------------------------------------
-// Y = X C on the tiles (X = S, H or H0 as 16 x 16 blocks).  One wave per output tile.
+// Workgroups go round-robin over the 8 XCDs of the chip, each with its own L2: linear
+// workgroup id L runs on XCD L % 8.  Kernels that work group by group decode L so that all
+// workgroups of one MO group land on one XCD, in group-major order, and share its L2.
 // ---------------------------------------------------------------------------------------
 
-template <int NT>
-__global__ void __launch_bounds__(256) k_spmm(int n_rb, const int* __restrict__ xs_ptr,
-                                              const int* __restrict__ xs_col, const double* __restrict__ X,
-                                              const double* __restrict__ C, const uint8_t* __restrict__ actC,
-                                              const unsigned int* __restrict__ cmask,
-                                              const int* __restrict__ listY, const int* __restrict__ cntY,
-                                              double* __restrict__ Y, unsigned int* __restrict__ ymask,
-                                              unsigned long long* ctr) {
-  constexpr int W = NT * 16;
-  const int g = blockIdx.y;
-  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (t >= cntY[g]) return;
-  unsigned int n_mfma = 0;
-  const int lane = threadIdx.x & 63;
-  const int lr = lane & 15, lk = lane >> 4;
-  const size_t pb = (size_t)g * n_rb;
-  const int r = listY[pb + t];
-  d4 acc[NT];
-#pragma unroll
-  for (int n = 0; n < NT; ++n) acc[n] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int kb = xs_ptr[r]; kb < xs_ptr[r + 1]; ++kb) {
-    const int c = xs_col[kb];
-    if (!actC[pb + c]) continue;
-    const unsigned int m = cmask[pb + c];
-    const double* Xb = X + (size_t)kb * 256;
-    const double* Ct = C + (pb + c) * (RB * W);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const double a = Xb[lr * 16 + 4 * s + lk];
-#pragma unroll
-      for (int n = 0; n < NT; ++n)
-        if (m & (1u << n)) { acc[n] = mfma64(a, Ct[(4 * s + lk) * W + n * 16 + lr], acc[n]); ++n_mfma; }
-    }
-  }
-  double* Yt = Y + (pb + r) * (RB * W);
-  unsigned int ym = 0;
-#pragma unroll
-  for (int n = 0; n < NT; ++n) {
-    int nz = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      Yt[(lk + 4 * q) * W + n * 16 + lr] = acc[n][q];
-      nz |= acc[n][q] != 0.0;
-    }
-    if (__ballot(nz)) ym |= 1u << n;
-  }
-  if (lane == 0) {
-    ymask[pb + r] = ym;
-    if (ctr) atomicAdd(ctr, (unsigned long long)n_mfma);
-  }
-}
+constexpr int N_XCD = 8;
 
-void launch_spmm_wave(const View& v, const double* X, const double* C, const uint8_t* actC, const unsigned int* cmask,
-                 const int* listY, const int* cntY, double* Y, unsigned int* ymask, unsigned long long* ctr,
-                 hipStream_t s) {
-  dim3 grid((v.n_rb + 3) / 4, v.G), blk(256);
-  switch (v.W / 16) {
-#define SSCF_SPMM(NT) case NT: hipLaunchKernelGGL(k_spmm<NT>, grid, blk, 0, s, v.n_rb, v.xs_ptr, v.xs_col, X, C, actC, cmask, listY, cntY, Y, ymask, ctr); break;
-    SSCF_SPMM(1) SSCF_SPMM(2) SSCF_SPMM(3) SSCF_SPMM(4) SSCF_SPMM(5) SSCF_SPMM(6) SSCF_SPMM(7) SSCF_SPMM(8)
-#undef SSCF_SPMM
-  }
+__device__ inline int xcd_group_chunk(int nchunk, int& chunk) {
+  const int L = (int)blockIdx.x, slot = L / N_XCD;
+  chunk = slot % nchunk;
+  return L % N_XCD + N_XCD * (slot / nchunk);
+}
+static inline unsigned int xcd_grid(int G, int nchunk) {
+  return (unsigned int)(N_XCD * ((G + N_XCD - 1) / N_XCD) * nchunk);
+}
+// item of a list sorted by group, placed by the host on the XCD of its group (-1: padding)
+__device__ inline int xcd_item(const int* perm, int maxc) {
+  const int L = (int)blockIdx.x;
+  return perm[(L % N_XCD) * maxc + L / N_XCD];
 }
 
 // ---------------------------------------------------------------------------------------
@@ -236,7 +191,8 @@ void launch_spmm_wave(const View& v, const double* X, const double* C, const uin
 // ---------------------------------------------------------------------------------------
 
 template <int MW, int NW>
-__global__ void __launch_bounds__(256) k_pair(int n_rb, int W, const int* __restrict__ pg,
+__global__ void __launch_bounds__(256) k_pair(int n_rb, int W, const int* __restrict__ perm, int maxc,
+                                              const int* __restrict__ pg,
                                               const int* __restrict__ ph, const double* __restrict__ C,
                                               const int* __restrict__ listC, const int* __restrict__ cntC,
                                               const unsigned int* __restrict__ cmask,
@@ -245,9 +201,10 @@ __global__ void __launch_bounds__(256) k_pair(int n_rb, int W, const int* __rest
                                               int row_off, int MT, int col_off, int NT,
                                               double* __restrict__ out, int ld, size_t out_stride,
                                               unsigned long long* ctr) {
-  const int p = blockIdx.x;
+  const int p = xcd_item(perm, maxc);
+  if (p < 0) return;
   const int g = pg[p], h = ph[p];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lr = lane & 15, lk = lane >> 4;
   const int MH = (MT + 1) / 2, NH = (NT + 1) / 2;
   const int mt0 = (w >> 1) * MH, nt0 = (w & 1) * NH;
@@ -261,30 +218,48 @@ __global__ void __launch_bounds__(256) k_pair(int n_rb, int W, const int* __rest
   const int cnt = cntC[g];
   unsigned int n_mfma = 0;
   if (mc > 0 && nc > 0) {
-    for (int t = 0; t < cnt; ++t) {
-      const int r = listC[gb + t];
-      if (!actY[hb + r]) continue;
-      const unsigned int ma = cmask[gb + r] >> (row_off / 16 + mt0);
-      const unsigned int mb = ymask[hb + r] >> (col_off / 16 + nt0);
-      if (!(ma & ((1u << mc) - 1u)) || !(mb & ((1u << nc) - 1u))) continue;
-      const double* Ct = C + (gb + r) * (size_t)(RB * W) + row_off + mt0 * 16 + lr;
-      const double* Yt = Y + (hb + r) * (size_t)(RB * W) + col_off + nt0 * 16 + lr;
+    const unsigned int mcm = (1u << mc) - 1u, ncm = (1u << nc) - 1u;
+    const int sa = row_off / 16 + mt0, sb = col_off / 16 + nt0;
+    // the rows active in both panels, 64 at a time, with their slice masks, before any product
+    for (int base = 0; base < cnt; base += 64) {
+      const int t = base + lane;
+      int rr = 0;
+      unsigned int mab = 0u;
+      if (t < cnt) {
+        rr = listC[gb + t];
+        if (actY[hb + rr]) {
+          const unsigned int ma = (cmask[gb + rr] >> sa) & mcm, mb = (ymask[hb + rr] >> sb) & ncm;
+          if (ma && mb) mab = ma | (mb << 16);
+        }
+      }
+      unsigned long long m = __ballot(mab != 0u);
+      while (m) {
+        const int j = __ffsll((long long)m) - 1;
+        m &= m - 1ull;
+        const int r = __shfl(rr, j);
+        const unsigned int mj = __builtin_amdgcn_readfirstlane(__shfl((int)mab, j));
+        const unsigned int ma = mj & 0xffffu, mb = mj >> 16;
+        const double* Ct = C + (gb + r) * (size_t)(RB * W) + row_off + mt0 * 16 + lr;
+        const double* Yt = Y + (hb + r) * (size_t)(RB * W) + col_off + nt0 * 16 + lr;
+        double a[4][MW], b[4][NW];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        double a[MW], b[NW];
-        const int ro = (4 * s + lk) * W;
+        for (int s = 0; s < 4; ++s) {
+          const int ro = (4 * s + lk) * W;
 #pragma unroll
-        for (int i = 0; i < MW; ++i) a[i] = (i < mc && (ma & (1u << i))) ? Ct[ro + i * 16] : 0.0;
+          for (int i = 0; i < MW; ++i) a[s][i] = (ma & (1u << i)) ? Ct[ro + i * 16] : 0.0;
 #pragma unroll
-        for (int j = 0; j < NW; ++j) b[j] = (j < nc && (mb & (1u << j))) ? Yt[ro + j * 16] : 0.0;
+          for (int jj = 0; jj < NW; ++jj) b[s][jj] = (mb & (1u << jj)) ? Yt[ro + jj * 16] : 0.0;
+        }
 #pragma unroll
-        for (int i = 0; i < MW; ++i)
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
-          for (int j = 0; j < NW; ++j)
-            if (i < mc && j < nc && (ma & (1u << i)) && (mb & (1u << j))) {
-              acc[i][j] = mfma64(a[i], b[j], acc[i][j]);
-              ++n_mfma;
-            }
+          for (int i = 0; i < MW; ++i)
+#pragma unroll
+            for (int jj = 0; jj < NW; ++jj)
+              if ((ma & (1u << i)) && (mb & (1u << jj))) {
+                acc[i][jj] = mfma64(a[s][i], b[s][jj], acc[i][jj]);
+                ++n_mfma;
+              }
       }
     }
   }
@@ -300,22 +275,23 @@ __global__ void __launch_bounds__(256) k_pair(int n_rb, int W, const int* __rest
   if (ctr && lane == 0 && n_mfma) atomicAdd(ctr, (unsigned long long)n_mfma);
 }
 
-void launch_pair(const View& v, int n_pairs, const int* pg, const int* ph, const double* C, const int* listC,
+void launch_pair(const View& v, int n_pairs, const int* perm, int maxc, const int* pg, const int* ph,
+                 const double* C, const int* listC,
                  const int* cntC, const unsigned int* cmask, const double* Y, const uint8_t* actY,
                  const unsigned int* ymask, int row_off, int MT, int col_off, int NT, double* out, int ld,
                  size_t out_stride, unsigned long long* ctr, hipStream_t s) {
   if (n_pairs <= 0) return;
   const int mw = (MT + 1) / 2, nw = (NT + 1) / 2;
   const int m = mw > nw ? mw : nw;
-  dim3 grid(n_pairs), blk(256);
+  dim3 grid(N_XCD * maxc), blk(256);
   if (m <= 1)
-    hipLaunchKernelGGL((k_pair<1, 1>), grid, blk, 0, s, v.n_rb, v.W, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+    hipLaunchKernelGGL((k_pair<1, 1>), grid, blk, 0, s, v.n_rb, v.W, perm, maxc, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
   else if (m <= 2)
-    hipLaunchKernelGGL((k_pair<2, 2>), grid, blk, 0, s, v.n_rb, v.W, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+    hipLaunchKernelGGL((k_pair<2, 2>), grid, blk, 0, s, v.n_rb, v.W, perm, maxc, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
   else if (m <= 3)
-    hipLaunchKernelGGL((k_pair<3, 3>), grid, blk, 0, s, v.n_rb, v.W, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+    hipLaunchKernelGGL((k_pair<3, 3>), grid, blk, 0, s, v.n_rb, v.W, perm, maxc, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
   else
-    hipLaunchKernelGGL((k_pair<4, 4>), grid, blk, 0, s, v.n_rb, v.W, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+    hipLaunchKernelGGL((k_pair<4, 4>), grid, blk, 0, s, v.n_rb, v.W, perm, maxc, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
 }
 
 // per-column dot products d[g][c] = sum_r sum_k C[g][r][k][c] Y[g][r][k][c]
@@ -426,26 +402,39 @@ void launch_scale_c(const View& v, double* C, const int* listC, const int* cntC,
   hipLaunchKernelGGL(k_scale_c, dim3(v.n_rb, v.G), dim3(256), 0, s, v.n_rb, v.W, C, listC, cntC, sc);
 }
 
+// Per pair: flag it when any |D| >= 1e-3 eta, flag the MOs that take part, and record which
+// 4 x 16 MFMA fragments of D (words 0..7) and of its transpose (words 8..15) hold such an entry.
 __global__ void __launch_bounds__(256) k_mark_selected(int W, const int* pg, const int* ph, const double* D,
-                                                       const Scalars* sd, uint8_t* pair_sel, uint8_t* upd) {
+                                                       const Scalars* sd, uint8_t* pair_sel, uint8_t* upd,
+                                                       unsigned int* fmask) {
   const int p = blockIdx.x;
   const int g = pg[p], h = ph[p];
+  const int NT = W / 16;
+  __shared__ unsigned int fm[16];
+  if (threadIdx.x < 16) fm[threadIdx.x] = 0u;
+  __syncthreads();
   const double thr = 1e-3 * __longlong_as_double((long long)sd->eta_bits);
   const double* Dp = D + (size_t)p * W * W;
   int any = 0;
   for (int e = threadIdx.x; e < W * W; e += 256) {
     if (fabs(Dp[e]) >= thr && Dp[e] != 0.0) {
+      const int i = e / W, j = e % W;
       any = 1;
-      upd[(size_t)g * W + e / W] = 1;
-      upd[(size_t)h * W + e % W] = 1;
+      upd[(size_t)g * W + i] = 1;
+      upd[(size_t)h * W + j] = 1;
+      const int bd = (i / 4) * NT + j / 16, bt = (j / 4) * NT + i / 16;
+      atomicOr(&fm[bd >> 5], 1u << (bd & 31));
+      atomicOr(&fm[8 + (bt >> 5)], 1u << (bt & 31));
     }
   }
   any = __syncthreads_or(any);
+  if (threadIdx.x < 16) fmask[(size_t)p * 16 + threadIdx.x] = fm[threadIdx.x];
   if (threadIdx.x == 0) pair_sel[p] = (uint8_t)(any ? 1 : 0);
 }
 void launch_mark_selected(const View& v, int n_pairs, const int* pg, const int* ph, const double* D,
-                          const Scalars* sd, uint8_t* pair_sel, uint8_t* upd, hipStream_t s) {
-  if (n_pairs > 0) hipLaunchKernelGGL(k_mark_selected, dim3(n_pairs), dim3(256), 0, s, v.W, pg, ph, D, sd, pair_sel, upd);
+                          const Scalars* sd, uint8_t* pair_sel, uint8_t* upd, unsigned int* fmask, hipStream_t s) {
+  if (n_pairs > 0)
+    hipLaunchKernelGGL(k_mark_selected, dim3(n_pairs), dim3(256), 0, s, v.W, pg, ph, D, sd, pair_sel, upd, fmask);
 }
 
 __global__ void k_update_support(int G, int n_rb, const uint8_t* actC, const int* gn_ptr, const int* gn,
@@ -484,60 +473,145 @@ void launch_clear_tiles(const View& v, double* C, uint8_t* act, unsigned int* cm
 // Cn[g][r] = C[g][r] - 1/2 sum_{h ~ g} C[h][r] D_sel(h, g), then |v| < cut -> 0 in the
 // columns that took part in a combination.  D is stored per unordered pair (a <= b) with
 // rows = MOs of a, columns = MOs of b; Dt holds the transposes, so D_sel(h, g) (rows = MOs
-// of h) is read row-contiguously in both orientations.  One wave per output tile, one
-// accumulator per 16-column slice; 16-column slices of C_h[r] known to be zero are skipped.
+// of h) is read row-contiguously in both orientations.
+//
+// A workgroup of UW waves owns UW output tiles of one group g (one per wave).  It first finds,
+// 64 neighbours at a time, the neighbours h whose pair is selected and whose C_h is active in
+// at least one of its rows.  For each such h it stages the fragments of D_sel(h, g) that hold
+// a selected entry in LDS, thresholded; the global loads of the next h are issued before the
+// MFMAs of the current one, so their latency is hidden behind them.  Each wave whose row has
+// C_h[r] active then runs its MFMAs from LDS, skipping zero fragments and 16-column slices of
+// C_h[r] known to be zero.  Skipping a zero fragment leaves the sum unchanged.
+constexpr int UW = 8;
+
 template <int NT>
-__global__ void __launch_bounds__(256) k_ortho_update(int G, int n_rb, const double* __restrict__ C,
-                                                      const uint8_t* __restrict__ actC,
-                                                      const unsigned int* __restrict__ cmask,
-                                                      const int* __restrict__ gn_ptr, const int* __restrict__ gn,
-                                                      const int* __restrict__ pair_of,
-                                                      const uint8_t* __restrict__ pair_sel,
-                                                      const double* __restrict__ D, const double* __restrict__ Dt,
-                                                      const Scalars* __restrict__ sd,
-                                                      const uint8_t* __restrict__ upd, double cut,
-                                                      const int* __restrict__ listN, const int* __restrict__ cntN,
-                                                      double* __restrict__ Cn, uint8_t* __restrict__ actN,
-                                                      unsigned int* __restrict__ cmaskN, unsigned long long* ctr) {
-  constexpr int W = NT * 16;
-  const int g = blockIdx.y;
-  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (t >= cntN[g]) return;
+__global__ void __launch_bounds__(UW * 64) k_ortho_update(int G, int n_rb, int nchunk, const double* __restrict__ C,
+                                                          const uint8_t* __restrict__ actC,
+                                                          const unsigned int* __restrict__ cmask,
+                                                          const int* __restrict__ gn_ptr, const int* __restrict__ gn,
+                                                          const int* __restrict__ pair_of,
+                                                          const uint8_t* __restrict__ pair_sel,
+                                                          const double* __restrict__ D, const double* __restrict__ Dt,
+                                                          const unsigned int* __restrict__ fmask,
+                                                          const Scalars* __restrict__ sd,
+                                                          const uint8_t* __restrict__ upd, double cut,
+                                                          const int* __restrict__ listN, const int* __restrict__ cntN,
+                                                          double* __restrict__ Cn, uint8_t* __restrict__ actN,
+                                                          unsigned int* __restrict__ cmaskN, unsigned long long* ctr) {
+  constexpr int W = NT * 16, KS = W / 4, SPW = (KS + UW - 1) / UW;
+  __shared__ double Ds[W * W];
+  __shared__ __align__(8) uint8_t frag[KS * 8];
+  __shared__ unsigned long long need;
+  int chunk;
+  const int g = xcd_group_chunk(nchunk, chunk);
+  if (g >= G) return;
+  const int cnt = cntN[g];
+  const int t0 = chunk * UW;
+  if (t0 >= cnt) return;
   const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lr = lane & 15, lk = lane >> 4;
-  const int r = listN[(size_t)g * n_rb + t];
+  const bool live = t0 + wv < cnt;
+  const int r = live ? listN[(size_t)g * n_rb + t0 + wv] : 0;
   const double thr = 1e-3 * __longlong_as_double((long long)sd->eta_bits);
   d4 acc[NT];
 #pragma unroll
   for (int n = 0; n < NT; ++n) acc[n] = d4{0.0, 0.0, 0.0, 0.0};
   unsigned int n_mfma = 0;
-  for (int k = gn_ptr[g]; k < gn_ptr[g + 1]; ++k) {
-    const int h = gn[k];
+  double dv[SPW][NT];       // this wave's fragments of the next D block
+  unsigned int fbits[SPW];  // which of them hold a selected entry (bit n)
+  // global loads of the fragments of D_sel(h, g) that this wave stages: strips wv, wv + UW, ...
+  auto fetch = [&](int h) {
     const int p = pair_of[(size_t)g * G + h];
-    const size_t th = (size_t)h * n_rb + r;
-    if (!pair_sel[p] || !actC[th]) continue;
-    const unsigned int am = cmask[th];
-    const double* Ch = C + th * (RB * W) + lr * W + lk;
-    const double* Dp = ((h > g) ? Dt : D) + (size_t)p * W * W + lr;
+    const bool tr = h > g;
+    const double* src = (tr ? Dt : D) + (size_t)p * W * W + lk * W + lr;
+    const unsigned int* fm = fmask + (size_t)p * 16 + (tr ? 8 : 0);
 #pragma unroll
-    for (int s = 0; s < W / 4; ++s) {
-      if (!(am & (1u << (s >> 2)))) continue;
-      const double a = Ch[4 * s];
-      const double* Dr = Dp + (size_t)(4 * s + lk) * W;
+    for (int i = 0; i < SPW; ++i) {
+      const int st = wv + i * UW;
+      fbits[i] = 0u;
 #pragma unroll
       for (int n = 0; n < NT; ++n) {
-        double d = Dr[n * 16];
-        d = (fabs(d) >= thr) ? d : 0.0;
-        acc[n] = mfma64(a, d, acc[n]);
+        const int bit = st * NT + n;
+        const bool on = st < KS && ((fm[bit >> 5] >> (bit & 31)) & 1u);
+        dv[i][n] = on ? src[st * 4 * W + n * 16] : 0.0;
+        fbits[i] |= on ? (1u << n) : 0u;
       }
-      n_mfma += NT;
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int i = 0; i < SPW; ++i) {
+      const int st = wv + i * UW;
+      if (st < KS) {
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+          if (fbits[i] & (1u << n)) Ds[st * 4 * W + lk * W + n * 16 + lr] = (fabs(dv[i][n]) >= thr) ? dv[i][n] : 0.0;
+          if (lane == 0) frag[st * 8 + n] = (uint8_t)((fbits[i] >> n) & 1u);
+        }
+      }
+    }
+  };
+  const int k_end = gn_ptr[g + 1];
+  for (int kb = gn_ptr[g]; kb < k_end; kb += 64) {
+    if (threadIdx.x == 0) need = 0ull;
+    __syncthreads();
+    {
+      const int k = kb + lane;
+      bool f = false;
+      if (live && k < k_end) {
+        const int h = gn[k];
+        f = pair_sel[pair_of[(size_t)g * G + h]] && actC[(size_t)h * n_rb + r];
+      }
+      const unsigned long long m = __ballot(f);
+      if (lane == 0 && m) atomicOr(&need, m);
+    }
+    __syncthreads();
+    unsigned long long M = need;
+    __syncthreads();
+    if (!M) continue;
+    int h = gn[kb + __ffsll((long long)M) - 1];
+    M &= M - 1ull;
+    fetch(h);
+    for (;;) {
+      stage();
+      __syncthreads();
+      const int hc = h;
+      const bool more = M != 0ull;
+      if (more) {
+        h = gn[kb + __ffsll((long long)M) - 1];
+        M &= M - 1ull;
+        fetch(h);
+      }
+      const size_t th = (size_t)hc * n_rb + r;
+      if (live && actC[th]) {
+        const unsigned int am = cmask[th];
+        const double* Ch = C + th * (RB * W) + lr * W + lk;
+        const double* Dl = Ds + lk * W + lr;
+#pragma unroll 4
+        for (int s = 0; s < KS; ++s) {
+          if (!(am & (1u << (s >> 2)))) continue;
+          const double a = Ch[4 * s];
+          const uint2 fl = *reinterpret_cast<const uint2*>(frag + s * 8);
+#pragma unroll
+          for (int n = 0; n < NT; ++n) {
+            const unsigned int fb = (n < 4) ? (fl.x >> (8 * n)) : (fl.y >> (8 * (n - 4)));
+            if (fb & 0xffu) {
+              acc[n] = mfma64(a, Dl[4 * s * W + n * 16], acc[n]);
+              ++n_mfma;
+            }
+          }
+        }
+      }
+      __syncthreads();
+      if (!more) break;
     }
   }
+  if (!live) return;
   const size_t tile = (size_t)g * n_rb + r;
   const bool own = actC[tile] != 0;
   const double* Cg = C + tile * (RB * W);
   double* Co = Cn + tile * (RB * W);
-  int any = 0;
   unsigned int cm = 0;
 #pragma unroll
   for (int n = 0; n < NT; ++n) {
@@ -553,7 +627,6 @@ __global__ void __launch_bounds__(256) k_ortho_update(int G, int n_rb, const dou
       nz |= (v != 0.0);
     }
     if (__ballot(nz)) cm |= 1u << n;
-    any |= nz;
   }
   if (lane == 0) {
     actN[tile] = (uint8_t)(cm != 0u);
@@ -564,12 +637,13 @@ __global__ void __launch_bounds__(256) k_ortho_update(int G, int n_rb, const dou
 
 void launch_ortho_update(const View& v, const double* C, const uint8_t* actC, const int* gn_ptr, const int* gn,
                          const int* pair_of, const uint8_t* pair_sel, const double* D, const double* Dt,
-                         const Scalars* sd, const uint8_t* upd, double cut, const int* listN, const int* cntN,
-                         double* Cn, uint8_t* actN, const unsigned int* cmask, unsigned int* cmaskN,
-                         unsigned long long* ctr, hipStream_t s) {
-  dim3 grid((v.n_rb + 3) / 4, v.G);
+                         const unsigned int* fmask, const Scalars* sd, const uint8_t* upd, double cut,
+                         const int* listN, const int* cntN, double* Cn, uint8_t* actN, const unsigned int* cmask,
+                         unsigned int* cmaskN, unsigned long long* ctr, hipStream_t s) {
+  const int nchunk = (v.n_rb + UW - 1) / UW;
+  dim3 grid(xcd_grid(v.G, nchunk)), blk(UW * 64);
   switch (v.W / 16) {
-#define SSCF_UPD(NT) case NT: hipLaunchKernelGGL(k_ortho_update<NT>, grid, dim3(256), 0, s, v.G, v.n_rb, C, actC, cmask, gn_ptr, gn, pair_of, pair_sel, D, Dt, sd, upd, cut, listN, cntN, Cn, actN, cmaskN, ctr); break;
+#define SSCF_UPD(NT) case NT: hipLaunchKernelGGL(k_ortho_update<NT>, grid, blk, 0, s, v.G, v.n_rb, nchunk, C, actC, cmask, gn_ptr, gn, pair_of, pair_sel, D, Dt, fmask, sd, upd, cut, listN, cntN, Cn, actN, cmaskN, ctr); break;
     SSCF_UPD(1) SSCF_UPD(2) SSCF_UPD(3) SSCF_UPD(4) SSCF_UPD(5) SSCF_UPD(6) SSCF_UPD(7) SSCF_UPD(8)
 #undef SSCF_UPD
   }
@@ -1039,75 +1113,110 @@ void launch_round_meta(int n_rounds, const int* round_ptr, const int* round_list
 }
 
 template <int NTMAX, typename Real>
-__global__ void __launch_bounds__(512) k_givens_rb(int G, int n_rb, int W, int OW, int n_rounds,
+__global__ void __launch_bounds__(256) k_givens_rb(int G, int n_rb, int W, int OW, int n_rounds,
                                                    const int* __restrict__ roff, const int4* __restrict__ meta,
                                                    const int* __restrict__ tcol,
                                                    const Real* __restrict__ R, double eps, double* C,
                                                    uint8_t* actC, unsigned int* cmask, unsigned long long* ctr) {
   typedef typename Mfma<Real>::acc_t acc_t;
-  extern __shared__ uint8_t act_l[];
+  extern __shared__ int4 gv_smem[];
+  int4* list_l = gv_smem;                                    // relevant blocks of the round
+  int* cnt_l = reinterpret_cast<int*>(gv_smem + 256);
+  uint8_t* act_l = reinterpret_cast<uint8_t*>(cnt_l + 4);   // activity of row block rb, per group
   const int rb = blockIdx.x;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   for (int g = threadIdx.x; g < G; g += blockDim.x) act_l[g] = actC[(size_t)g * n_rb + rb];
-  __syncthreads();
   unsigned long long bytes = 0;
+  // the first 256 rotating blocks of round r + 1 are fetched while round r is applied
+  auto fetch_round = [&](int r) {
+    return (int)threadIdx.x < roff[r + 1] - roff[r] ? meta[roff[r] + threadIdx.x] : make_int4(-1, 0, 0, 0);
+  };
+  int4 nxt = fetch_round(0);
   for (int r = 0; r < n_rounds; ++r) {
     const int b0 = roff[r], b1 = roff[r + 1];
-    for (int i = b0 + w; i < b1; i += nw) {
-      const int4 mt = meta[i];
-      const int b = mt.x, g = mt.y, h = mt.z, T = mt.w;
-      if (!act_l[g] && !act_l[h]) continue;
-      const int nt_n = (T + 15) >> 4;
-      const int* tc = tcol + (size_t)b * W;
-      const Real* Rb = R + (size_t)b * W * W;
-      double* Cg = C + ((size_t)g * n_rb + rb) * RB * W;
-      double* Ch = C + ((size_t)h * n_rb + rb) * RB * W;
-      acc_t acc[NTMAX];
+    const int4 cur = nxt;
+    if (r + 1 < n_rounds) nxt = fetch_round(r + 1);
+    for (int c0 = b0; c0 < b1; c0 += 256) {
+      // every thread checks one rotating block of the round; the relevant ones go to LDS
+      int4 mt = cur;
+      if (c0 != b0) mt = (c0 + (int)threadIdx.x < b1) ? meta[c0 + threadIdx.x] : make_int4(-1, 0, 0, 0);
+      if (threadIdx.x == 0) cnt_l[0] = 0;
+      __syncthreads();
+      const bool rel = mt.x >= 0 && (act_l[mt.y] || act_l[mt.z]);
+      const unsigned long long m = __ballot(rel);
+      int off = 0;
+      if (lane == 0 && m) off = atomicAdd(cnt_l, __popcll(m));
+      off = __shfl(off, 0);
+      if (rel) list_l[off + __popcll(m & ((1ull << lane) - 1ull))] = mt;
+      __syncthreads();
+      const int nl = cnt_l[0];
+      for (int e = wv; e < nl; e += nw) {
+        const int4 it = list_l[e];
+        const int b = it.x, g = it.y, h = it.z, T = it.w;
+        const int nt_n = (T + 15) >> 4;
+        const int* tc = tcol + (size_t)b * W;
+        const Real* Rb = R + (size_t)b * W * W;
+        double* Cg = C + ((size_t)g * n_rb + rb) * RB * W;
+        double* Ch = C + ((size_t)h * n_rb + rb) * RB * W;
+        // the touched-column list is read once (two entries per lane) and shuffled to the
+        // lanes that gather; gathers go out 8 k-steps at a time
+        const int tcl0 = (lane < T) ? tc[lane] : 0;
+        const int tcl1 = (lane + 64 < T) ? tc[lane + 64] : 0;
+        const int ns = 4 * nt_n;
+        acc_t acc[NTMAX];
 #pragma unroll
-      for (int n = 0; n < NTMAX; ++n) acc[n] = acc_t{0, 0, 0, 0};
-      for (int s = 0; s < 4 * nt_n; ++s) {
-        const int k = 4 * s + lk;
-        Real a = 0;
-        if (k < T) {
-          const int col = tc[k];
-          a = (Real)(col < OW ? Cg : Ch)[lr * W + col];
+        for (int n = 0; n < NTMAX; ++n) acc[n] = acc_t{0, 0, 0, 0};
+        for (int s0 = 0; s0 < ns; s0 += 8) {
+          Real a[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int k = 4 * (s0 + u) + lk;
+            const int c0 = __shfl(tcl0, k & 63), c1 = __shfl(tcl1, k & 63);
+            const int col = (k < 64) ? c0 : c1;
+            a[u] = (s0 + u < ns && k < T) ? (Real)(col < OW ? Cg : Ch)[lr * W + col] : Real(0);
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (s0 + u < ns)
+#pragma unroll
+              for (int n = 0; n < NTMAX; ++n)
+                if (n < nt_n) acc[n] = Mfma<Real>::op(a[u], Rb[(size_t)(4 * (s0 + u) + lk) * W + n * 16 + lr], acc[n]);
         }
+        int nzg = 0, nzh = 0;
+        unsigned int bg = 0, bh = 0;
 #pragma unroll
-        for (int n = 0; n < NTMAX; ++n)
-          if (n < nt_n) acc[n] = Mfma<Real>::op(a, Rb[(size_t)k * W + n * 16 + lr], acc[n]);
-      }
-      int nzg = 0, nzh = 0;
-      unsigned int bg = 0, bh = 0;
+        for (int n = 0; n < NTMAX; ++n) {
+          const int j = n * 16 + lr;
+          const int c0 = __shfl(tcl0, j & 63), c1 = __shfl(tcl1, j & 63);
+          if (n < nt_n && j < T) {
+            const int col = (j < 64) ? c0 : c1;
+            double* base = (col < OW) ? Cg : Ch;
 #pragma unroll
-      for (int n = 0; n < NTMAX; ++n) {
-        const int j = n * 16 + lr;
-        if (n < nt_n && j < T) {
-          const int col = tc[j];
-          double* base = (col < OW) ? Cg : Ch;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            double x = (double)acc[n][q];
-            if (fabs(x) < eps) x = 0.0;
-            base[Mfma<Real>::row(lk, q) * W + col] = x;
-            if (x != 0.0) {
-              if (col < OW) { nzg = 1; bg |= 1u << (col >> 4); }
-              else { nzh = 1; bh |= 1u << (col >> 4); }
+            for (int q = 0; q < 4; ++q) {
+              double x = (double)acc[n][q];
+              if (fabs(x) < eps) x = 0.0;
+              base[Mfma<Real>::row(lk, q) * W + col] = x;
+              if (x != 0.0) {
+                if (col < OW) { nzg = 1; bg |= 1u << (col >> 4); }
+                else { nzh = 1; bh |= 1u << (col >> 4); }
+              }
             }
           }
         }
+        const bool anyg = __ballot(nzg) != 0ULL, anyh = __ballot(nzh) != 0ULL;
+        for (int o = 32; o > 0; o >>= 1) { bg |= __shfl_xor(bg, o); bh |= __shfl_xor(bh, o); }
+        if (lane == 0) {
+          if (bg) atomicOr(&cmask[(size_t)g * n_rb + rb], bg);
+          if (bh) atomicOr(&cmask[(size_t)h * n_rb + rb], bh);
+          if (anyg && !act_l[g]) { act_l[g] = 1; actC[(size_t)g * n_rb + rb] = 1; }
+          if (anyh && !act_l[h]) { act_l[h] = 1; actC[(size_t)h * n_rb + rb] = 1; }
+        }
+        bytes += (unsigned long long)T * RB * 16ULL;
       }
-      const bool anyg = __ballot(nzg) != 0ULL, anyh = __ballot(nzh) != 0ULL;
-      for (int o = 32; o > 0; o >>= 1) { bg |= __shfl_xor(bg, o); bh |= __shfl_xor(bh, o); }
-      if (lane == 0) {
-        if (bg) atomicOr(&cmask[(size_t)g * n_rb + rb], bg);
-        if (bh) atomicOr(&cmask[(size_t)h * n_rb + rb], bh);
-        if (anyg && !act_l[g]) { act_l[g] = 1; actC[(size_t)g * n_rb + rb] = 1; }
-        if (anyh && !act_l[h]) { act_l[h] = 1; actC[(size_t)h * n_rb + rb] = 1; }
-      }
-      bytes += (unsigned long long)T * RB * 16ULL;
+      __syncthreads();
     }
-    __syncthreads();
   }
   if (ctr && lane == 0 && bytes) atomicAdd(ctr, bytes);
 }
@@ -1116,11 +1225,11 @@ void launch_givens_rb(const View& v, int n_rounds, const int* roff, const int4* 
                       const float* R32, double eps, double* C, uint8_t* actC, unsigned int* cmask,
                       unsigned long long* ctr, hipStream_t s) {
   if (n_rounds <= 0) return;
-  const size_t lds = (size_t)v.G;
+  const size_t lds = 256 * sizeof(int4) + 4 * sizeof(int) + (size_t)v.G;
   switch ((v.W + 15) / 16) {
 #define SSCF_GIV(N) case N: \
-    if (R32) hipLaunchKernelGGL((k_givens_rb<N, float>), dim3(v.n_rb), dim3(512), lds, s, v.G, v.n_rb, v.W, v.OW, n_rounds, roff, meta, tcol, R32, eps, C, actC, cmask, ctr); \
-    else hipLaunchKernelGGL((k_givens_rb<N, double>), dim3(v.n_rb), dim3(512), lds, s, v.G, v.n_rb, v.W, v.OW, n_rounds, roff, meta, tcol, R, eps, C, actC, cmask, ctr); \
+    if (R32) hipLaunchKernelGGL((k_givens_rb<N, float>), dim3(v.n_rb), dim3(256), lds, s, v.G, v.n_rb, v.W, v.OW, n_rounds, roff, meta, tcol, R32, eps, C, actC, cmask, ctr); \
+    else hipLaunchKernelGGL((k_givens_rb<N, double>), dim3(v.n_rb), dim3(256), lds, s, v.G, v.n_rb, v.W, v.OW, n_rounds, roff, meta, tcol, R, eps, C, actC, cmask, ctr); \
     break;
     SSCF_GIV(1) SSCF_GIV(2) SSCF_GIV(3) SSCF_GIV(4) SSCF_GIV(5) SSCF_GIV(6) SSCF_GIV(7) SSCF_GIV(8)
 #undef SSCF_GIV
@@ -1261,80 +1370,19 @@ void launch_density_blocks(const View& v, const double* C, const uint8_t* actC, 
 // with FP32 accumulation; C itself stays FP64 and is rounded on load.
 // ---------------------------------------------------------------------------------------
 
-template <int NT>
-__global__ void __launch_bounds__(256) k_spmm32(int n_rb, const int* __restrict__ xs_ptr,
-                                                const int* __restrict__ xs_col, const float* __restrict__ X,
-                                                const double* __restrict__ C, const uint8_t* __restrict__ actC,
-                                                const unsigned int* __restrict__ cmask,
-                                                const int* __restrict__ listY, const int* __restrict__ cntY,
-                                                float* __restrict__ Y, unsigned int* __restrict__ ymask,
-                                                unsigned long long* ctr) {
-  constexpr int W = NT * 16;
-  const int g = blockIdx.y;
-  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (t >= cntY[g]) return;
-  unsigned int n_mfma = 0;
-  const int lane = threadIdx.x & 63;
-  const int lr = lane & 15, lk = lane >> 4;
-  const size_t pb = (size_t)g * n_rb;
-  const int r = listY[pb + t];
-  f4 acc[NT];
-#pragma unroll
-  for (int n = 0; n < NT; ++n) acc[n] = f4{0.f, 0.f, 0.f, 0.f};
-  for (int kb = xs_ptr[r]; kb < xs_ptr[r + 1]; ++kb) {
-    const int c = xs_col[kb];
-    if (!actC[pb + c]) continue;
-    const unsigned int m = cmask[pb + c];
-    const float* Xb = X + (size_t)kb * 256;
-    const double* Ct = C + (pb + c) * (RB * W);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const float a = Xb[lr * 16 + 4 * s + lk];
-#pragma unroll
-      for (int n = 0; n < NT; ++n)
-        if (m & (1u << n)) { acc[n] = mfma32(a, (float)Ct[(4 * s + lk) * W + n * 16 + lr], acc[n]); ++n_mfma; }
-    }
-  }
-  float* Yt = Y + (pb + r) * (RB * W);
-  unsigned int ym = 0;
-#pragma unroll
-  for (int n = 0; n < NT; ++n) {
-    int nz = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      Yt[(4 * lk + q) * W + n * 16 + lr] = acc[n][q];
-      nz |= acc[n][q] != 0.f;
-    }
-    if (__ballot(nz)) ym |= 1u << n;
-  }
-  if (lane == 0) {
-    ymask[pb + r] = ym;
-    if (ctr) atomicAdd(ctr, (unsigned long long)n_mfma);
-  }
-}
-
-void launch_spmm32_wave(const View& v, const float* X, const double* C, const uint8_t* actC, const unsigned int* cmask,
-                   const int* listY, const int* cntY, float* Y, unsigned int* ymask, unsigned long long* ctr,
-                   hipStream_t s) {
-  dim3 grid((v.n_rb + 3) / 4, v.G), blk(256);
-  switch (v.W / 16) {
-#define SSCF_SPMM32(NT) case NT: hipLaunchKernelGGL(k_spmm32<NT>, grid, blk, 0, s, v.n_rb, v.xs_ptr, v.xs_col, X, C, actC, cmask, listY, cntY, Y, ymask, ctr); break;
-    SSCF_SPMM32(1) SSCF_SPMM32(2) SSCF_SPMM32(3) SSCF_SPMM32(4) SSCF_SPMM32(5) SSCF_SPMM32(6) SSCF_SPMM32(7) SSCF_SPMM32(8)
-#undef SSCF_SPMM32
-  }
-}
-
 template <int MW, int NW>
-__global__ void __launch_bounds__(256) k_pair32(int n_rb, int W, const int* __restrict__ pg, const int* __restrict__ ph,
+__global__ void __launch_bounds__(256) k_pair32(int n_rb, int W, const int* __restrict__ perm, int maxc,
+                                                const int* __restrict__ pg, const int* __restrict__ ph,
                                                 const double* __restrict__ C, const int* __restrict__ listC,
                                                 const int* __restrict__ cntC, const unsigned int* __restrict__ cmask,
                                                 const float* __restrict__ Y, const uint8_t* __restrict__ actY,
                                                 const unsigned int* __restrict__ ymask, int row_off, int MT,
                                                 int col_off, int NT, double* __restrict__ out, int ld,
                                                 size_t out_stride, unsigned long long* ctr) {
-  const int p = blockIdx.x;
+  const int p = xcd_item(perm, maxc);
+  if (p < 0) return;
   const int g = pg[p], h = ph[p];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lr = lane & 15, lk = lane >> 4;
   const int MH = (MT + 1) / 2, NH = (NT + 1) / 2;
   const int mt0 = (w >> 1) * MH, nt0 = (w & 1) * NH;
@@ -1348,30 +1396,48 @@ __global__ void __launch_bounds__(256) k_pair32(int n_rb, int W, const int* __re
   const int cnt = cntC[g];
   unsigned int n_mfma = 0;
   if (mc > 0 && nc > 0) {
-    for (int t = 0; t < cnt; ++t) {
-      const int r = listC[gb + t];
-      if (!actY[hb + r]) continue;
-      const unsigned int ma = cmask[gb + r] >> (row_off / 16 + mt0);
-      const unsigned int mb = ymask[hb + r] >> (col_off / 16 + nt0);
-      if (!(ma & ((1u << mc) - 1u)) || !(mb & ((1u << nc) - 1u))) continue;
-      const double* Ct = C + (gb + r) * (size_t)(RB * W) + row_off + mt0 * 16 + lr;
-      const float* Yt = Y + (hb + r) * (size_t)(RB * W) + col_off + nt0 * 16 + lr;
+    const unsigned int mcm = (1u << mc) - 1u, ncm = (1u << nc) - 1u;
+    const int sa = row_off / 16 + mt0, sb = col_off / 16 + nt0;
+    // the rows active in both panels, 64 at a time, with their slice masks, before any product
+    for (int base = 0; base < cnt; base += 64) {
+      const int t = base + lane;
+      int rr = 0;
+      unsigned int mab = 0u;
+      if (t < cnt) {
+        rr = listC[gb + t];
+        if (actY[hb + rr]) {
+          const unsigned int ma = (cmask[gb + rr] >> sa) & mcm, mb = (ymask[hb + rr] >> sb) & ncm;
+          if (ma && mb) mab = ma | (mb << 16);
+        }
+      }
+      unsigned long long m = __ballot(mab != 0u);
+      while (m) {
+        const int j = __ffsll((long long)m) - 1;
+        m &= m - 1ull;
+        const int r = __shfl(rr, j);
+        const unsigned int mj = __builtin_amdgcn_readfirstlane(__shfl((int)mab, j));
+        const unsigned int ma = mj & 0xffffu, mb = mj >> 16;
+        const double* Ct = C + (gb + r) * (size_t)(RB * W) + row_off + mt0 * 16 + lr;
+        const float* Yt = Y + (hb + r) * (size_t)(RB * W) + col_off + nt0 * 16 + lr;
+        float a[4][MW], b[4][NW];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        float a[MW], b[NW];
-        const int ro = (4 * s + lk) * W;
+        for (int s = 0; s < 4; ++s) {
+          const int ro = (4 * s + lk) * W;
 #pragma unroll
-        for (int i = 0; i < MW; ++i) a[i] = (i < mc && (ma & (1u << i))) ? (float)Ct[ro + i * 16] : 0.f;
+          for (int i = 0; i < MW; ++i) a[s][i] = (ma & (1u << i)) ? (float)Ct[ro + i * 16] : 0.f;
 #pragma unroll
-        for (int j = 0; j < NW; ++j) b[j] = (j < nc && (mb & (1u << j))) ? Yt[ro + j * 16] : 0.f;
+          for (int jj = 0; jj < NW; ++jj) b[s][jj] = (mb & (1u << jj)) ? Yt[ro + jj * 16] : 0.f;
+        }
 #pragma unroll
-        for (int i = 0; i < MW; ++i)
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
-          for (int j = 0; j < NW; ++j)
-            if (i < mc && j < nc && (ma & (1u << i)) && (mb & (1u << j))) {
-              acc[i][j] = mfma32(a[i], b[j], acc[i][j]);
-              ++n_mfma;
-            }
+          for (int i = 0; i < MW; ++i)
+#pragma unroll
+            for (int jj = 0; jj < NW; ++jj)
+              if ((ma & (1u << i)) && (mb & (1u << jj))) {
+                acc[i][jj] = mfma32(a[s][i], b[s][jj], acc[i][jj]);
+                ++n_mfma;
+              }
       }
     }
   }
@@ -1387,22 +1453,23 @@ __global__ void __launch_bounds__(256) k_pair32(int n_rb, int W, const int* __re
   if (ctr && lane == 0 && n_mfma) atomicAdd(ctr, (unsigned long long)n_mfma);
 }
 
-void launch_pair32(const View& v, int n_pairs, const int* pg, const int* ph, const double* C, const int* listC,
+void launch_pair32(const View& v, int n_pairs, const int* perm, int maxc, const int* pg, const int* ph,
+                   const double* C, const int* listC,
                    const int* cntC, const unsigned int* cmask, const float* Y, const uint8_t* actY,
                    const unsigned int* ymask, int row_off, int MT, int col_off, int NT, double* out, int ld,
                    size_t out_stride, unsigned long long* ctr, hipStream_t s) {
   if (n_pairs <= 0) return;
   const int mw = (MT + 1) / 2, nw = (NT + 1) / 2;
   const int m = mw > nw ? mw : nw;
-  dim3 grid(n_pairs), blk(256);
+  dim3 grid(N_XCD * maxc), blk(256);
   if (m <= 1)
-    hipLaunchKernelGGL((k_pair32<1, 1>), grid, blk, 0, s, v.n_rb, v.W, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+    hipLaunchKernelGGL((k_pair32<1, 1>), grid, blk, 0, s, v.n_rb, v.W, perm, maxc, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
   else if (m <= 2)
-    hipLaunchKernelGGL((k_pair32<2, 2>), grid, blk, 0, s, v.n_rb, v.W, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+    hipLaunchKernelGGL((k_pair32<2, 2>), grid, blk, 0, s, v.n_rb, v.W, perm, maxc, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
   else if (m <= 3)
-    hipLaunchKernelGGL((k_pair32<3, 3>), grid, blk, 0, s, v.n_rb, v.W, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+    hipLaunchKernelGGL((k_pair32<3, 3>), grid, blk, 0, s, v.n_rb, v.W, perm, maxc, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
   else
-    hipLaunchKernelGGL((k_pair32<4, 4>), grid, blk, 0, s, v.n_rb, v.W, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+    hipLaunchKernelGGL((k_pair32<4, 4>), grid, blk, 0, s, v.n_rb, v.W, perm, maxc, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
 }
 
 __global__ void k_coldot32(int n_rb, int W, const double* C, const int* listC, const int* cntC, const float* Y,
@@ -1437,7 +1504,7 @@ void launch_coldot32(const View& v, const double* C, const int* listC, const int
 constexpr int SCH = 8;
 
 template <int NT, typename Real>
-__global__ void __launch_bounds__(SCH * 64) k_spmm_lds(int n_rb, const int* __restrict__ xs_ptr,
+__global__ void __launch_bounds__(SCH * 64) k_spmm_lds(int G, int n_rb, int nchunk, const int* __restrict__ xs_ptr,
                                                        const int* __restrict__ xs_col, const Real* __restrict__ X,
                                                        const double* __restrict__ C, const uint8_t* __restrict__ actC,
                                                        const unsigned int* __restrict__ cmask,
@@ -1448,8 +1515,10 @@ __global__ void __launch_bounds__(SCH * 64) k_spmm_lds(int n_rb, const int* __re
   typedef typename Mfma<Real>::acc_t acc_t;
   extern __shared__ unsigned int cbits[];             // n_rb bits, then the staged tile
   Real* tile = reinterpret_cast<Real*>(cbits + ((n_rb + 63) / 64) * 2);
-  const int g = blockIdx.y;
-  const int t0 = blockIdx.x * SCH;
+  int chunk;
+  const int g = xcd_group_chunk(nchunk, chunk);
+  if (g >= G) return;
+  const int t0 = chunk * SCH;
   const int cnt = cntY[g];
   if (t0 >= cnt) return;
   const int nt = min(SCH, cnt - t0);
@@ -1517,14 +1586,111 @@ __global__ void __launch_bounds__(SCH * 64) k_spmm_lds(int n_rb, const int* __re
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// Y = X C with one wave per output tile (g, r) and no workgroup synchronization.  A ballot
+// over the row's X blocks finds, 64 at a time, those whose C tile is active in panel g, with
+// its 16-column slice mask, before any product starts; the wave then streams the products,
+// the X block (A operand) and the C tile slices (B operand) read straight from L2 with all
+// of a product's loads issued together.  Real as above.
+// ---------------------------------------------------------------------------------------
+template <int NT, typename Real>
+__global__ void __launch_bounds__(256) k_spmm_row(int G, int n_rb, int nchunk, const int* __restrict__ xs_ptr,
+                                                  const int* __restrict__ xs_col, const Real* __restrict__ X,
+                                                  const double* __restrict__ C, const uint8_t* __restrict__ actC,
+                                                  const unsigned int* __restrict__ cmask,
+                                                  const int* __restrict__ listY, const int* __restrict__ cntY,
+                                                  Real* __restrict__ Y, unsigned int* __restrict__ ymask,
+                                                  unsigned long long* ctr) {
+  constexpr int W = NT * 16;
+  typedef typename Mfma<Real>::acc_t acc_t;
+  int chunk;
+  const int g = xcd_group_chunk(nchunk, chunk);
+  if (g >= G) return;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int t = chunk * 4 + wv;
+  if (t >= cntY[g]) return;
+  const int lane = threadIdx.x & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+  const size_t pb = (size_t)g * n_rb;
+  const int r = listY[pb + t];
+  const int k0 = xs_ptr[r], k1 = xs_ptr[r + 1];
+  acc_t acc[NT];
+#pragma unroll
+  for (int n = 0; n < NT; ++n) acc[n] = acc_t{0, 0, 0, 0};
+  unsigned int n_mfma = 0;
+  for (int base = k0; base < k1; base += 64) {
+    const int k = base + lane;
+    int c = 0;
+    unsigned int mk = 0u;
+    if (k < k1) {
+      c = xs_col[k];
+      mk = actC[pb + c] ? cmask[pb + c] : 0u;
+    }
+    unsigned long long m = __ballot(mk != 0u);
+    while (m) {
+      const int j = __ffsll((long long)m) - 1;
+      m &= m - 1ull;
+      const int cj = __shfl(c, j);
+      const unsigned int mj = __builtin_amdgcn_readfirstlane(__shfl((int)mk, j));
+      const Real* Xb = X + (size_t)(base + j) * 256 + lr * 16 + lk;
+      const double* Ct = C + (pb + cj) * (RB * W) + lk * W + lr;
+      Real xa[4], cb[4][NT];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) xa[s] = Xb[4 * s];
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) cb[s][n] = ((mj >> n) & 1u) ? (Real)Ct[4 * s * W + n * 16] : Real(0);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int n = 0; n < NT; ++n)
+          if ((mj >> n) & 1u) {
+            acc[n] = Mfma<Real>::op(xa[s], cb[s][n], acc[n]);
+            ++n_mfma;
+          }
+    }
+  }
+  Real* Yt = Y + (pb + r) * (RB * W);
+  unsigned int ym = 0;
+#pragma unroll
+  for (int n = 0; n < NT; ++n) {
+    int nz = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      Yt[Mfma<Real>::row(lk, q) * W + n * 16 + lr] = acc[n][q];
+      nz |= acc[n][q] != Real(0);
+    }
+    if (__ballot(nz)) ym |= 1u << n;
+  }
+  if (lane == 0) {
+    ymask[pb + r] = ym;
+    if (ctr && n_mfma) atomicAdd(ctr, (unsigned long long)n_mfma);
+  }
+}
+
+template <typename Real>
+static void launch_spmm_row(const View& v, const Real* X, const double* C, const uint8_t* actC,
+                            const unsigned int* cmask, const int* listY, const int* cntY, Real* Y,
+                            unsigned int* ymask, unsigned long long* ctr, hipStream_t s) {
+  const int nchunk = (v.n_rb + 3) / 4;
+  dim3 grid(xcd_grid(v.G, nchunk)), blk(256);
+  switch (v.W / 16) {
+#define SSCF_SPR(NT) case NT: hipLaunchKernelGGL((k_spmm_row<NT, Real>), grid, blk, 0, s, v.G, v.n_rb, nchunk, v.xs_ptr, v.xs_col, X, C, actC, cmask, listY, cntY, Y, ymask, ctr); break;
+    SSCF_SPR(1) SSCF_SPR(2) SSCF_SPR(3) SSCF_SPR(4) SSCF_SPR(5) SSCF_SPR(6) SSCF_SPR(7) SSCF_SPR(8)
+#undef SSCF_SPR
+  }
+}
+
 template <typename Real>
 static void launch_spmm_lds(const View& v, const Real* X, const double* C, const uint8_t* actC,
                             const unsigned int* cmask, const int* listY, const int* cntY, Real* Y,
                             unsigned int* ymask, unsigned long long* ctr, hipStream_t s) {
-  dim3 grid((v.n_rb + SCH - 1) / SCH, v.G), blk(SCH * 64);
+  const int nchunk = (v.n_rb + SCH - 1) / SCH;
+  dim3 grid(xcd_grid(v.G, nchunk)), blk(SCH * 64);
   const size_t lds = ((v.n_rb + 63) / 64) * 2 * sizeof(unsigned int) + (size_t)RB * v.W * sizeof(Real);
   switch (v.W / 16) {
-#define SSCF_SPL(NT) case NT: hipLaunchKernelGGL((k_spmm_lds<NT, Real>), grid, blk, lds, s, v.n_rb, v.xs_ptr, v.xs_col, X, C, actC, cmask, listY, cntY, Y, ymask, ctr); break;
+#define SSCF_SPL(NT) case NT: hipLaunchKernelGGL((k_spmm_lds<NT, Real>), grid, blk, lds, s, v.G, v.n_rb, nchunk, v.xs_ptr, v.xs_col, X, C, actC, cmask, listY, cntY, Y, ymask, ctr); break;
     SSCF_SPL(1) SSCF_SPL(2) SSCF_SPL(3) SSCF_SPL(4) SSCF_SPL(5) SSCF_SPL(6) SSCF_SPL(7) SSCF_SPL(8)
 #undef SSCF_SPL
   }
@@ -1533,13 +1699,13 @@ static void launch_spmm_lds(const View& v, const Real* X, const double* C, const
 void launch_spmm(const View& v, const double* X, const double* C, const uint8_t* actC, const unsigned int* cmask,
                  const int* listY, const int* cntY, double* Y, unsigned int* ymask, unsigned long long* ctr,
                  hipStream_t s) {
-  launch_spmm_lds<double>(v, X, C, actC, cmask, listY, cntY, Y, ymask, ctr, s);
+  launch_spmm_row<double>(v, X, C, actC, cmask, listY, cntY, Y, ymask, ctr, s);
 }
 
 void launch_spmm32(const View& v, const float* X, const double* C, const uint8_t* actC, const unsigned int* cmask,
                    const int* listY, const int* cntY, float* Y, unsigned int* ymask, unsigned long long* ctr,
                    hipStream_t s) {
-  launch_spmm_lds<float>(v, X, C, actC, cmask, listY, cntY, Y, ymask, ctr, s);
+  launch_spmm_row<float>(v, X, C, actC, cmask, listY, cntY, Y, ymask, ctr, s);
 }
 
 }  // namespace sscf
