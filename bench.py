@@ -20,6 +20,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SCF steps/sec + HBM GB/s at 12k atoms; FP32 vs FP64 form at 1e-6 Ha"
 PEAK = {"hbm": 8000.0, "fp64": 78.6, "fp32": 157.3}   # GB/s, TFLOP/s (MI355X, dense)
+# Measured HBM traffic per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a copy kernel);
+# it is reported only while the kernel source is the one the counters were taken from.
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic_water4096_fp64.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1402_2880_amd", "csrc", "sscf_kernels.hip")
+KERNEL_OF_CLASS = {"ortho_update": "sscf::k_ortho_update<6>", "spmm_tiles": "sscf::k_spmm_row<6, double>",
+                   "pair_overlap": "sscf::k_pair<3, 3>", "pair_fock": "sscf::k_pair<2, 2>",
+                   "rotations": "sscf::k_givens_rb<6, double>"}
 
 
 def log(*a):
@@ -43,6 +50,18 @@ def cpu_baseline(system, budget_s: float, eps: float, e_conv: float):
     return dict(value=n / t_sum, unit="SCF steps/s", cores=threads, kind="oracle",
                 sample=f"oracle SCF steps 1..{n} of the same {system.name} system (set-up not timed), "
                        f"{t_sum:.1f} s")
+
+
+def measured_traffic(kclass: str, config: str, precision: str):
+    """HBM bytes per launch of the kernel class from the committed counter summary, or None."""
+    import hashlib
+    if config != "water4096" or precision != "fp64" or not os.path.exists(TRAFFIC):
+        return None
+    rec = json.load(open(TRAFFIC))
+    if hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest() != rec.get("kernel_source_sha256"):
+        return None
+    k = rec["kernels"].get(KERNEL_OF_CLASS.get(kclass, ""))
+    return None if k is None else round(k["hbm_bytes_per_launch"] / 1e9, 3)
 
 
 def main():
@@ -127,12 +146,16 @@ def main():
             achieved = st["flops"] / st["launches"] / (per_launch_ms * 1e-3) / 1e12
             peak = PEAK["fp64"] if args.precision == "fp64" else PEAK["fp32"]
             roofline = dict(kernel=name, bound="mfma", achieved=round(achieved, 3), peak=peak,
-                            unit="TFLOP/s", frac=round(achieved / peak, 4), traffic=None,
+                            unit="TFLOP/s", frac=round(achieved / peak, 4),
+                            traffic=measured_traffic(name, args.config, args.precision),
+                            traffic_unit="GB per launch",
                             avg_launch_ms=round(per_launch_ms, 4), launches=st["launches"])
         else:
             achieved = st["bytes"] / st["launches"] / (per_launch_ms * 1e-3) / 1e9
             roofline = dict(kernel=name, bound="hbm", achieved=round(achieved, 1), peak=PEAK["hbm"],
-                            unit="GB/s", frac=round(achieved / PEAK["hbm"], 4), traffic=None,
+                            unit="GB/s", frac=round(achieved / PEAK["hbm"], 4),
+                            traffic=measured_traffic(name, args.config, args.precision),
+                            traffic_unit="GB per launch",
                             avg_launch_ms=round(per_launch_ms, 4), launches=st["launches"])
     cpu = None
     if not args.no_cpu_baseline:

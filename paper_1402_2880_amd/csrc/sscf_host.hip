@@ -120,7 +120,8 @@ struct sscf_ctx {
   double* Dt = nullptr;                 // transposes of the off-diagonal D blocks
   double* sc = nullptr;
   uint8_t *upd = nullptr, *pair_sel = nullptr;
-  unsigned int* fmask = nullptr;        // per pair: nonzero-fragment masks of D_sel and its transpose
+  unsigned int* fmask = nullptr;
+  double* part = nullptr;               // partial sums of the split reductions (coldot, coulomb)        // per pair: nonzero-fragment masks of D_sel and its transpose
   int *jb_g = nullptr, *jb_h = nullptr, *jb_nocc = nullptr, *jb_nvirt = nullptr, *round_list = nullptr;
   double *F = nullptr, *Fdiag = nullptr, *dvec = nullptr;
   int *rot_cnt = nullptr, *tcnt = nullptr, *tcol = nullptr, *round_ptr = nullptr;
@@ -303,10 +304,10 @@ struct sscf_ctx {
   // Q = gamma dq (kept current in every mode, for the next Fock build), the Coulomb
   // energy and the band energy sum P H0 (or P F with a complete Fock matrix)
   void energy_terms() {
-    launch_coulomb(v, scc, dq, Q, stream);
+    launch_coulomb(v, scc, dq, part, Q, stream);
     launch_sum_coul(v, scc && !fock_full, dq, Q, sd, stream);
     product(fock_full ? Hfull : H0, false);   // support of C unchanged since the last dilation
-    launch_coldot(v, C[cur], listC[cur], cntC[cur], Y, actY, dvec, stream);
+    launch_coldot(v, C[cur], listC[cur], cntC[cur], Y, actY, part, dvec, stream);
     launch_sum_band(v, dvec, pnocc, sd, stream);
   }
 
@@ -659,6 +660,7 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
   x->upd = x->dalloc<uint8_t>((size_t)G * v.W);
   x->pair_sel = x->dalloc<uint8_t>(x->n_pairs);
   x->fmask = x->dalloc<unsigned int>((size_t)x->n_pairs * 16);
+  x->part = x->dalloc<double>(std::max((size_t)CD_SPLIT * x->v.G * x->v.W, (size_t)CL_SPLIT * x->v.n_atoms));
   x->jb_g = x->upload(x->h_jb_g.data(), x->n_blocks);
   {
     std::vector<int> perm = xcd_perm(x->h_jb_g, &x->jb_maxc);
@@ -782,7 +784,7 @@ static void step(sscf_ctx* x, sscf_step_info* out) {
                 x->cmask[x->cur], x->Y, x->actY, x->ymask, 0, v.OW / 16, v.OW, v.VW / 16, x->F, v.VW,
                 (size_t)v.OW * v.VW, x->ctr(KC_PAIR_F), s);
     x->pend(pi);
-    launch_coldot(v, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur], x->Y, x->actY, x->Fdiag, s);
+    launch_coldot(v, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur], x->Y, x->actY, x->part, x->Fdiag, s);
   }
   HIPC(hipEventRecord(x->ev[2], s));
   // step V: selection of the rotations

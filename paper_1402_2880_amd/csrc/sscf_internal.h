@@ -25,6 +25,8 @@
 namespace sscf {
 
 constexpr int RB = 16;           // AOs per row block
+// strided parts of the split reductions (column dot products; Coulomb sums over atoms)
+constexpr int CD_SPLIT = 16, CL_SPLIT = 16;
 constexpr int MAX_W = 128;       // widest panel supported
 constexpr int MAX_TIES = 4096;   // candidates sharing the cut-off |F| that can be ordered
 
@@ -79,8 +81,8 @@ void launch_pair(const View& v, int n_pairs, const int* perm, int maxc, const in
                  const uint8_t* actY, const unsigned int* ymask, int row_off, int MT, int col_off,
                  int NT, double* out, int ld, size_t out_stride, unsigned long long* ctr,
                  hipStream_t s);
-void launch_coldot(const View& v, const double* C, const int* listC, const int* cntC,
-                   const double* Y, const uint8_t* actY, double* out, hipStream_t s);
+void launch_coldot(const View& v, const double* C, const int* listC, const int* cntC, const double* Y,
+                   const uint8_t* actY, double* part, double* out, hipStream_t s);
 void launch_ortho_scale(const View& v, int n_pairs_self, const int* self_pair, const double* O,
                         const int* pnocc, const int* pnvirt, int occ_only, double* sc,
                         Scalars* sd, hipStream_t s);
@@ -101,7 +103,7 @@ void launch_ortho_update(const View& v, const double* C, const uint8_t* actC, co
                          const double* Dt, const unsigned int* fmask, const Scalars* sd, const uint8_t* upd,
                          double cut, const int* listN, const int* cntN, double* Cn, uint8_t* actN,
                          const unsigned int* cmask, unsigned int* cmaskN, unsigned long long* ctr, hipStream_t s);
-void launch_coulomb(const View& v, int scc, const double* dq, double* Q, hipStream_t s);
+void launch_coulomb(const View& v, int scc, const double* dq, double* part, double* Q, hipStream_t s);
 void launch_fock(const View& v, const double* S, const double* H0, const double* Hfull,
                  const double* Q, double eps, double* H, float* H32, hipStream_t s);
 void launch_count_candidates(int nb, int OW, int VW, const int* jb_nocc, const int* jb_nvirt,

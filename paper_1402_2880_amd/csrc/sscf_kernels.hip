@@ -295,13 +295,16 @@ void launch_pair(const View& v, int n_pairs, const int* perm, int maxc, const in
 }
 
 // per-column dot products d[g][c] = sum_r sum_k C[g][r][k][c] Y[g][r][k][c]
+// The active row blocks of panel g are split into CD_SPLIT strided parts, one workgroup each;
+// the parts' sums are added in a fixed order by k_coldot_sum.
+
 __global__ void k_coldot(int n_rb, int W, const double* C, const int* listC, const int* cntC, const double* Y,
-                         const uint8_t* actY, double* out) {
-  const int g = blockIdx.x, c = threadIdx.x;
+                         const uint8_t* actY, double* part) {
+  const int g = blockIdx.x, sp = blockIdx.y, c = threadIdx.x;
   if (c >= W) return;
   const size_t gb = (size_t)g * n_rb;
   double s = 0.0;
-  for (int t = 0; t < cntC[g]; ++t) {
+  for (int t = sp; t < cntC[g]; t += CD_SPLIT) {
     const int r = listC[gb + t];
     if (!actY[gb + r]) continue;
     const double* Ct = C + (gb + r) * (size_t)(RB * W) + c;
@@ -309,12 +312,21 @@ __global__ void k_coldot(int n_rb, int W, const double* C, const int* listC, con
 #pragma unroll
     for (int k = 0; k < RB; ++k) s += Ct[k * W] * Yt[k * W];
   }
-  out[(size_t)g * W + c] = s;
+  part[((size_t)sp * gridDim.x + g) * W + c] = s;
+}
+__global__ void k_coldot_sum(size_t n, const double* part, double* out) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int sp = 0; sp < CD_SPLIT; ++sp) s += part[(size_t)sp * n + i];
+  out[i] = s;
 }
 void launch_coldot(const View& v, const double* C, const int* listC, const int* cntC, const double* Y,
-                   const uint8_t* actY, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_coldot, dim3(v.G), dim3(v.W <= 64 ? 64 : (v.W <= 128 ? 128 : 256)), 0, s, v.n_rb, v.W, C,
-                     listC, cntC, Y, actY, out);
+                   const uint8_t* actY, double* part, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_coldot, dim3(v.G, CD_SPLIT), dim3(v.W <= 64 ? 64 : (v.W <= 128 ? 128 : 256)), 0, s, v.n_rb,
+                     v.W, C, listC, cntC, Y, actY, part);
+  const size_t n = (size_t)v.G * v.W;
+  hipLaunchKernelGGL(k_coldot_sum, dim3(nblk(n, 256)), dim3(256), 0, s, n, part, out);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -654,42 +666,56 @@ void launch_ortho_update(const View& v, const double* C, const uint8_t* actC, co
 // H = H0 + 1/2 S (Q_a + Q_b) with |H| < eps -> 0 (section 4.1)
 // ---------------------------------------------------------------------------------------
 
+// Atom a's sum over b is split into CL_SPLIT contiguous ranges of b, one workgroup each
+// (the grid then fills the chip); k_coulomb_sum adds the ranges' sums in a fixed order.
+
 __global__ void __launch_bounds__(256) k_coulomb(int n, int scc, const double* __restrict__ xyz,
                                                  const double* __restrict__ U, const double* __restrict__ dq,
-                                                 double* __restrict__ Q) {
-  __shared__ double sx[256], sy[256], sz[256], su[256], sq[256];
+                                                 double* __restrict__ part) {
+  __shared__ double sx[256], sy[256], sz[256], siu[256], sq[256];
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = a < n;
   const double xa = live ? xyz[3 * a] : 0.0, ya = live ? xyz[3 * a + 1] : 0.0, za = live ? xyz[3 * a + 2] : 0.0;
-  const double ia = live ? 1.0 / U[a] : 0.0;
+  const double ua = live ? U[a] : 0.0, ia = live ? 1.0 / ua : 0.0;
+  const int per = (n + CL_SPLIT - 1) / CL_SPLIT;
+  const int b0 = blockIdx.y * per, b1 = min(n, b0 + per);
   double s = 0.0;
-  for (int base = 0; base < n; base += 256) {
+  for (int base = b0; base < b1; base += 256) {
     const int x = base + threadIdx.x;
     __syncthreads();
-    if (x < n) {
+    if (x < b1) {
       sx[threadIdx.x] = xyz[3 * x]; sy[threadIdx.x] = xyz[3 * x + 1]; sz[threadIdx.x] = xyz[3 * x + 2];
-      su[threadIdx.x] = U[x]; sq[threadIdx.x] = dq[x];
+      siu[threadIdx.x] = 1.0 / U[x]; sq[threadIdx.x] = dq[x];
     }
     __syncthreads();
-    const int m = min(256, n - base);
+    const int m = min(256, b1 - base);
     if (live && scc) {
       for (int k = 0; k < m; ++k) {
         double gam;
         if (base + k == a) {
-          gam = su[k];
+          gam = ua;
         } else {
           const double dx = xa - sx[k], dy = ya - sy[k], dz = za - sz[k];
-          const double u = 0.5 * (ia + 1.0 / su[k]);
+          const double u = 0.5 * (ia + siu[k]);
           gam = 1.0 / sqrt(dx * dx + dy * dy + dz * dz + u * u);
         }
         s += gam * sq[k];
       }
     }
   }
-  if (live) Q[a] = s;
+  if (live) part[(size_t)blockIdx.y * n + a] = s;
 }
-void launch_coulomb(const View& v, int scc, const double* dq, double* Q, hipStream_t s) {
-  hipLaunchKernelGGL(k_coulomb, dim3(nblk(v.n_atoms, 256)), dim3(256), 0, s, v.n_atoms, scc, v.xyz, v.U, dq, Q);
+__global__ void k_coulomb_sum(int n, const double* part, double* Q) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  double s = 0.0;
+  for (int sp = 0; sp < CL_SPLIT; ++sp) s += part[(size_t)sp * n + a];
+  Q[a] = s;
+}
+void launch_coulomb(const View& v, int scc, const double* dq, double* part, double* Q, hipStream_t s) {
+  hipLaunchKernelGGL(k_coulomb, dim3(nblk(v.n_atoms, 256), CL_SPLIT), dim3(256), 0, s, v.n_atoms, scc, v.xyz, v.U,
+                     dq, part);
+  hipLaunchKernelGGL(k_coulomb_sum, dim3(nblk(v.n_atoms, 256)), dim3(256), 0, s, v.n_atoms, part, Q);
 }
 
 __global__ void k_fock(size_t n, int n_ao, const int* xs_row, const int* xs_col, const int* ao_atom,
