@@ -101,6 +101,10 @@ int orc_fdiag(const orc_t* o, double* out);
 int orc_n_rot(const orc_t* o);
 int orc_rotations(const orc_t* o, int32_t* i, int32_t* a, double* c, double* s);
 
+/* energy gradient at the current MOs (atom-block pattern, layout of S_val):
+ * dx = dE/dH0 (dE/dF with a complete Fock matrix), ds = dE/dS */
+int orc_gradient(orc_t* o, double* dx_val, double* ds_val);
+
 /* the 2x2 rotation of one (occupied i, virtual a) pair from F_ii, F_aa, F_ia */
 void orc_jacobi_angle(double fii, double faa, double fia, double* c, double* s);
 

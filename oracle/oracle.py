@@ -78,6 +78,7 @@ def lib():
         L.orc_energy.argtypes = [ct.c_void_p]
         L.orc_energy.restype = ct.c_double
         L.orc_density.argtypes = [ct.c_void_p, ct.c_void_p]
+        L.orc_gradient.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p]
         L.orc_charges.argtypes = [ct.c_void_p, ct.c_void_p]
         L.orc_nnz_c.argtypes = [ct.c_void_p]
         L.orc_nnz_c.restype = ct.c_int64
@@ -170,6 +171,16 @@ class Oracle:
 
     def energy(self) -> float:
         return lib().orc_energy(self._h)
+
+    def gradient(self):
+        """(dE/dH0, dE/dS) at the current MOs on the atom-block pattern (dE/dF with a complete
+        Fock matrix): P and -W + 1/2 P (Q_a + Q_b), W = 2 C_occ (C_occ^T H C_occ) C_occ^T."""
+        dx = np.zeros(len(self.system.S_val))
+        ds = np.zeros(len(self.system.S_val))
+        rc = lib().orc_gradient(self._h, _p(dx), _p(ds))
+        if rc != 0:
+            raise OracleError(lib().orc_last_error(self._h).decode())
+        return dx, ds
 
     def density(self) -> np.ndarray:
         out = np.zeros(self.system.S_val.shape[0])

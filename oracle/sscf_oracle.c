@@ -765,6 +765,112 @@ static void energy(orc_t* o) {
   o->E = o->e_band + o->e_coul;
 }
 
+/* ----------------------------------------------------------------------------------- */
+/* Energy gradient at the current MOs (differentiation form).                          */
+/* At self-consistency the energy of section 3.7 is stationary in the occupied MOs     */
+/* under C^T S C = 1, and dE/dP = H (the Fock matrix of the current charges).  Hence   */
+/*   dE/dX_uv = P_uv              (X = H0; with a complete Fock matrix, X = F)          */
+/*   dE/dS_uv = -W_uv + 1/2 P_uv (Q_a + Q_b)   (the second term with the charge term)  */
+/* where the first term of dE/dS comes from the orthonormality constraint and the      */
+/* second from the S in the Mulliken charges (eq. pop).  W = 2 C_occ F C_occ^T with    */
+/* F_ij = C_i^T H C_j over every occupied pair of neighbouring groups: the MOs are     */
+/* localized, not canonical, so the whole occupied-occupied block of F enters.  H is   */
+/* not truncated here.  Values on the atom-block pattern (the layout of S_val).        */
+
+int orc_gradient(orc_t* o, double* dx_val, double* ds_val) {
+  const int G = o->n_groups;
+  const int64_t nnz = o->rp[o->n_ao];
+  coulomb_q(o);
+  double* Hg = xcalloc(nnz, sizeof(double));
+  for (int mu = 0; mu < o->n_ao; ++mu) {
+    const double qa = o->Q[o->ao_atom[mu]];
+    for (int64_t k = o->rp[mu]; k < o->rp[mu + 1]; ++k)
+      Hg[k] = o->fock_full ? o->Fuser[k] : o->H0[k] + 0.5 * o->S[k] * (qa + o->Q[o->ao_atom[o->ci[k]]]);
+  }
+  /* F_ij = C_i^T H C_j, i and j occupied in neighbouring groups; block (g, h) as in O */
+  double* F = xcalloc(o->ob_off[o->gn_ptr[G]], sizeof(double));
+#pragma omp parallel
+  {
+    double* y = xcalloc(o->n_ao, sizeof(double));
+    uint8_t* mark = xcalloc(o->n_ao, 1);
+    int32_t* list = xcalloc(o->n_ao, sizeof(int32_t));
+#pragma omp for schedule(dynamic, 4)
+    for (int j = 0; j < o->n_occ; ++j) {
+      const int32_t nt = spmv_col(o, Hg, &o->C[j], y, mark, list);
+      const int h = o->mo_group[j], jl = o->mo_local[j], nh = n_in_group(o, h);
+      for (int k = o->gn_ptr[h]; k < o->gn_ptr[h + 1]; ++k) {
+        const int g = o->gn[k];
+        const int kk = o->gn_pos[(size_t)g * G + h];
+        double* Fgh = F + o->ob_off[o->gn_ptr[g] + kk];
+        for (int il = 0; il < n_in_group(o, g); ++il) {
+          const int i = o->gm[o->gm_ptr[g] + il];
+          if (i >= o->n_occ) break;
+          Fgh[(size_t)il * nh + jl] = col_dot_dense(&o->C[i], y);
+        }
+      }
+      clear_touched(y, mark, list, nt);
+    }
+    free(y); free(mark); free(list);
+  }
+  /* Z_j = sum_i C_i F_ij (dense column per occupied j, kept as rows of Z) */
+  double* Z = xcalloc((size_t)o->n_ao * o->n_occ, sizeof(double));   /* Z[u * n_occ + j] */
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int j = 0; j < o->n_occ; ++j) {
+    const int h = o->mo_group[j], jl = o->mo_local[j], nh = n_in_group(o, h);
+    for (int k = o->gn_ptr[h]; k < o->gn_ptr[h + 1]; ++k) {
+      const int g = o->gn[k];
+      const int kk = o->gn_pos[(size_t)g * G + h];
+      const double* Fgh = F + o->ob_off[o->gn_ptr[g] + kk];
+      for (int il = 0; il < n_in_group(o, g); ++il) {
+        const int i = o->gm[o->gm_ptr[g] + il];
+        if (i >= o->n_occ) break;
+        const double f = Fgh[(size_t)il * nh + jl];
+        for (int32_t t = 0; t < o->C[i].n; ++t) Z[(size_t)o->C[i].row[t] * o->n_occ + j] += o->C[i].val[t] * f;
+      }
+    }
+  }
+  /* W_uv = 2 sum_j C_uj Z_vj on the pattern of S (Z is dense, n_ao x n_occ: this
+   * reference is meant for systems of a few thousand atoms) */
+  double* W = xcalloc(nnz, sizeof(double));
+  {
+    int64_t* rptr = xcalloc(o->n_ao + 1, sizeof(int64_t));
+    for (int j = 0; j < o->n_occ; ++j)
+      for (int32_t t = 0; t < o->C[j].n; ++t) rptr[o->C[j].row[t] + 1]++;
+    for (int mu = 0; mu < o->n_ao; ++mu) rptr[mu + 1] += rptr[mu];
+    int32_t* rmo = xcalloc(rptr[o->n_ao] + 1, sizeof(int32_t));
+    double* rval = xcalloc(rptr[o->n_ao] + 1, sizeof(double));
+    int64_t* fillp = xcalloc(o->n_ao, sizeof(int64_t));
+    for (int j = 0; j < o->n_occ; ++j)
+      for (int32_t t = 0; t < o->C[j].n; ++t) {
+        const int mu = o->C[j].row[t];
+        const int64_t q = rptr[mu] + fillp[mu]++;
+        rmo[q] = j; rval[q] = o->C[j].val[t];
+      }
+    free(fillp);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int mu = 0; mu < o->n_ao; ++mu)
+      for (int64_t k = o->rp[mu]; k < o->rp[mu + 1]; ++k) {
+        const double* zr = Z + (size_t)o->ci[k] * o->n_occ;
+        double s = 0.0;
+        for (int64_t t = rptr[mu]; t < rptr[mu + 1]; ++t) s += rval[t] * zr[rmo[t]];
+        W[k] = 2.0 * s;
+      }
+    free(rptr); free(rmo); free(rval);
+  }
+  memset(dx_val, 0, sizeof(double) * o->nblkval);
+  memset(ds_val, 0, sizeof(double) * o->nblkval);
+  for (int mu = 0; mu < o->n_ao; ++mu) {
+    const double qa = o->Q[o->ao_atom[mu]];
+    for (int64_t k = o->rp[mu]; k < o->rp[mu + 1]; ++k) {
+      const double qb = o->Q[o->ao_atom[o->ci[k]]];
+      dx_val[o->ao2blk[k]] = o->P[k];
+      ds_val[o->ao2blk[k]] = -W[k] + (o->fock_full ? 0.0 : 0.5 * o->P[k] * (qa + qb));
+    }
+  }
+  free(Hg); free(F); free(Z); free(W);
+  return ORC_OK;
+}
+
 static int64_t nnz_c(const orc_t* o) {
   int64_t n = 0;
   for (int j = 0; j < o->n_mo; ++j) n += o->C[j].n;
