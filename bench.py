@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel HIP events")
+    ap.add_argument("--gradient", action="store_true",
+                    help="after the timed steps, time one energy-gradient evaluation (dE/dH0, dE/dS)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="before the SCF, copy a buffer of this size three times: a kernel of known "
                          "traffic against which hardware byte counters are scaled")
@@ -157,6 +159,16 @@ def main():
                             traffic=measured_traffic(name, args.config, args.precision),
                             traffic_unit="GB per launch",
                             avg_launch_ms=round(per_launch_ms, 4), launches=st["launches"])
+    grad = None
+    if args.gradient:
+        g.energy_gradient()                     # first call allocates its buffers
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        gx, gs = g.energy_gradient()
+        grad = dict(ms=round(1e3 * (time.perf_counter() - t), 3), n_val=int(gx.shape[0]),
+                    includes="device kernels (untruncated Fock, H C, occupied-occupied pair blocks, "
+                             "C_occ F, P and W on the pattern) + device-to-host copy of P and W + host assembly")
+        log(f"[bench] gradient {grad}")
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle) ...")
@@ -185,6 +197,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if grad is not None:
+        out["gradient"] = grad
     if kstats is not None:
         out["kernels"] = {k: dict(launches=v["launches"], ms=round(v["ms"], 3),
                                   tflops=round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 3),

@@ -159,6 +159,21 @@ sscf_status sscf_get_energy(const sscf_ctx* ctx, double* e_total);
  * caller's host buffer p_val of n_val >= desc.n_val doubles (layout of S_val). */
 sscf_status sscf_get_density(const sscf_ctx* ctx, double* p_val, size_t n_val);
 
+/* Energy gradient at the current MOs (differentiation form).  The energy of
+ * section 3.7 is stationary in the orthonormal occupied MOs at self-consistency,
+ * so with the Fock matrix H = H0 + 1/2 S (Q_a + Q_b) of the current charges (not
+ * truncated; H = F after sscf_set_fock(SSCF_FOCK_FULL)):
+ *   dE_dX = dE/dH0 (dE/dF in complete-Fock mode) = P = 2 C_occ C_occ^T,
+ *   dE_dS = dE/dS = -W + 1/2 P (Q_a + Q_b)   (charge term with H0 and SCC only),
+ *   W = 2 C_occ (C_occ^T H C_occ) C_occ^T over neighbouring groups (the MOs are
+ *   localized, not canonical: the whole occupied-occupied block enters).
+ * Each value is the derivative with respect to that stored entry, in the layout of
+ * S_val; both are caller-owned host buffers of n_val >= desc.n_val doubles.  The
+ * values are derivatives of E once the SCF has converged (|dE| and the
+ * occupied-virtual coupling small); before that they are the same expressions at
+ * the current MOs.  SSCF_E_INVALID_ARG for NULL buffers or a short n_val. */
+sscf_status sscf_get_energy_gradient(sscf_ctx* ctx, double* dE_dX, double* dE_dS, size_t n_val);
+
 /* Mulliken populations q_a (section 3.7, eq. pop) into q[n_atoms] (host). */
 sscf_status sscf_get_charges(const sscf_ctx* ctx, double* q, size_t n);
 

@@ -121,7 +121,10 @@ struct sscf_ctx {
   double* sc = nullptr;
   uint8_t *upd = nullptr, *pair_sel = nullptr;
   unsigned int* fmask = nullptr;
-  double* part = nullptr;               // partial sums of the split reductions (coldot, coulomb)        // per pair: nonzero-fragment masks of D_sel and its transpose
+  double* part = nullptr;               // partial sums of the split reductions (coldot, coulomb)
+  // energy gradient (allocated on first use)
+  double *foo_a = nullptr, *foo_b = nullptr, *wblk = nullptr, *wval = nullptr;
+  uint8_t* pair_all = nullptr;        // per pair: nonzero-fragment masks of D_sel and its transpose
   int *jb_g = nullptr, *jb_h = nullptr, *jb_nocc = nullptr, *jb_nvirt = nullptr, *round_list = nullptr;
   double *F = nullptr, *Fdiag = nullptr, *dvec = nullptr;
   int *rot_cnt = nullptr, *tcnt = nullptr, *tcol = nullptr, *round_ptr = nullptr;
@@ -979,10 +982,64 @@ sscf_status sscf_get_density(const sscf_ctx* cx, double* p_val, size_t n_val) {
   return guarded(x, [&] {
     if (!x->pblk) x->pblk = x->dalloc<double>((size_t)x->v.nbx * 256);
     if (!x->pval) x->pval = x->dalloc<double>(x->n_val);
-    launch_density_blocks(x->v, x->C[x->cur], x->actC[x->cur], x->pnocc, x->pblk, x->stream);
+    launch_density_blocks(x->v, x->C[x->cur], x->actC[x->cur], x->C[x->cur], x->actC[x->cur], x->pblk, x->stream);
     launch_gather(x->val_map, x->n_val, x->pblk, x->pval, x->stream);
     HIPC(hipMemcpyAsync(p_val, x->pval, sizeof(double) * x->n_val, hipMemcpyDeviceToHost, x->stream));
     x->sync();
+  });
+}
+
+sscf_status sscf_get_energy_gradient(sscf_ctx* x, double* dE_dX, double* dE_dS, size_t n_val) {
+  if (!x || !dE_dX || !dE_dS || n_val < (size_t)x->n_val) return SSCF_E_INVALID_ARG;
+  return guarded(x, [&] {
+    const View& v = x->v;
+    hipStream_t s = x->stream;
+    const size_t fo = (size_t)v.OW * v.OW;
+    if (!x->foo_a) {
+      x->foo_a = x->dalloc<double>((size_t)x->n_pairs * fo);
+      x->foo_b = x->dalloc<double>((size_t)x->n_pairs * fo);
+      x->wblk = x->dalloc<double>((size_t)v.nbx * 256);
+      x->wval = x->dalloc<double>(x->n_val);
+      x->pair_all = x->dalloc<uint8_t>(x->n_pairs);
+      launch_fill_u8(x->pair_all, x->n_pairs, 1, s);
+    }
+    if (!x->pblk) x->pblk = x->dalloc<double>((size_t)v.nbx * 256);
+    if (!x->pval) x->pval = x->dalloc<double>(x->n_val);
+    // the Fock matrix of the current charges, not truncated, and Y = H C
+    launch_fock(v, x->S, x->H0, x->fock_full ? x->Hfull : nullptr, x->Q, 0.0, x->H, nullptr, s);
+    x->product(x->H, true);
+    // occupied-occupied blocks C_g^T H C_h of every neighbouring pair, in both orientations
+    const int no = v.OW / 16;
+    launch_pair(v, x->n_pairs, x->pair_perm, x->pair_maxc, x->pg, x->ph, x->C[x->cur], x->listC[x->cur],
+                x->cntC[x->cur], x->cmask[x->cur], x->Y, x->actY, x->ymask, 0, no, 0, no, x->foo_a, v.OW, fo,
+                nullptr, s);
+    launch_pair(v, x->n_pairs, x->pair_perm, x->pair_maxc, x->ph, x->pg, x->C[x->cur], x->listC[x->cur],
+                x->cntC[x->cur], x->cmask[x->cur], x->Y, x->actY, x->ymask, 0, no, 0, no, x->foo_b, v.OW, fo,
+                nullptr, s);
+    // Z = C_occ F on the row blocks where a neighbouring group is active (Z overwrites Y)
+    launch_update_support(v, x->actC[x->cur], x->gn_ptr, x->gn, x->pair_of, x->pair_all, x->act_tmp, s);
+    launch_list(v, x->act_tmp, x->list_tmp, x->cnt_tmp, s);
+    launch_apply_occ(v, x->C[x->cur], x->actC[x->cur], x->gn_ptr, x->gn, x->pair_of, x->pg, x->foo_a, x->foo_b,
+                     x->list_tmp, x->cnt_tmp, x->Y, s);
+    // P = 2 C_occ C_occ^T and W = 2 C_occ Z^T on the pattern of S
+    launch_density_blocks(v, x->C[x->cur], x->actC[x->cur], x->C[x->cur], x->actC[x->cur], x->pblk, s);
+    launch_density_blocks(v, x->C[x->cur], x->actC[x->cur], x->Y, x->act_tmp, x->wblk, s);
+    launch_gather(x->val_map, x->n_val, x->pblk, x->pval, s);
+    launch_gather(x->val_map, x->n_val, x->wblk, x->wval, s);
+    std::vector<double> w(x->n_val), q(v.n_atoms);
+    HIPC(hipMemcpyAsync(dE_dX, x->pval, sizeof(double) * x->n_val, hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(w.data(), x->wval, sizeof(double) * x->n_val, hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(q.data(), x->Q, sizeof(double) * v.n_atoms, hipMemcpyDeviceToHost, s));
+    x->sync();
+    // dE/dS = -W + 1/2 P (Q_a + Q_b); the charge term only with H0 (the Mulliken charges' S)
+    const bool qterm = x->scc && !x->fock_full;
+    for (int a = 0; a < v.n_atoms; ++a)
+      for (int64_t k = x->h_blk_rowptr[a]; k < x->h_blk_rowptr[a + 1]; ++k) {
+        const int b = x->h_blk_col[k];
+        const int64_t n = (int64_t)x->h_atom_nao[a] * x->h_atom_nao[b];
+        const double qs = qterm ? 0.5 * (q[a] + q[b]) : 0.0;
+        for (int64_t e = x->h_blk_off[k]; e < x->h_blk_off[k] + n; ++e) dE_dS[e] = -w[e] + dE_dX[e] * qs;
+      }
   });
 }
 

@@ -146,8 +146,11 @@ void launch_atom_charges(const View& v, const int64_t* ao_off, const double* row
 void launch_sum_band(const View& v, const double* d, const int* pnocc, Scalars* sd, hipStream_t s);
 void launch_sum_coul(const View& v, int scc, const double* dq, const double* Q, Scalars* sd,
                      hipStream_t s);
-void launch_density_blocks(const View& v, const double* C, const uint8_t* actC, const int* pnocc,
-                           double* P, hipStream_t s);
+void launch_density_blocks(const View& v, const double* A, const uint8_t* actA, const double* B,
+                           const uint8_t* actB, double* P, hipStream_t s);
+void launch_apply_occ(const View& v, const double* C, const uint8_t* actC, const int* gn_ptr, const int* gn,
+                      const int* pair_of, const int* pg, const double* FA, const double* FB, const int* listZ,
+                      const int* cntZ, double* Z, hipStream_t s);
 void launch_gather(const int64_t* map, int64_t n, const double* src, double* dst, hipStream_t s);
 void launch_scatter(const int64_t* map, int64_t n, const double* src, double* dst, hipStream_t s);
 

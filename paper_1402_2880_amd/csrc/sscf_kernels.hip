@@ -1368,8 +1368,8 @@ void launch_sum_coul(const View& v, int scc, const double* dq, const double* Q, 
 // ---------------------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(256) k_density_blocks(int nbx, int G, int n_rb, int W, int OW, const int* xs_row,
-                                                        const int* xs_col, const double* C, const uint8_t* actC,
-                                                        double* P) {
+                                                        const int* xs_col, const double* A, const uint8_t* actA,
+                                                        const double* B, const uint8_t* actB, double* P) {
   const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (b >= nbx) return;
   const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
@@ -1377,17 +1377,78 @@ __global__ void __launch_bounds__(256) k_density_blocks(int nbx, int G, int n_rb
   d4 acc = d4{0.0, 0.0, 0.0, 0.0};
   for (int g = 0; g < G; ++g) {
     const size_t tr = (size_t)g * n_rb + r, tc = (size_t)g * n_rb + c;
-    if (!actC[tr] || !actC[tc]) continue;
-    const double* A = C + tr * (RB * W);
-    const double* B = C + tc * (RB * W);
-    for (int s = 0; s < OW / 4; ++s) acc = mfma64(A[lr * W + 4 * s + lk], B[lr * W + 4 * s + lk], acc);
+    if (!actA[tr] || !actB[tc]) continue;
+    const double* At = A + tr * (RB * W);
+    const double* Bt = B + tc * (RB * W);
+    for (int s = 0; s < OW / 4; ++s) acc = mfma64(At[lr * W + 4 * s + lk], Bt[lr * W + 4 * s + lk], acc);
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) P[(size_t)b * 256 + (lk + 4 * q) * 16 + lr] = 2.0 * acc[q];
 }
-void launch_density_blocks(const View& v, const double* C, const uint8_t* actC, const int*, double* P, hipStream_t s) {
+// 2 A_occ B_occ^T on the 16 x 16 blocks of the S pattern: the density P (A = B = C) or
+// W = 2 C_occ Z_occ^T (B = Z) of the energy gradient
+void launch_density_blocks(const View& v, const double* A, const uint8_t* actA, const double* B, const uint8_t* actB,
+                           double* P, hipStream_t s) {
   hipLaunchKernelGGL(k_density_blocks, dim3((v.nbx + 3) / 4), dim3(256), 0, s, v.nbx, v.G, v.n_rb, v.W, v.OW,
-                     v.xs_row, v.xs_col, C, actC, P);
+                     v.xs_row, v.xs_col, A, actA, B, actB, P);
+}
+
+// ---------------------------------------------------------------------------------------
+// Energy gradient (differentiation form): Z_g[r] = sum_{h ~ g} C_h,occ[r] F(h, g) with
+// F(h, g) = C_h,occ^T H C_g,occ (OW x OW; FA holds the blocks with rows = MOs of pg[p],
+// FB those with rows = MOs of ph[p]).  One wave per output tile, occupied columns only.
+// ---------------------------------------------------------------------------------------
+template <int NO>
+__global__ void __launch_bounds__(256) k_apply_occ(int G, int n_rb, int W, int nchunk, const double* __restrict__ C,
+                                                   const uint8_t* __restrict__ actC, const int* __restrict__ gn_ptr,
+                                                   const int* __restrict__ gn, const int* __restrict__ pair_of,
+                                                   const int* __restrict__ pg, const double* __restrict__ FA,
+                                                   const double* __restrict__ FB, const int* __restrict__ listZ,
+                                                   const int* __restrict__ cntZ, double* __restrict__ Z) {
+  constexpr int OW = NO * 16;
+  int chunk;
+  const int g = xcd_group_chunk(nchunk, chunk);
+  if (g >= G) return;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int t = chunk * 4 + wv;
+  if (t >= cntZ[g]) return;
+  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+  const int r = listZ[(size_t)g * n_rb + t];
+  d4 acc[NO];
+#pragma unroll
+  for (int n = 0; n < NO; ++n) acc[n] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int k = gn_ptr[g]; k < gn_ptr[g + 1]; ++k) {
+    const int h = gn[k];
+    const size_t th = (size_t)h * n_rb + r;
+    if (!actC[th]) continue;
+    const int p = pair_of[(size_t)g * G + h];
+    const double* Fp = ((pg[p] == h) ? FA : FB) + (size_t)p * OW * OW + lr;
+    const double* Ch = C + th * (RB * W) + lr * W + lk;
+#pragma unroll 4
+    for (int s = 0; s < OW / 4; ++s) {
+      const double a = Ch[4 * s];
+#pragma unroll
+      for (int n = 0; n < NO; ++n) acc[n] = mfma64(a, Fp[(4 * s + lk) * OW + n * 16], acc[n]);
+    }
+  }
+  double* Zt = Z + ((size_t)g * n_rb + r) * (RB * W);
+#pragma unroll
+  for (int n = 0; n < NO; ++n)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Zt[(lk + 4 * q) * W + n * 16 + lr] = acc[n][q];
+}
+
+void launch_apply_occ(const View& v, const double* C, const uint8_t* actC, const int* gn_ptr, const int* gn,
+                      const int* pair_of, const int* pg, const double* FA, const double* FB, const int* listZ,
+                      const int* cntZ, double* Z, hipStream_t s) {
+  const int nchunk = (v.n_rb + 3) / 4;
+  dim3 grid(xcd_grid(v.G, nchunk)), blk(256);
+  switch (v.OW / 16) {
+#define SSCF_APO(NO) case NO: hipLaunchKernelGGL(k_apply_occ<NO>, grid, blk, 0, s, v.G, v.n_rb, v.W, nchunk, C, actC, gn_ptr, gn, pair_of, pg, FA, FB, listZ, cntZ, Z); break;
+    SSCF_APO(1) SSCF_APO(2) SSCF_APO(3) SSCF_APO(4) SSCF_APO(5) SSCF_APO(6) SSCF_APO(7) SSCF_APO(8)
+#undef SSCF_APO
+    default: break;
+  }
 }
 
 // ---------------------------------------------------------------------------------------

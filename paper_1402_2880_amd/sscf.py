@@ -8,6 +8,7 @@ module's entry points raises.
 from __future__ import annotations
 
 import ctypes as ct
+import dataclasses
 import os
 from typing import Dict, Optional
 
@@ -70,7 +71,7 @@ class KernelStat(ct.Structure):
 
 EXPORTS = ["sscf_get_kernel_stats", "sscf_reset_kernel_stats", "sscf_init_system", "sscf_set_fock", "sscf_scf_step", "sscf_get_energy",
            "sscf_get_density", "sscf_get_charges", "sscf_get_mo_coefficients", "sscf_init_info",
-           "sscf_get_schedule", "sscf_destroy", "sscf_last_error"]
+           "sscf_get_schedule", "sscf_get_energy_gradient", "sscf_destroy", "sscf_last_error"]
 
 _lib = None
 
@@ -89,6 +90,7 @@ def lib():
         L.sscf_scf_step.argtypes = [vp, ct.POINTER(StepInfo)]
         L.sscf_get_energy.argtypes = [vp, ct.POINTER(ct.c_double)]
         L.sscf_get_density.argtypes = [vp, vp, sz]
+        L.sscf_get_energy_gradient.argtypes = [vp, vp, vp, sz]
         L.sscf_get_charges.argtypes = [vp, vp, sz]
         L.sscf_get_mo_coefficients.argtypes = [vp, vp, vp, vp, ct.POINTER(i64)]
         L.sscf_init_info.argtypes = [vp, ct.POINTER(StepInfo)]
@@ -225,6 +227,14 @@ class SparseSCF:
         self._check(lib().sscf_get_density(self._h, _p(out), out.shape[0]))
         return out
 
+    def energy_gradient(self):
+        """(dE/dH0, dE/dS) at the current MOs on the atom-block pattern (dE/dF in complete-Fock
+        mode): P and -W + 1/2 P (Q_a + Q_b).  Derivatives of E once the SCF has converged."""
+        gx = np.zeros(self.system.S_val.shape[0])
+        gs = np.zeros(self.system.S_val.shape[0])
+        self._check(lib().sscf_get_energy_gradient(self._h, _p(gx), _p(gs), gx.shape[0]))
+        return gx, gs
+
     def charges(self) -> np.ndarray:
         out = np.zeros(self.system.n_atoms)
         self._check(lib().sscf_get_charges(self._h, _p(out), out.shape[0]))
@@ -264,3 +274,48 @@ class SparseSCF:
         r = np.zeros_like(g)
         self._check(lib().sscf_get_schedule(self._h, _p(g), _p(h), _p(r), ct.byref(n)))
         return g[:n.value], h[:n.value], r[:n.value]
+
+
+def _torch_function():
+    import torch
+
+    class SCFEnergy(torch.autograd.Function):
+        """Self-consistent energy E(H0_val, S_val) of the sparse SCF, differentiable.
+
+        forward runs the library to convergence from the system's initial guess and evaluates
+        dE/dH0 = P and dE/dS = -W + 1/2 P (Q_a + Q_b) once there; only these two vectors are
+        kept for backward (no MO state).  Inputs are float64 tensors in the layout of S_val.
+        """
+
+        @staticmethod
+        def forward(ctx, H0_val, S_val, system, opts):
+            s = dataclasses.replace(system, H0_val=H0_val.detach().cpu().double().numpy().copy(),
+                                    S_val=S_val.detach().cpu().double().numpy().copy())
+            g = SparseSCF(s, **opts.get("scf", {}))
+            fov_tol = opts.get("fov_tol", 0.0)
+            try:
+                for _ in range(opts.get("max_steps", 200)):
+                    info = g.step()
+                    if info["converged"] and (fov_tol <= 0.0 or info["max_abs_fov"] < fov_tol):
+                        break
+                else:
+                    raise RuntimeError("sparse SCF did not converge within max_steps")
+                E = g.energy()
+                gx, gs = g.energy_gradient()
+            finally:
+                g.close()
+            ctx.save_for_backward(torch.from_numpy(gx).to(H0_val.device), torch.from_numpy(gs).to(S_val.device))
+            return torch.tensor(E, dtype=torch.float64, device=H0_val.device)
+
+        @staticmethod
+        def backward(ctx, gE):
+            gx, gs = ctx.saved_tensors
+            return gE * gx, gE * gs, None, None
+
+    return SCFEnergy
+
+
+def scf_energy(system, H0_val, S_val, max_steps: int = 200, fov_tol: float = 0.0, **scf_kw):
+    """Differentiable self-consistent energy (torch float64 scalar) for H0_val and S_val tensors."""
+    return _torch_function().apply(H0_val, S_val, system,
+                                   dict(max_steps=max_steps, fov_tol=fov_tol, scf=scf_kw))
