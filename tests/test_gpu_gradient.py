@@ -135,3 +135,43 @@ def test_autograd_function():
     E2 = scf_energy(s, H0b, torch.tensor(s.S_val, dtype=torch.float64), **kw)
     (2.0 * E2 ** 2).backward()
     assert np.abs(H0b.grad.numpy() - 4.0 * E2.item() * gx).max() < 1e-8 * abs(E2.item())
+
+
+def test_onsite_gradient_water512_finite_differences():
+    """32 seeded onsite parameters (one atom's shell each) of the 512-molecule box:
+    dE/d(eps_shell) = sum of P over the shell's diagonal, against central differences of
+    re-converged energies (every group pair a neighbour pair, tight thresholds)."""
+    s = synth.make_config("water512", 1)
+    kw = dict(eps=1e-11, e_conv=1e-12, group_nbr_bohr=1e6)
+    g = gpu(s, **kw)
+    run(g, fov_tol=1e-9)
+    gx, _ = g.energy_gradient()
+    g.close()
+    rng = np.random.default_rng(512)
+    aoo = s.ao_offset()
+    n = s.n_ao
+    diag = np.full(n, -1, dtype=np.int64)          # value index of each AO's diagonal entry
+    for a in range(s.n_atoms):
+        k = s.blk_rowptr[a] + np.searchsorted(s.blk_col[s.blk_rowptr[a]:s.blk_rowptr[a + 1]], a)
+        na = s.atom_nao[a]
+        for i in range(na):
+            diag[aoo[a] + i] = s.blk_off[k] + i * na + i
+    atoms = rng.choice(s.n_atoms, size=32, replace=False)
+    h = 1e-5
+    worst = 0.0
+    for a in atoms:
+        shell = [aoo[a]] if (s.atom_nao[a] == 1 or rng.random() < 0.5) else list(range(aoo[a] + 1, aoo[a] + 4))
+        idx = diag[shell]
+        ana = float(gx[idx].sum())
+        vals = []
+        for sign in (1, -1):
+            H0 = s.H0_val.copy()
+            H0[idx] += sign * h
+            gg = gpu(dataclasses.replace(s, H0_val=H0), **kw)
+            run(gg, fov_tol=1e-9)
+            vals.append(gg.energy())
+            gg.close()
+        num = (vals[0] - vals[1]) / (2 * h)
+        worst = max(worst, abs(num - ana))
+        assert abs(num - ana) < 1e-7, (int(a), shell, num, ana)
+    print(f"[gradient] water512 onsite FD: 32 parameters, max |FD - analytic| {worst:.2e}", flush=True)
