@@ -79,6 +79,15 @@ int orc_step(orc_t* o, orc_step_info* info);
  * mode 0: new H0 (charge term still added); mode 1: complete Fock, no charge term */
 int orc_set_fock(orc_t* o, const double* f_val, int32_t mode);
 
+/* thresholds and schedule from the next step on (section 4.1): sparse threshold eps;
+ * convergence criterion 0 = |dE| < e_conv, 1 = dq_max < dq_conv (the paper's);
+ * step_ortho 1 = step III after every step, 0 = only at set-up and after convergence
+ * (the order in which section 2 lists the steps) */
+int orc_set_control(orc_t* o, double eps, double e_conv, double dq_conv, int32_t criterion, int32_t step_ortho);
+
+/* step III on demand: all MOs (only_occ = 0) or the occupied ones; then charges, energy */
+int orc_orthonormalize(orc_t* o, int32_t only_occ, orc_step_info* info);
+
 /* set-up summary: orthonormalization sweeps, final eta, energy */
 int orc_init_info(const orc_t* o, orc_step_info* info);
 

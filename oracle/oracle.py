@@ -79,6 +79,8 @@ def lib():
         L.orc_energy.restype = ct.c_double
         L.orc_density.argtypes = [ct.c_void_p, ct.c_void_p]
         L.orc_gradient.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p]
+        L.orc_orthonormalize.argtypes = [ct.c_void_p, ct.c_int32, ct.c_void_p]
+        L.orc_set_control.argtypes = [ct.c_void_p, ct.c_double, ct.c_double, ct.c_double, ct.c_int32, ct.c_int32]
         L.orc_charges.argtypes = [ct.c_void_p, ct.c_void_p]
         L.orc_nnz_c.argtypes = [ct.c_void_p]
         L.orc_nnz_c.restype = ct.c_int64
@@ -163,6 +165,14 @@ class Oracle:
             raise OracleError(f"orc_step failed ({rc}): {lib().orc_last_error(self._h).decode()}")
         return si.as_dict()
 
+    def orthonormalize(self, occ_only: bool = False) -> Dict:
+        """Step III on demand (all MOs, or the occupied ones), then charges and energy."""
+        si = StepInfo()
+        rc = lib().orc_orthonormalize(self._h, 1 if occ_only else 0, ct.byref(si))
+        if rc != 0:
+            raise OracleError(lib().orc_last_error(self._h).decode())
+        return si.as_dict()
+
     def set_fock(self, f_val: np.ndarray, mode: int) -> None:
         f = np.ascontiguousarray(f_val, dtype=np.float64)
         rc = lib().orc_set_fock(self._h, _p(f), mode)
@@ -171,6 +181,13 @@ class Oracle:
 
     def energy(self) -> float:
         return lib().orc_energy(self._h)
+
+    def set_control(self, eps: float, e_conv: float = 0.0, dq_conv: float = 0.0, criterion: int = 0,
+                    step_ortho: int = 1) -> None:
+        """Thresholds and schedule from the next step on (see orc_set_control)."""
+        rc = lib().orc_set_control(self._h, eps, e_conv, dq_conv, criterion, step_ortho)
+        if rc != 0:
+            raise OracleError(lib().orc_last_error(self._h).decode())
 
     def gradient(self):
         """(dE/dH0, dE/dS) at the current MOs on the atom-block pattern (dE/dF with a complete

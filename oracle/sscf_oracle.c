@@ -58,6 +58,9 @@ typedef struct {
 
 struct orc {
   double eps, e_conv, r_nbr, rot_cap_factor;
+  double dq_conv;       /* dq_max criterion (section 4.1)                           */
+  int criterion;        /* 0: |dE| < e_conv; 1: dq_max < dq_conv                     */
+  int step_ortho;       /* 1: step III after every step; 0: at set-up and after convergence */
   int max_sweeps_init, max_sweeps_step, scc, fock_full;
   int n_atoms, n_ao, n_mo, n_occ, n_groups;
   int32_t* atom_nao;
@@ -905,6 +908,7 @@ int orc_create(const orc_desc* d, orc_t** out) {
 #endif
   orc_t* o = calloc(1, sizeof(orc_t));
   *out = o;
+  o->criterion = 0; o->step_ortho = 1; o->dq_conv = 0.0;
   o->eps = d->eps; o->e_conv = d->e_conv; o->r_nbr = d->r_nbr_bohr; o->rot_cap_factor = d->rot_cap_factor;
   o->max_sweeps_init = d->max_sweeps_init; o->max_sweeps_step = d->max_sweeps_step; o->scc = d->scc;
   o->n_atoms = d->n_atoms; o->n_mo = d->n_mo; o->n_occ = d->n_occ; o->n_groups = d->n_groups;
@@ -1045,10 +1049,12 @@ int orc_step(orc_t* o, orc_step_info* info) {
   t2 = now_s(); s.t_select = t2 - t; t = t2;
   apply_rotations(o);
   t2 = now_s(); s.t_rotate = t2 - t; t = t2;
-  int sweeps = 0, conv = 0;
+  int sweeps = 0, conv = 0, rc = ORC_OK;
   double eta = 0.0;
-  int rc = orthonormalize(o, 0, o->max_sweeps_step, &sweeps, &eta, &conv);  /* step III */
-  if (rc != ORC_OK) return rc;
+  if (o->step_ortho) {
+    rc = orthonormalize(o, 0, o->max_sweeps_step, &sweeps, &eta, &conv);  /* step III */
+    if (rc != ORC_OK) return rc;
+  }
   s.n_ortho_sweeps = sweeps; s.ortho_eta = eta; s.ortho_converged = conv;
   t2 = now_s(); s.t_ortho = t2 - t; t = t2;
   memcpy(o->q_prev, o->q, o->n_atoms * sizeof(double));
@@ -1059,7 +1065,7 @@ int orc_step(orc_t* o, orc_step_info* info) {
   t2 = now_s(); s.t_charges = t2 - t; t = t2;
   energy(o);
   s.delta_e = o->E - E_prev;
-  s.converged = fabs(s.delta_e) < o->e_conv;
+  s.converged = o->criterion ? (dqm < o->dq_conv) : (fabs(s.delta_e) < o->e_conv);
   if (s.converged) {
     /* occupied-only orthonormalization after convergence (section 4.1) */
     int sw2 = 0, cv2 = 0;
@@ -1073,6 +1079,33 @@ int orc_step(orc_t* o, orc_step_info* info) {
   t2 = now_s(); s.t_energy = t2 - t;
   s.energy = o->E; s.e_band = o->e_band; s.e_coul = o->e_coul;
   s.nnz_c = nnz_c(o);
+  if (info) *info = s;
+  return ORC_OK;
+}
+
+int orc_set_control(orc_t* o, double eps, double e_conv, double dq_conv, int32_t criterion, int32_t step_ortho) {
+  if (!(eps >= 0.0) || !isfinite(eps) || !(e_conv >= 0.0) || !(dq_conv >= 0.0) || (criterion != 0 && criterion != 1) ||
+      (step_ortho != 0 && step_ortho != 1))
+    return fail(o, ORC_E_ARG, "bad control values");
+  o->eps = eps; o->e_conv = e_conv; o->dq_conv = dq_conv; o->criterion = criterion; o->step_ortho = step_ortho;
+  return ORC_OK;
+}
+
+/* step III on demand (section 2): all MOs (restart from improved MOs, e.g. between the
+ * loose and the user thresholds of section 4.1) or the occupied ones only; then charges
+ * and energy.  Up to max_sweeps_init sweeps; not reaching eps/100 is an error. */
+int orc_orthonormalize(orc_t* o, int32_t only_occ, orc_step_info* info) {
+  orc_step_info s;
+  memset(&s, 0, sizeof(s));
+  int sweeps = 0, conv = 0;
+  double eta = 0.0;
+  int rc = orthonormalize(o, only_occ ? 1 : 0, o->max_sweeps_init, &sweeps, &eta, &conv);
+  if (rc != ORC_OK) return rc;
+  if (!conv) return fail(o, ORC_E_ORTHO, "orthonormalization did not converge");
+  density_charges(o);
+  energy(o);
+  s.energy = o->E; s.e_band = o->e_band; s.e_coul = o->e_coul;
+  s.n_ortho_sweeps = sweeps; s.ortho_eta = eta; s.ortho_converged = conv; s.nnz_c = nnz_c(o);
   if (info) *info = s;
   return ORC_OK;
 }
