@@ -52,6 +52,23 @@ enum { SSCF_FOCK_H0 = 0, SSCF_FOCK_FULL = 1 };
 /* bits of sscf_system_desc.flags */
 enum { SSCF_FLAG_PROFILE = 1 };  /* time kernel classes with HIP events; count their work */
 
+/* Convergence criterion of sscf_control (section 4.1 uses the charge criterion). */
+enum { SSCF_CONV_ENERGY = 0, SSCF_CONV_CHARGE = 1 };
+
+/* Thresholds and schedule, changeable between steps (sscf_set_control).  The values
+ * at sscf_init_system are eps and e_conv of the descriptor, SSCF_CONV_ENERGY,
+ * dq_conv = 0 and step_ortho = 1. */
+typedef struct {
+  double eps;          /* sparse threshold: H and C cut at eps, Jacobi threshold eps,
+                          orthonormalization cut 1e-3 eps and tolerance eps/100 (sec. 4.1) */
+  double e_conv;       /* converged when |E(n) - E(n-1)| < e_conv (SSCF_CONV_ENERGY), Ha  */
+  double dq_conv;      /* converged when max_a |q_a(n) - q_a(n-1)| < dq_conv (SSCF_CONV_CHARGE) */
+  int32_t criterion;   /* SSCF_CONV_ENERGY or SSCF_CONV_CHARGE                           */
+  int32_t step_ortho;  /* 1: step III after every step; 0: only at set-up, after
+                          convergence (occupied MOs) and on sscf_orthonormalize, the
+                          order in which section 2 lists the steps                      */
+} sscf_control;
+
 #define SSCF_N_KERNEL_CLASSES 7
 
 typedef struct sscf_ctx sscf_ctx; /* opaque, owned by the library */
@@ -143,6 +160,18 @@ sscf_status sscf_init_system(const sscf_system_desc* desc, sscf_ctx** out);
  *                      and the energy becomes sum_uv P_uv F_uv.
  * Errors: SSCF_E_INVALID_ARG (NULL, bad mode, NaN/Inf, not symmetric). */
 sscf_status sscf_set_fock(sscf_ctx* ctx, const double* f_val, int32_t mode);
+
+/* Thresholds, criterion and schedule for the following steps (section 4.1; the
+ * loose-then-tight run of that section is: loose values, steps until converged,
+ * user values, sscf_orthonormalize(ctx, 0, ...), steps).  SSCF_E_INVALID_ARG for
+ * negative or non-finite thresholds or unknown criterion / step_ortho values. */
+sscf_status sscf_set_control(sscf_ctx* ctx, const sscf_control* c);
+sscf_status sscf_get_control(const sscf_ctx* ctx, sscf_control* c);
+
+/* Step III on demand (section 3.4): all MOs (occ_only = 0) or the occupied ones,
+ * until eta < eps/100 within the set-up sweep cap, then charges and energy (info
+ * may be NULL).  SSCF_E_ORTHO if the cap is reached, SSCF_E_NOT_SPD as at set-up. */
+sscf_status sscf_orthonormalize(sscf_ctx* ctx, int32_t occ_only, sscf_step_info* info);
 
 /* One SCF step (section 2, steps IV and V, then step III): Fock build with the
  * charges of the previous step, C^T H C on neighbouring groups, selection and

@@ -71,6 +71,8 @@ const double KC_BYTE_PER_UNIT[SSCF_N_KERNEL_CLASSES] = {0.0, 0.0, 0.0, 0.0, 1.0,
 struct sscf_ctx {
   // parameters
   double eps = 0, e_conv = 0, r_nbr = 0, rot_cap = 0;
+  double dq_conv = 0;                   // charge criterion (section 4.1)
+  int criterion = SSCF_CONV_ENERGY, step_ortho = 1;
   int max_sweeps_init = 0, max_sweeps_step = 0, scc = 1, precision = 0;
   int fock_full = 0;
   hipStream_t stream = nullptr;
@@ -827,7 +829,13 @@ static void step(sscf_ctx* x, sscf_step_info* out) {
   // step III: re-orthonormalization
   double eta = 0.0;
   int conv = 0;
-  info.n_ortho_sweeps = x->orthonormalize(0, x->max_sweeps_step, &eta, &conv);
+  if (x->step_ortho) {
+    info.n_ortho_sweeps = x->orthonormalize(0, x->max_sweeps_step, &eta, &conv);
+  } else {
+    // no step III: the charges take S C of the rotated MOs as they are
+    x->product(x->S, true);
+    launch_fill(x->sc, (size_t)v.G * v.W, 1.0, s);
+  }
   info.ortho_eta = eta;
   info.ortho_converged = conv;
   HIPC(hipEventRecord(x->ev[5], s));
@@ -843,7 +851,8 @@ static void step(sscf_ctx* x, sscf_step_info* out) {
   info.n_candidates = h.n_cand;
   info.n_rotations = h.n_rot;
   info.delta_e = E - E_prev;
-  info.converged = std::fabs(info.delta_e) < x->e_conv;
+  info.converged = (x->criterion == SSCF_CONV_CHARGE) ? (info.dq_max < x->dq_conv)
+                                                      : (std::fabs(info.delta_e) < x->e_conv);
   if (info.converged) {
     // occupied-only orthonormalization after convergence (section 4.1)
     double eta2 = 0.0;
@@ -952,6 +961,59 @@ sscf_status sscf_scf_step(sscf_ctx* x, sscf_step_info* info) {
   return guarded(x, [&] {
     if (x->failed) fail(SSCF_E_STATE, "context failed earlier: %s", x->err.c_str());
     step(x, info);
+  });
+}
+
+sscf_status sscf_set_control(sscf_ctx* x, const sscf_control* c) {
+  if (!x || !c) return SSCF_E_INVALID_ARG;
+  return guarded(x, [&] {
+    if (!(c->eps >= 0.0) || !std::isfinite(c->eps) || !(c->e_conv >= 0.0) || !std::isfinite(c->e_conv) ||
+        !(c->dq_conv >= 0.0) || !std::isfinite(c->dq_conv))
+      fail(SSCF_E_INVALID_ARG, "thresholds must be finite and non-negative");
+    if (c->criterion != SSCF_CONV_ENERGY && c->criterion != SSCF_CONV_CHARGE)
+      fail(SSCF_E_INVALID_ARG, "unknown criterion %d", c->criterion);
+    if (c->step_ortho != 0 && c->step_ortho != 1) fail(SSCF_E_INVALID_ARG, "step_ortho must be 0 or 1");
+    x->eps = c->eps;
+    x->e_conv = c->e_conv;
+    x->dq_conv = c->dq_conv;
+    x->criterion = c->criterion;
+    x->step_ortho = c->step_ortho;
+  });
+}
+
+sscf_status sscf_get_control(const sscf_ctx* x, sscf_control* c) {
+  if (!x || !c) return SSCF_E_INVALID_ARG;
+  c->eps = x->eps;
+  c->e_conv = x->e_conv;
+  c->dq_conv = x->dq_conv;
+  c->criterion = x->criterion;
+  c->step_ortho = x->step_ortho;
+  return SSCF_OK;
+}
+
+sscf_status sscf_orthonormalize(sscf_ctx* x, int32_t occ_only, sscf_step_info* out) {
+  if (!x || (occ_only != 0 && occ_only != 1)) return SSCF_E_INVALID_ARG;
+  return guarded(x, [&] {
+    if (x->failed) fail(SSCF_E_STATE, "context failed earlier: %s", x->err.c_str());
+    sscf_step_info info;
+    std::memset(&info, 0, sizeof(info));
+    double eta = 0.0;
+    int conv = 0;
+    const int sweeps = x->orthonormalize(occ_only, x->max_sweeps_init, &eta, &conv);
+    if (!conv) fail(SSCF_E_ORTHO, "orthonormalization did not reach eps/100 in %d sweeps (eta %.3e)", sweeps, eta);
+    x->charges(0);
+    x->energy_terms();
+    const Scalars h = x->read_scalars();
+    x->E = h.e_band + h.e_coul;
+    info.energy = x->E;
+    info.e_band = h.e_band;
+    info.e_coul = h.e_coul;
+    info.n_ortho_sweeps = sweeps;
+    info.ortho_eta = eta;
+    info.ortho_converged = conv;
+    info.nnz_tiles = x->active_tiles();
+    x->pcollect();
+    if (out) *out = info;
   });
 }
 

@@ -64,6 +64,14 @@ class StepInfo(ct.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Control(ct.Structure):
+    _fields_ = [("eps", ct.c_double), ("e_conv", ct.c_double), ("dq_conv", ct.c_double),
+                ("criterion", ct.c_int32), ("step_ortho", ct.c_int32)]
+
+
+CONV_ENERGY, CONV_CHARGE = 0, 1
+
+
 class KernelStat(ct.Structure):
     _fields_ = [("name", ct.c_char * 32), ("launches", ct.c_int64), ("ms", ct.c_double),
                 ("flops", ct.c_double), ("bytes", ct.c_double)]
@@ -71,7 +79,8 @@ class KernelStat(ct.Structure):
 
 EXPORTS = ["sscf_get_kernel_stats", "sscf_reset_kernel_stats", "sscf_init_system", "sscf_set_fock", "sscf_scf_step", "sscf_get_energy",
            "sscf_get_density", "sscf_get_charges", "sscf_get_mo_coefficients", "sscf_init_info",
-           "sscf_get_schedule", "sscf_get_energy_gradient", "sscf_destroy", "sscf_last_error"]
+           "sscf_get_schedule", "sscf_get_energy_gradient", "sscf_set_control", "sscf_get_control",
+           "sscf_orthonormalize", "sscf_destroy", "sscf_last_error"]
 
 _lib = None
 
@@ -91,6 +100,9 @@ def lib():
         L.sscf_get_energy.argtypes = [vp, ct.POINTER(ct.c_double)]
         L.sscf_get_density.argtypes = [vp, vp, sz]
         L.sscf_get_energy_gradient.argtypes = [vp, vp, vp, sz]
+        L.sscf_set_control.argtypes = [vp, ct.POINTER(Control)]
+        L.sscf_get_control.argtypes = [vp, ct.POINTER(Control)]
+        L.sscf_orthonormalize.argtypes = [vp, i32, ct.POINTER(StepInfo)]
         L.sscf_get_charges.argtypes = [vp, vp, sz]
         L.sscf_get_mo_coefficients.argtypes = [vp, vp, vp, vp, ct.POINTER(i64)]
         L.sscf_init_info.argtypes = [vp, ct.POINTER(StepInfo)]
@@ -226,6 +238,23 @@ class SparseSCF:
         out = np.zeros(self.system.S_val.shape[0])
         self._check(lib().sscf_get_density(self._h, _p(out), out.shape[0]))
         return out
+
+    def set_control(self, eps: float, e_conv: float = 0.0, dq_conv: float = 0.0, criterion: int = CONV_ENERGY,
+                    step_ortho: bool = True) -> None:
+        """Thresholds, convergence criterion and schedule for the following steps."""
+        c = Control(eps=eps, e_conv=e_conv, dq_conv=dq_conv, criterion=criterion, step_ortho=1 if step_ortho else 0)
+        self._check(lib().sscf_set_control(self._h, ct.byref(c)))
+
+    def control(self) -> Dict:
+        c = Control()
+        self._check(lib().sscf_get_control(self._h, ct.byref(c)))
+        return {k: getattr(c, k) for k, _ in c._fields_}
+
+    def orthonormalize(self, occ_only: bool = False) -> Dict:
+        """Step III on demand (all MOs, or the occupied ones), then charges and energy."""
+        si = StepInfo()
+        self._check(lib().sscf_orthonormalize(self._h, 1 if occ_only else 0, ct.byref(si)))
+        return si.as_dict()
 
     def energy_gradient(self):
         """(dE/dH0, dE/dS) at the current MOs on the atom-block pattern (dE/dF in complete-Fock

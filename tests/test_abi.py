@@ -36,10 +36,12 @@ def test_struct_layout_matches_c(tmp_path):
     src = tmp_path / "layout.c"
     fields_d = [f for f, _ in sscf.SystemDesc._fields_]
     fields_i = [f for f, _ in sscf.StepInfo._fields_]
+    fields_c = [f for f, _ in sscf.Control._fields_]
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', 'int main(void){',
-             'printf("%zu %zu\\n", sizeof(sscf_system_desc), sizeof(sscf_step_info));']
+             'printf("%zu %zu %zu\\n", sizeof(sscf_system_desc), sizeof(sscf_step_info), sizeof(sscf_control));']
     lines += [f'printf("%zu\\n", offsetof(sscf_system_desc, {f}));' for f in fields_d]
     lines += [f'printf("%zu\\n", offsetof(sscf_step_info, {f}));' for f in fields_i]
+    lines += [f'printf("%zu\\n", offsetof(sscf_control, {f}));' for f in fields_c]
     lines += ['return 0;}']
     src.write_text("\n".join(lines))
     exe = tmp_path / "layout"
@@ -47,9 +49,12 @@ def test_struct_layout_matches_c(tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
     vals = [int(x) for x in out]
     assert vals[0] == ct.sizeof(sscf.SystemDesc) and vals[1] == ct.sizeof(sscf.StepInfo)
-    offs = vals[2:]
-    assert offs[:len(fields_d)] == [getattr(sscf.SystemDesc, f).offset for f in fields_d]
-    assert offs[len(fields_d):] == [getattr(sscf.StepInfo, f).offset for f in fields_i]
+    assert vals[2] == ct.sizeof(sscf.Control)
+    offs = vals[3:]
+    nd, ni = len(fields_d), len(fields_i)
+    assert offs[:nd] == [getattr(sscf.SystemDesc, f).offset for f in fields_d]
+    assert offs[nd:nd + ni] == [getattr(sscf.StepInfo, f).offset for f in fields_i]
+    assert offs[nd + ni:] == [getattr(sscf.Control, f).offset for f in fields_c]
 
 
 def _desc(system, keep, **over):
