@@ -77,6 +77,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel HIP events")
+    ap.add_argument("--schedule", default="step", choices=["step", "paper"],
+                    help="step: step III after every step, |dE| < e-conv (default); paper: step III only at "
+                         "set-up and after convergence, dq_max < 10 eps (section 4.1)")
     ap.add_argument("--gradient", action="store_true",
                     help="after the timed steps, time one energy-gradient evaluation (dE/dH0, dE/dS)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -111,6 +114,9 @@ def main():
     prec = FP64 if args.precision == "fp64" else FP32_MIXED
     t = time.time()
     g = SparseSCF(system, eps=args.eps, e_conv=args.e_conv, precision=prec, profile=not args.no_profile)
+    if args.schedule == "paper":
+        from paper_1402_2880_amd.sscf import CONV_CHARGE
+        g.set_control(args.eps, dq_conv=10 * args.eps, criterion=CONV_CHARGE, step_ortho=False)
     log(f"[bench] set-up + initial orthonormalization {time.time() - t:.1f} s "
         f"({g.init_info()['n_ortho_sweeps']} sweeps)")
     for k in range(args.warmup):
@@ -190,9 +196,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.config} seed {args.seed}: {system.n_atoms} atoms, {system.n_ao} AOs, "
                                f"{system.n_mo} MOs ({system.n_occ} occupied), {system.n_groups} MO groups; "
-                               f"eps {args.eps}, e_conv {args.e_conv}; SCF steps "
+                               + (f"eps {args.eps}, e_conv {args.e_conv}" if args.schedule == "step" else
+                                  f"paper schedule: eps {args.eps}, dq_max < {10 * args.eps}, step III at set-up "
+                                  "and after convergence only")
+                               + "; SCF steps "
                                f"{args.warmup + 1}..{args.warmup + args.steps}",
-                   "precision": args.precision, "energy_last": last["energy"],
+                   "precision": args.precision, "schedule": args.schedule, "energy_last": last["energy"],
                    "converged_last": bool(last["converged"])},
         "roofline": roofline,
         "cpu_baseline": cpu,

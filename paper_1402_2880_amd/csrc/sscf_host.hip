@@ -665,6 +665,11 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
   x->upd = x->dalloc<uint8_t>((size_t)G * v.W);
   x->pair_sel = x->dalloc<uint8_t>(x->n_pairs);
   x->fmask = x->dalloc<unsigned int>((size_t)x->n_pairs * 16);
+  {
+    double* z = x->dalloc<double>(ZERO_DOUBLES);
+    launch_fill(z, ZERO_DOUBLES, 0.0, s);
+    v.zeros = z;
+  }
   x->part = x->dalloc<double>(std::max((size_t)CD_SPLIT * x->v.G * x->v.W, (size_t)CL_SPLIT * x->v.n_atoms));
   x->jb_g = x->upload(x->h_jb_g.data(), x->n_blocks);
   {

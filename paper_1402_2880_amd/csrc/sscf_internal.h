@@ -27,6 +27,7 @@ namespace sscf {
 constexpr int RB = 16;           // AOs per row block
 // strided parts of the split reductions (column dot products; Coulomb sums over atoms)
 constexpr int CD_SPLIT = 16, CL_SPLIT = 16;
+constexpr int ZERO_DOUBLES = 128 * 64;  // zero buffer of the kernels' masked loads (64 KB)
 constexpr int MAX_W = 128;       // widest panel supported
 constexpr int MAX_TIES = 4096;   // candidates sharing the cut-off |F| that can be ordered
 
@@ -61,6 +62,8 @@ struct View {
   const int* xs_ptr;
   const int* xs_col;
   const int* xs_row;
+  // ZERO_DOUBLES zero doubles: the target of loads that are known to give zero
+  const double* zeros;
 };
 
 // ---- launchers (sscf_kernels.hip) ------------------------------------------------------

@@ -185,6 +185,19 @@ __device__ inline int xcd_item(const int* perm, int maxc) {
   return perm[(L % N_XCD) * maxc + L / N_XCD];
 }
 
+// A load that may be known to give zero reads a lane's entry of an all-zero page instead:
+// the pointer is selected, the load is unconditional, so every load of a loop body is issued
+// before the first wait instead of one at a time behind branches.  The zero buffer holds
+// ZCHUNKS chunks of 64 doubles; zl(zp, salt) picks one by a salt that varies between loads,
+// so that these reads spread over the L2 channels instead of piling onto one line.
+constexpr int ZCHUNKS = ZERO_DOUBLES / 64;
+__device__ __forceinline__ const double* zl(const double* zp, unsigned int salt) {
+  return zp + ((salt & (ZCHUNKS - 1)) << 6) + (threadIdx.x & 63);
+}
+__device__ __forceinline__ double ld_or_zero(bool on, const double* p, const double* z) {
+  return *(on ? p : z);
+}
+
 // ---------------------------------------------------------------------------------------
 // out_p = C_g[:, row_off : row_off + 16 MT]^T Y_h[:, col_off : col_off + 16 NT] for pair p = (g, h),
 // summed over the row blocks active in both.  Four waves split the MT x NT output tiles 2 x 2.
@@ -1140,6 +1153,7 @@ void launch_round_meta(int n_rounds, const int* round_ptr, const int* round_list
 
 template <int NTMAX, typename Real>
 __global__ void __launch_bounds__(256) k_givens_rb(int G, int n_rb, int W, int OW, int n_rounds,
+                                                   const double* __restrict__ zp,
                                                    const int* __restrict__ roff, const int4* __restrict__ meta,
                                                    const int* __restrict__ tcol,
                                                    const Real* __restrict__ R, double eps, double* C,
@@ -1195,20 +1209,26 @@ __global__ void __launch_bounds__(256) k_givens_rb(int G, int n_rb, int W, int O
 #pragma unroll
         for (int n = 0; n < NTMAX; ++n) acc[n] = acc_t{0, 0, 0, 0};
         for (int s0 = 0; s0 < ns; s0 += 8) {
+          // gathers, all in flight together (a lane past T reads the zero page)
           Real a[8];
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
             const int k = 4 * (s0 + u) + lk;
             const int c0 = __shfl(tcl0, k & 63), c1 = __shfl(tcl1, k & 63);
+            const bool in = s0 + u < ns && k < T;
             const int col = (k < 64) ? c0 : c1;
-            a[u] = (s0 + u < ns && k < T) ? (Real)(col < OW ? Cg : Ch)[lr * W + col] : Real(0);
+            a[u] = (Real)ld_or_zero(in, (col < OW ? Cg : Ch) + lr * W + col, zl(zp, rb * 8 + u));
           }
 #pragma unroll
-          for (int u = 0; u < 8; ++u)
-            if (s0 + u < ns)
+          for (int n = 0; n < NTMAX; ++n) {
+            if (n >= nt_n) break;
+            Real rv[8];
 #pragma unroll
-              for (int n = 0; n < NTMAX; ++n)
-                if (n < nt_n) acc[n] = Mfma<Real>::op(a[u], Rb[(size_t)(4 * (s0 + u) + lk) * W + n * 16 + lr], acc[n]);
+            for (int u = 0; u < 8; ++u) rv[u] = Rb[(size_t)min(4 * (s0 + u) + lk, W - 1) * W + n * 16 + lr];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              if (s0 + u < ns) acc[n] = Mfma<Real>::op(a[u], rv[u], acc[n]);
+          }
         }
         int nzg = 0, nzh = 0;
         unsigned int bg = 0, bh = 0;
@@ -1254,8 +1274,8 @@ void launch_givens_rb(const View& v, int n_rounds, const int* roff, const int4* 
   const size_t lds = 256 * sizeof(int4) + 4 * sizeof(int) + (size_t)v.G;
   switch ((v.W + 15) / 16) {
 #define SSCF_GIV(N) case N: \
-    if (R32) hipLaunchKernelGGL((k_givens_rb<N, float>), dim3(v.n_rb), dim3(256), lds, s, v.G, v.n_rb, v.W, v.OW, n_rounds, roff, meta, tcol, R32, eps, C, actC, cmask, ctr); \
-    else hipLaunchKernelGGL((k_givens_rb<N, double>), dim3(v.n_rb), dim3(256), lds, s, v.G, v.n_rb, v.W, v.OW, n_rounds, roff, meta, tcol, R, eps, C, actC, cmask, ctr); \
+    if (R32) hipLaunchKernelGGL((k_givens_rb<N, float>), dim3(v.n_rb), dim3(256), lds, s, v.G, v.n_rb, v.W, v.OW, n_rounds, v.zeros, roff, meta, tcol, R32, eps, C, actC, cmask, ctr); \
+    else hipLaunchKernelGGL((k_givens_rb<N, double>), dim3(v.n_rb), dim3(256), lds, s, v.G, v.n_rb, v.W, v.OW, n_rounds, v.zeros, roff, meta, tcol, R, eps, C, actC, cmask, ctr); \
     break;
     SSCF_GIV(1) SSCF_GIV(2) SSCF_GIV(3) SSCF_GIV(4) SSCF_GIV(5) SSCF_GIV(6) SSCF_GIV(7) SSCF_GIV(8)
 #undef SSCF_GIV
@@ -1724,10 +1744,24 @@ __global__ void __launch_bounds__(256) k_spmm_row(int G, int n_rb, int nchunk, c
       Real xa[4], cb[4][NT];
 #pragma unroll
       for (int s = 0; s < 4; ++s) xa[s] = Xb[4 * s];
+      if constexpr (sizeof(Real) == sizeof(double)) {
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int n = 0; n < NT; ++n) cb[s][n] = ((mj >> n) & 1u) ? (Real)Ct[4 * s * W + n * 16] : Real(0);
+          for (int n = 0; n < NT; ++n) cb[s][n] = ((mj >> n) & 1u) ? Ct[4 * s * W + n * 16] : 0.0;
+      } else {
+        // FP32 form: C is rounded after loading; every slice is loaded (a slice outside the
+        // mask holds zeros) so that the loads are not serialized behind their conversions
+        double cd[4][NT];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int n = 0; n < NT; ++n) cd[s][n] = Ct[4 * s * W + n * 16];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int n = 0; n < NT; ++n) cb[s][n] = (Real)cd[s][n];
+      }
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
