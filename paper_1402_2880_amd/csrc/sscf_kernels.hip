@@ -1526,15 +1526,20 @@ __global__ void __launch_bounds__(256) k_pair32(int n_rb, int W, const int* __re
         const unsigned int ma = mj & 0xffffu, mb = mj >> 16;
         const double* Ct = C + (gb + r) * (size_t)(RB * W) + row_off + mt0 * 16 + lr;
         const float* Yt = Y + (hb + r) * (size_t)(RB * W) + col_off + nt0 * 16 + lr;
+        double ad[4][MW];
         float a[4][MW], b[4][NW];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           const int ro = (4 * s + lk) * W;
 #pragma unroll
-          for (int i = 0; i < MW; ++i) a[s][i] = (ma & (1u << i)) ? (float)Ct[ro + i * 16] : 0.f;
+          for (int i = 0; i < MW; ++i) ad[s][i] = (ma & (1u << i)) ? Ct[ro + i * 16] : 0.0;
 #pragma unroll
           for (int jj = 0; jj < NW; ++jj) b[s][jj] = (mb & (1u << jj)) ? Yt[ro + jj * 16] : 0.f;
         }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int i = 0; i < MW; ++i) a[s][i] = (float)ad[s][i];   // C rounded after the loads
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -1744,32 +1749,34 @@ __global__ void __launch_bounds__(256) k_spmm_row(int G, int n_rb, int nchunk, c
       Real xa[4], cb[4][NT];
 #pragma unroll
       for (int s = 0; s < 4; ++s) xa[s] = Xb[4 * s];
+      // C slices in FP64 (rounded afterwards in the FP32 form, outside the masked loads)
+      double cd[4][NT];
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) cd[s][n] = ((mj >> n) & 1u) ? Ct[4 * s * W + n * 16] : 0.0;
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) cb[s][n] = (Real)cd[s][n];
       if constexpr (sizeof(Real) == sizeof(double)) {
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
-          for (int n = 0; n < NT; ++n) cb[s][n] = ((mj >> n) & 1u) ? Ct[4 * s * W + n * 16] : 0.0;
+          for (int n = 0; n < NT; ++n)
+            if ((mj >> n) & 1u) {
+              acc[n] = Mfma<Real>::op(xa[s], cb[s][n], acc[n]);
+              ++n_mfma;
+            }
       } else {
-        // FP32 form: C is rounded after loading; every slice is loaded (a slice outside the
-        // mask holds zeros) so that the loads are not serialized behind their conversions
-        double cd[4][NT];
+        // FP32: branch-free (a masked slice is zero); branches around FP32 MFMAs make the
+        // compiler move the accumulators between register files at every join
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
-          for (int n = 0; n < NT; ++n) cd[s][n] = Ct[4 * s * W + n * 16];
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-          for (int n = 0; n < NT; ++n) cb[s][n] = (Real)cd[s][n];
+          for (int n = 0; n < NT; ++n) acc[n] = Mfma<Real>::op(xa[s], cb[s][n], acc[n]);
+        n_mfma += 4 * NT;
       }
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int n = 0; n < NT; ++n)
-          if ((mj >> n) & 1u) {
-            acc[n] = Mfma<Real>::op(xa[s], cb[s][n], acc[n]);
-            ++n_mfma;
-          }
     }
   }
   Real* Yt = Y + (pb + r) * (RB * W);
