@@ -161,6 +161,41 @@ sscf_status sscf_init_system(const sscf_system_desc* desc, sscf_ctx** out);
  * Errors: SSCF_E_INVALID_ARG (NULL, bad mode, NaN/Inf, not symmetric). */
 sscf_status sscf_set_fock(sscf_ctx* ctx, const double* f_val, int32_t mode);
 
+/* Inputs of the GPU initial guess (section 3.3).  A fragment (a molecule) is a run of
+ * consecutive atoms; fragments are numbered in atom order. */
+typedef struct {
+  int32_t n_atoms;
+  const int32_t* atom_nao;      /* AOs per atom                                        */
+  const int64_t* blk_rowptr;    /* atom-block pattern and values, as in sscf_system_desc */
+  const int32_t* blk_col;
+  const int64_t* blk_off;
+  const double* S_val;
+  const double* H0_val;
+  int64_t n_val;
+  int32_t n_frag;
+  const int32_t* atom_frag;     /* fragment of each atom: 0, 0, .., 1, 1, .. (non-decreasing) */
+  const int32_t* frag_nocc;     /* doubly occupied MOs of each fragment                */
+  const int32_t* frag_group;    /* MO group of each fragment, in [0, n_groups)          */
+  int32_t n_groups;
+  double drop;                  /* coefficients with |c| < drop are left out of C0       */
+  void* hip_stream;             /* stream of the work; NULL = default stream             */
+} sscf_guess_desc;
+
+/* Initial guess of section 3.3 on the GPU (one thread per fragment): for every fragment,
+ * H0 c = lambda S c restricted to its own AOs (at most 8), solved by Cholesky of S and
+ * cyclic Jacobi; each vector's first entry within a relative 1e-10 of its largest |c|
+ * is made positive.  C0 is written as CSC
+ * into caller-owned host arrays: c0_colptr[n_mo + 1] (n_mo = number of AOs), c0_row[cap],
+ * c0_val[cap], mo_group[n_mo].  Column order (the input order of sscf_system_desc): the
+ * occupied MOs of group 0, 1, .. (fragments ascending within a group, lambda ascending
+ * within a fragment), then the virtual MOs in the same order.  *nnz receives the number of
+ * stored coefficients and *n_occ the number of occupied columns, also when cap is too
+ * small (then SSCF_E_CAPACITY and nothing else is written).  SSCF_E_INVALID_ARG for
+ * inconsistent inputs or a fragment of more than 8 AOs, SSCF_E_NOT_SPD if a fragment's
+ * overlap block is not positive definite.  Error text: sscf_last_error(NULL). */
+sscf_status sscf_fragment_guess(const sscf_guess_desc* d, int64_t* c0_colptr, int32_t* c0_row, double* c0_val,
+                                int64_t cap, int32_t* mo_group, int64_t* nnz, int32_t* n_occ);
+
 /* Thresholds, criterion and schedule for the following steps (section 4.1; the
  * loose-then-tight run of that section is: loose values, steps until converged,
  * user values, sscf_orthonormalize(ctx, 0, ...), steps).  SSCF_E_INVALID_ARG for

@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -519,22 +520,29 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
   const int64_t nnz0 = cp[v.n_mo];
   if (nnz0 > (1LL << 31) - 1) fail(SSCF_E_CAPACITY, "C0 too large");
 
-  // group neighbour map: some atom pair closer than r_nbr (section 3.2)
+  // group neighbour map: some atom pair closer than r_nbr (section 3.2), on the GPU
   std::vector<uint8_t> gnbr((size_t)G * G, 0);
   {
-    const double r2 = x->r_nbr * x->r_nbr;
-    for (int g = 0; g < G; ++g) gnbr[(size_t)g * G + g] = 1;
-    for (int a = 0; a < na; ++a) {
-      const double* pa = d->xyz_bohr + 3 * a;
-      const int ga = d->atom_group[a];
-      for (int b = a + 1; b < na; ++b) {
-        const int gb = d->atom_group[b];
-        if (gnbr[(size_t)ga * G + gb]) continue;
-        const double* pb = d->xyz_bohr + 3 * b;
-        const double dx = pa[0] - pb[0], dy = pa[1] - pb[1], dz = pa[2] - pb[2];
-        if (dx * dx + dy * dy + dz * dz < r2) { gnbr[(size_t)ga * G + gb] = 1; gnbr[(size_t)gb * G + ga] = 1; }
+    std::vector<int> ga_ptr(G + 1, 0), ga(na), fillp(G, 0);
+    for (int a = 0; a < na; ++a) ga_ptr[d->atom_group[a] + 1]++;
+    for (int g = 0; g < G; ++g) ga_ptr[g + 1] += ga_ptr[g];
+    for (int a = 0; a < na; ++a) ga[ga_ptr[d->atom_group[a]] + fillp[d->atom_group[a]]++] = a;
+    double* dxyz = x->upload(d->xyz_bohr, (size_t)3 * na);
+    int* dag = x->upload(d->atom_group, (size_t)na);
+    int* dgp = x->upload(ga_ptr.data(), ga_ptr.size());
+    int* dga = x->upload(ga.data(), ga.size());
+    uint8_t* dn = x->dalloc<uint8_t>((size_t)G * G);
+    launch_fill_u8(dn, (size_t)G * G, 0, x->stream);
+    launch_group_nbr(na, G, dxyz, dag, dgp, dga, x->r_nbr, dn, x->stream);
+    HIPC(hipMemcpyAsync(gnbr.data(), dn, (size_t)G * G, hipMemcpyDeviceToHost, x->stream));
+    x->sync();
+    x->dfree(dxyz); x->dfree(dag); x->dfree(dgp); x->dfree(dga); x->dfree(dn);
+    // the relation is symmetric by construction; keep it exactly so
+    for (int g = 0; g < G; ++g)
+      for (int h2 = g + 1; h2 < G; ++h2) {
+        const uint8_t e = gnbr[(size_t)g * G + h2] | gnbr[(size_t)h2 * G + g];
+        gnbr[(size_t)g * G + h2] = gnbr[(size_t)h2 * G + g] = e;
       }
-    }
   }
   std::vector<int> gn_ptr(G + 1, 0), gn;
   for (int g = 0; g < G; ++g) {
@@ -967,6 +975,130 @@ sscf_status sscf_scf_step(sscf_ctx* x, sscf_step_info* info) {
     if (x->failed) fail(SSCF_E_STATE, "context failed earlier: %s", x->err.c_str());
     step(x, info);
   });
+}
+
+sscf_status sscf_fragment_guess(const sscf_guess_desc* d, int64_t* c0_colptr, int32_t* c0_row, double* c0_val,
+                                int64_t cap, int32_t* mo_group, int64_t* nnz, int32_t* n_occ) {
+  if (!d || !nnz || !n_occ) return SSCF_E_INVALID_ARG;
+  std::vector<void*> mem;
+  auto freeall = [&] { for (void* m : mem) hipFree(m); mem.clear(); };
+  try {
+    const int na = d->n_atoms, nf = d->n_frag;
+    if (na <= 0 || nf <= 0 || d->n_groups <= 0 || !d->atom_nao || !d->blk_rowptr || !d->blk_col || !d->blk_off ||
+        !d->S_val || !d->H0_val || !d->atom_frag || !d->frag_nocc || !d->frag_group || !(d->drop >= 0.0))
+      fail(SSCF_E_INVALID_ARG, "guess: missing arrays or bad sizes");
+    std::vector<int64_t> ao_off(na + 1, 0);
+    for (int a = 0; a < na; ++a) {
+      if (d->atom_nao[a] < 1) fail(SSCF_E_INVALID_ARG, "guess: atom %d has no AO", a);
+      ao_off[a + 1] = ao_off[a] + d->atom_nao[a];
+    }
+    std::vector<int> atom0(nf + 1, -1);
+    for (int a = 0; a < na; ++a) {
+      const int f = d->atom_frag[a];
+      if (f < 0 || f >= nf || (a > 0 && f < d->atom_frag[a - 1]) || (a > 0 && f > d->atom_frag[a - 1] + 1) ||
+          (a == 0 && f != 0))
+        fail(SSCF_E_INVALID_ARG, "guess: atom_frag must run 0, 0, .., 1, .. over the atoms");
+      if (atom0[f] < 0) atom0[f] = a;
+    }
+    if (d->atom_frag[na - 1] != nf - 1) fail(SSCF_E_INVALID_ARG, "guess: n_frag does not match atom_frag");
+    atom0[nf] = na;
+    std::vector<int64_t> coff(nf + 1, 0);
+    int64_t n_mo = ao_off[na];
+    int nocc_total = 0;
+    for (int f = 0; f < nf; ++f) {
+      const int64_t n = ao_off[atom0[f + 1]] - ao_off[atom0[f]];
+      if (n > GUESS_MAXN) fail(SSCF_E_INVALID_ARG, "guess: fragment %d has %lld AOs (at most %d)", f, (long long)n, GUESS_MAXN);
+      if (d->frag_nocc[f] < 0 || d->frag_nocc[f] > n) fail(SSCF_E_INVALID_ARG, "guess: fragment %d: bad frag_nocc", f);
+      if (d->frag_group[f] < 0 || d->frag_group[f] >= d->n_groups) fail(SSCF_E_INVALID_ARG, "guess: fragment %d: bad group", f);
+      coff[f + 1] = coff[f] + n * n;
+      nocc_total += d->frag_nocc[f];
+    }
+    const int64_t nblk = d->blk_rowptr[na];
+    if (d->blk_rowptr[0] != 0 || nblk <= 0 || d->n_val <= 0) fail(SSCF_E_INVALID_ARG, "guess: empty or bad pattern");
+    for (int a = 0; a < na; ++a) {
+      if (d->blk_rowptr[a + 1] < d->blk_rowptr[a]) fail(SSCF_E_INVALID_ARG, "guess: bad blk_rowptr");
+      for (int64_t k = d->blk_rowptr[a]; k < d->blk_rowptr[a + 1]; ++k) {
+        const int b = d->blk_col[k];
+        if (b < 0 || b >= na) fail(SSCF_E_INVALID_ARG, "guess: bad blk_col");
+        if (d->blk_off[k] < 0 || d->blk_off[k] + (int64_t)d->atom_nao[a] * d->atom_nao[b] > d->n_val)
+          fail(SSCF_E_INVALID_ARG, "guess: block %lld lies outside the %lld values", (long long)k, (long long)d->n_val);
+      }
+    }
+    for (int64_t k = 0; k < d->n_val; ++k)
+      if (!std::isfinite(d->S_val[k]) || !std::isfinite(d->H0_val[k])) fail(SSCF_E_INVALID_ARG, "guess: non-finite value");
+    hipStream_t s = (hipStream_t)d->hip_stream;
+    auto up = [&](const void* src, size_t bytes) {
+      void* p = nullptr;
+      HIPC(hipMalloc(&p, bytes ? bytes : 1));
+      mem.push_back(p);
+      if (src && bytes) HIPC(hipMemcpyAsync(p, src, bytes, hipMemcpyHostToDevice, s));
+      return p;
+    };
+    auto* datom0 = (int*)up(atom0.data(), sizeof(int) * (nf + 1));
+    auto* daoo = (int64_t*)up(ao_off.data(), sizeof(int64_t) * (na + 1));
+    auto* drp = (int64_t*)up(d->blk_rowptr, sizeof(int64_t) * (na + 1));
+    auto* dbc = (int*)up(d->blk_col, sizeof(int) * nblk);
+    auto* dbo = (int64_t*)up(d->blk_off, sizeof(int64_t) * nblk);
+    auto* dnao = (int*)up(d->atom_nao, sizeof(int) * na);
+    auto* dS = (double*)up(d->S_val, sizeof(double) * d->n_val);
+    auto* dH = (double*)up(d->H0_val, sizeof(double) * d->n_val);
+    auto* dco = (int64_t*)up(coff.data(), sizeof(int64_t) * (nf + 1));
+    auto* dout = (double*)up(nullptr, sizeof(double) * coff[nf]);
+    auto* dlam = (double*)up(nullptr, sizeof(double) * n_mo);
+    int zero = 0;
+    auto* derr = (int*)up(&zero, sizeof(int));
+    launch_fragment_guess(nf, datom0, daoo, drp, dbc, dbo, dnao, dS, dH, dco, dout, dlam, derr, s);
+    std::vector<double> out(coff[nf]);
+    int err = 0;
+    HIPC(hipMemcpyAsync(out.data(), dout, sizeof(double) * coff[nf], hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(&err, derr, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    freeall();
+    if (err & 1) fail(SSCF_E_NOT_SPD, "guess: a fragment's overlap block is not positive definite");
+    // columns: occupied of group 0, 1, .., then virtual; fragments ascending in a group
+    std::vector<std::vector<int>> frags(d->n_groups);
+    for (int f = 0; f < nf; ++f) frags[d->frag_group[f]].push_back(f);
+    int64_t count = 0;
+    std::vector<std::array<int64_t, 3>> cols;   // (fragment, local MO, nonzeros)
+    cols.reserve(n_mo);
+    for (int pass = 0; pass < 2; ++pass)
+      for (int g = 0; g < d->n_groups; ++g)
+        for (int f : frags[g]) {
+          const int n = (int)(ao_off[atom0[f + 1]] - ao_off[atom0[f]]);
+          const int j0 = pass == 0 ? 0 : d->frag_nocc[f], j1 = pass == 0 ? d->frag_nocc[f] : n;
+          for (int j = j0; j < j1; ++j) {
+            int64_t c = 0;
+            for (int i = 0; i < n; ++i) c += std::fabs(out[coff[f] + (int64_t)i * n + j]) >= d->drop;
+            cols.push_back({f, j, c});
+            count += c;
+          }
+        }
+    *nnz = count;
+    *n_occ = nocc_total;
+    if (count > cap || !c0_colptr || !c0_row || !c0_val || !mo_group)
+      fail(SSCF_E_CAPACITY, "guess: %lld coefficients do not fit in cap %lld", (long long)count, (long long)cap);
+    c0_colptr[0] = 0;
+    for (size_t col = 0; col < cols.size(); ++col) {
+      const int f = (int)cols[col][0], j = (int)cols[col][1];
+      const int n = (int)(ao_off[atom0[f + 1]] - ao_off[atom0[f]]);
+      int64_t w = c0_colptr[col];
+      for (int i = 0; i < n; ++i) {
+        const double v = out[coff[f] + (int64_t)i * n + j];
+        if (std::fabs(v) >= d->drop) { c0_row[w] = (int32_t)(ao_off[atom0[f]] + i); c0_val[w] = v; ++w; }
+      }
+      c0_colptr[col + 1] = w;
+      mo_group[col] = d->frag_group[f];
+    }
+    return SSCF_OK;
+  } catch (const Fail& f) {
+    freeall();
+    g_init_error = f.msg;
+    return f.code;
+  } catch (const std::exception& e) {
+    freeall();
+    g_init_error = e.what();
+    return SSCF_E_NOMEM;
+  }
 }
 
 sscf_status sscf_set_control(sscf_ctx* x, const sscf_control* c) {

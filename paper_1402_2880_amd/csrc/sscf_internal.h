@@ -28,6 +28,7 @@ constexpr int RB = 16;           // AOs per row block
 // strided parts of the split reductions (column dot products; Coulomb sums over atoms)
 constexpr int CD_SPLIT = 16, CL_SPLIT = 16;
 constexpr int ZERO_DOUBLES = 128 * 64;  // zero buffer of the kernels' masked loads (64 KB)
+constexpr int GUESS_MAXN = 8;            // AOs of the largest fragment of the initial guess
 constexpr int MAX_W = 128;       // widest panel supported
 constexpr int MAX_TIES = 4096;   // candidates sharing the cut-off |F| that can be ordered
 
@@ -128,6 +129,12 @@ void launch_compose_rot(const View& v, int nb, const int* rot_cnt, const int2* r
 void launch_round_meta(int n_rounds, const int* round_ptr, const int* round_list, const int* rot_cnt,
                        const int* jb_g, const int* jb_h, const int* tcnt, int* rcnt, int* roff, int4* meta,
                        hipStream_t s);
+void launch_group_nbr(int n_atoms, int G, const double* xyz, const int* atom_group, const int* ga_ptr, const int* ga,
+                      double r_nbr, uint8_t* gnbr, hipStream_t s);
+void launch_fragment_guess(int n_frag, const int* frag_atom0, const int64_t* ao_off, const int64_t* blk_rowptr,
+                           const int* blk_col, const int64_t* blk_off, const int* atom_nao, const double* S,
+                           const double* H, const int64_t* frag_coff, double* out, double* lam, int* err,
+                           hipStream_t s);
 void launch_givens_rb(const View& v, int n_rounds, const int* roff, const int4* meta, const int* tcol,
                       const double* R, const float* R32, double eps, double* C, uint8_t* actC,
                       unsigned int* cmask, unsigned long long* ctr, hipStream_t s);

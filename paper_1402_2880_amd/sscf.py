@@ -18,6 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsscf.so")
 
 SSCF_OK = 0
+STATUS_CAPACITY = -6
 STATUS = {0: "SSCF_OK", -1: "SSCF_E_INVALID_ARG", -2: "SSCF_E_NOT_SPD", -3: "SSCF_E_ORTHO",
           -4: "SSCF_E_HIP", -5: "SSCF_E_STATE", -6: "SSCF_E_CAPACITY", -7: "SSCF_E_NOMEM"}
 FP64, FP32_MIXED = 0, 1
@@ -64,6 +65,14 @@ class StepInfo(ct.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class GuessDesc(ct.Structure):
+    _fields_ = [("n_atoms", ct.c_int32), ("atom_nao", ct.c_void_p), ("blk_rowptr", ct.c_void_p),
+                ("blk_col", ct.c_void_p), ("blk_off", ct.c_void_p), ("S_val", ct.c_void_p),
+                ("H0_val", ct.c_void_p), ("n_val", ct.c_int64), ("n_frag", ct.c_int32),
+                ("atom_frag", ct.c_void_p), ("frag_nocc", ct.c_void_p), ("frag_group", ct.c_void_p),
+                ("n_groups", ct.c_int32), ("drop", ct.c_double), ("hip_stream", ct.c_void_p)]
+
+
 class Control(ct.Structure):
     _fields_ = [("eps", ct.c_double), ("e_conv", ct.c_double), ("dq_conv", ct.c_double),
                 ("criterion", ct.c_int32), ("step_ortho", ct.c_int32)]
@@ -80,7 +89,7 @@ class KernelStat(ct.Structure):
 EXPORTS = ["sscf_get_kernel_stats", "sscf_reset_kernel_stats", "sscf_init_system", "sscf_set_fock", "sscf_scf_step", "sscf_get_energy",
            "sscf_get_density", "sscf_get_charges", "sscf_get_mo_coefficients", "sscf_init_info",
            "sscf_get_schedule", "sscf_get_energy_gradient", "sscf_set_control", "sscf_get_control",
-           "sscf_orthonormalize", "sscf_destroy", "sscf_last_error"]
+           "sscf_orthonormalize", "sscf_fragment_guess", "sscf_destroy", "sscf_last_error"]
 
 _lib = None
 
@@ -103,6 +112,8 @@ def lib():
         L.sscf_set_control.argtypes = [vp, ct.POINTER(Control)]
         L.sscf_get_control.argtypes = [vp, ct.POINTER(Control)]
         L.sscf_orthonormalize.argtypes = [vp, i32, ct.POINTER(StepInfo)]
+        L.sscf_fragment_guess.argtypes = [ct.POINTER(GuessDesc), vp, vp, vp, i64, vp, ct.POINTER(i64),
+                                          ct.POINTER(i32)]
         L.sscf_get_charges.argtypes = [vp, vp, sz]
         L.sscf_get_mo_coefficients.argtypes = [vp, vp, vp, vp, ct.POINTER(i64)]
         L.sscf_init_info.argtypes = [vp, ct.POINTER(StepInfo)]
@@ -348,3 +359,43 @@ def scf_energy(system, H0_val, S_val, max_steps: int = 200, fov_tol: float = 0.0
     """Differentiable self-consistent energy (torch float64 scalar) for H0_val and S_val tensors."""
     return _torch_function().apply(H0_val, S_val, system,
                                    dict(max_steps=max_steps, fov_tol=fov_tol, scf=scf_kw))
+
+
+def fragment_guess(system, atom_frag, frag_nocc, frag_group, drop: float = 0.0, stream=None):
+    """Initial guess of section 3.3 on the GPU for the system's S and H0 (see sscf_fragment_guess).
+
+    Returns (c0_colptr, c0_row, c0_val, mo_group, n_occ) in the column order the library expects.
+    """
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the sparse SCF library needs a GPU")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    k = dict(nao=np.ascontiguousarray(system.atom_nao, dtype=np.int32),
+             rp=np.ascontiguousarray(system.blk_rowptr, dtype=np.int64),
+             bc=np.ascontiguousarray(system.blk_col, dtype=np.int32),
+             bo=np.ascontiguousarray(system.blk_off, dtype=np.int64),
+             S=np.ascontiguousarray(system.S_val, dtype=np.float64),
+             H0=np.ascontiguousarray(system.H0_val, dtype=np.float64),
+             af=np.ascontiguousarray(atom_frag, dtype=np.int32),
+             fn=np.ascontiguousarray(frag_nocc, dtype=np.int32),
+             fg=np.ascontiguousarray(frag_group, dtype=np.int32))
+    d = GuessDesc(n_atoms=system.n_atoms, atom_nao=_p(k["nao"]), blk_rowptr=_p(k["rp"]), blk_col=_p(k["bc"]),
+                  blk_off=_p(k["bo"]), S_val=_p(k["S"]), H0_val=_p(k["H0"]), n_val=k["S"].shape[0],
+                  n_frag=int(k["fn"].shape[0]), atom_frag=_p(k["af"]), frag_nocc=_p(k["fn"]),
+                  frag_group=_p(k["fg"]), n_groups=int(k["fg"].max()) + 1, drop=drop,
+                  hip_stream=st.cuda_stream)
+    n_mo = int(k["nao"].sum())
+    nnz = ct.c_int64(0)
+    nocc = ct.c_int32(0)
+    rc = lib().sscf_fragment_guess(ct.byref(d), None, None, None, 0, None, ct.byref(nnz), ct.byref(nocc))
+    if rc not in (SSCF_OK, STATUS_CAPACITY):
+        raise SSCFError(rc, lib().sscf_last_error(None).decode())
+    cp = np.zeros(n_mo + 1, dtype=np.int64)
+    row = np.zeros(max(nnz.value, 1), dtype=np.int32)
+    val = np.zeros(max(nnz.value, 1))
+    mg = np.zeros(n_mo, dtype=np.int32)
+    rc = lib().sscf_fragment_guess(ct.byref(d), _p(cp), _p(row), _p(val), nnz.value, _p(mg), ct.byref(nnz),
+                                   ct.byref(nocc))
+    if rc != SSCF_OK:
+        raise SSCFError(rc, lib().sscf_last_error(None).decode())
+    return cp, row[:nnz.value], val[:nnz.value], mg, nocc.value

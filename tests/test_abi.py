@@ -37,11 +37,14 @@ def test_struct_layout_matches_c(tmp_path):
     fields_d = [f for f, _ in sscf.SystemDesc._fields_]
     fields_i = [f for f, _ in sscf.StepInfo._fields_]
     fields_c = [f for f, _ in sscf.Control._fields_]
+    fields_g = [f for f, _ in sscf.GuessDesc._fields_]
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', 'int main(void){',
              'printf("%zu %zu %zu\\n", sizeof(sscf_system_desc), sizeof(sscf_step_info), sizeof(sscf_control));']
     lines += [f'printf("%zu\\n", offsetof(sscf_system_desc, {f}));' for f in fields_d]
     lines += [f'printf("%zu\\n", offsetof(sscf_step_info, {f}));' for f in fields_i]
     lines += [f'printf("%zu\\n", offsetof(sscf_control, {f}));' for f in fields_c]
+    lines += ['printf("%zu\\n", sizeof(sscf_guess_desc));']
+    lines += [f'printf("%zu\\n", offsetof(sscf_guess_desc, {f}));' for f in fields_g]
     lines += ['return 0;}']
     src.write_text("\n".join(lines))
     exe = tmp_path / "layout"
@@ -54,7 +57,11 @@ def test_struct_layout_matches_c(tmp_path):
     nd, ni = len(fields_d), len(fields_i)
     assert offs[:nd] == [getattr(sscf.SystemDesc, f).offset for f in fields_d]
     assert offs[nd:nd + ni] == [getattr(sscf.StepInfo, f).offset for f in fields_i]
-    assert offs[nd + ni:] == [getattr(sscf.Control, f).offset for f in fields_c]
+    nc = len(fields_c)
+    assert offs[nd + ni:nd + ni + nc] == [getattr(sscf.Control, f).offset for f in fields_c]
+    rest = offs[nd + ni + nc:]
+    assert rest[0] == ct.sizeof(sscf.GuessDesc)
+    assert rest[1:] == [getattr(sscf.GuessDesc, f).offset for f in fields_g]
 
 
 def _desc(system, keep, **over):
