@@ -80,6 +80,9 @@ def main():
     ap.add_argument("--schedule", default="step", choices=["step", "paper"],
                     help="step: step III after every step, |dE| < e-conv (default); paper: step III only at "
                          "set-up and after convergence, dq_max < 10 eps (section 4.1)")
+    ap.add_argument("--setup-timing", action="store_true",
+                    help="time the GPU initial guess (section 3.3) and the library set-up (neighbour maps, "
+                         "schedule, initial orthonormalization)")
     ap.add_argument("--gradient", action="store_true",
                     help="after the timed steps, time one energy-gradient evaluation (dE/dH0, dE/dS)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -112,8 +115,25 @@ def main():
     log(f"[bench] {args.config}: {system.n_atoms} atoms, {system.n_ao} AOs, {system.n_mo} MOs "
         f"(generated in {time.time() - t:.1f} s)")
     prec = FP64 if args.precision == "fp64" else FP32_MIXED
+    setup = None
+    if args.setup_timing:
+        import numpy as np
+        from paper_1402_2880_amd.sscf import fragment_guess
+        n_mol = int(system.atom_mol.max()) + 1
+        first = np.searchsorted(system.atom_mol, np.arange(n_mol))
+        last = np.searchsorted(system.atom_mol, np.arange(n_mol), side="right")
+        nocc = np.array([int(round(system.q0[a:b].sum())) // 2 for a, b in zip(first, last)], dtype=np.int32)
+        fragment_guess(system, system.atom_mol, nocc, system.atom_group[first])      # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fragment_guess(system, system.atom_mol, nocc, system.atom_group[first], drop=1e-13)
+        setup = dict(guess_ms=round(1e3 * (time.perf_counter() - t), 2), fragments=n_mol)
     t = time.time()
     g = SparseSCF(system, eps=args.eps, e_conv=args.e_conv, precision=prec, profile=not args.no_profile)
+    if setup is not None:
+        setup["init_ms"] = round(1e3 * (time.time() - t), 1)
+        setup["includes"] = ("guess: host-to-device copies, one thread per fragment, copy back, CSC assembly; "
+                             "init: validation, neighbour map (GPU), pairs, rounds, uploads, initial orthonormalization")
     if args.schedule == "paper":
         from paper_1402_2880_amd.sscf import CONV_CHARGE
         g.set_control(args.eps, dq_conv=10 * args.eps, criterion=CONV_CHARGE, step_ortho=False)
@@ -208,6 +228,8 @@ def main():
     }
     if grad is not None:
         out["gradient"] = grad
+    if setup is not None:
+        out["setup"] = setup
     if kstats is not None:
         out["kernels"] = {k: dict(launches=v["launches"], ms=round(v["ms"], 3),
                                   tflops=round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 3),

@@ -1607,98 +1607,6 @@ void launch_coldot32(const View& v, const double* C, const int* listC, const int
 }
 
 // ---------------------------------------------------------------------------------------
-// Y = X C with the C tiles staged in LDS: one workgroup per SCH consecutive output row
-// blocks of panel g (one wave each).  The union of the blocks' S-row columns that are
-// active in panel g is collected in an LDS bitmap; each such C tile is loaded once into
-// LDS and applied by every wave whose row holds a block of X in that column.
-// Real = double (FP64 form) or float (FP32 form of H C; C is rounded when staged).
-// ---------------------------------------------------------------------------------------
-constexpr int SCH = 8;
-
-template <int NT, typename Real>
-__global__ void __launch_bounds__(SCH * 64) k_spmm_lds(int G, int n_rb, int nchunk, const int* __restrict__ xs_ptr,
-                                                       const int* __restrict__ xs_col, const Real* __restrict__ X,
-                                                       const double* __restrict__ C, const uint8_t* __restrict__ actC,
-                                                       const unsigned int* __restrict__ cmask,
-                                                       const int* __restrict__ listY, const int* __restrict__ cntY,
-                                                       Real* __restrict__ Y, unsigned int* __restrict__ ymask,
-                                                       unsigned long long* ctr) {
-  constexpr int W = NT * 16;
-  typedef typename Mfma<Real>::acc_t acc_t;
-  extern __shared__ unsigned int cbits[];             // n_rb bits, then the staged tile
-  Real* tile = reinterpret_cast<Real*>(cbits + ((n_rb + 63) / 64) * 2);
-  int chunk;
-  const int g = xcd_group_chunk(nchunk, chunk);
-  if (g >= G) return;
-  const int t0 = chunk * SCH;
-  const int cnt = cntY[g];
-  if (t0 >= cnt) return;
-  const int nt = min(SCH, cnt - t0);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int lr = lane & 15, lk = lane >> 4;
-  const size_t pb = (size_t)g * n_rb;
-  const int nwords = (n_rb + 31) / 32;
-  for (int i = threadIdx.x; i < nwords; i += blockDim.x) cbits[i] = 0u;
-  __syncthreads();
-  const bool live = w < nt;
-  const int r = live ? listY[pb + t0 + w] : 0;
-  int kb = live ? xs_ptr[r] : 0;
-  const int kend = live ? xs_ptr[r + 1] : 0;
-  for (int k = kb + lane; k < kend; k += 64) {
-    const int c = xs_col[k];
-    if (actC[pb + c]) atomicOr(&cbits[c >> 5], 1u << (c & 31));
-  }
-  __syncthreads();
-  acc_t acc[NT];
-#pragma unroll
-  for (int n = 0; n < NT; ++n) acc[n] = acc_t{0, 0, 0, 0};
-  unsigned int n_mfma = 0;
-  for (int wd = 0; wd < nwords; ++wd) {
-    unsigned int bits = cbits[wd];
-    while (bits) {
-      const int c = wd * 32 + __ffs(bits) - 1;
-      bits &= bits - 1u;
-      const double* Ct = C + (pb + c) * (RB * W);
-      for (int e = threadIdx.x; e < RB * W; e += blockDim.x) tile[e] = (Real)Ct[e];
-      const unsigned int m = cmask[pb + c];
-      __syncthreads();
-      while (kb < kend && xs_col[kb] < c) ++kb;
-      if (kb < kend && xs_col[kb] == c) {
-        const Real* Xb = X + (size_t)kb * 256;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const Real a = Xb[lr * 16 + 4 * s + lk];
-#pragma unroll
-          for (int n = 0; n < NT; ++n)
-            if (m & (1u << n)) {
-              acc[n] = Mfma<Real>::op(a, tile[(4 * s + lk) * W + n * 16 + lr], acc[n]);
-              ++n_mfma;
-            }
-        }
-      }
-      __syncthreads();
-    }
-  }
-  if (!live) return;
-  Real* Yt = Y + (pb + r) * (RB * W);
-  unsigned int ym = 0;
-#pragma unroll
-  for (int n = 0; n < NT; ++n) {
-    int nz = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      Yt[Mfma<Real>::row(lk, q) * W + n * 16 + lr] = acc[n][q];
-      nz |= acc[n][q] != Real(0);
-    }
-    if (__ballot(nz)) ym |= 1u << n;
-  }
-  if (lane == 0) {
-    ymask[pb + r] = ym;
-    if (ctr && n_mfma) atomicAdd(ctr, (unsigned long long)n_mfma);
-  }
-}
-
-// ---------------------------------------------------------------------------------------
 // Y = X C with one wave per output tile (g, r) and no workgroup synchronization.  A ballot
 // over the row's X blocks finds, 64 at a time, those whose C tile is active in panel g, with
 // its 16-column slice mask, before any product starts; the wave then streams the products,
@@ -1807,20 +1715,6 @@ static void launch_spmm_row(const View& v, const Real* X, const double* C, const
 #define SSCF_SPR(NT) case NT: hipLaunchKernelGGL((k_spmm_row<NT, Real>), grid, blk, 0, s, v.G, v.n_rb, nchunk, v.xs_ptr, v.xs_col, X, C, actC, cmask, listY, cntY, Y, ymask, ctr); break;
     SSCF_SPR(1) SSCF_SPR(2) SSCF_SPR(3) SSCF_SPR(4) SSCF_SPR(5) SSCF_SPR(6) SSCF_SPR(7) SSCF_SPR(8)
 #undef SSCF_SPR
-  }
-}
-
-template <typename Real>
-static void launch_spmm_lds(const View& v, const Real* X, const double* C, const uint8_t* actC,
-                            const unsigned int* cmask, const int* listY, const int* cntY, Real* Y,
-                            unsigned int* ymask, unsigned long long* ctr, hipStream_t s) {
-  const int nchunk = (v.n_rb + SCH - 1) / SCH;
-  dim3 grid(xcd_grid(v.G, nchunk)), blk(SCH * 64);
-  const size_t lds = ((v.n_rb + 63) / 64) * 2 * sizeof(unsigned int) + (size_t)RB * v.W * sizeof(Real);
-  switch (v.W / 16) {
-#define SSCF_SPL(NT) case NT: hipLaunchKernelGGL((k_spmm_lds<NT, Real>), grid, blk, lds, s, v.G, v.n_rb, nchunk, v.xs_ptr, v.xs_col, X, C, actC, cmask, listY, cntY, Y, ymask, ctr); break;
-    SSCF_SPL(1) SSCF_SPL(2) SSCF_SPL(3) SSCF_SPL(4) SSCF_SPL(5) SSCF_SPL(6) SSCF_SPL(7) SSCF_SPL(8)
-#undef SSCF_SPL
   }
 }
 
