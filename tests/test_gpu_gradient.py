@@ -175,3 +175,7 @@ def test_onsite_gradient_water512_finite_differences():
         worst = max(worst, abs(num - ana))
         assert abs(num - ana) < 1e-7, (int(a), shell, num, ana)
     print(f"[gradient] water512 onsite FD: 32 parameters, max |FD - analytic| {worst:.2e}", flush=True)
+
+
+def test_gradient_maximum_panel_width():
+    compare(synth.water_box(60, 12.5, 7, n_link=20), "panel width 128", steps=4)

@@ -215,3 +215,27 @@ def test_fp32_form_water4096():
         err = abs(gs["energy"] - st["energy"])
         print(f"[fp32] water4096 step {k + 1} |dE| {err:.2e} ms {gs['ms_total']:.1f}", flush=True)
         assert err < FP32_TOL
+
+
+def test_maximum_panel_width():
+    """20 molecules per group: 80 occupied + 48 virtual columns, the widest panel (128)."""
+    s = synth.water_box(60, 12.5, 7, n_link=20)
+    compare_steps(s, 6, label="panel width 128")
+
+
+def test_fp32_form_maximum_panel_width():
+    from paper_1402_2880_amd.sscf import FP32_MIXED
+    s = synth.water_box(60, 12.5, 7, n_link=20)
+    o = Oracle(s)
+    g = gpu(s, precision=FP32_MIXED)
+    for k in range(6):
+        os_, gs = o.step(), g.step()
+        assert abs(gs["energy"] - os_["energy"]) < FP32_TOL, k
+
+
+def test_panel_wider_than_128_is_refused():
+    from paper_1402_2880_amd.sscf import SSCFError
+    s = synth.water_box(63, 12.5, 7, n_link=21)          # 84 + 42 columns -> 96 + 48 = 144
+    with pytest.raises(SSCFError) as e:
+        gpu(s)
+    assert e.value.status == -6
