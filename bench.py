@@ -52,6 +52,20 @@ def cpu_baseline(system, budget_s: float, eps: float, e_conv: float):
                        f"{t_sum:.1f} s")
 
 
+def step_traffic(kstats, elapsed_s: float, steps: int, config: str, precision: str):
+    """HBM traffic of the timed steps: each profiled kernel's measured bytes per launch times its
+    launches in the timed window (the five MFMA / gather kernels; the rest move < 5% of the
+    bytes), or None when the counter summary does not match the kernel source."""
+    if kstats is None:
+        return None
+    per = {k: measured_traffic(k, config, precision) for k in KERNEL_OF_CLASS}
+    if any(v is None for v in per.values()):
+        return None
+    total = sum(per[k] * kstats[k]["launches"] for k in per if k in kstats)
+    return dict(gb_per_step=round(total / steps, 2), gb_per_s=round(total / elapsed_s, 1),
+                kernels=sorted(per), source="profiles/traffic_water4096_fp64.json")
+
+
 def measured_traffic(kclass: str, config: str, precision: str):
     """HBM bytes per launch of the kernel class from the committed counter summary, or None."""
     import hashlib
@@ -91,8 +105,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs the sparse SCF path on one GPU only; "
-              "--gpus N with N > 1 is not supported", file=sys.stderr)
+        print("bench.py: the sparse SCF path runs on one GPU; --gpus N with N > 1 is not supported "
+              "(how it would shard is described in the design notes)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -226,6 +240,9 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    hbm = step_traffic(kstats, elapsed, args.steps, args.config, args.precision)
+    if hbm is not None:
+        out["hbm"] = hbm
     if grad is not None:
         out["gradient"] = grad
     if setup is not None:

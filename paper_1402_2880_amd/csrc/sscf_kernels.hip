@@ -9,7 +9,9 @@
 // combinations of section 3.4 are the product C D_sel on the same tiles.  The
 // Jacobi rotations of section 3.5 are composed per block into small orthogonal
 // matrices and applied in one pass over row blocks, since rows of C are
-// independent under right multiplication.
+// independent under right multiplication.  The energy gradient reuses these
+// products plus C_occ F (k_apply_occ); the set-up kernels of sections 3.2 and 3.3
+// (group neighbour map, per-fragment initial guess) close the file.
 //
 // FP64 16x16x4 MFMA operand layout (lane l of the wave): A[l % 16][l / 16],
 // B[l / 16][l % 16]; result register r holds D[l / 16 + 4 r][l % 16].
