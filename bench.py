@@ -95,7 +95,7 @@ def main():
                     help="step: step III after every step, |dE| < e-conv (default); paper: step III only at "
                          "set-up and after convergence, dq_max < 10 eps (section 4.1)")
     ap.add_argument("--setup-timing", action="store_true",
-                    help="time the GPU initial guess (section 3.3) and the library set-up (neighbour maps, "
+                    help="time the GPU constrained k-means (section 3.2), initial guess (section 3.3) and the library set-up (neighbour maps, "
                          "schedule, initial orthonormalization)")
     ap.add_argument("--gradient", action="store_true",
                     help="after the timed steps, time one energy-gradient evaluation (dE/dH0, dE/dS)")
@@ -142,11 +142,22 @@ def main():
         t = time.perf_counter()
         fragment_guess(system, system.atom_mol, nocc, system.atom_group[first], drop=1e-13)
         setup = dict(guess_ms=round(1e3 * (time.perf_counter() - t), 2), fragments=n_mol)
+        # constrained k-means (section 3.2) on the molecules' first atoms, N_link per group
+        from paper_1402_2880_amd.sscf import constrained_kmeans
+        pts = system.xyz_bohr[first]
+        m0 = synth.initial_means(np.random.default_rng(args.seed), pts, -(-n_mol // synth.N_LINK))
+        constrained_kmeans(pts, m0, synth.N_LINK, max_iter=2)                            # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, _, kinfo = constrained_kmeans(pts, m0, synth.N_LINK, max_iter=100, tol=1e-4)
+        setup.update(kmeans_ms=round(1e3 * (time.perf_counter() - t), 2), kmeans_iterations=kinfo["iterations"],
+                     kmeans_rounds=kinfo["rounds"], kmeans_means=int(m0.shape[0]))
     t = time.time()
     g = SparseSCF(system, eps=args.eps, e_conv=args.e_conv, precision=prec, profile=not args.no_profile)
     if setup is not None:
         setup["init_ms"] = round(1e3 * (time.time() - t), 1)
-        setup["includes"] = ("guess: host-to-device copies, one thread per fragment, copy back, CSC assembly; "
+        setup["includes"] = ("kmeans: copies, up to 100 iterations of attribution rounds + centroid move, copy back; "
+                             "guess: host-to-device copies, one thread per fragment, copy back, CSC assembly; "
                              "init: validation, neighbour map (GPU), pairs, rounds, uploads, initial orthonormalization")
     if args.schedule == "paper":
         from paper_1402_2880_amd.sscf import CONV_CHARGE

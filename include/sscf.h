@@ -196,6 +196,43 @@ typedef struct {
 sscf_status sscf_fragment_guess(const sscf_guess_desc* d, int64_t* c0_colptr, int32_t* c0_row, double* c0_val,
                                 int64_t cap, int32_t* mo_group, int64_t* nnz, int32_t* n_occ);
 
+/* Inputs of the constrained k-means of section 3.2 (host memory, read during the call). */
+typedef struct {
+  int32_t n_points;
+  const double* points;         /* n_points x 3, row-major (x, y, z of each point)       */
+  int32_t n_means;              /* m; m * n_link >= n_points, m <= 4096                   */
+  const double* means0;         /* m x 3: starting means (the caller spreads them evenly) */
+  int32_t n_link;               /* most points one mean may hold (N_link), <= 1024       */
+  int32_t max_iter;             /* iteration cap (>= 1)                                  */
+  double tol;                   /* stop once the average displacement of the means < tol */
+  void* hip_stream;             /* stream of the work; NULL = default stream             */
+} sscf_kmeans_desc;
+
+typedef struct {
+  int32_t iterations;           /* attribution + move iterations done                    */
+  int64_t rounds;               /* parallel proposal rounds, summed over the iterations  */
+  double displacement;          /* average displacement of the means in the last one     */
+} sscf_kmeans_info;
+
+/* Constrained k-means of section 3.2 on the GPU.  Each iteration links every point to a
+ * mean, no mean holding more than n_link points, then moves every mean to the centroid of
+ * its points; it stops when the average displacement of the means (sum of |new - old| over
+ * the means, divided by m) is below tol, or after max_iter iterations.  The link of each
+ * point is the stable attribution: points rank means by increasing squared distance (ties:
+ * lower mean index), a full mean keeps its n_link closest points (ties: lower point index),
+ * and no point could move to a mean it ranks higher that has room or holds a point ranked
+ * below it.  This attribution is unique, so the result does not depend on any visiting
+ * order; the section's reshuffling of the means has nothing left to do.  Squared distances are (dx*dx + dy*dy) + dz*dz in IEEE double,
+ * rounded operation by operation; centroids are sums in point order divided by the count
+ * (an empty mean stays in place).  Outputs (caller-owned host memory): group[n_points] =
+ * mean of each point in the last attribution, means[m x 3] = the means after the last
+ * move; info may be NULL.  The ordered atom list of the section is the points sorted by
+ * (group, index).  SSCF_E_INVALID_ARG for NULL arrays, sizes out of range, m * n_link <
+ * n_points, non-finite or |coordinate| > 1e100, max_iter < 1, tol < 0.
+ * Error text: sscf_last_error(NULL). */
+sscf_status sscf_constrained_kmeans(const sscf_kmeans_desc* d, int32_t* group, double* means,
+                                    sscf_kmeans_info* info);
+
 /* Thresholds, criterion and schedule for the following steps (section 4.1; the
  * loose-then-tight run of that section is: loose values, steps until converged,
  * user values, sscf_orthonormalize(ctx, 0, ...), steps).  SSCF_E_INVALID_ARG for

@@ -1101,6 +1101,102 @@ sscf_status sscf_fragment_guess(const sscf_guess_desc* d, int64_t* c0_colptr, in
   }
 }
 
+sscf_status sscf_constrained_kmeans(const sscf_kmeans_desc* d, int32_t* group, double* means_out,
+                                    sscf_kmeans_info* info) {
+  if (!d || !group || !means_out) {
+    g_init_error = "kmeans: NULL argument";
+    return SSCF_E_INVALID_ARG;
+  }
+  std::vector<void*> mem;
+  auto freeall = [&] { for (void* m : mem) hipFree(m); mem.clear(); };
+  try {
+    const int n = d->n_points, m = d->n_means, nl = d->n_link;
+    if (n <= 0 || m <= 0 || nl <= 0 || !d->points || !d->means0)
+      fail(SSCF_E_INVALID_ARG, "kmeans: need n_points, n_means, n_link > 0 and both coordinate arrays");
+    if (nl > KM_MAX_LINK) fail(SSCF_E_INVALID_ARG, "kmeans: n_link %d exceeds %d", nl, KM_MAX_LINK);
+    if (m > KM_MAX_MEANS) fail(SSCF_E_INVALID_ARG, "kmeans: %d means exceed %d", m, KM_MAX_MEANS);
+    if ((int64_t)m * nl < n)
+      fail(SSCF_E_INVALID_ARG, "kmeans: %d means of at most %d points cannot hold %d points", m, nl, n);
+    if (d->max_iter < 1 || !(d->tol >= 0.0) || !std::isfinite(d->tol))
+      fail(SSCF_E_INVALID_ARG, "kmeans: max_iter >= 1 and a finite tol >= 0 are required");
+    for (int64_t i = 0; i < 3LL * n; ++i)
+      if (!std::isfinite(d->points[i]) || std::fabs(d->points[i]) > 1e100) fail(SSCF_E_INVALID_ARG, "kmeans: bad point coordinate");
+    for (int64_t i = 0; i < 3LL * m; ++i)
+      if (!std::isfinite(d->means0[i]) || std::fabs(d->means0[i]) > 1e100) fail(SSCF_E_INVALID_ARG, "kmeans: bad mean coordinate");
+    hipStream_t s = (hipStream_t)d->hip_stream;
+    auto alloc = [&](size_t bytes) {
+      void* p = nullptr;
+      HIPC(hipMalloc(&p, bytes ? bytes : 1));
+      mem.push_back(p);
+      return p;
+    };
+    auto* pts = (double*)alloc(sizeof(double) * 3 * n);
+    auto* ma = (double*)alloc(sizeof(double) * 3 * m);
+    auto* mb = (double*)alloc(sizeof(double) * 3 * m);
+    auto* rank = (int*)alloc(sizeof(int) * (size_t)n * m);
+    auto* assign = (int*)alloc(sizeof(int) * n);
+    auto* next = (int*)alloc(sizeof(int) * n);
+    auto* prop = (int*)alloc(sizeof(int) * n);
+    auto* held = (int*)alloc(sizeof(int) * (size_t)m * nl);
+    auto* n_held = (int*)alloc(sizeof(int) * m);
+    constexpr int BATCH = 8;                 // rounds between two looks at the free counts
+    auto* n_free = (int*)alloc(sizeof(int) * BATCH);
+    auto* disp = (double*)alloc(sizeof(double));
+    HIPC(hipMemcpyAsync(pts, d->points, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s));
+    HIPC(hipMemcpyAsync(ma, d->means0, sizeof(double) * 3 * m, hipMemcpyHostToDevice, s));
+    // every round that turns a point away advances that point's next[] by one, and next
+    // stays below m (the means hold m * n_link >= n points), so the rounds of one
+    // attribution are at most n * (m - 1) + 1
+    const int64_t max_rounds = (int64_t)n * (m - 1) + 1;
+    int it = 0;
+    int64_t rounds_total = 0;
+    double dsum = 0.0;
+    for (it = 0; it < d->max_iter;) {
+      launch_km_rank(n, m, pts, ma, rank, s);
+      launch_km_reset(n, m, assign, next, n_held, s);
+      int64_t r = 0;
+      bool placed = false;
+      while (!placed) {
+        for (int b = 0; b < BATCH; ++b)
+          launch_km_round(n, m, nl, pts, ma, rank, assign, next, prop, held, n_held, n_free + b, s);
+        int nf[BATCH];
+        HIPC(hipMemcpyAsync(nf, n_free, sizeof(nf), hipMemcpyDeviceToHost, s));
+        HIPC(hipStreamSynchronize(s));
+        for (int b = 0; b < BATCH && !placed; ++b) {
+          ++r;
+          placed = nf[b] == 0;
+        }
+        if (!placed && r > max_rounds) fail(SSCF_E_HIP, "kmeans: attribution did not settle in %lld rounds", (long long)r);
+      }
+      rounds_total += r;
+      launch_km_move(n, m, pts, assign, ma, mb, disp, s);
+      HIPC(hipMemcpyAsync(&dsum, disp, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPC(hipStreamSynchronize(s));
+      std::swap(ma, mb);
+      ++it;
+      if (dsum / m < d->tol) break;
+    }
+    HIPC(hipMemcpyAsync(group, assign, sizeof(int) * n, hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(means_out, ma, sizeof(double) * 3 * m, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    freeall();
+    if (info) {
+      info->iterations = it;
+      info->rounds = rounds_total;
+      info->displacement = dsum / m;
+    }
+    return SSCF_OK;
+  } catch (const Fail& f) {
+    freeall();
+    g_init_error = f.msg;
+    return f.code;
+  } catch (const std::exception& e) {
+    freeall();
+    g_init_error = e.what();
+    return SSCF_E_NOMEM;
+  }
+}
+
 sscf_status sscf_set_control(sscf_ctx* x, const sscf_control* c) {
   if (!x || !c) return SSCF_E_INVALID_ARG;
   return guarded(x, [&] {

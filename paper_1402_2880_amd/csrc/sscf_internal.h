@@ -30,6 +30,9 @@ constexpr int CD_SPLIT = 16, CL_SPLIT = 16;
 constexpr int ZERO_DOUBLES = 128 * 64;  // zero buffer of the kernels' masked loads (64 KB)
 constexpr int GUESS_MAXN = 8;            // AOs of the largest fragment of the initial guess
 constexpr int MAX_W = 128;       // widest panel supported
+constexpr int KM_SLOTS = 2048;         // LDS candidates of one mean in a k-means round
+constexpr int KM_MAX_LINK = 1024;      // largest n_link (a chunk scans KM_SLOTS - n_link points)
+constexpr int KM_MAX_MEANS = 4096;     // most means (the per-point sort of means lives in LDS)
 constexpr int MAX_TIES = 4096;   // candidates sharing the cut-off |F| that can be ordered
 
 // scalars shared between kernels and the host (one device copy per context)
@@ -135,6 +138,12 @@ void launch_fragment_guess(int n_frag, const int* frag_atom0, const int64_t* ao_
                            const int* blk_col, const int64_t* blk_off, const int* atom_nao, const double* S,
                            const double* H, const int64_t* frag_coff, double* out, double* lam, int* err,
                            hipStream_t s);
+void launch_km_rank(int n, int m, const double* pts, const double* means, int* rank, hipStream_t s);
+void launch_km_reset(int n, int m, int* assign, int* next, int* n_held, hipStream_t s);
+void launch_km_round(int n, int m, int n_link, const double* pts, const double* means, const int* rank, int* assign,
+                     int* next, int* prop, int* held, int* n_held, int* n_free, hipStream_t s);
+void launch_km_move(int n, int m, const double* pts, const int* assign, const double* means, double* out,
+                    double* disp, hipStream_t s);
 void launch_givens_rb(const View& v, int n_rounds, const int* roff, const int4* meta, const int* tcol,
                       const double* R, const float* R32, double eps, double* C, uint8_t* actC,
                       unsigned int* cmask, unsigned long long* ctr, hipStream_t s);

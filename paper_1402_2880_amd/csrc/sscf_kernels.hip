@@ -10,8 +10,8 @@
 // Jacobi rotations of section 3.5 are composed per block into small orthogonal
 // matrices and applied in one pass over row blocks, since rows of C are
 // independent under right multiplication.  The energy gradient reuses these
-// products plus C_occ F (k_apply_occ); the set-up kernels of sections 3.2 and 3.3
-// (group neighbour map, per-fragment initial guess) close the file.
+// products plus C_occ F (k_apply_occ).  The set-up kernels of sections 3.2 and 3.3
+// live in sscf_setup.hip.
 //
 // FP64 16x16x4 MFMA operand layout (lane l of the wave): A[l % 16][l / 16],
 // B[l / 16][l % 16]; result register r holds D[l / 16 + 4 r][l % 16].
@@ -1730,169 +1730,6 @@ void launch_spmm32(const View& v, const float* X, const double* C, const uint8_t
                    const int* listY, const int* cntY, float* Y, unsigned int* ymask, unsigned long long* ctr,
                    hipStream_t s) {
   launch_spmm_row<float>(v, X, C, actC, cmask, listY, cntY, Y, ymask, ctr, s);
-}
-
-}  // namespace sscf
-
-namespace sscf {
-
-// ---------------------------------------------------------------------------------------
-// Set-up on the GPU (sections 3.2 and 3.3)
-// ---------------------------------------------------------------------------------------
-
-// Groups g and h are neighbours when an atom of g and an atom of h are closer than r_nbr.
-// Workgroup g walks its atoms against all atoms; every hit stores 1 (no ordering needed).
-// Products and sums are rounded one by one (no fused multiply-add) so that the squared
-// distance is the same double as the plain sum dx*dx + dy*dy + dz*dz.
-__global__ void __launch_bounds__(256) k_group_nbr(int n_atoms, int G, const double* __restrict__ xyz,
-                                                   const int* __restrict__ atom_group, const int* __restrict__ ga_ptr,
-                                                   const int* __restrict__ ga, double r2, uint8_t* __restrict__ gnbr) {
-  const int g = blockIdx.x;
-  if (threadIdx.x == 0) gnbr[(size_t)g * G + g] = 1;
-  const int n_g = ga_ptr[g + 1] - ga_ptr[g];
-  for (size_t e = threadIdx.x; e < (size_t)n_g * n_atoms; e += blockDim.x) {
-    const int a = ga[ga_ptr[g] + (int)(e / n_atoms)], b = (int)(e % n_atoms);
-    const double dx = xyz[3 * a] - xyz[3 * b], dy = xyz[3 * a + 1] - xyz[3 * b + 1], dz = xyz[3 * a + 2] - xyz[3 * b + 2];
-    const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-    if (d2 < r2) gnbr[(size_t)g * G + atom_group[b]] = 1;
-  }
-}
-
-void launch_group_nbr(int n_atoms, int G, const double* xyz, const int* atom_group, const int* ga_ptr, const int* ga,
-                      double r_nbr, uint8_t* gnbr, hipStream_t s) {
-  hipLaunchKernelGGL(k_group_nbr, dim3(G), dim3(256), 0, s, n_atoms, G, xyz, atom_group, ga_ptr, ga, r_nbr * r_nbr,
-                     gnbr);
-}
-
-// Initial guess of one fragment (section 3.3): H c = lambda S c on the fragment's own AOs,
-// one thread per fragment (n <= GUESS_MAXN).  S = L L^T (Cholesky), A = L^-1 H L^-T, cyclic
-// Jacobi on A with the 2 x 2 symmetric Schur rotation of each off-diagonal pair until the
-// off-diagonal part is negligible, c = L^-T y; eigenpairs sorted by increasing lambda (stable),
-// each vector's first entry within a relative 1e-10 of its largest |c| made positive (exactly
-// equal entries of symmetric molecules would otherwise be decided by rounding).  out: n x n, column j =
-// MO j, at frag_coff[f]; lam: n values at frag_aoff[f].  err |= 1: S not positive definite.
-__global__ void __launch_bounds__(64) k_fragment_guess(int n_frag, const int* __restrict__ frag_atom0,
-                                                       const int64_t* __restrict__ ao_off,
-                                                       const int64_t* __restrict__ blk_rowptr,
-                                                       const int* __restrict__ blk_col, const int64_t* __restrict__ blk_off,
-                                                       const int* __restrict__ atom_nao, const double* __restrict__ Sv,
-                                                       const double* __restrict__ Hv, const int64_t* __restrict__ frag_coff,
-                                                       double* __restrict__ out, double* __restrict__ lam,
-                                                       int* __restrict__ err) {
-  constexpr int N = GUESS_MAXN;
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= n_frag) return;
-  const int a0 = frag_atom0[f], a1 = frag_atom0[f + 1];
-  const int64_t lo = ao_off[a0];
-  const int n = (int)(ao_off[a1] - lo);
-  double S[N][N], A[N][N], V[N][N], L[N][N];
-  for (int i = 0; i < N; ++i)
-    for (int j = 0; j < N; ++j) { S[i][j] = 0.0; A[i][j] = 0.0; L[i][j] = 0.0; V[i][j] = (i == j) ? 1.0 : 0.0; }
-  for (int a = a0; a < a1; ++a)
-    for (int64_t k = blk_rowptr[a]; k < blk_rowptr[a + 1]; ++k) {
-      const int b = blk_col[k];
-      if (b < a0 || b >= a1) continue;
-      const int na = atom_nao[a], nb = atom_nao[b];
-      const int ra = (int)(ao_off[a] - lo), rb = (int)(ao_off[b] - lo);
-      for (int i = 0; i < na; ++i)
-        for (int j = 0; j < nb; ++j) {
-          S[ra + i][rb + j] = Sv[blk_off[k] + i * nb + j];
-          A[ra + i][rb + j] = Hv[blk_off[k] + i * nb + j];
-        }
-    }
-  // Cholesky S = L L^T
-  for (int j = 0; j < n; ++j) {
-    double d = S[j][j];
-    for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
-    if (!(d > 0.0)) { atomicOr(err, 1); return; }
-    L[j][j] = sqrt(d);
-    for (int i = j + 1; i < n; ++i) {
-      double v = S[i][j];
-      for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
-      L[i][j] = v / L[j][j];
-    }
-  }
-  // A <- L^-1 H (rows), then A <- A L^-T (columns); S is reused as scratch
-  for (int c = 0; c < n; ++c)
-    for (int i = 0; i < n; ++i) {
-      double v = A[i][c];
-      for (int k = 0; k < i; ++k) v -= L[i][k] * S[k][c];
-      S[i][c] = v / L[i][i];
-    }
-  for (int r = 0; r < n; ++r)
-    for (int i = 0; i < n; ++i) {
-      double v = S[r][i];
-      for (int k = 0; k < i; ++k) v -= L[i][k] * A[r][k];
-      A[r][i] = v / L[i][i];
-    }
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < i; ++j) A[i][j] = A[j][i] = 0.5 * (A[i][j] + A[j][i]);
-  // cyclic Jacobi
-  for (int sweep = 0; sweep < 64; ++sweep) {
-    double off = 0.0, dia = 0.0;
-    for (int i = 0; i < n; ++i) {
-      dia += A[i][i] * A[i][i];
-      for (int j = i + 1; j < n; ++j) off += A[i][j] * A[i][j];
-    }
-    if (off <= 1e-34 * dia || off == 0.0) break;
-    for (int p = 0; p < n - 1; ++p)
-      for (int q = p + 1; q < n; ++q) {
-        const double apq = A[p][q];
-        if (apq == 0.0) continue;
-        const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
-        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-        const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
-        for (int k = 0; k < n; ++k) {
-          const double akp = A[k][p], akq = A[k][q];
-          A[k][p] = c * akp - s * akq;
-          A[k][q] = s * akp + c * akq;
-        }
-        for (int k = 0; k < n; ++k) {
-          const double apk = A[p][k], aqk = A[q][k];
-          A[p][k] = c * apk - s * aqk;
-          A[q][k] = s * apk + c * aqk;
-        }
-        for (int k = 0; k < n; ++k) {
-          const double vkp = V[k][p], vkq = V[k][q];
-          V[k][p] = c * vkp - s * vkq;
-          V[k][q] = s * vkp + c * vkq;
-        }
-      }
-  }
-  // order by increasing eigenvalue (stable)
-  int ord[N];
-  for (int i = 0; i < n; ++i) ord[i] = i;
-  for (int i = 1; i < n; ++i) {
-    const int o = ord[i];
-    int j = i - 1;
-    while (j >= 0 && A[ord[j]][ord[j]] > A[o][o]) { ord[j + 1] = ord[j]; --j; }
-    ord[j + 1] = o;
-  }
-  double* C = out + frag_coff[f];
-  for (int jj = 0; jj < n; ++jj) {
-    const int j = ord[jj];
-    double cv[N];
-    for (int i = n - 1; i >= 0; --i) {        // c = L^-T y
-      double v = V[i][j];
-      for (int k = i + 1; k < n; ++k) v -= L[k][i] * cv[k];
-      cv[i] = v / L[i][i];
-    }
-    double cm = 0.0;
-    for (int i = 0; i < n; ++i) cm = fmax(cm, fabs(cv[i]));
-    int km = 0;
-    while (km < n - 1 && fabs(cv[km]) < cm * (1.0 - 1e-10)) ++km;
-    const double sg = (cv[km] < 0.0) ? -1.0 : 1.0;
-    for (int i = 0; i < n; ++i) C[i * n + jj] = sg * cv[i];
-    lam[lo + jj] = A[j][j];
-  }
-}
-
-void launch_fragment_guess(int n_frag, const int* frag_atom0, const int64_t* ao_off, const int64_t* blk_rowptr,
-                           const int* blk_col, const int64_t* blk_off, const int* atom_nao, const double* S,
-                           const double* H, const int64_t* frag_coff, double* out, double* lam, int* err,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_fragment_guess, dim3((n_frag + 63) / 64), dim3(64), 0, s, n_frag, frag_atom0, ao_off,
-                     blk_rowptr, blk_col, blk_off, atom_nao, S, H, frag_coff, out, lam, err);
 }
 
 }  // namespace sscf

@@ -73,6 +73,16 @@ class GuessDesc(ct.Structure):
                 ("n_groups", ct.c_int32), ("drop", ct.c_double), ("hip_stream", ct.c_void_p)]
 
 
+class KmeansDesc(ct.Structure):
+    _fields_ = [("n_points", ct.c_int32), ("points", ct.c_void_p), ("n_means", ct.c_int32),
+                ("means0", ct.c_void_p), ("n_link", ct.c_int32), ("max_iter", ct.c_int32),
+                ("tol", ct.c_double), ("hip_stream", ct.c_void_p)]
+
+
+class KmeansInfo(ct.Structure):
+    _fields_ = [("iterations", ct.c_int32), ("rounds", ct.c_int64), ("displacement", ct.c_double)]
+
+
 class Control(ct.Structure):
     _fields_ = [("eps", ct.c_double), ("e_conv", ct.c_double), ("dq_conv", ct.c_double),
                 ("criterion", ct.c_int32), ("step_ortho", ct.c_int32)]
@@ -89,7 +99,8 @@ class KernelStat(ct.Structure):
 EXPORTS = ["sscf_get_kernel_stats", "sscf_reset_kernel_stats", "sscf_init_system", "sscf_set_fock", "sscf_scf_step", "sscf_get_energy",
            "sscf_get_density", "sscf_get_charges", "sscf_get_mo_coefficients", "sscf_init_info",
            "sscf_get_schedule", "sscf_get_energy_gradient", "sscf_set_control", "sscf_get_control",
-           "sscf_orthonormalize", "sscf_fragment_guess", "sscf_destroy", "sscf_last_error"]
+           "sscf_orthonormalize", "sscf_fragment_guess", "sscf_constrained_kmeans", "sscf_destroy",
+           "sscf_last_error"]
 
 _lib = None
 
@@ -115,6 +126,7 @@ def lib():
         L.sscf_fragment_guess.argtypes = [ct.POINTER(GuessDesc), vp, vp, vp, i64, vp, ct.POINTER(i64),
                                           ct.POINTER(i32)]
         L.sscf_get_charges.argtypes = [vp, vp, sz]
+        L.sscf_constrained_kmeans.argtypes = [ct.POINTER(KmeansDesc), vp, vp, ct.POINTER(KmeansInfo)]
         L.sscf_get_mo_coefficients.argtypes = [vp, vp, vp, vp, ct.POINTER(i64)]
         L.sscf_init_info.argtypes = [vp, ct.POINTER(StepInfo)]
         L.sscf_get_schedule.argtypes = [vp, vp, vp, vp, ct.POINTER(i32)]
@@ -399,3 +411,27 @@ def fragment_guess(system, atom_frag, frag_nocc, frag_group, drop: float = 0.0, 
     if rc != SSCF_OK:
         raise SSCFError(rc, lib().sscf_last_error(None).decode())
     return cp, row[:nnz.value], val[:nnz.value], mg, nocc.value
+
+
+def constrained_kmeans(points, means0, n_link: int, max_iter: int = 100, tol: float = 1e-4, stream=None):
+    """Constrained k-means of section 3.2 on the GPU (see sscf_constrained_kmeans).
+
+    points: (n, 3), means0: (m, 3) starting means.  Returns (group[n] int32, means (m, 3),
+    info dict with iterations, rounds and the last average displacement).
+    """
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the sparse SCF library needs a GPU")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+    m0 = np.ascontiguousarray(means0, dtype=np.float64).reshape(-1, 3)
+    d = KmeansDesc(n_points=pts.shape[0], points=_p(pts), n_means=m0.shape[0], means0=_p(m0), n_link=n_link,
+                   max_iter=max_iter, tol=tol, hip_stream=st.cuda_stream)
+    group = np.zeros(max(pts.shape[0], 1), dtype=np.int32)
+    means = np.zeros((max(m0.shape[0], 1), 3))
+    info = KmeansInfo()
+    rc = lib().sscf_constrained_kmeans(ct.byref(d), _p(group), _p(means), ct.byref(info))
+    if rc != SSCF_OK:
+        raise SSCFError(rc, lib().sscf_last_error(None).decode())
+    return group[:pts.shape[0]], means[:m0.shape[0]], dict(iterations=info.iterations, rounds=info.rounds,
+                                                           displacement=info.displacement)

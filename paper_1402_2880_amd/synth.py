@@ -294,6 +294,18 @@ def _morton_key(p: np.ndarray, lo: np.ndarray, span: float, bits: int = 10) -> n
     return key
 
 
+def initial_means(rng: np.random.Generator, centres: np.ndarray, m: int) -> np.ndarray:
+    """m starting means spread evenly over the points' bounding box: a random pick of m
+    cells of the smallest k x k x k grid with k^3 >= m (cell centres, ascending cell order)."""
+    lo = centres.min(axis=0)
+    hi = centres.max(axis=0)
+    k = int(math.ceil(m ** (1.0 / 3.0) - 1e-9))
+    g = (np.arange(k) + 0.5) / k
+    grid = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    pick = np.sort(rng.permutation(grid.shape[0])[:m])
+    return lo + grid[pick] * (hi - lo)
+
+
 def constrained_kmeans(rng: np.random.Generator, centres: np.ndarray, n_link: int,
                        max_iter: int = 100, tol: float = 1e-4):
     """Assign points to m = ceil(n / n_link) means, no mean holding more than n_link points.
@@ -306,13 +318,7 @@ def constrained_kmeans(rng: np.random.Generator, centres: np.ndarray, n_link: in
     """
     n = centres.shape[0]
     m = max(1, -(-n // n_link))
-    lo = centres.min(axis=0)
-    hi = centres.max(axis=0)
-    k = int(math.ceil(m ** (1.0 / 3.0) - 1e-9))
-    g = (np.arange(k) + 0.5) / k
-    grid = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
-    pick = np.sort(rng.permutation(grid.shape[0])[:m])
-    means = lo + grid[pick] * (hi - lo)
+    means = initial_means(rng, centres, m)
     assign = np.zeros(n, dtype=np.int64)
     for _ in range(max_iter):
         mean_perm = rng.permutation(m)          # shuffled list of means

@@ -45,6 +45,11 @@ def test_struct_layout_matches_c(tmp_path):
     lines += [f'printf("%zu\\n", offsetof(sscf_control, {f}));' for f in fields_c]
     lines += ['printf("%zu\\n", sizeof(sscf_guess_desc));']
     lines += [f'printf("%zu\\n", offsetof(sscf_guess_desc, {f}));' for f in fields_g]
+    fields_k = [f for f, _ in sscf.KmeansDesc._fields_]
+    fields_ki = [f for f, _ in sscf.KmeansInfo._fields_]
+    lines += ['printf("%zu %zu\\n", sizeof(sscf_kmeans_desc), sizeof(sscf_kmeans_info));']
+    lines += [f'printf("%zu\\n", offsetof(sscf_kmeans_desc, {f}));' for f in fields_k]
+    lines += [f'printf("%zu\\n", offsetof(sscf_kmeans_info, {f}));' for f in fields_ki]
     lines += ['return 0;}']
     src.write_text("\n".join(lines))
     exe = tmp_path / "layout"
@@ -60,8 +65,36 @@ def test_struct_layout_matches_c(tmp_path):
     nc = len(fields_c)
     assert offs[nd + ni:nd + ni + nc] == [getattr(sscf.Control, f).offset for f in fields_c]
     rest = offs[nd + ni + nc:]
+    ng = len(fields_g)
     assert rest[0] == ct.sizeof(sscf.GuessDesc)
-    assert rest[1:] == [getattr(sscf.GuessDesc, f).offset for f in fields_g]
+    assert rest[1:1 + ng] == [getattr(sscf.GuessDesc, f).offset for f in fields_g]
+    k = rest[1 + ng:]
+    assert k[0] == ct.sizeof(sscf.KmeansDesc) and k[1] == ct.sizeof(sscf.KmeansInfo)
+    assert k[2:2 + len(fields_k)] == [getattr(sscf.KmeansDesc, f).offset for f in fields_k]
+    assert k[2 + len(fields_k):] == [getattr(sscf.KmeansInfo, f).offset for f in fields_ki]
+
+
+def test_kmeans_host_checks():
+    """Bad k-means inputs are refused before any device work."""
+    rng = np.random.default_rng(0)
+    pts = rng.uniform(0, 1, (10, 3))
+    means = pts[:5].copy()
+    g = np.zeros(10, dtype=np.int32)
+    mo = np.zeros((5, 3))
+    info = sscf.KmeansInfo()
+    for n, m, nl, it, tol, P in [(10, 3, 3, 10, 1e-4, pts),       # 3 means x 3 < 10 points
+                                 (10, 5, 1025, 10, 1e-4, pts),    # n_link above the limit
+                                 (10, 5, 2, 0, 1e-4, pts),        # max_iter 0
+                                 (10, 5, 2, 10, float("nan"), pts),
+                                 (0, 5, 2, 10, 1e-4, pts),
+                                 (10, 5, 2, 10, 1e-4, np.where(pts > 0.9, np.inf, pts))]:
+        P = np.ascontiguousarray(P)
+        d = sscf.KmeansDesc(n_points=n, points=P.ctypes.data, n_means=m, means0=means.ctypes.data, n_link=nl,
+                            max_iter=it, tol=tol, hip_stream=None)
+        rc = sscf.lib().sscf_constrained_kmeans(ct.byref(d), g.ctypes.data, mo.ctypes.data, ct.byref(info))
+        assert rc == -1, (n, m, nl, it, tol)
+        assert "kmeans" in sscf.lib().sscf_last_error(None).decode()
+    assert sscf.lib().sscf_constrained_kmeans(None, None, None, None) == -1
 
 
 def _desc(system, keep, **over):
