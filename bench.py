@@ -95,7 +95,7 @@ def main():
                     help="step: step III after every step, |dE| < e-conv (default); paper: step III only at "
                          "set-up and after convergence, dq_max < 10 eps (section 4.1)")
     ap.add_argument("--setup-timing", action="store_true",
-                    help="time the GPU constrained k-means (section 3.2), initial guess (section 3.3) and the library set-up (neighbour maps, "
+                    help="time the GPU atom neighbour map and constrained k-means (section 3.2), initial guess (section 3.3) and the library set-up (neighbour maps, "
                          "schedule, initial orthonormalization)")
     ap.add_argument("--gradient", action="store_true",
                     help="after the timed steps, time one energy-gradient evaluation (dE/dH0, dE/dS)")
@@ -142,6 +142,14 @@ def main():
         t = time.perf_counter()
         fragment_guess(system, system.atom_mol, nocc, system.atom_group[first], drop=1e-13)
         setup = dict(guess_ms=round(1e3 * (time.perf_counter() - t), 2), fragments=n_mol)
+        # atom neighbour map (section 3.2): the pattern S and H are given on
+        from paper_1402_2880_amd.sscf import atom_neighbours
+        cut = synth.SK_CUTOFF * synth.BOHR_PER_ANGSTROM
+        atom_neighbours(system.xyz_bohr, cut)                                            # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        nrp, _ = atom_neighbours(system.xyz_bohr, cut)
+        setup.update(atom_map_ms=round(1e3 * (time.perf_counter() - t), 2), atom_map_nnz=int(nrp[-1]))
         # constrained k-means (section 3.2) on the molecules' first atoms, N_link per group
         from paper_1402_2880_amd.sscf import constrained_kmeans
         pts = system.xyz_bohr[first]
@@ -156,7 +164,8 @@ def main():
     g = SparseSCF(system, eps=args.eps, e_conv=args.e_conv, precision=prec, profile=not args.no_profile)
     if setup is not None:
         setup["init_ms"] = round(1e3 * (time.time() - t), 1)
-        setup["includes"] = ("kmeans: copies, up to 100 iterations of attribution rounds + centroid move, copy back; "
+        setup["includes"] = ("atom map: copy, count pass, scan, fill pass, copy back (two calls: size, then map); "
+                             "kmeans: copies, up to 100 iterations of attribution rounds + centroid move, copy back; "
                              "guess: host-to-device copies, one thread per fragment, copy back, CSC assembly; "
                              "init: validation, neighbour map (GPU), pairs, rounds, uploads, initial orthonormalization")
     if args.schedule == "paper":

@@ -196,6 +196,21 @@ typedef struct {
 sscf_status sscf_fragment_guess(const sscf_guess_desc* d, int64_t* c0_colptr, int32_t* c0_row, double* c0_val,
                                 int64_t cap, int32_t* mo_group, int64_t* nnz, int32_t* n_occ);
 
+/* Atom neighbour map of section 3.2 on the GPU: the atom-block pattern of S and H.  Atoms a
+ * and b are neighbours when (dx*dx + dy*dy) + dz*dz < cutoff*cutoff in IEEE double, every
+ * operation rounded on its own (two-centre elements vanish beyond their radial cut-off, so
+ * every other pair has only zero elements); every atom is its own neighbour.  xyz: n_atoms x 3
+ * (host), in the unit of cutoff.  Output in caller-owned host arrays: rowptr[n_atoms + 1],
+ * col[cap], the CSR of the map in atom order with ascending columns; the cost grows with the
+ * number of 64-atom tiles whose bounding boxes come within the cut-off, so spatially ordered
+ * atoms (as the groups of the constrained k-means give) are cheapest.  *nnz receives the number
+ * of entries, also when cap is too small or rowptr/col are NULL (then SSCF_E_CAPACITY and
+ * nothing else is written).  SSCF_E_INVALID_ARG for n_atoms < 1, a NULL xyz or nnz, a
+ * non-finite or |coordinate| > 1e100, or a cutoff outside (0, 1e100].  Error text:
+ * sscf_last_error(NULL). */
+sscf_status sscf_atom_neighbours(int32_t n_atoms, const double* xyz, double cutoff, void* hip_stream,
+                                 int64_t* rowptr, int32_t* col, int64_t cap, int64_t* nnz);
+
 /* Inputs of the constrained k-means of section 3.2 (host memory, read during the call). */
 typedef struct {
   int32_t n_points;

@@ -1101,6 +1101,58 @@ sscf_status sscf_fragment_guess(const sscf_guess_desc* d, int64_t* c0_colptr, in
   }
 }
 
+sscf_status sscf_atom_neighbours(int32_t n_atoms, const double* xyz, double cutoff, void* hip_stream,
+                                 int64_t* rowptr, int32_t* col, int64_t cap, int64_t* nnz) {
+  if (!xyz || !nnz) {
+    g_init_error = "atom neighbours: NULL argument";
+    return SSCF_E_INVALID_ARG;
+  }
+  std::vector<void*> mem;
+  auto freeall = [&] { for (void* m : mem) hipFree(m); mem.clear(); };
+  try {
+    const int n = n_atoms;
+    if (n <= 0) fail(SSCF_E_INVALID_ARG, "atom neighbours: n_atoms must be positive");
+    if (!(cutoff > 0.0) || !(cutoff <= 1e100)) fail(SSCF_E_INVALID_ARG, "atom neighbours: cutoff must be in (0, 1e100]");
+    for (int64_t i = 0; i < 3LL * n; ++i)
+      if (!std::isfinite(xyz[i]) || std::fabs(xyz[i]) > 1e100) fail(SSCF_E_INVALID_ARG, "atom neighbours: bad coordinate");
+    hipStream_t s = (hipStream_t)hip_stream;
+    auto alloc = [&](size_t bytes) {
+      void* p = nullptr;
+      HIPC(hipMalloc(&p, bytes ? bytes : 1));
+      mem.push_back(p);
+      return p;
+    };
+    const int nt = (n + 63) / 64;
+    auto* dxyz = (double*)alloc(sizeof(double) * 3 * n);
+    auto* box = (double*)alloc(sizeof(double) * 6 * nt);
+    auto* cnt = (int*)alloc(sizeof(int) * n);
+    auto* drp = (int64_t*)alloc(sizeof(int64_t) * (n + 1));
+    HIPC(hipMemcpyAsync(dxyz, xyz, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s));
+    launch_atom_nbr_count(n, dxyz, cutoff, box, cnt, drp, s);
+    int64_t total = 0;
+    HIPC(hipMemcpyAsync(&total, drp + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    *nnz = total;
+    if (total > cap || !rowptr || !col)
+      fail(SSCF_E_CAPACITY, "atom neighbours: %lld entries do not fit in cap %lld", (long long)total, (long long)cap);
+    auto* dcol = (int*)alloc(sizeof(int) * total);
+    launch_atom_nbr_fill(n, dxyz, cutoff, box, drp, dcol, s);
+    HIPC(hipMemcpyAsync(rowptr, drp, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(col, dcol, sizeof(int) * total, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    freeall();
+    return SSCF_OK;
+  } catch (const Fail& f) {
+    freeall();
+    g_init_error = f.msg;
+    return f.code;
+  } catch (const std::exception& e) {
+    freeall();
+    g_init_error = e.what();
+    return SSCF_E_NOMEM;
+  }
+}
+
 sscf_status sscf_constrained_kmeans(const sscf_kmeans_desc* d, int32_t* group, double* means_out,
                                     sscf_kmeans_info* info) {
   if (!d || !group || !means_out) {

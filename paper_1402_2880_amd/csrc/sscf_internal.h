@@ -138,6 +138,10 @@ void launch_fragment_guess(int n_frag, const int* frag_atom0, const int64_t* ao_
                            const int* blk_col, const int64_t* blk_off, const int* atom_nao, const double* S,
                            const double* H, const int64_t* frag_coff, double* out, double* lam, int* err,
                            hipStream_t s);
+void launch_atom_nbr_count(int n, const double* xyz, double cutoff, double* box, int* cnt, int64_t* rowptr,
+                           hipStream_t s);
+void launch_atom_nbr_fill(int n, const double* xyz, double cutoff, const double* box, const int64_t* rowptr, int* col,
+                          hipStream_t s);
 void launch_km_rank(int n, int m, const double* pts, const double* means, int* rank, hipStream_t s);
 void launch_km_reset(int n, int m, int* assign, int* next, int* n_held, hipStream_t s);
 void launch_km_round(int n, int m, int n_link, const double* pts, const double* means, const int* rank, int* assign,

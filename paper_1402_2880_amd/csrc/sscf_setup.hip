@@ -376,3 +376,121 @@ void launch_km_move(int n, int m, const double* pts, const int* assign, const do
 }
 
 }  // namespace sscf
+
+namespace sscf {
+
+// ---------------------------------------------------------------------------------------
+// Atom neighbour map of section 3.2: atoms a and b are neighbours when some S or H element
+// between their AOs can be nonzero, which for two-centre elements with a radial cut-off means
+// |r_a - r_b|^2 < cutoff^2 (every atom is its own neighbour).  Output: CSR rows in atom order,
+// columns ascending.  The atoms are cut into tiles of 64 consecutive atoms; the wave of tile A
+// (one lane per atom a) walks every tile B whose bounding box can come within the cut-off and
+// tests the 64 atoms of B one after the other, so each lane meets its columns in ascending
+// order.  The bounding-box test only skips a tile when its gap exceeds the cut-off by a
+// relative 1e-9, far more than the rounding of the gap, so no neighbour is ever skipped; the
+// decision on each pair is taken on the rounded squared distance alone.
+// ---------------------------------------------------------------------------------------
+
+constexpr int NB_TILE = 64;
+
+// lo/hi corners of each tile's atoms (exact: min and max round nothing)
+__global__ void __launch_bounds__(64) k_tile_bbox(int n, const double* __restrict__ xyz, double* __restrict__ box) {
+  const int t = blockIdx.x, a = t * NB_TILE + threadIdx.x;
+  const bool in = a < n;
+  double lo[3], hi[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = in ? xyz[3 * a + d] : INFINITY;
+    hi[d] = in ? xyz[3 * a + d] : -INFINITY;
+  }
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = fmin(lo[d], __shfl_xor(lo[d], o));
+      hi[d] = fmax(hi[d], __shfl_xor(hi[d], o));
+    }
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) { box[6 * t + d] = lo[d]; box[6 * t + 3 + d] = hi[d]; }
+}
+
+// fill = 0: cnt[a] = number of neighbours of a.  fill = 1: col[rowptr[a] ..] = neighbours.
+__global__ void __launch_bounds__(64) k_atom_nbr(int n, const double* __restrict__ xyz, const double* __restrict__ box,
+                                                 double c2, double c2_skip, int fill, int* __restrict__ cnt,
+                                                 const int64_t* __restrict__ rowptr, int* __restrict__ col) {
+  __shared__ double bx[NB_TILE * 3];
+  const int ta = blockIdx.x, n_tiles = (n + NB_TILE - 1) / NB_TILE;
+  const int a = ta * NB_TILE + threadIdx.x;
+  const bool in = a < n;
+  const double ax = in ? xyz[3 * a] : 0.0, ay = in ? xyz[3 * a + 1] : 0.0, az = in ? xyz[3 * a + 2] : 0.0;
+  const double* A = box + 6 * ta;
+  int k = 0;
+  int64_t w = (fill && in) ? rowptr[a] : 0;
+  for (int tb = 0; tb < n_tiles; ++tb) {
+    const double* B = box + 6 * tb;
+    const double gx = fmax(0.0, fmax(B[0] - A[3], A[0] - B[3]));
+    const double gy = fmax(0.0, fmax(B[1] - A[4], A[1] - B[4]));
+    const double gz = fmax(0.0, fmax(B[2] - A[5], A[2] - B[5]));
+    if (sq_norm_rn(gx, gy, gz) > c2_skip) continue;          // wave-uniform
+    const int b0 = tb * NB_TILE, nb = min(NB_TILE, n - b0);
+    __syncthreads();
+    if ((int)threadIdx.x < nb) {
+      bx[3 * threadIdx.x] = xyz[3 * (b0 + threadIdx.x)];
+      bx[3 * threadIdx.x + 1] = xyz[3 * (b0 + threadIdx.x) + 1];
+      bx[3 * threadIdx.x + 2] = xyz[3 * (b0 + threadIdx.x) + 2];
+    }
+    __syncthreads();
+    if (!in) continue;
+    for (int j = 0; j < nb; ++j) {
+      const bool hit = sq_norm_rn(ax - bx[3 * j], ay - bx[3 * j + 1], az - bx[3 * j + 2]) < c2;
+      if (hit) {
+        if (fill) col[w++] = b0 + j;
+        else ++k;
+      }
+    }
+  }
+  if (!fill && in) cnt[a] = k;
+}
+
+// rowptr[0] = 0, rowptr[a + 1] = rowptr[a] + cnt[a] (one workgroup of 1024 threads; thread t
+// sums a contiguous chunk, the chunk sums are scanned in LDS, then every chunk is written)
+__global__ void __launch_bounds__(1024) k_row_scan(int n, const int* __restrict__ cnt, int64_t* __restrict__ rowptr) {
+  __shared__ int64_t part[1024];
+  const int t = threadIdx.x, per = (n + 1023) / 1024;
+  const int i0 = min(n, t * per), i1 = min(n, i0 + per);
+  int64_t s = 0;
+  for (int i = i0; i < i1; ++i) s += cnt[i];
+  part[t] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int64_t v = t >= o ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int64_t run = part[t] - s;                                // exclusive prefix of chunk t
+  if (t == 0) rowptr[0] = 0;
+  for (int i = i0; i < i1; ++i) {
+    run += cnt[i];
+    rowptr[i + 1] = run;
+  }
+}
+
+void launch_atom_nbr_count(int n, const double* xyz, double cutoff, double* box, int* cnt, int64_t* rowptr,
+                           hipStream_t s) {
+  const int nt = (n + NB_TILE - 1) / NB_TILE;
+  const double c2 = cutoff * cutoff;
+  hipLaunchKernelGGL(k_tile_bbox, dim3(nt), dim3(64), 0, s, n, xyz, box);
+  hipLaunchKernelGGL(k_atom_nbr, dim3(nt), dim3(64), 0, s, n, xyz, box, c2, c2 * (1.0 + 1e-9), 0, cnt,
+                     (const int64_t*)nullptr, (int*)nullptr);
+  hipLaunchKernelGGL(k_row_scan, dim3(1), dim3(1024), 0, s, n, cnt, rowptr);
+}
+void launch_atom_nbr_fill(int n, const double* xyz, double cutoff, const double* box, const int64_t* rowptr, int* col,
+                          hipStream_t s) {
+  const int nt = (n + NB_TILE - 1) / NB_TILE;
+  const double c2 = cutoff * cutoff;
+  hipLaunchKernelGGL(k_atom_nbr, dim3(nt), dim3(64), 0, s, n, xyz, box, c2, c2 * (1.0 + 1e-9), 1, (int*)nullptr,
+                     rowptr, col);
+}
+
+}  // namespace sscf

@@ -99,7 +99,8 @@ class KernelStat(ct.Structure):
 EXPORTS = ["sscf_get_kernel_stats", "sscf_reset_kernel_stats", "sscf_init_system", "sscf_set_fock", "sscf_scf_step", "sscf_get_energy",
            "sscf_get_density", "sscf_get_charges", "sscf_get_mo_coefficients", "sscf_init_info",
            "sscf_get_schedule", "sscf_get_energy_gradient", "sscf_set_control", "sscf_get_control",
-           "sscf_orthonormalize", "sscf_fragment_guess", "sscf_constrained_kmeans", "sscf_destroy",
+           "sscf_orthonormalize", "sscf_fragment_guess", "sscf_constrained_kmeans", "sscf_atom_neighbours",
+           "sscf_destroy",
            "sscf_last_error"]
 
 _lib = None
@@ -127,6 +128,7 @@ def lib():
                                           ct.POINTER(i32)]
         L.sscf_get_charges.argtypes = [vp, vp, sz]
         L.sscf_constrained_kmeans.argtypes = [ct.POINTER(KmeansDesc), vp, vp, ct.POINTER(KmeansInfo)]
+        L.sscf_atom_neighbours.argtypes = [i32, vp, ct.c_double, vp, vp, vp, i64, ct.POINTER(i64)]
         L.sscf_get_mo_coefficients.argtypes = [vp, vp, vp, vp, ct.POINTER(i64)]
         L.sscf_init_info.argtypes = [vp, ct.POINTER(StepInfo)]
         L.sscf_get_schedule.argtypes = [vp, vp, vp, vp, ct.POINTER(i32)]
@@ -435,3 +437,27 @@ def constrained_kmeans(points, means0, n_link: int, max_iter: int = 100, tol: fl
         raise SSCFError(rc, lib().sscf_last_error(None).decode())
     return group[:pts.shape[0]], means[:m0.shape[0]], dict(iterations=info.iterations, rounds=info.rounds,
                                                            displacement=info.displacement)
+
+
+def atom_neighbours(xyz, cutoff: float, stream=None):
+    """Atom neighbour map of section 3.2 on the GPU (see sscf_atom_neighbours).
+
+    Returns (rowptr int64[n + 1], col int32[nnz]): the CSR of the pairs closer than cutoff,
+    self pairs included, columns ascending.
+    """
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the sparse SCF library needs a GPU")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    x = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    n = x.shape[0]
+    nnz = ct.c_int64(0)
+    rc = lib().sscf_atom_neighbours(n, _p(x), cutoff, st.cuda_stream, None, None, 0, ct.byref(nnz))
+    if rc not in (SSCF_OK, STATUS_CAPACITY):
+        raise SSCFError(rc, lib().sscf_last_error(None).decode())
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    col = np.zeros(max(nnz.value, 1), dtype=np.int32)
+    rc = lib().sscf_atom_neighbours(n, _p(x), cutoff, st.cuda_stream, _p(rowptr), _p(col), nnz.value, ct.byref(nnz))
+    if rc != SSCF_OK:
+        raise SSCFError(rc, lib().sscf_last_error(None).decode())
+    return rowptr, col[:nnz.value]

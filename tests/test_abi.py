@@ -172,3 +172,16 @@ def test_fp32_form_flag_checked(small):
     d.precision = 7
     rc, msg, _ = _init(d)
     assert rc == -1 and "precision" in msg
+
+
+def test_atom_neighbours_host_checks():
+    """Bad neighbour-map inputs are refused before any device work."""
+    x = np.ascontiguousarray(np.random.default_rng(1).uniform(0, 1, (10, 3)))
+    nnz = ct.c_int64(0)
+    L = sscf.lib()
+    for n, xs, cut in [(0, x, 1.0), (10, x, 0.0), (10, x, float("nan")), (10, x, -1.0),
+                       (10, np.ascontiguousarray(np.where(x > 0.9, np.inf, x)), 1.0)]:
+        rc = L.sscf_atom_neighbours(n, xs.ctypes.data, cut, None, None, None, 0, ct.byref(nnz))
+        assert rc == -1, (n, cut)
+        assert "atom neighbours" in L.sscf_last_error(None).decode()
+    assert L.sscf_atom_neighbours(10, None, 1.0, None, None, None, 0, ct.byref(nnz)) == -1
