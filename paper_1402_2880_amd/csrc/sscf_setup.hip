@@ -4,8 +4,9 @@
 // Paper: A. Scemama, N. Renon, M. Rapacioli, "A Sparse SCF algorithm and its
 // parallel implementation: Application to DFTB", arXiv:1402.2880.
 //
-// Section 3.2: the MO-group neighbour map (k_group_nbr) and the constrained k-means that
-// defines the groups (k_km_*).  Section 3.3: the per-fragment initial guess
+// Section 3.2: the atom neighbour map (k_tile_bbox, k_atom_nbr, k_row_scan), the MO-group
+// neighbour map (k_group_nbr) and the constrained k-means that defines the groups (k_km_*).
+// Section 3.3: the per-fragment initial guess
 // (k_fragment_guess).  Squared distances are rounded operation by operation so that
 // decisions taken on them (a neighbour cut, a nearest mean) are the ones of the plain IEEE
 // expression.
