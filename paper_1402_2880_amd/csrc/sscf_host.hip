@@ -136,7 +136,7 @@ struct sscf_ctx {
   int2* rot_slot = nullptr;
   double* Rrot = nullptr;               // composed rotation of each Jacobi block, W x W
   // FP32 form: H, H C and the composed rotations in single precision
-  float *H32 = nullptr, *Y32 = nullptr, *R32 = nullptr;
+  float *H32 = nullptr, *Y32 = nullptr, *R32 = nullptr, *C32 = nullptr;
   double2* rot_cs = nullptr;
   unsigned int* hist = nullptr;
   long long* ties = nullptr;
@@ -697,6 +697,7 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
   if (x->precision == SSCF_FP32_MIXED) {
     x->H32 = x->dalloc<float>(nxe);
     x->Y32 = x->dalloc<float>(ntiles * tile_elems);
+    x->C32 = x->dalloc<float>(ntiles * tile_elems);
     x->R32 = x->dalloc<float>((size_t)x->n_blocks * v.W * v.W);
   } else {
     x->Rrot = x->dalloc<double>((size_t)x->n_blocks * v.W * v.W);
@@ -786,15 +787,16 @@ static void step(sscf_ctx* x, sscf_step_info* out) {
     launch_dilate(v, x->actC[x->cur], x->actY, s);
     launch_list(v, x->actY, x->listY, x->cntY, s);
     pi = x->pbegin(KC_SPMM);
-    launch_spmm32(v, x->H32, x->C[x->cur], x->actC[x->cur], x->cmask[x->cur], x->listY, x->cntY, x->Y32, x->ymask,
+    launch_round_c32(v, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur], x->C32, s);
+    launch_spmm32(v, x->H32, x->C32, x->actC[x->cur], x->cmask[x->cur], x->listY, x->cntY, x->Y32, x->ymask,
                   x->ctr(KC_SPMM), s);
     x->pend(pi);
     pi = x->pbegin(KC_PAIR_F);
-    launch_pair32(v, x->n_blocks, x->jb_perm, x->jb_maxc, x->jb_g, x->jb_h, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur],
+    launch_pair32(v, x->n_blocks, x->jb_perm, x->jb_maxc, x->jb_g, x->jb_h, x->C32, x->listC[x->cur], x->cntC[x->cur],
                   x->cmask[x->cur], x->Y32, x->actY, x->ymask, 0, v.OW / 16, v.OW, v.VW / 16, x->F, v.VW,
                   (size_t)v.OW * v.VW, x->ctr(KC_PAIR_F), s);
     x->pend(pi);
-    launch_coldot32(v, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur], x->Y32, x->actY, x->Fdiag, s);
+    launch_coldot32(v, x->C32, x->listC[x->cur], x->cntC[x->cur], x->Y32, x->actY, x->Fdiag, s);
   } else {
     x->product(x->H, true);
     pi = x->pbegin(KC_PAIR_F);

@@ -151,15 +151,16 @@ void launch_km_move(int n, int m, const double* pts, const int* assign, const do
 void launch_givens_rb(const View& v, int n_rounds, const int* roff, const int4* meta, const int* tcol,
                       const double* R, const float* R32, double eps, double* C, uint8_t* actC,
                       unsigned int* cmask, unsigned long long* ctr, hipStream_t s);
-void launch_spmm32(const View& v, const float* X, const double* C, const uint8_t* actC,
+void launch_spmm32(const View& v, const float* X, const float* C, const uint8_t* actC,
                    const unsigned int* cmask, const int* listY, const int* cntY, float* Y,
                    unsigned int* ymask, unsigned long long* ctr, hipStream_t s);
-void launch_pair32(const View& v, int n_pairs, const int* perm, int maxc, const int* pg, const int* ph, const double* C,
+void launch_pair32(const View& v, int n_pairs, const int* perm, int maxc, const int* pg, const int* ph, const float* C,
                    const int* listC, const int* cntC, const unsigned int* cmask, const float* Y,
                    const uint8_t* actY, const unsigned int* ymask, int row_off, int MT, int col_off,
                    int NT, double* out, int ld, size_t out_stride, unsigned long long* ctr,
                    hipStream_t s);
-void launch_coldot32(const View& v, const double* C, const int* listC, const int* cntC,
+void launch_round_c32(const View& v, const double* C, const int* list, const int* cnt, float* C32, hipStream_t s);
+void launch_coldot32(const View& v, const float* C, const int* listC, const int* cntC,
                      const float* Y, const uint8_t* actY, double* out, hipStream_t s);
 void launch_charges_rows(const View& v, const double* C, const uint8_t* actC, const double* Y,
                          const uint8_t* actY, const double* sc, const int* pnocc, double* rowq,

@@ -1475,14 +1475,27 @@ void launch_apply_occ(const View& v, const double* C, const uint8_t* actC, const
 
 // ---------------------------------------------------------------------------------------
 // FP32 form of C^T H C (the paper already runs this product in single precision, §4.1):
-// Y32 = H32 C and the occupied-virtual blocks and diagonal of C^T Y32, FP32 matrix cores
-// with FP32 accumulation; C itself stays FP64 and is rounded on load.
+// Y32 = H32 C32 and the occupied-virtual blocks and diagonal of C32^T Y32, FP32 matrix cores
+// with FP32 accumulation.  C itself stays FP64; C32 is its rounding to FP32, made once per
+// step for the active tiles (k_round_c32), so every product reads half the bytes.
 // ---------------------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_round_c32(int n_rb, int W, const double* __restrict__ C,
+                                                   const int* __restrict__ list, const int* __restrict__ cnt,
+                                                   float* __restrict__ C32) {
+  const int g = blockIdx.y, t = blockIdx.x;
+  if (t >= cnt[g]) return;
+  const size_t base = ((size_t)g * n_rb + list[(size_t)g * n_rb + t]) * (size_t)(RB * W);
+  for (int e = threadIdx.x; e < RB * W; e += 256) C32[base + e] = (float)C[base + e];
+}
+void launch_round_c32(const View& v, const double* C, const int* list, const int* cnt, float* C32, hipStream_t s) {
+  hipLaunchKernelGGL(k_round_c32, dim3(v.n_rb, v.G), dim3(256), 0, s, v.n_rb, v.W, C, list, cnt, C32);
+}
 
 template <int MW, int NW>
 __global__ void __launch_bounds__(256) k_pair32(int n_rb, int W, const int* __restrict__ perm, int maxc,
                                                 const int* __restrict__ pg, const int* __restrict__ ph,
-                                                const double* __restrict__ C, const int* __restrict__ listC,
+                                                const float* __restrict__ C, const int* __restrict__ listC,
                                                 const int* __restrict__ cntC, const unsigned int* __restrict__ cmask,
                                                 const float* __restrict__ Y, const uint8_t* __restrict__ actY,
                                                 const unsigned int* __restrict__ ymask, int row_off, int MT,
@@ -1526,22 +1539,17 @@ __global__ void __launch_bounds__(256) k_pair32(int n_rb, int W, const int* __re
         const int r = __shfl(rr, j);
         const unsigned int mj = __builtin_amdgcn_readfirstlane(__shfl((int)mab, j));
         const unsigned int ma = mj & 0xffffu, mb = mj >> 16;
-        const double* Ct = C + (gb + r) * (size_t)(RB * W) + row_off + mt0 * 16 + lr;
+        const float* Ct = C + (gb + r) * (size_t)(RB * W) + row_off + mt0 * 16 + lr;
         const float* Yt = Y + (hb + r) * (size_t)(RB * W) + col_off + nt0 * 16 + lr;
-        double ad[4][MW];
         float a[4][MW], b[4][NW];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           const int ro = (4 * s + lk) * W;
 #pragma unroll
-          for (int i = 0; i < MW; ++i) ad[s][i] = (ma & (1u << i)) ? Ct[ro + i * 16] : 0.0;
+          for (int i = 0; i < MW; ++i) a[s][i] = (ma & (1u << i)) ? Ct[ro + i * 16] : 0.f;
 #pragma unroll
           for (int jj = 0; jj < NW; ++jj) b[s][jj] = (mb & (1u << jj)) ? Yt[ro + jj * 16] : 0.f;
         }
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-          for (int i = 0; i < MW; ++i) a[s][i] = (float)ad[s][i];   // C rounded after the loads
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -1568,7 +1576,7 @@ __global__ void __launch_bounds__(256) k_pair32(int n_rb, int W, const int* __re
 }
 
 void launch_pair32(const View& v, int n_pairs, const int* perm, int maxc, const int* pg, const int* ph,
-                   const double* C, const int* listC,
+                   const float* C, const int* listC,
                    const int* cntC, const unsigned int* cmask, const float* Y, const uint8_t* actY,
                    const unsigned int* ymask, int row_off, int MT, int col_off, int NT, double* out, int ld,
                    size_t out_stride, unsigned long long* ctr, hipStream_t s) {
@@ -1586,7 +1594,7 @@ void launch_pair32(const View& v, int n_pairs, const int* perm, int maxc, const 
     hipLaunchKernelGGL((k_pair32<4, 4>), grid, blk, 0, s, v.n_rb, v.W, perm, maxc, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
 }
 
-__global__ void k_coldot32(int n_rb, int W, const double* C, const int* listC, const int* cntC, const float* Y,
+__global__ void k_coldot32(int n_rb, int W, const float* C, const int* listC, const int* cntC, const float* Y,
                            const uint8_t* actY, double* out) {
   const int g = blockIdx.x, c = threadIdx.x;
   if (c >= W) return;
@@ -1595,14 +1603,14 @@ __global__ void k_coldot32(int n_rb, int W, const double* C, const int* listC, c
   for (int t = 0; t < cntC[g]; ++t) {
     const int r = listC[gb + t];
     if (!actY[gb + r]) continue;
-    const double* Ct = C + (gb + r) * (size_t)(RB * W) + c;
+    const float* Ct = C + (gb + r) * (size_t)(RB * W) + c;
     const float* Yt = Y + (gb + r) * (size_t)(RB * W) + c;
 #pragma unroll
-    for (int k = 0; k < RB; ++k) s += (float)Ct[k * W] * Yt[k * W];
+    for (int k = 0; k < RB; ++k) s += Ct[k * W] * Yt[k * W];
   }
   out[(size_t)g * W + c] = (double)s;
 }
-void launch_coldot32(const View& v, const double* C, const int* listC, const int* cntC, const float* Y,
+void launch_coldot32(const View& v, const float* C, const int* listC, const int* cntC, const float* Y,
                      const uint8_t* actY, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_coldot32, dim3(v.G), dim3(v.W <= 64 ? 64 : (v.W <= 128 ? 128 : 256)), 0, s, v.n_rb, v.W, C,
                      listC, cntC, Y, actY, out);
@@ -1618,7 +1626,7 @@ void launch_coldot32(const View& v, const double* C, const int* listC, const int
 template <int NT, typename Real>
 __global__ void __launch_bounds__(256) k_spmm_row(int G, int n_rb, int nchunk, const int* __restrict__ xs_ptr,
                                                   const int* __restrict__ xs_col, const Real* __restrict__ X,
-                                                  const double* __restrict__ C, const uint8_t* __restrict__ actC,
+                                                  const Real* __restrict__ C, const uint8_t* __restrict__ actC,
                                                   const unsigned int* __restrict__ cmask,
                                                   const int* __restrict__ listY, const int* __restrict__ cntY,
                                                   Real* __restrict__ Y, unsigned int* __restrict__ ymask,
@@ -1655,20 +1663,14 @@ __global__ void __launch_bounds__(256) k_spmm_row(int G, int n_rb, int nchunk, c
       const int cj = __shfl(c, j);
       const unsigned int mj = __builtin_amdgcn_readfirstlane(__shfl((int)mk, j));
       const Real* Xb = X + (size_t)(base + j) * 256 + lr * 16 + lk;
-      const double* Ct = C + (pb + cj) * (RB * W) + lk * W + lr;
+      const Real* Ct = C + (pb + cj) * (RB * W) + lk * W + lr;
       Real xa[4], cb[4][NT];
 #pragma unroll
       for (int s = 0; s < 4; ++s) xa[s] = Xb[4 * s];
-      // C slices in FP64 (rounded afterwards in the FP32 form, outside the masked loads)
-      double cd[4][NT];
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int n = 0; n < NT; ++n) cd[s][n] = ((mj >> n) & 1u) ? Ct[4 * s * W + n * 16] : 0.0;
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int n = 0; n < NT; ++n) cb[s][n] = (Real)cd[s][n];
+        for (int n = 0; n < NT; ++n) cb[s][n] = ((mj >> n) & 1u) ? Ct[4 * s * W + n * 16] : Real(0);
       if constexpr (sizeof(Real) == sizeof(double)) {
 #pragma unroll
         for (int s = 0; s < 4; ++s)
@@ -1708,7 +1710,7 @@ __global__ void __launch_bounds__(256) k_spmm_row(int G, int n_rb, int nchunk, c
 }
 
 template <typename Real>
-static void launch_spmm_row(const View& v, const Real* X, const double* C, const uint8_t* actC,
+static void launch_spmm_row(const View& v, const Real* X, const Real* C, const uint8_t* actC,
                             const unsigned int* cmask, const int* listY, const int* cntY, Real* Y,
                             unsigned int* ymask, unsigned long long* ctr, hipStream_t s) {
   const int nchunk = (v.n_rb + 3) / 4;
@@ -1726,7 +1728,7 @@ void launch_spmm(const View& v, const double* X, const double* C, const uint8_t*
   launch_spmm_row<double>(v, X, C, actC, cmask, listY, cntY, Y, ymask, ctr, s);
 }
 
-void launch_spmm32(const View& v, const float* X, const double* C, const uint8_t* actC, const unsigned int* cmask,
+void launch_spmm32(const View& v, const float* X, const float* C, const uint8_t* actC, const unsigned int* cmask,
                    const int* listY, const int* cntY, float* Y, unsigned int* ymask, unsigned long long* ctr,
                    hipStream_t s) {
   launch_spmm_row<float>(v, X, C, actC, cmask, listY, cntY, Y, ymask, ctr, s);
