@@ -247,13 +247,15 @@ struct sscf_ctx {
   void rebuild_list(int b) { launch_list(v, actC[b], listC[b], cntC[b], stream); }
 
   // Y = X C on the dilated support of C
-  void product(const double* X, bool dilate) {
+  // Y = X C; occ_only: only the occupied columns of every panel are formed
+  void product(const double* X, bool dilate, bool occ_only = false) {
     if (dilate) {
       launch_dilate(v, actC[cur], actY, stream);
       launch_list(v, actY, listY, cntY, stream);
     }
+    const unsigned int smask = occ_only ? (1u << (v.OW / 16)) - 1u : 0xffffffffu;
     const int pi = pbegin(KC_SPMM);
-    launch_spmm(v, X, C[cur], actC[cur], cmask[cur], listY, cntY, Y, ymask, ctr(KC_SPMM), stream);
+    launch_spmm(v, X, C[cur], actC[cur], cmask[cur], listY, cntY, Y, ymask, smask, ctr(KC_SPMM), stream);
     pend(pi);
   }
 
@@ -263,7 +265,7 @@ struct sscf_ctx {
     int sweeps = 0;
     *converged = 0;
     for (;;) {
-      product(S, true);
+      product(S, true, occ_only != 0);
       const int W = v.W;
       const int pi = pbegin(KC_PAIR_O);
       const int nt = (occ_only ? v.OW : W) / 16;
@@ -312,7 +314,7 @@ struct sscf_ctx {
   void energy_terms() {
     launch_coulomb(v, scc, dq, part, Q, stream);
     launch_sum_coul(v, scc && !fock_full, dq, Q, sd, stream);
-    product(fock_full ? Hfull : H0, false);   // support of C unchanged since the last dilation
+    product(fock_full ? Hfull : H0, false, true);   // support of C unchanged since the last dilation
     launch_coldot(v, C[cur], listC[cur], cntC[cur], Y, actY, part, dvec, stream);
     launch_sum_band(v, dvec, pnocc, sd, stream);
   }
@@ -848,7 +850,7 @@ static void step(sscf_ctx* x, sscf_step_info* out) {
     info.n_ortho_sweeps = x->orthonormalize(0, x->max_sweeps_step, &eta, &conv);
   } else {
     // no step III: the charges take S C of the rotated MOs as they are
-    x->product(x->S, true);
+    x->product(x->S, true, true);
     launch_fill(x->sc, (size_t)v.G * v.W, 1.0, s);
   }
   info.ortho_eta = eta;
@@ -1354,9 +1356,9 @@ sscf_status sscf_get_energy_gradient(sscf_ctx* x, double* dE_dX, double* dE_dS, 
     }
     if (!x->pblk) x->pblk = x->dalloc<double>((size_t)v.nbx * 256);
     if (!x->pval) x->pval = x->dalloc<double>(x->n_val);
-    // the Fock matrix of the current charges, not truncated, and Y = H C
+    // the Fock matrix of the current charges, not truncated, and Y = H C_occ
     launch_fock(v, x->S, x->H0, x->fock_full ? x->Hfull : nullptr, x->Q, 0.0, x->H, nullptr, s);
-    x->product(x->H, true);
+    x->product(x->H, true, true);
     // occupied-occupied blocks C_g^T H C_h of every neighbouring pair, in both orientations
     const int no = v.OW / 16;
     launch_pair(v, x->n_pairs, x->pair_perm, x->pair_maxc, x->pg, x->ph, x->C[x->cur], x->listC[x->cur],

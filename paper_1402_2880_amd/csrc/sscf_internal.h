@@ -81,7 +81,7 @@ void launch_dilate(const View& v, const uint8_t* actC, uint8_t* actY, hipStream_
 void launch_list(const View& v, const uint8_t* act, int* list, int* cnt, hipStream_t s);
 void launch_spmm(const View& v, const double* X, const double* C, const uint8_t* actC,
                  const unsigned int* cmask, const int* listY, const int* cntY, double* Y,
-                 unsigned int* ymask, unsigned long long* ctr, hipStream_t s);
+                 unsigned int* ymask, unsigned int smask, unsigned long long* ctr, hipStream_t s);
 // perm / maxc: the items of a list sorted by group, laid out per XCD (see xcd_perm)
 void launch_pair(const View& v, int n_pairs, const int* perm, int maxc, const int* pg, const int* ph, const double* C,
                  const int* listC, const int* cntC, const unsigned int* cmask, const double* Y,

@@ -1617,7 +1617,8 @@ void launch_coldot32(const View& v, const float* C, const int* listC, const int*
 }
 
 // ---------------------------------------------------------------------------------------
-// Y = X C with one wave per output tile (g, r) and no workgroup synchronization.  A ballot
+// Y = X C with one wave per output tile (g, r) and no workgroup synchronization; only the
+// 16-column slices in smask are formed (the others are left zero).  A ballot
 // over the row's X blocks finds, 64 at a time, those whose C tile is active in panel g, with
 // its 16-column slice mask, before any product starts; the wave then streams the products,
 // the X block (A operand) and the C tile slices (B operand) read straight from L2 with all
@@ -1630,7 +1631,7 @@ __global__ void __launch_bounds__(256) k_spmm_row(int G, int n_rb, int nchunk, c
                                                   const unsigned int* __restrict__ cmask,
                                                   const int* __restrict__ listY, const int* __restrict__ cntY,
                                                   Real* __restrict__ Y, unsigned int* __restrict__ ymask,
-                                                  unsigned long long* ctr) {
+                                                  unsigned int smask, unsigned long long* ctr) {
   constexpr int W = NT * 16;
   typedef typename Mfma<Real>::acc_t acc_t;
   int chunk;
@@ -1654,7 +1655,7 @@ __global__ void __launch_bounds__(256) k_spmm_row(int G, int n_rb, int nchunk, c
     unsigned int mk = 0u;
     if (k < k1) {
       c = xs_col[k];
-      mk = actC[pb + c] ? cmask[pb + c] : 0u;
+      mk = actC[pb + c] ? (cmask[pb + c] & smask) : 0u;
     }
     unsigned long long m = __ballot(mk != 0u);
     while (m) {
@@ -1712,26 +1713,26 @@ __global__ void __launch_bounds__(256) k_spmm_row(int G, int n_rb, int nchunk, c
 template <typename Real>
 static void launch_spmm_row(const View& v, const Real* X, const Real* C, const uint8_t* actC,
                             const unsigned int* cmask, const int* listY, const int* cntY, Real* Y,
-                            unsigned int* ymask, unsigned long long* ctr, hipStream_t s) {
+                            unsigned int* ymask, unsigned int smask, unsigned long long* ctr, hipStream_t s) {
   const int nchunk = (v.n_rb + 3) / 4;
   dim3 grid(xcd_grid(v.G, nchunk)), blk(256);
   switch (v.W / 16) {
-#define SSCF_SPR(NT) case NT: hipLaunchKernelGGL((k_spmm_row<NT, Real>), grid, blk, 0, s, v.G, v.n_rb, nchunk, v.xs_ptr, v.xs_col, X, C, actC, cmask, listY, cntY, Y, ymask, ctr); break;
+#define SSCF_SPR(NT) case NT: hipLaunchKernelGGL((k_spmm_row<NT, Real>), grid, blk, 0, s, v.G, v.n_rb, nchunk, v.xs_ptr, v.xs_col, X, C, actC, cmask, listY, cntY, Y, ymask, smask, ctr); break;
     SSCF_SPR(1) SSCF_SPR(2) SSCF_SPR(3) SSCF_SPR(4) SSCF_SPR(5) SSCF_SPR(6) SSCF_SPR(7) SSCF_SPR(8)
 #undef SSCF_SPR
   }
 }
 
 void launch_spmm(const View& v, const double* X, const double* C, const uint8_t* actC, const unsigned int* cmask,
-                 const int* listY, const int* cntY, double* Y, unsigned int* ymask, unsigned long long* ctr,
-                 hipStream_t s) {
-  launch_spmm_row<double>(v, X, C, actC, cmask, listY, cntY, Y, ymask, ctr, s);
+                 const int* listY, const int* cntY, double* Y, unsigned int* ymask, unsigned int smask,
+                 unsigned long long* ctr, hipStream_t s) {
+  launch_spmm_row<double>(v, X, C, actC, cmask, listY, cntY, Y, ymask, smask, ctr, s);
 }
 
 void launch_spmm32(const View& v, const float* X, const float* C, const uint8_t* actC, const unsigned int* cmask,
                    const int* listY, const int* cntY, float* Y, unsigned int* ymask, unsigned long long* ctr,
                    hipStream_t s) {
-  launch_spmm_row<float>(v, X, C, actC, cmask, listY, cntY, Y, ymask, ctr, s);
+  launch_spmm_row<float>(v, X, C, actC, cmask, listY, cntY, Y, ymask, 0xffffffffu, ctr, s);
 }
 
 }  // namespace sscf
