@@ -502,139 +502,97 @@ void launch_clear_tiles(const View& v, double* C, uint8_t* act, unsigned int* cm
 // rows = MOs of a, columns = MOs of b; Dt holds the transposes, so D_sel(h, g) (rows = MOs
 // of h) is read row-contiguously in both orientations.
 //
-// A workgroup of UW waves owns UW output tiles of one group g (one per wave).  It first finds,
-// 64 neighbours at a time, the neighbours h whose pair is selected and whose C_h is active in
-// at least one of its rows.  For each such h it stages the fragments of D_sel(h, g) that hold
-// a selected entry in LDS, thresholded; the global loads of the next h are issued before the
-// MFMAs of the current one, so their latency is hidden behind them.  Each wave whose row has
-// C_h[r] active then runs its MFMAs from LDS, skipping zero fragments and 16-column slices of
-// C_h[r] known to be zero.  Skipping a zero fragment leaves the sum unchanged.
-constexpr int UW = 8;
-
+// One wave per output tile (g, r), no workgroup synchronization.  A ballot over g's
+// neighbours finds, 64 at a time, those h whose pair is selected and whose C_h is active at
+// row block r, with its 16-column slice mask.  Per such h the wave walks the k-steps four at
+// a time: the four C_h elements (A operand) and the D fragments that hold a selected entry
+// (B operand, thresholded at 1e-3 eta) are loaded together, straight from L2, then multiplied
+// on the matrix cores.  Fragments without a selected entry and k-steps in zero slices of
+// C_h[r] are skipped (adding zero would leave the sum unchanged).  The sum runs over h in
+// neighbour order and over k-steps in order, so the result does not depend on the launch.
+// (A form that staged each D block in LDS for 8 row blocks at a time spent a third of its
+// time in staging and barriers, with 39% of its waves idle per block: 16.8 against 14.0 ms
+// per launch over the same SCF steps of water4096.)
 template <int NT>
-__global__ void __launch_bounds__(UW * 64) k_ortho_update(int G, int n_rb, int nchunk, const double* __restrict__ C,
-                                                          const uint8_t* __restrict__ actC,
-                                                          const unsigned int* __restrict__ cmask,
-                                                          const int* __restrict__ gn_ptr, const int* __restrict__ gn,
-                                                          const int* __restrict__ pair_of,
-                                                          const uint8_t* __restrict__ pair_sel,
-                                                          const double* __restrict__ D, const double* __restrict__ Dt,
-                                                          const unsigned int* __restrict__ fmask,
-                                                          const Scalars* __restrict__ sd,
-                                                          const uint8_t* __restrict__ upd, double cut,
-                                                          const int* __restrict__ listN, const int* __restrict__ cntN,
-                                                          double* __restrict__ Cn, uint8_t* __restrict__ actN,
-                                                          unsigned int* __restrict__ cmaskN, unsigned long long* ctr) {
-  constexpr int W = NT * 16, KS = W / 4, SPW = (KS + UW - 1) / UW;
-  __shared__ double Ds[W * W];
-  __shared__ __align__(8) uint8_t frag[KS * 8];
-  __shared__ unsigned long long need;
+__global__ void __launch_bounds__(256) k_ortho_update(int G, int n_rb, int nchunk, const double* __restrict__ C,
+                                                      const uint8_t* __restrict__ actC,
+                                                      const unsigned int* __restrict__ cmask,
+                                                      const int* __restrict__ gn_ptr, const int* __restrict__ gn,
+                                                      const int* __restrict__ pair_of,
+                                                      const uint8_t* __restrict__ pair_sel,
+                                                      const double* __restrict__ D, const double* __restrict__ Dt,
+                                                      const unsigned int* __restrict__ fmask,
+                                                      const Scalars* __restrict__ sd,
+                                                      const uint8_t* __restrict__ upd, double cut,
+                                                      const int* __restrict__ listN, const int* __restrict__ cntN,
+                                                      double* __restrict__ Cn, uint8_t* __restrict__ actN,
+                                                      unsigned int* __restrict__ cmaskN, unsigned long long* ctr) {
+  constexpr int W = NT * 16, KS = W / 4;
   int chunk;
   const int g = xcd_group_chunk(nchunk, chunk);
   if (g >= G) return;
-  const int cnt = cntN[g];
-  const int t0 = chunk * UW;
-  if (t0 >= cnt) return;
-  const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int t = chunk * 4 + wv;
+  if (t >= cntN[g]) return;
+  const int lane = threadIdx.x & 63;
   const int lr = lane & 15, lk = lane >> 4;
-  const bool live = t0 + wv < cnt;
-  const int r = live ? listN[(size_t)g * n_rb + t0 + wv] : 0;
+  const int r = listN[(size_t)g * n_rb + t];
   const double thr = 1e-3 * __longlong_as_double((long long)sd->eta_bits);
   d4 acc[NT];
 #pragma unroll
   for (int n = 0; n < NT; ++n) acc[n] = d4{0.0, 0.0, 0.0, 0.0};
   unsigned int n_mfma = 0;
-  double dv[SPW][NT];       // this wave's fragments of the next D block
-  unsigned int fbits[SPW];  // which of them hold a selected entry (bit n)
-  // global loads of the fragments of D_sel(h, g) that this wave stages: strips wv, wv + UW, ...
-  auto fetch = [&](int h) {
-    const int p = pair_of[(size_t)g * G + h];
-    const bool tr = h > g;
-    const double* src = (tr ? Dt : D) + (size_t)p * W * W + lk * W + lr;
-    const unsigned int* fm = fmask + (size_t)p * 16 + (tr ? 8 : 0);
-#pragma unroll
-    for (int i = 0; i < SPW; ++i) {
-      const int st = wv + i * UW;
-      fbits[i] = 0u;
-#pragma unroll
-      for (int n = 0; n < NT; ++n) {
-        const int bit = st * NT + n;
-        const bool on = st < KS && ((fm[bit >> 5] >> (bit & 31)) & 1u);
-        dv[i][n] = on ? src[st * 4 * W + n * 16] : 0.0;
-        fbits[i] |= on ? (1u << n) : 0u;
-      }
-    }
-  };
-  auto stage = [&]() {
-#pragma unroll
-    for (int i = 0; i < SPW; ++i) {
-      const int st = wv + i * UW;
-      if (st < KS) {
-#pragma unroll
-        for (int n = 0; n < NT; ++n) {
-          if (fbits[i] & (1u << n)) Ds[st * 4 * W + lk * W + n * 16 + lr] = (fabs(dv[i][n]) >= thr) ? dv[i][n] : 0.0;
-          if (lane == 0) frag[st * 8 + n] = (uint8_t)((fbits[i] >> n) & 1u);
-        }
-      }
-    }
-  };
   const int k_end = gn_ptr[g + 1];
   for (int kb = gn_ptr[g]; kb < k_end; kb += 64) {
-    if (threadIdx.x == 0) need = 0ull;
-    __syncthreads();
-    {
-      const int k = kb + lane;
-      bool f = false;
-      if (live && k < k_end) {
-        const int h = gn[k];
-        f = pair_sel[pair_of[(size_t)g * G + h]] && actC[(size_t)h * n_rb + r];
-      }
-      const unsigned long long m = __ballot(f);
-      if (lane == 0 && m) atomicOr(&need, m);
+    const int k = kb + lane;
+    int h = 0;
+    unsigned int am = 0u;
+    if (k < k_end) {
+      h = gn[k];
+      const size_t th = (size_t)h * n_rb + r;
+      if (pair_sel[pair_of[(size_t)g * G + h]] && actC[th]) am = cmask[th];
     }
-    __syncthreads();
-    unsigned long long M = need;
-    __syncthreads();
-    if (!M) continue;
-    int h = gn[kb + __ffsll((long long)M) - 1];
-    M &= M - 1ull;
-    fetch(h);
-    for (;;) {
-      stage();
-      __syncthreads();
-      const int hc = h;
-      const bool more = M != 0ull;
-      if (more) {
-        h = gn[kb + __ffsll((long long)M) - 1];
-        M &= M - 1ull;
-        fetch(h);
-      }
-      const size_t th = (size_t)hc * n_rb + r;
-      if (live && actC[th]) {
-        const unsigned int am = cmask[th];
-        const double* Ch = C + th * (RB * W) + lr * W + lk;
-        const double* Dl = Ds + lk * W + lr;
-#pragma unroll 4
-        for (int s = 0; s < KS; ++s) {
-          if (!(am & (1u << (s >> 2)))) continue;
-          const double a = Ch[4 * s];
-          const uint2 fl = *reinterpret_cast<const uint2*>(frag + s * 8);
+    unsigned long long M = __ballot(am != 0u);
+    while (M) {
+      const int j = __ffsll((long long)M) - 1;
+      M &= M - 1ull;
+      const int hc = __shfl(h, j);
+      const unsigned int amj = __builtin_amdgcn_readfirstlane(__shfl((int)am, j));
+      const int p = pair_of[(size_t)g * G + hc];
+      const bool tr = hc > g;
+      const double* Dp = (tr ? Dt : D) + (size_t)p * W * W + lk * W + lr;
+      const unsigned int* fm = fmask + (size_t)p * 16 + (tr ? 8 : 0);
+      const double* Ch = C + ((size_t)hc * n_rb + r) * (RB * W) + lr * W + lk;
+      for (int s0 = 0; s0 < KS; s0 += 4) {
+        if (!(amj & (1u << (s0 >> 2)))) continue;        // the 4 k-steps share one slice
+        double a[4], b[4][NT];
+        unsigned int fb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int st = s0 + u;
+          a[u] = Ch[4 * st];
+          unsigned int f = 0u;
 #pragma unroll
           for (int n = 0; n < NT; ++n) {
-            const unsigned int fb = (n < 4) ? (fl.x >> (8 * n)) : (fl.y >> (8 * (n - 4)));
-            if (fb & 0xffu) {
-              acc[n] = mfma64(a, Dl[4 * s * W + n * 16], acc[n]);
+            const int bit = st * NT + n;
+            const bool on = (fm[bit >> 5] >> (bit & 31)) & 1u;
+            f |= on ? (1u << n) : 0u;
+            b[u][n] = on ? Dp[st * 4 * W + n * 16] : 0.0;
+          }
+          fb[u] = f;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int n = 0; n < NT; ++n)
+            if (fb[u] & (1u << n)) {
+              const double bv = (fabs(b[u][n]) >= thr) ? b[u][n] : 0.0;
+              acc[n] = mfma64(a[u], bv, acc[n]);
               ++n_mfma;
             }
-          }
-        }
       }
-      __syncthreads();
-      if (!more) break;
     }
   }
-  if (!live) return;
   const size_t tile = (size_t)g * n_rb + r;
   const bool own = actC[tile] != 0;
   const double* Cg = C + tile * (RB * W);
@@ -642,15 +600,15 @@ __global__ void __launch_bounds__(UW * 64) k_ortho_update(int G, int n_rb, int n
   unsigned int cm = 0;
 #pragma unroll
   for (int n = 0; n < NT; ++n) {
-    const int j = n * 16 + lr;
-    const bool u = upd[(size_t)g * W + j] != 0;
+    const int jj = n * 16 + lr;
+    const bool u = upd[(size_t)g * W + jj] != 0;
     int nz = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = lk + 4 * q;
-      double v = (own ? Cg[i * W + j] : 0.0) - 0.5 * acc[n][q];
+      double v = (own ? Cg[i * W + jj] : 0.0) - 0.5 * acc[n][q];
       if (u && fabs(v) < cut) v = 0.0;
-      Co[i * W + j] = v;
+      Co[i * W + jj] = v;
       nz |= (v != 0.0);
     }
     if (__ballot(nz)) cm |= 1u << n;
@@ -667,8 +625,8 @@ void launch_ortho_update(const View& v, const double* C, const uint8_t* actC, co
                          const unsigned int* fmask, const Scalars* sd, const uint8_t* upd, double cut,
                          const int* listN, const int* cntN, double* Cn, uint8_t* actN, const unsigned int* cmask,
                          unsigned int* cmaskN, unsigned long long* ctr, hipStream_t s) {
-  const int nchunk = (v.n_rb + UW - 1) / UW;
-  dim3 grid(xcd_grid(v.G, nchunk)), blk(UW * 64);
+  const int nchunk = (v.n_rb + 3) / 4;
+  dim3 grid(xcd_grid(v.G, nchunk)), blk(256);
   switch (v.W / 16) {
 #define SSCF_UPD(NT) case NT: hipLaunchKernelGGL(k_ortho_update<NT>, grid, blk, 0, s, v.G, v.n_rb, nchunk, C, actC, cmask, gn_ptr, gn, pair_of, pair_sel, D, Dt, fmask, sd, upd, cut, listN, cntN, Cn, actN, cmaskN, ctr); break;
     SSCF_UPD(1) SSCF_UPD(2) SSCF_UPD(3) SSCF_UPD(4) SSCF_UPD(5) SSCF_UPD(6) SSCF_UPD(7) SSCF_UPD(8)
