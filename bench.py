@@ -206,7 +206,11 @@ def main():
         per_launch_ms = st["ms"] / max(st["launches"], 1)
         if st["flops"] > 0:
             achieved = st["flops"] / st["launches"] / (per_launch_ms * 1e-3) / 1e12
-            peak = PEAK["fp64"] if args.precision == "fp64" else PEAK["fp32"]
+            # each class at the peak of the arithmetic it runs: FP64 matrix cores, except in the
+            # FP32 form the C^T H C blocks and the products (whose H C launches are FP32; priced at
+            # the FP32 peak, the lower fraction, although their S C launches stay FP64)
+            fp32_class = args.precision == "fp32" and name in ("pair_fock", "spmm_tiles")
+            peak = PEAK["fp32"] if fp32_class else PEAK["fp64"]
             roofline = dict(kernel=name, bound="mfma", achieved=round(achieved, 3), peak=peak,
                             unit="TFLOP/s", frac=round(achieved / peak, 4),
                             traffic=measured_traffic(name, args.config, args.precision),
