@@ -220,7 +220,7 @@ typedef struct {
   int32_t n_link;               /* most points one mean may hold (N_link), <= 1024       */
   int32_t max_iter;             /* iteration cap (>= 1)                                  */
   double tol;                   /* stop once the average displacement of the means < tol */
-  void* hip_stream;             /* stream of the work; NULL = default stream             */
+  void* hip_stream;             /* stream of the work; NULL = a stream of the call's own  */
 } sscf_kmeans_desc;
 
 typedef struct {
@@ -243,7 +243,9 @@ typedef struct {
  * mean of each point in the last attribution, means[m x 3] = the means after the last
  * move; info may be NULL.  The ordered atom list of the section is the points sorted by
  * (group, index).  SSCF_E_INVALID_ARG for NULL arrays, sizes out of range, m * n_link <
- * n_points, non-finite or |coordinate| > 1e100, max_iter < 1, tol < 0.
+ * n_points, non-finite or |coordinate| > 1e100, max_iter < 1, tol < 0.  The proposal rounds
+ * are replayed from a HIP graph captured on the work stream during the call (hence a stream of
+ * the call's own when hip_stream is NULL); the call returns after that stream has finished.
  * Error text: sscf_last_error(NULL). */
 sscf_status sscf_constrained_kmeans(const sscf_kmeans_desc* d, int32_t* group, double* means,
                                     sscf_kmeans_info* info);

@@ -1164,7 +1164,20 @@ sscf_status sscf_constrained_kmeans(const sscf_kmeans_desc* d, int32_t* group, d
     return SSCF_E_INVALID_ARG;
   }
   std::vector<void*> mem;
-  auto freeall = [&] { for (void* m : mem) hipFree(m); mem.clear(); };
+  hipStream_t own = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  auto freeall = [&] {
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    if (own) hipStreamSynchronize(own);
+    for (void* m : mem) hipFree(m);
+    mem.clear();
+    if (own) hipStreamDestroy(own);
+    own = nullptr;
+  };
   try {
     const int n = d->n_points, m = d->n_means, nl = d->n_link;
     if (n <= 0 || m <= 0 || nl <= 0 || !d->points || !d->means0)
@@ -1179,7 +1192,13 @@ sscf_status sscf_constrained_kmeans(const sscf_kmeans_desc* d, int32_t* group, d
       if (!std::isfinite(d->points[i]) || std::fabs(d->points[i]) > 1e100) fail(SSCF_E_INVALID_ARG, "kmeans: bad point coordinate");
     for (int64_t i = 0; i < 3LL * m; ++i)
       if (!std::isfinite(d->means0[i]) || std::fabs(d->means0[i]) > 1e100) fail(SSCF_E_INVALID_ARG, "kmeans: bad mean coordinate");
+    // the rounds are replayed from a captured graph, which needs a stream other than the
+    // legacy default one: without a caller's stream the work goes to a stream of its own
     hipStream_t s = (hipStream_t)d->hip_stream;
+    if (!s) {
+      HIPC(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+      s = own;
+    }
     auto alloc = [&](size_t bytes) {
       void* p = nullptr;
       HIPC(hipMalloc(&p, bytes ? bytes : 1));
@@ -1187,8 +1206,8 @@ sscf_status sscf_constrained_kmeans(const sscf_kmeans_desc* d, int32_t* group, d
       return p;
     };
     auto* pts = (double*)alloc(sizeof(double) * 3 * n);
-    auto* ma = (double*)alloc(sizeof(double) * 3 * m);
-    auto* mb = (double*)alloc(sizeof(double) * 3 * m);
+    auto* ma = (double*)alloc(sizeof(double) * 3 * m);     // current means (fixed: the graph reads it)
+    auto* mb = (double*)alloc(sizeof(double) * 3 * m);     // moved means
     auto* rank = (int*)alloc(sizeof(int) * (size_t)n * m);
     auto* assign = (int*)alloc(sizeof(int) * n);
     auto* next = (int*)alloc(sizeof(int) * n);
@@ -1204,6 +1223,12 @@ sscf_status sscf_constrained_kmeans(const sscf_kmeans_desc* d, int32_t* group, d
     // stays below m (the means hold m * n_link >= n points), so the rounds of one
     // attribution are at most n * (m - 1) + 1
     const int64_t max_rounds = (int64_t)n * (m - 1) + 1;
+    // one batch of rounds, captured once and replayed: the rounds are short and launch-bound
+    HIPC(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (int b = 0; b < BATCH; ++b)
+      launch_km_round(n, m, nl, pts, ma, rank, assign, next, prop, held, n_held, n_free + b, s);
+    HIPC(hipStreamEndCapture(s, &graph));
+    HIPC(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
     int it = 0;
     int64_t rounds_total = 0;
     double dsum = 0.0;
@@ -1213,8 +1238,7 @@ sscf_status sscf_constrained_kmeans(const sscf_kmeans_desc* d, int32_t* group, d
       int64_t r = 0;
       bool placed = false;
       while (!placed) {
-        for (int b = 0; b < BATCH; ++b)
-          launch_km_round(n, m, nl, pts, ma, rank, assign, next, prop, held, n_held, n_free + b, s);
+        HIPC(hipGraphLaunch(exec, s));
         int nf[BATCH];
         HIPC(hipMemcpyAsync(nf, n_free, sizeof(nf), hipMemcpyDeviceToHost, s));
         HIPC(hipStreamSynchronize(s));
@@ -1226,9 +1250,9 @@ sscf_status sscf_constrained_kmeans(const sscf_kmeans_desc* d, int32_t* group, d
       }
       rounds_total += r;
       launch_km_move(n, m, pts, assign, ma, mb, disp, s);
+      HIPC(hipMemcpyAsync(ma, mb, sizeof(double) * 3 * m, hipMemcpyDeviceToDevice, s));
       HIPC(hipMemcpyAsync(&dsum, disp, sizeof(double), hipMemcpyDeviceToHost, s));
       HIPC(hipStreamSynchronize(s));
-      std::swap(ma, mb);
       ++it;
       if (dsum / m < d->tol) break;
     }
