@@ -84,6 +84,11 @@ int orc_set_fock(orc_t* o, const double* f_val, int32_t mode);
  * step_ortho 1 = step III after every step, 0 = only at set-up and after convergence
  * (the order in which section 2 lists the steps) */
 int orc_set_control(orc_t* o, double eps, double e_conv, double dq_conv, int32_t criterion, int32_t step_ortho);
+/* The paper's literal variants, for quantifying the readings (not for parity):
+ * literal_rot: truncation |C| < eps after every single rotation instead of after each block;
+ * literal_ortho: the selected pairs combined one at a time in ascending (i, j) order, each
+ * pair's columns cut at 1e-3 eps at once, instead of C <- C - 1/2 C D_sel. */
+int orc_set_literal(orc_t* o, int32_t literal_rot, int32_t literal_ortho);
 
 /* step III on demand: all MOs (only_occ = 0) or the occupied ones; then charges, energy */
 int orc_orthonormalize(orc_t* o, int32_t only_occ, orc_step_info* info);

@@ -81,6 +81,7 @@ def lib():
         L.orc_gradient.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p]
         L.orc_orthonormalize.argtypes = [ct.c_void_p, ct.c_int32, ct.c_void_p]
         L.orc_set_control.argtypes = [ct.c_void_p, ct.c_double, ct.c_double, ct.c_double, ct.c_int32, ct.c_int32]
+        L.orc_set_literal.argtypes = [ct.c_void_p, ct.c_int32, ct.c_int32]
         L.orc_charges.argtypes = [ct.c_void_p, ct.c_void_p]
         L.orc_nnz_c.argtypes = [ct.c_void_p]
         L.orc_nnz_c.restype = ct.c_int64
@@ -186,6 +187,13 @@ class Oracle:
                     step_ortho: int = 1) -> None:
         """Thresholds and schedule from the next step on (see orc_set_control)."""
         rc = lib().orc_set_control(self._h, eps, e_conv, dq_conv, criterion, step_ortho)
+        if rc != 0:
+            raise OracleError(lib().orc_last_error(self._h).decode())
+
+    def set_literal(self, rotations: bool = True, combinations: bool = True) -> None:
+        """From the next step on, the paper's literal variants (see orc_set_literal): truncation
+        after every single rotation, and pair combinations one at a time in list order."""
+        rc = lib().orc_set_literal(self._h, int(rotations), int(combinations))
         if rc != 0:
             raise OracleError(lib().orc_last_error(self._h).decode())
 

@@ -36,6 +36,12 @@
  *  - each SCF step ends with a full re-orthonormalization; once |dE| < e_conv
  *    the occupied MOs are orthonormalized among themselves (section 4.1) and
  *    the charges and energy recomputed.
+ *
+ * A literal mode (orc_set_literal, not used for parity) takes the two
+ * order-dependent steps as the sections print them: truncation after every
+ * single rotation, and the pairs combined one at a time in ascending (i, j)
+ * order, each from the columns as they stand.  It measures how far the two
+ * readings above move the converged energy.
  */
 #include "oracle.h"
 
@@ -62,6 +68,7 @@ struct orc {
   int criterion;        /* 0: |dE| < e_conv; 1: dq_max < dq_conv                     */
   int step_ortho;       /* 1: step III after every step; 0: at set-up and after convergence */
   int max_sweeps_init, max_sweeps_step, scc, fock_full;
+  int literal_rot, literal_ortho;   /* the paper's literal variants (quantification only) */
   int n_atoms, n_ao, n_mo, n_occ, n_groups;
   int32_t* atom_nao;
   int64_t* ao_off;
@@ -369,6 +376,64 @@ static void overlap_mo(orc_t* o, int only_occ) {
 
 /* Orthonormalization loop (section 3.4; thresholds of section 4.1).
  * Returns ORC_OK, ORC_E_NOT_SPD; *converged tells whether eta < eps/100 was reached. */
+/* The section's combination taken literally: every selected pair (i, j), i < j, in
+ * ascending order, combined from the two columns as they stand at that moment,
+ * C'_i = C_i - 1/2 D_ij C_j and C'_j = C_j - 1/2 D_ij C_i, and the pair's two columns cut at
+ * |C| < cut right away.  Sequential; for quantifying the simultaneous reading only. */
+static void combine_pairs_in_order(orc_t* o, int n_scope, double thr, double cut) {
+  double* yi = xcalloc(o->n_ao, sizeof(double));
+  double* yj = xcalloc(o->n_ao, sizeof(double));
+  uint8_t* mark = xcalloc(o->n_ao, 1);
+  int32_t* list = xcalloc(o->n_ao, sizeof(int32_t));
+  for (int i = 0; i < n_scope; ++i) {
+    const int g = o->mo_group[i], il = o->mo_local[i], ng = n_in_group(o, g);
+    (void)ng;
+    for (int j = i + 1; j < n_scope; ++j) {
+      const int h = o->mo_group[j], jl = o->mo_local[j], nh = n_in_group(o, h);
+      int nbr = 0;
+      for (int k = o->gn_ptr[h]; k < o->gn_ptr[h + 1]; ++k) if (o->gn[k] == g) { nbr = 1; break; }
+      if (!nbr) continue;
+      const double d = oblk(o, g, h)[(size_t)il * nh + jl];
+      if (fabs(d) < thr) continue;
+      int32_t nt = 0;
+      for (int32_t t = 0; t < o->C[i].n; ++t) {
+        const int32_t mu = o->C[i].row[t];
+        if (!mark[mu]) { mark[mu] = 1; list[nt++] = mu; }
+        yi[mu] = o->C[i].val[t];
+      }
+      for (int32_t t = 0; t < o->C[j].n; ++t) {
+        const int32_t mu = o->C[j].row[t];
+        if (!mark[mu]) { mark[mu] = 1; list[nt++] = mu; }
+        yj[mu] = o->C[j].val[t];
+      }
+      qsort(list, nt, sizeof(int32_t), cmp_i32);
+      int32_t ki = 0, kj = 0;
+      for (int32_t t = 0; t < nt; ++t) {
+        const int32_t mu = list[t];
+        const double xi = yi[mu], xj = yj[mu];
+        yi[mu] = xi - 0.5 * d * xj;
+        yj[mu] = xj - 0.5 * d * xi;
+        ki += fabs(yi[mu]) >= cut;
+        kj += fabs(yj[mu]) >= cut;
+      }
+      col_t* ci = &o->C[i];
+      col_t* cj = &o->C[j];
+      col_free(ci);
+      col_free(cj);
+      ci->n = ki; ci->row = malloc(sizeof(int32_t) * (ki ? ki : 1)); ci->val = malloc(sizeof(double) * (ki ? ki : 1));
+      cj->n = kj; cj->row = malloc(sizeof(int32_t) * (kj ? kj : 1)); cj->val = malloc(sizeof(double) * (kj ? kj : 1));
+      int32_t wi = 0, wj = 0;
+      for (int32_t t = 0; t < nt; ++t) {
+        const int32_t mu = list[t];
+        if (fabs(yi[mu]) >= cut) { ci->row[wi] = mu; ci->val[wi] = yi[mu]; ++wi; }
+        if (fabs(yj[mu]) >= cut) { cj->row[wj] = mu; cj->val[wj] = yj[mu]; ++wj; }
+        yi[mu] = 0.0; yj[mu] = 0.0; mark[mu] = 0;
+      }
+    }
+  }
+  free(yi); free(yj); free(mark); free(list);
+}
+
 static int orthonormalize(orc_t* o, int only_occ, int max_sweeps, int* sweeps_out,
                           double* eta_out, int* converged) {
   const int n_scope = only_occ ? o->n_occ : o->n_mo;
@@ -415,6 +480,11 @@ static int orthonormalize(orc_t* o, int only_occ, int max_sweeps, int* sweeps_ou
     if (sweeps >= max_sweeps) break;
     /* pair combinations C'_j = C_j - 1/2 sum_i C_i D_ij over |D_ij| >= 1e-3 eta */
     const double thr = 1e-3 * eta;
+    if (o->literal_ortho) {
+      combine_pairs_in_order(o, n_scope, thr, cut);
+      ++sweeps;
+      continue;
+    }
 #pragma omp parallel
     {
       double* y = xcalloc(o->n_ao, sizeof(double));
@@ -678,6 +748,11 @@ static void apply_rotations(orc_t* o) {
             vi[k] = c * xi + s * xa;
             va[k] = -s * xi + c * xa;
           }
+          if (o->literal_rot)        /* truncation after every single rotation */
+            for (int32_t k = 0; k < nu; ++k) {
+              if (fabs(vi[k]) < o->eps) vi[k] = 0.0;
+              if (fabs(va[k]) < o->eps) va[k] = 0.0;
+            }
         }
         for (int t = 0; t < nc; ++t) {
           col_t* c = &o->C[cols[t]];
@@ -1080,6 +1155,13 @@ int orc_step(orc_t* o, orc_step_info* info) {
   s.energy = o->E; s.e_band = o->e_band; s.e_coul = o->e_coul;
   s.nnz_c = nnz_c(o);
   if (info) *info = s;
+  return ORC_OK;
+}
+
+int orc_set_literal(orc_t* o, int32_t literal_rot, int32_t literal_ortho) {
+  if (!o) return ORC_E_ARG;
+  o->literal_rot = literal_rot != 0;
+  o->literal_ortho = literal_ortho != 0;
   return ORC_OK;
 }
 
