@@ -52,13 +52,13 @@ def cpu_baseline(system, budget_s: float, eps: float, e_conv: float):
                        f"{t_sum:.1f} s")
 
 
-def step_traffic(kstats, elapsed_s: float, steps: int, config: str, precision: str):
+def step_traffic(kstats, elapsed_s: float, steps: int, config: str, precision: str, seed: int):
     """HBM traffic of the timed steps: each profiled kernel's measured bytes per launch times its
     launches in the timed window (the five MFMA / gather kernels; the rest move < 5% of the
     bytes), or None when the counter summary does not match the kernel source."""
     if kstats is None:
         return None
-    per = {k: measured_traffic(k, config, precision) for k in KERNEL_OF_CLASS}
+    per = {k: measured_traffic(k, config, precision, seed) for k in KERNEL_OF_CLASS}
     if any(v is None for v in per.values()):
         return None
     total = sum(per[k] * kstats[k]["launches"] for k in per if k in kstats)
@@ -66,10 +66,11 @@ def step_traffic(kstats, elapsed_s: float, steps: int, config: str, precision: s
                 kernels=sorted(per), source="profiles/traffic_water4096_fp64.json")
 
 
-def measured_traffic(kclass: str, config: str, precision: str):
+def measured_traffic(kclass: str, config: str, precision: str, seed: int):
     """HBM bytes per launch of the kernel class from the committed counter summary, or None."""
     import hashlib
-    if config != "water4096" or precision != "fp64" or not os.path.exists(TRAFFIC):
+    # the counters were taken on water4096 seed 1 in the FP64 form: no other workload uses them
+    if config != "water4096" or precision != "fp64" or seed != 1 or not os.path.exists(TRAFFIC):
         return None
     rec = json.load(open(TRAFFIC))
     if hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest() != rec.get("kernel_source_sha256"):
@@ -213,14 +214,14 @@ def main():
             peak = PEAK["fp32"] if fp32_class else PEAK["fp64"]
             roofline = dict(kernel=name, bound="mfma", achieved=round(achieved, 3), peak=peak,
                             unit="TFLOP/s", frac=round(achieved / peak, 4),
-                            traffic=measured_traffic(name, args.config, args.precision),
+                            traffic=measured_traffic(name, args.config, args.precision, args.seed),
                             traffic_unit="GB per launch",
                             avg_launch_ms=round(per_launch_ms, 4), launches=st["launches"])
         else:
             achieved = st["bytes"] / st["launches"] / (per_launch_ms * 1e-3) / 1e9
             roofline = dict(kernel=name, bound="hbm", achieved=round(achieved, 1), peak=PEAK["hbm"],
                             unit="GB/s", frac=round(achieved / PEAK["hbm"], 4),
-                            traffic=measured_traffic(name, args.config, args.precision),
+                            traffic=measured_traffic(name, args.config, args.precision, args.seed),
                             traffic_unit="GB per launch",
                             avg_launch_ms=round(per_launch_ms, 4), launches=st["launches"])
     grad = None
@@ -264,7 +265,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
-    hbm = step_traffic(kstats, elapsed, args.steps, args.config, args.precision)
+    hbm = step_traffic(kstats, elapsed, args.steps, args.config, args.precision, args.seed)
     if hbm is not None:
         out["hbm"] = hbm
     if grad is not None:
