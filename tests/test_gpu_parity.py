@@ -53,6 +53,24 @@ def test_water128_twenty_steps(water128):
     compare_steps(water128, 20, label="water128 seed 1")
 
 
+def test_water512_per_step():
+    """The 512-molecule box (the differentiation workload, 32 groups): every step to convergence,
+    candidate, rotation and sweep counts included."""
+    compare_steps(synth.make_config("water512", 1), 14, label="water512 seed 1")
+
+
+def test_fp32_form_water512():
+    from paper_1402_2880_amd.sscf import FP32_MIXED
+    s = synth.make_config("water512", 1)
+    o = Oracle(s)
+    g = gpu(s, precision=FP32_MIXED)
+    for k in range(14):
+        os_, gs = o.step(), g.step()
+        err = abs(gs["energy"] - os_["energy"])
+        print(f"[fp32] water512 step {k + 1} |dE| vs FP64 oracle {err:.2e}", flush=True)
+        assert err < FP32_TOL, (k, err)
+
+
 @pytest.mark.parametrize("seed", [2, 3])
 def test_water128_other_seeds(seed):
     compare_steps(synth.make_config("water128", seed), 8, label=f"water128 seed {seed}")
