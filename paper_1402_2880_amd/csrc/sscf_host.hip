@@ -1214,6 +1214,8 @@ sscf_status sscf_constrained_kmeans(const sscf_kmeans_desc* d, int32_t* group, d
     auto* prop = (int*)alloc(sizeof(int) * n);
     auto* held = (int*)alloc(sizeof(int) * (size_t)m * nl);
     auto* n_held = (int*)alloc(sizeof(int) * m);
+    auto* pcnt = (int*)alloc(sizeof(int) * m);
+    auto* plist = (int*)alloc(sizeof(int) * (size_t)m * KM_PCAP);
     constexpr int BATCH = 8;                 // rounds between two looks at the free counts
     auto* n_free = (int*)alloc(sizeof(int) * BATCH);
     auto* disp = (double*)alloc(sizeof(double));
@@ -1226,7 +1228,7 @@ sscf_status sscf_constrained_kmeans(const sscf_kmeans_desc* d, int32_t* group, d
     // one batch of rounds, captured once and replayed: the rounds are short and launch-bound
     HIPC(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     for (int b = 0; b < BATCH; ++b)
-      launch_km_round(n, m, nl, pts, ma, rank, assign, next, prop, held, n_held, n_free + b, s);
+      launch_km_round(n, m, nl, pts, ma, rank, assign, next, prop, pcnt, plist, held, n_held, n_free + b, s);
     HIPC(hipStreamEndCapture(s, &graph));
     HIPC(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
     int it = 0;
@@ -1234,7 +1236,7 @@ sscf_status sscf_constrained_kmeans(const sscf_kmeans_desc* d, int32_t* group, d
     double dsum = 0.0;
     for (it = 0; it < d->max_iter;) {
       launch_km_rank(n, m, pts, ma, rank, s);
-      launch_km_reset(n, m, assign, next, n_held, s);
+      launch_km_reset(n, m, assign, next, n_held, pcnt, s);
       int64_t r = 0;
       bool placed = false;
       while (!placed) {

@@ -33,6 +33,8 @@ constexpr int MAX_W = 128;       // widest panel supported
 constexpr int KM_SLOTS = 2048;         // LDS candidates of one mean in a k-means round
 constexpr int KM_MAX_LINK = 1024;      // largest n_link (a chunk scans KM_SLOTS - n_link points)
 constexpr int KM_MAX_MEANS = 4096;     // most means (the per-point sort of means lives in LDS)
+constexpr int KM_PCAP = 256;           // proposals listed per mean and round (more: a scan of all points)
+static_assert(KM_MAX_LINK + KM_PCAP <= KM_SLOTS, "listed proposals and kept points must fit in the LDS slots");
 constexpr int MAX_TIES = 4096;   // candidates sharing the cut-off |F| that can be ordered
 
 // scalars shared between kernels and the host (one device copy per context)
@@ -143,9 +145,10 @@ void launch_atom_nbr_count(int n, const double* xyz, double cutoff, double* box,
 void launch_atom_nbr_fill(int n, const double* xyz, double cutoff, const double* box, const int64_t* rowptr, int* col,
                           hipStream_t s);
 void launch_km_rank(int n, int m, const double* pts, const double* means, int* rank, hipStream_t s);
-void launch_km_reset(int n, int m, int* assign, int* next, int* n_held, hipStream_t s);
+void launch_km_reset(int n, int m, int* assign, int* next, int* n_held, int* pcnt, hipStream_t s);
 void launch_km_round(int n, int m, int n_link, const double* pts, const double* means, const int* rank, int* assign,
-                     int* next, int* prop, int* held, int* n_held, int* n_free, hipStream_t s);
+                     int* next, int* prop, int* pcnt, int* plist, int* held, int* n_held, int* n_free,
+                     hipStream_t s);
 void launch_km_move(int n, int m, const double* pts, const int* assign, const double* means, double* out,
                     double* disp, hipStream_t s);
 void launch_givens_rb(const View& v, int n_rounds, const int* roff, const int4* meta, const int* tcol,

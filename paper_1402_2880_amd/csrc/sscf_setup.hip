@@ -243,30 +243,41 @@ __global__ void __launch_bounds__(256) k_km_rank(int m, int m2, const double* __
 }
 
 // every point free, every mean empty
-__global__ void k_km_reset(int n, int m, int* __restrict__ assign, int* __restrict__ next, int* __restrict__ n_held) {
+__global__ void k_km_reset(int n, int m, int* __restrict__ assign, int* __restrict__ next, int* __restrict__ n_held,
+                           int* __restrict__ pcnt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) { assign[i] = -1; next[i] = 0; }
-  if (i < m) n_held[i] = 0;
+  if (i < m) { n_held[i] = 0; pcnt[i] = 0; }
 }
 
-// prop[p] = mean that free point p proposes to this round (-1: p is placed); clears the
-// round's count of turned-away points
+// prop[p] = mean that free point p proposes to this round (-1: p is placed); pcnt[c] counts
+// the proposals to mean c and plist holds the first KM_PCAP of them (in no particular order);
+// clears the round's count of turned-away points
 __global__ void k_km_propose(int n, int m, const int* __restrict__ rank, const int* __restrict__ assign,
-                             const int* __restrict__ next, int* __restrict__ prop, int* __restrict__ n_free) {
+                             const int* __restrict__ next, int* __restrict__ prop, int* __restrict__ pcnt,
+                             int* __restrict__ plist, int* __restrict__ n_free) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p == 0) *n_free = 0;
   if (p >= n) return;
-  prop[p] = (assign[p] < 0 && next[p] < m) ? rank[(size_t)p * m + next[p]] : -1;
+  const int c = (assign[p] < 0 && next[p] < m) ? rank[(size_t)p * m + next[p]] : -1;
+  prop[p] = c;
+  if (c >= 0) {
+    const int slot = atomicAdd(&pcnt[c], 1);
+    if (slot < KM_PCAP) plist[(size_t)c * KM_PCAP + slot] = p;
+  }
 }
 
-// Workgroup c: candidates are the points it holds and the points proposing to it.  The
-// proposals are scanned in chunks of KM_SLOTS - n_link points so that the candidates always
-// fit in LDS; after every chunk with more than n_link candidates they are sorted and the
-// ones past n_link are turned away at once (a held point loses its place, a proposer moves
-// on to its next mean).  A point is a candidate of exactly one mean in a round, so its
-// assign/next entries are written by one workgroup only.
+// Workgroup c: candidates are the points it holds and the points proposing to it.  With at
+// most KM_PCAP proposals they come from the mean's own list; otherwise the proposals are
+// scanned in chunks of KM_SLOTS - n_link points so that the candidates always fit in LDS.
+// Whenever there are more than n_link candidates they are sorted and the ones past n_link are
+// turned away at once (a held point loses its place, a proposer moves on to its next mean).
+// The sort by (squared distance, index) makes the arrival order of the proposals irrelevant.
+// A point is a candidate of exactly one mean in a round, so its assign/next entries are
+// written by one workgroup only.  A mean without proposals keeps what it holds.
 __global__ void __launch_bounds__(256) k_km_accept(int n, int n_link, const double* __restrict__ pts,
                                                    const double* __restrict__ means, const int* __restrict__ prop,
+                                                   int* __restrict__ pcnt, const int* __restrict__ plist,
                                                    int* __restrict__ assign, int* __restrict__ next,
                                                    int* __restrict__ held, int* __restrict__ n_held,
                                                    int* __restrict__ n_free) {
@@ -274,6 +285,8 @@ __global__ void __launch_bounds__(256) k_km_accept(int n, int n_link, const doub
   __shared__ int id[KM_SLOTS];
   __shared__ int cnt;
   const int c = blockIdx.x;
+  const int np = pcnt[c];
+  if (np == 0) return;
   const double cx = means[3 * c], cy = means[3 * c + 1], cz = means[3 * c + 2];
   int kept = n_held[c];
   for (int t = threadIdx.x; t < kept; t += blockDim.x) {
@@ -281,60 +294,94 @@ __global__ void __launch_bounds__(256) k_km_accept(int n, int n_link, const doub
     id[t] = p;
     key[t] = km_d2(pts + 3 * p, cx, cy, cz);
   }
-  const int chunk = KM_SLOTS - n_link;
-  for (int base = 0; base < n; base += chunk) {
+  // candidates [0, total) in LDS: keep the best n_link, turn the rest away
+  auto settle = [&](int total) -> int {
+    if (total <= n_link) return total;
+    int n2 = 1;
+    while (n2 < total) n2 <<= 1;                  // n2 <= KM_SLOTS
+    for (int s = total + threadIdx.x; s < n2; s += blockDim.x) { key[s] = INFINITY; id[s] = 0x7fffffff; }
+    __syncthreads();
+    km_bitonic(key, id, n2);
+    for (int s = n_link + threadIdx.x; s < total; s += blockDim.x) {
+      const int p = id[s];
+      if (assign[p] == c) assign[p] = -1;
+      next[p] += 1;
+      atomicAdd(n_free, 1);
+    }
+    return n_link;
+  };
+  if (np <= KM_PCAP) {
     if (threadIdx.x == 0) cnt = kept;
     __syncthreads();
-    const int end = min(n, base + chunk);
-    for (int p = base + threadIdx.x; p < end; p += blockDim.x)
-      if (prop[p] == c) {
-        const int s = atomicAdd(&cnt, 1);         // s < kept + chunk <= KM_SLOTS
-        id[s] = p;
-        key[s] = km_d2(pts + 3 * p, cx, cy, cz);
-      }
-    __syncthreads();
-    const int total = cnt;
-    if (total > n_link) {
-      int n2 = 1;
-      while (n2 < total) n2 <<= 1;                // n2 <= KM_SLOTS
-      for (int s = total + threadIdx.x; s < n2; s += blockDim.x) { key[s] = INFINITY; id[s] = 0x7fffffff; }
-      __syncthreads();
-      km_bitonic(key, id, n2);
-      for (int s = n_link + threadIdx.x; s < total; s += blockDim.x) {
-        const int p = id[s];
-        if (assign[p] == c) assign[p] = -1;
-        next[p] += 1;
-        atomicAdd(n_free, 1);
-      }
-      kept = n_link;
-    } else {
-      kept = total;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+      const int p = plist[(size_t)c * KM_PCAP + i];
+      const int s = atomicAdd(&cnt, 1);           // s < n_link + KM_PCAP <= KM_SLOTS
+      id[s] = p;
+      key[s] = km_d2(pts + 3 * p, cx, cy, cz);
     }
     __syncthreads();
+    kept = settle(cnt);
+    __syncthreads();
+  } else {
+    const int chunk = KM_SLOTS - n_link;
+    for (int base = 0; base < n; base += chunk) {
+      if (threadIdx.x == 0) cnt = kept;
+      __syncthreads();
+      const int end = min(n, base + chunk);
+      for (int p = base + threadIdx.x; p < end; p += blockDim.x)
+        if (prop[p] == c) {
+          const int s = atomicAdd(&cnt, 1);       // s < kept + chunk <= KM_SLOTS
+          id[s] = p;
+          key[s] = km_d2(pts + 3 * p, cx, cy, cz);
+        }
+      __syncthreads();
+      kept = settle(cnt);
+      __syncthreads();
+    }
   }
   for (int s = threadIdx.x; s < kept; s += blockDim.x) {
     const int p = id[s];
     held[(size_t)c * n_link + s] = p;
     assign[p] = c;
   }
-  if (threadIdx.x == 0) n_held[c] = kept;
+  if (threadIdx.x == 0) { n_held[c] = kept; pcnt[c] = 0; }
 }
 
-// one thread per mean: centroid of its points, coordinates summed in point order and
-// divided by the count (a mean without points stays where it is)
-__global__ void k_km_centroid(int n, int m, const double* __restrict__ pts, const int* __restrict__ assign,
-                              const double* __restrict__ means, double* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= m) return;
-  double sx = 0.0, sy = 0.0, sz = 0.0;
-  int k = 0;
-  for (int p = 0; p < n; ++p)
-    if (assign[p] == c) {
-      sx += pts[3 * p];
-      sy += pts[3 * p + 1];
-      sz += pts[3 * p + 2];
-      ++k;
+// workgroup c: centroid of mean c's points, coordinates summed in point order and divided by
+// the count (a mean without points stays where it is).  The points are first listed in
+// ascending order (ballot compaction, waves in order), then summed by one thread.
+__global__ void __launch_bounds__(256) k_km_centroid(int n, int m, const double* __restrict__ pts,
+                                                     const int* __restrict__ assign,
+                                                     const double* __restrict__ means, double* __restrict__ out) {
+  __shared__ int idx[KM_MAX_LINK];
+  __shared__ int wcnt[4];
+  const int c = blockIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int k = 0;                                          // points listed so far (same in every thread)
+  for (int base = 0; base < n; base += 256) {
+    const int p = base + (int)threadIdx.x;
+    const bool f = p < n && assign[p] == c;
+    const unsigned long long bal = __ballot(f);
+    if (lane == 0) wcnt[w] = __popcll(bal);
+    __syncthreads();
+    int off = k;
+    for (int v = 0; v < w; ++v) off += wcnt[v];
+    if (f) {
+      const int slot = off + __popcll(bal & ((1ull << lane) - 1ull));
+      if (slot < KM_MAX_LINK) idx[slot] = p;          // a mean holds at most n_link <= KM_MAX_LINK points
     }
+    k += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  k = min(k, KM_MAX_LINK);
+  double sx = 0.0, sy = 0.0, sz = 0.0;
+  for (int i = 0; i < k; ++i) {
+    const int p = idx[i];
+    sx += pts[3 * p];
+    sy += pts[3 * p + 1];
+    sz += pts[3 * p + 2];
+  }
   if (k == 0) {
     out[3 * c] = means[3 * c]; out[3 * c + 1] = means[3 * c + 1]; out[3 * c + 2] = means[3 * c + 2];
   } else {
@@ -360,19 +407,20 @@ void launch_km_rank(int n, int m, const double* pts, const double* means, int* r
   hipLaunchKernelGGL(k_km_rank, dim3(n), dim3(256), (size_t)m2 * (sizeof(double) + sizeof(int)), s, m, m2, pts,
                      means, rank);
 }
-void launch_km_reset(int n, int m, int* assign, int* next, int* n_held, hipStream_t s) {
+void launch_km_reset(int n, int m, int* assign, int* next, int* n_held, int* pcnt, hipStream_t s) {
   const int t = std::max(n, m);
-  hipLaunchKernelGGL(k_km_reset, dim3((t + 255) / 256), dim3(256), 0, s, n, m, assign, next, n_held);
+  hipLaunchKernelGGL(k_km_reset, dim3((t + 255) / 256), dim3(256), 0, s, n, m, assign, next, n_held, pcnt);
 }
 void launch_km_round(int n, int m, int n_link, const double* pts, const double* means, const int* rank, int* assign,
-                     int* next, int* prop, int* held, int* n_held, int* n_free, hipStream_t s) {
-  hipLaunchKernelGGL(k_km_propose, dim3((n + 255) / 256), dim3(256), 0, s, n, m, rank, assign, next, prop, n_free);
-  hipLaunchKernelGGL(k_km_accept, dim3(m), dim3(256), 0, s, n, n_link, pts, means, prop, assign, next, held, n_held,
-                     n_free);
+                     int* next, int* prop, int* pcnt, int* plist, int* held, int* n_held, int* n_free, hipStream_t s) {
+  hipLaunchKernelGGL(k_km_propose, dim3((n + 255) / 256), dim3(256), 0, s, n, m, rank, assign, next, prop, pcnt,
+                     plist, n_free);
+  hipLaunchKernelGGL(k_km_accept, dim3(m), dim3(256), 0, s, n, n_link, pts, means, prop, pcnt, plist, assign, next,
+                     held, n_held, n_free);
 }
 void launch_km_move(int n, int m, const double* pts, const int* assign, const double* means, double* out,
                     double* disp, hipStream_t s) {
-  hipLaunchKernelGGL(k_km_centroid, dim3((m + 63) / 64), dim3(64), 0, s, n, m, pts, assign, means, out);
+  hipLaunchKernelGGL(k_km_centroid, dim3(m), dim3(256), 0, s, n, m, pts, assign, means, out);
   hipLaunchKernelGGL(k_km_disp, dim3(1), dim3(64), 0, s, m, means, out, disp);
 }
 
