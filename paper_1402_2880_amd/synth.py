@@ -580,3 +580,98 @@ def water_molecules(o_pos_angstrom: np.ndarray, seed: int, mol_group=None, name:
     mg = np.zeros(n, dtype=np.int64) if mol_group is None else np.asarray(mol_group, dtype=np.int64)
     return assemble(name, seed, float(np.ptp(o)) if n > 1 else 0.0, xyz, el, np.repeat(np.arange(n), 3),
                     mg, int(mg.max()) + 1)
+
+
+# --------------------------------------------------------------------------------------
+# alkane-like chains: non-water molecules (carbon s+p, hydrogen s) and groups of chains
+# --------------------------------------------------------------------------------------
+
+CC_BOND, CH_BOND = 1.54, 1.09          # Angstrom
+CCC_ANGLE = np.deg2rad(112.0)
+TETRA = np.deg2rad(109.47)
+
+
+def _place(a, b, c, bond, angle, torsion):
+    """Atom d with |cd| = bond, angle(b, c, d) = angle, dihedral(a, b, c, d) = torsion."""
+    bc = c - b
+    bc /= np.linalg.norm(bc)
+    n = np.cross(b - a, bc)
+    n /= np.linalg.norm(n)
+    m = np.cross(n, bc)
+    d2 = np.array([-bond * np.cos(angle), bond * np.sin(angle) * np.cos(torsion), bond * np.sin(angle) * np.sin(torsion)])
+    return c + d2[0] * bc + d2[1] * m + d2[2] * n
+
+
+def alkane_chain(rng: np.random.Generator, n_c: int):
+    """One C_nH_(2n+2) chain in local coordinates, atoms ordered C, its H's, next C, ...:
+    a carbon backbone with C-C 1.54 A and C-C-C 112 degrees, torsions trans (180) or gauche
+    (+-65) drawn with probabilities 0.7 / 0.15 / 0.15 plus +-10 degrees of seeded noise, and
+    tetrahedral hydrogens at 1.09 A (three on each end carbon, two on the others)."""
+    c = [np.zeros(3), np.array([CC_BOND, 0.0, 0.0])]
+    if n_c >= 3:
+        c.append(c[1] + CC_BOND * np.array([-np.cos(CCC_ANGLE), np.sin(CCC_ANGLE), 0.0]))
+    for i in range(3, n_c):
+        u = rng.random()
+        tor = np.pi if u < 0.7 else (np.deg2rad(65.0) if u < 0.85 else -np.deg2rad(65.0))
+        tor += np.deg2rad(10.0) * (2.0 * rng.random() - 1.0)
+        c.append(_place(c[i - 3], c[i - 2], c[i - 1], CC_BOND, CCC_ANGLE, tor))
+    c = c[:n_c]
+    xyz, el = [], []
+    for i in range(n_c):
+        xyz.append(c[i])
+        el.append(EL_C)
+        if n_c == 1:
+            nb = []
+        else:
+            nb = [c[j] for j in (i - 1, i + 1) if 0 <= j < n_c]
+        if len(nb) == 2:                       # CH2: the two H in the plane bisecting C-C-C
+            u = (c[i] - nb[0]) / np.linalg.norm(c[i] - nb[0]) + (c[i] - nb[1]) / np.linalg.norm(c[i] - nb[1])
+            u /= np.linalg.norm(u)
+            v = np.cross(nb[0] - c[i], nb[1] - c[i])
+            v /= np.linalg.norm(v)
+            for sgn in (1.0, -1.0):
+                xyz.append(c[i] + CH_BOND * (np.cos(TETRA / 2) * u + sgn * np.sin(TETRA / 2) * v))
+                el.append(EL_H)
+        else:                                  # CH3 end: three H around the C-C axis
+            other = nb[0]
+            if n_c > 2:
+                ref = c[2] if i == 0 else c[i - 2]
+            else:
+                ref = other + np.array([0.0, 1.0, 0.0])
+            for k in range(3):
+                xyz.append(_place(ref, other, c[i], CH_BOND, TETRA, np.pi + k * 2.0 * np.pi / 3.0))
+                el.append(EL_H)
+    return np.array(xyz), np.array(el, dtype=np.int32)
+
+
+def alkane_box(n_chains: int, n_c: int, box: float, seed: int, n_link: int = 2, name: str = "") -> System:
+    """A seeded open box of n_chains C_nH_(2n+2) chains (each its own molecule and guess fragment),
+    placed with uniformly random centres and orientations and no two atoms of different chains
+    closer than 2.2 A; MO groups of n_link chains from the constrained k-means on chain centres."""
+    rng = np.random.default_rng(seed)
+    xyz_all, el_all, centres = [], [], []
+    for _ in range(n_chains):
+        local, el = alkane_chain(rng, n_c)
+        local = local - local.mean(axis=0)
+        for attempt in range(2000):
+            R = _random_rotations(rng, 1)[0]
+            pos = rng.uniform(0.0, box, 3)
+            cand = local @ R.T + pos
+            if all(np.min(((cand[:, None, :] - x[None, :, :]) ** 2).sum(-1)) >= 2.2 ** 2 for x in xyz_all):
+                break
+        else:
+            raise RuntimeError(f"alkane_box: no room for chain {len(xyz_all)} (seed {seed})")
+        xyz_all.append(cand)
+        el_all.append(el)
+        centres.append(pos)
+    centres = np.array(centres)
+    assign, means = constrained_kmeans(rng, centres, n_link)
+    used = np.unique(assign)
+    ren = np.full(assign.max() + 1, -1)
+    ren[used] = np.arange(used.size)
+    order = np.lexsort((np.arange(n_chains), ren[assign]))
+    per = len(el_all[0])
+    xyz = np.concatenate([xyz_all[i] for i in order])
+    el = np.concatenate([el_all[i] for i in order])
+    atom_mol = np.repeat(np.arange(n_chains), per)
+    return assemble(name or f"alkane{n_chains}x{n_c}", seed, box, xyz, el, atom_mol, ren[assign[order]], used.size)
