@@ -55,6 +55,10 @@ Q0 = {EL_O: 6.0, EL_H: 1.0, EL_C: 4.0}
 SK_V0 = 0.3       # Ha
 SK_SIGMA0 = 0.2   # dimensionless
 SK_R0 = 0.9       # Angstrom
+# pairs with a carbon atom: the curve above gives 0.05-0.09 Ha hoppings at C-C and C-H bond
+# lengths and metallic chains (H0 gap ~4e-4 Ha); covalent chains need stronger, longer-ranged
+# two-centre elements (gap ~0.6 Ha for octanes with these)
+SK_C_V0, SK_C_SIGMA0, SK_C_R0 = 1.5, 0.3, 1.2
 SK_CUTOFF = 6.0   # Angstrom
 
 OH_BOND = 0.96              # Angstrom
@@ -350,14 +354,16 @@ def _sk_block(el_a: int, el_b: int, d: np.ndarray, r: np.ndarray, kind: str) -> 
     """Blocks for many pairs of (el_a, el_b) atoms.  d: unit vectors a->b [P, 3], r in A.
 
     Returns [P, nao_a, nao_b].  kind 'H' -> (ss, sp, pp_sigma, pp_pi) = (-V, +V, +V, -V/2);
-    kind 'S' -> (+s, -s, -s, +s/2), with V = 0.3 exp(-r/0.9), s = 0.2 exp(-r/0.9).
+    kind 'S' -> (+s, -s, -s, +s/2), with V = 0.3 exp(-r/0.9), s = 0.2 exp(-r/0.9) (pairs with a
+    carbon: V = 1.5 exp(-r/1.2), s = 0.3 exp(-r/1.2)).
     """
-    e = np.exp(-r / SK_R0) * (r < SK_CUTOFF)
+    v0, s0, r0 = (SK_C_V0, SK_C_SIGMA0, SK_C_R0) if EL_C in (el_a, el_b) else (SK_V0, SK_SIGMA0, SK_R0)
+    e = np.exp(-r / r0) * (r < SK_CUTOFF)
     if kind == "H":
-        v = SK_V0 * e
+        v = v0 * e
         ss, sp, pps, ppp = -v, v, v, -0.5 * v
     else:
-        s = SK_SIGMA0 * e
+        s = s0 * e
         ss, sp, pps, ppp = s, -s, -s, 0.5 * s
     na, nb = NAO[el_a], NAO[el_b]
     P = r.shape[0]

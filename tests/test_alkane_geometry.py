@@ -43,3 +43,19 @@ def test_box_packing_and_seed():
     assert d[other].min() >= 2.2 - 1e-9
     assert s1.n_occ == 12 * (4 * 6 + 2 * 6 + 2) // 2                  # 19 doubly occupied MOs per C6H14
     assert np.bincount(s1.mo_group).max() <= 2 * (4 * 6 + 2 * 6 + 2)   # at most two chains per group
+
+
+def test_alkane_box_dense_limit_and_config_eps():
+    """Octane chains (carbon s+p, hydrogen s, groups of two chains): the oracle reaches the dense
+    SCC-DFTB energy in the dense limit, and stays within 1e-5 Ha of it at eps = 1e-5."""
+    from oracle.oracle import Oracle
+    from tests.dense_ref import dense_scf
+    s = synth.alkane_box(4, 8, 12.0, 2)
+    ref = dense_scf(s)
+    assert ref["converged"] and ref["gap"] > 0.3
+    for kw, tol in [(dict(eps=1e-12, e_conv=1e-13, r_nbr_bohr=1e6, max_sweeps_step=50), 1e-9), ({}, 1e-5)]:
+        o = Oracle(s, **kw)
+        for _ in range(80):
+            if o.step()["converged"]:
+                break
+        assert abs(o.energy() - ref["energy"]) < tol, (kw, o.energy() - ref["energy"])
