@@ -556,11 +556,16 @@ CONFIGS = {
     "water4096": dict(n_mol=4096, box=50.0),
     # differentiation case: 512 molecules, 25 A cube
     "water512": dict(n_mol=512, box=25.0),
+    # alkane-like chains at about the headline size: 400 octanes (10,400 atoms, 20,000 AOs),
+    # 60 A cube (about half the liquid density), groups of two chains
+    "octane400": dict(n_chains=400, n_c=8, box=60.0),
 }
 
 
 def make_config(name: str, seed: int = 1) -> System:
     c = CONFIGS[name]
+    if "n_chains" in c:
+        return alkane_box(c["n_chains"], c["n_c"], c["box"], seed, name=name)
     return water_box(c["n_mol"], c["box"], seed, name=name)
 
 
