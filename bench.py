@@ -98,6 +98,9 @@ def main():
     ap.add_argument("--setup-timing", action="store_true",
                     help="time the GPU atom neighbour map and constrained k-means (section 3.2), initial guess (section 3.3) and the library set-up (neighbour maps, "
                          "schedule, initial orthonormalization)")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="a step is the forward SCF step plus the energy gradient (dE/dH0, dE/dS) at its MOs, "
+                         "both inside the timed region")
     ap.add_argument("--gradient", action="store_true",
                     help="after the timed steps, time one energy-gradient evaluation (dE/dH0, dE/dS)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -176,6 +179,8 @@ def main():
         f"({g.init_info()['n_ortho_sweeps']} sweeps)")
     for k in range(args.warmup):
         si = g.step()
+        if args.adjoint:
+            g.energy_gradient()
         log(f"[bench] warmup {k + 1}: E {si['energy']:.10f} rot {si['n_rotations']} "
             f"{si['ms_total']:.1f} ms")
     if not args.no_profile:
@@ -185,6 +190,8 @@ def main():
     infos = []
     for k in range(args.steps):
         infos.append(g.step())
+        if args.adjoint:
+            g.energy_gradient()      # includes the copy of dE/dH0 and dE/dS to host memory
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     for k, si in enumerate(infos):
@@ -259,7 +266,9 @@ def main():
                                   f"paper schedule: eps {args.eps}, dq_max < {10 * args.eps}, step III at set-up "
                                   "and after convergence only")
                                + "; SCF steps "
-                               f"{args.warmup + 1}..{args.warmup + args.steps}",
+                               f"{args.warmup + 1}..{args.warmup + args.steps}"
+                               + ("; each step forward + adjoint (energy gradient, copied to the host)"
+                                  if args.adjoint else ""),
                    "precision": args.precision, "schedule": args.schedule, "energy_last": last["energy"],
                    "converged_last": bool(last["converged"])},
         "roofline": roofline,
