@@ -141,11 +141,16 @@ def main():
         first = np.searchsorted(system.atom_mol, np.arange(n_mol))
         last = np.searchsorted(system.atom_mol, np.arange(n_mol), side="right")
         nocc = np.array([int(round(system.q0[a:b].sum())) // 2 for a, b in zip(first, last)], dtype=np.int32)
-        fragment_guess(system, system.atom_mol, nocc, system.atom_group[first])      # warm-up
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        fragment_guess(system, system.atom_mol, nocc, system.atom_group[first], drop=1e-13)
-        setup = dict(guess_ms=round(1e3 * (time.perf_counter() - t), 2), fragments=n_mol)
+        aoo = system.ao_offset()
+        if int((aoo[last] - aoo[first]).max()) <= 8:
+            fragment_guess(system, system.atom_mol, nocc, system.atom_group[first])      # warm-up
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            fragment_guess(system, system.atom_mol, nocc, system.atom_group[first], drop=1e-13)
+            setup = dict(guess_ms=round(1e3 * (time.perf_counter() - t), 2), fragments=n_mol)
+        else:
+            setup = dict(guess_ms=None, fragments=n_mol,
+                         guess_note="molecules of more than 8 AOs: the GPU guess takes fragments of at most 8")
         # atom neighbour map (section 3.2): the pattern S and H are given on
         from paper_1402_2880_amd.sscf import atom_neighbours
         cut = synth.SK_CUTOFF * synth.BOHR_PER_ANGSTROM
