@@ -1,10 +1,10 @@
-"""Write the stored oracle values for the 12,288-atom water box (4096 molecules, seed 1).
+"""Write the stored oracle values for the 12,288-atom water box (4096 molecules, one seed).
 
 Calls only the FP64 oracle (oracle/) on inputs from the seeded generator.  The GPU
 test compares the library's set-up and first steps with these values because the
 oracle needs minutes per step at this size.
 
-    python tests/golden/make_golden.py [n_steps]
+    python tests/golden/make_golden.py [n_steps] [seed]
 """
 import json
 import os
@@ -20,13 +20,13 @@ from oracle.oracle import Oracle  # noqa: E402
 from paper_1402_2880_amd import synth  # noqa: E402
 
 
-def main(n_steps: int = 4):
-    s = synth.make_config("water4096", 1)
+def main(n_steps: int = 4, seed: int = 1):
+    s = synth.make_config("water4096", seed)
     t = time.time()
     o = Oracle(s, eps=1e-5, e_conv=1e-6)
     init = o.init_info()
     sample = np.arange(0, s.n_atoms, 97)
-    rec = dict(config="water4096", seed=1, eps=1e-5, e_conv=1e-6, n_atoms=s.n_atoms, n_ao=s.n_ao,
+    rec = dict(config="water4096", seed=seed, eps=1e-5, e_conv=1e-6, n_atoms=s.n_atoms, n_ao=s.n_ao,
                init=dict(energy=init["energy"], n_ortho_sweeps=init["n_ortho_sweeps"],
                          charges_sample=o.charges()[sample].tolist()),
                charge_sample_atoms=sample.tolist(), steps=[])
@@ -40,11 +40,11 @@ def main(n_steps: int = 4):
                                  max_abs_fov=si["max_abs_fov"],
                                  charges_sample=o.charges()[sample].tolist()))
         print("step", k + 1, round(time.time() - t, 1), si["energy"], flush=True)
-    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "water4096_seed1.json")
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"water4096_seed{seed}.json")
     with open(out, "w") as f:
         json.dump(rec, f, indent=1)
     print("wrote", out)
 
 
 if __name__ == "__main__":
-    main(int(sys.argv[1]) if len(sys.argv) > 1 else 4)
+    main(int(sys.argv[1]) if len(sys.argv) > 1 else 4, int(sys.argv[2]) if len(sys.argv) > 2 else 1)

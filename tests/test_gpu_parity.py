@@ -174,10 +174,12 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "wat
 
 
 @pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden values not generated")
-def test_water4096_against_stored_oracle():
-    """The 12,288-atom box: set-up and first steps against stored oracle values."""
-    rec = json.load(open(GOLDEN))
-    s = synth.make_config("water4096", 1)
+@pytest.mark.parametrize("seed", [1, 2])
+def test_water4096_against_stored_oracle(seed):
+    """The 12,288-atom box (two geometries): set-up and first steps against stored oracle values."""
+    rec = json.load(open(GOLDEN.replace("seed1", f"seed{seed}")))
+    assert rec["seed"] == seed
+    s = synth.make_config("water4096", seed)
     print(f"[parity] water4096 n_atoms={s.n_atoms}", flush=True)
     g = gpu(s, eps=rec["eps"], e_conv=rec["e_conv"])
     sample = np.array(rec["charge_sample_atoms"])
