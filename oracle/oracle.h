@@ -122,6 +122,59 @@ int orc_gradient(orc_t* o, double* dx_val, double* ds_val);
 /* the 2x2 rotation of one (occupied i, virtual a) pair from F_ii, F_aa, F_ia */
 void orc_jacobi_angle(double fii, double faa, double fia, double* c, double* s);
 
+/* ---- measurement only: nothing below changes a result ------------------------------ */
+
+/* Algorithmic work of the passes of one step, counted on the oracle's own state at the
+ * point where each pass runs (counting on: orc_set_count).  "nnz" counts stored values
+ * that are not zero; a flop is one multiplication or addition of the sparse operation
+ * itself, never of a padded or tiled form of it; bytes count each nonzero FP64 value read
+ * or written once (8 bytes).
+ *  ORC_W_PRODUCT:  Y = X C on the MOs of the pass (X = H for C^T H C, S in every sweep
+ *                  of step III, H0 on the occupied MOs for the band energy sum_i C_i^T H0 C_i):
+ *                  flops 2 sum_{nu, j} [C_nu,j != 0] nnz(X row nu); bytes 8 (nnz X + nnz C + nnz Y)
+ *  ORC_W_OVERLAP:  C^T S C over neighbouring groups, each unordered MO pair once, i from
+ *                  the lower group (lower local index within a group):
+ *                  flops 2 sum |supp C_i ∩ supp Y_j|; bytes 8 (nnz C + nnz Y + pairs)
+ *  ORC_W_FOCK_BLOCKS: occupied-virtual C_i^T (H C)_a of the Jacobi blocks, same counts
+ *  ORC_W_COMBINE:  C <- C - 1/2 C D_sel: flops 2 sum_{(i, j) selected, i != j} nnz C_i;
+ *                  bytes 8 (nnz C before + nnz C after + selected pairs)
+ *  ORC_W_ROTATE:   per Jacobi block, its rotations over the union U_b of the rows of its
+ *                  columns at the block's start: flops 6 n_rot_b |U_b|; bytes 16 times the
+ *                  nonzeros of those columns at the block's start (read and written once) */
+enum { ORC_W_PRODUCT = 0, ORC_W_OVERLAP = 1, ORC_W_FOCK_BLOCKS = 2, ORC_W_COMBINE = 3, ORC_W_ROTATE = 4,
+       ORC_W_N = 5 };
+#define ORC_W_MAX_SWEEPS 64
+typedef struct {
+  double flops[ORC_W_N];
+  double bytes[ORC_W_N];
+  int32_t passes[ORC_W_N];
+  int32_t n_sweeps;                          /* combination sweeps of the call           */
+  int64_t sweep_sel[ORC_W_MAX_SWEEPS];       /* selected ordered pairs (i, j), i != j     */
+  int64_t sweep_nnz_in[ORC_W_MAX_SWEEPS];    /* nnz of C (MOs of the sweep) entering      */
+  int64_t sweep_nnz_out[ORC_W_MAX_SWEEPS];   /* and leaving the combination               */
+  double sweep_flops[ORC_W_MAX_SWEEPS];
+} orc_work;
+
+/* counting on (1) or off (0, the default); the counts cover the last orc_step, set-up or
+ * orc_orthonormalize call made with counting on */
+int orc_set_count(orc_t* o, int32_t on);
+int orc_work_get(const orc_t* o, orc_work* out);
+
+/* Trace of the combination sweeps of the last call (on: orc_set_trace; for small systems):
+ * for sweep k, C entering the combination (normalized; CSC over the sweep's MOs) and the
+ * selected ordered pairs (i, j) with their D_ij, in the order the sweep visits them. */
+int orc_set_trace(orc_t* o, int32_t on);
+int orc_trace_sweeps(const orc_t* o);
+int orc_trace_sizes(const orc_t* o, int32_t k, int32_t* n_scope, int64_t* nnz, int64_t* n_sel, double* eta);
+int orc_trace_get(const orc_t* o, int32_t k, int64_t* colptr, int32_t* row, double* val, int32_t* sel_i,
+                  int32_t* sel_j, double* sel_d);
+
+/* last step's occupied-virtual C^T H C blocks, concatenated in block order, each row-major
+ * (occupied MOs of g) x (virtual MOs of h); *n receives the length (call with out NULL) */
+int orc_fov(const orc_t* o, double* out, int64_t* n);
+/* the truncated Fock matrix of the last step on the atom-block pattern (layout of S_val) */
+int orc_fock(const orc_t* o, double* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -58,6 +58,28 @@ class StepInfo(ct.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+W_CLASSES = ("product", "overlap", "fock_blocks", "combine", "rotate")
+W_MAX_SWEEPS = 64
+
+
+class Work(ct.Structure):
+    """Algorithmic work of one call (see orc_work in oracle.h); measurement only."""
+    _fields_ = [
+        ("flops", ct.c_double * 5), ("bytes", ct.c_double * 5), ("passes", ct.c_int32 * 5),
+        ("n_sweeps", ct.c_int32), ("sweep_sel", ct.c_int64 * W_MAX_SWEEPS),
+        ("sweep_nnz_in", ct.c_int64 * W_MAX_SWEEPS), ("sweep_nnz_out", ct.c_int64 * W_MAX_SWEEPS),
+        ("sweep_flops", ct.c_double * W_MAX_SWEEPS),
+    ]
+
+    def as_dict(self) -> Dict:
+        n = min(self.n_sweeps, W_MAX_SWEEPS)
+        return dict(
+            classes={c: dict(flops=self.flops[k], bytes=self.bytes[k], passes=self.passes[k])
+                     for k, c in enumerate(W_CLASSES)},
+            sweeps=[dict(sel=self.sweep_sel[k], nnz_in=self.sweep_nnz_in[k], nnz_out=self.sweep_nnz_out[k],
+                         flops=self.sweep_flops[k]) for k in range(n)])
+
+
 _lib = None
 
 
@@ -95,6 +117,15 @@ def lib():
         L.orc_jacobi_angle.argtypes = [ct.c_double, ct.c_double, ct.c_double,
                                        ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)]
         L.orc_jacobi_angle.restype = None
+        L.orc_set_count.argtypes = [ct.c_void_p, ct.c_int32]
+        L.orc_work_get.argtypes = [ct.c_void_p, ct.POINTER(Work)]
+        L.orc_set_trace.argtypes = [ct.c_void_p, ct.c_int32]
+        L.orc_trace_sweeps.argtypes = [ct.c_void_p]
+        L.orc_trace_sizes.argtypes = [ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int64),
+                                      ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)]
+        L.orc_trace_get.argtypes = [ct.c_void_p, ct.c_int32] + [ct.c_void_p] * 6
+        L.orc_fov.argtypes = [ct.c_void_p, ct.c_void_p, ct.POINTER(ct.c_int64)]
+        L.orc_fock.argtypes = [ct.c_void_p, ct.c_void_p]
         _lib = L
     return _lib
 
@@ -259,6 +290,51 @@ class Oracle:
         s = np.zeros(max(n, 1))
         lib().orc_rotations(self._h, _p(i), _p(a), _p(c), _p(s))
         return i[:n], a[:n], c[:n], s[:n]
+
+    # ---- measurement only ------------------------------------------------------------------
+    def set_count(self, on: bool = True) -> None:
+        """Count the algorithmic work of the following calls (see orc_work)."""
+        lib().orc_set_count(self._h, 1 if on else 0)
+
+    def work(self) -> Dict:
+        w = Work()
+        lib().orc_work_get(self._h, ct.byref(w))
+        return w.as_dict()
+
+    def set_trace(self, on: bool = True) -> None:
+        """Keep C and the selected pairs of each combination sweep of the following calls."""
+        lib().orc_set_trace(self._h, 1 if on else 0)
+
+    def trace(self):
+        """[(dict(n_scope, eta), (colptr, row, val), (sel_i, sel_j, sel_d))] of the last call."""
+        out = []
+        for k in range(lib().orc_trace_sweeps(self._h)):
+            ns, nnz, nsel, eta = ct.c_int32(), ct.c_int64(), ct.c_int64(), ct.c_double()
+            lib().orc_trace_sizes(self._h, k, ct.byref(ns), ct.byref(nnz), ct.byref(nsel), ct.byref(eta))
+            cp = np.zeros(ns.value + 1, dtype=np.int64)
+            r = np.zeros(max(nnz.value, 1), dtype=np.int32)
+            v = np.zeros(max(nnz.value, 1))
+            si = np.zeros(max(nsel.value, 1), dtype=np.int32)
+            sj = np.zeros(max(nsel.value, 1), dtype=np.int32)
+            sd = np.zeros(max(nsel.value, 1))
+            lib().orc_trace_get(self._h, k, _p(cp), _p(r), _p(v), _p(si), _p(sj), _p(sd))
+            out.append((dict(n_scope=ns.value, eta=eta.value), (cp, r[:nnz.value], v[:nnz.value]),
+                        (si[:nsel.value], sj[:nsel.value], sd[:nsel.value])))
+        return out
+
+    def fov(self) -> np.ndarray:
+        """Last step's occupied-virtual C^T H C blocks, concatenated in Jacobi-block order."""
+        n = ct.c_int64()
+        lib().orc_fov(self._h, None, ct.byref(n))
+        out = np.zeros(n.value)
+        lib().orc_fov(self._h, _p(out), ct.byref(n))
+        return out
+
+    def fock(self) -> np.ndarray:
+        """The truncated Fock matrix of the last step on the atom-block pattern."""
+        out = np.zeros(self.system.S_val.shape[0])
+        lib().orc_fock(self._h, _p(out))
+        return out
 
 
 def jacobi_angle(fii: float, faa: float, fia: float):

@@ -108,6 +108,20 @@ struct orc {
   double E, e_band, e_coul;
   orc_step_info init_info;
   char err[256];
+  /* measurement only (orc_set_count, orc_set_trace) */
+  int count_on, trace_on;
+  orc_work work;
+  int n_trace, cap_trace;
+  struct trace_sweep* trace;
+};
+
+struct trace_sweep {
+  int32_t n_scope;
+  int64_t nnz, n_sel;
+  double eta;
+  int64_t* colptr;
+  int32_t *row, *si, *sj;
+  double *val, *sd;
 };
 
 /* ----------------------------------------------------------------------------------- */
@@ -374,6 +388,215 @@ static void overlap_mo(orc_t* o, int only_occ) {
   }
 }
 
+/* ----------------------------------------------------------------------------------- */
+/* Work accounting (measurement only; see orc_work in oracle.h).  Each function counts  */
+/* one pass on the current state and adds to o->work; none changes a value.            */
+
+static int64_t count_nonzero(const double* x, int64_t n) {
+  int64_t c = 0;
+  for (int64_t t = 0; t < n; ++t) c += x[t] != 0.0;
+  return c;
+}
+
+static int64_t col_nnz(const col_t* c) { return count_nonzero(c->val, c->n); }
+
+/* nonzeros of row nu of the AO matrix X */
+static int64_t x_row_nnz(const orc_t* o, const double* X, int nu) {
+  return count_nonzero(X + o->rp[nu], o->rp[nu + 1] - o->rp[nu]);
+}
+
+/* Y = X C over MOs [0, n_scope) */
+static void work_product(orc_t* o, const double* X, int n_scope) {
+  const int64_t nnz_x = count_nonzero(X, o->rp[o->n_ao]);
+  double fl = 0.0, nc = 0.0, ny = 0.0;
+#pragma omp parallel reduction(+ : fl, nc, ny)
+  {
+    double* y = xcalloc(o->n_ao, sizeof(double));
+    uint8_t* mark = xcalloc(o->n_ao, 1);
+    int32_t* list = xcalloc(o->n_ao, sizeof(int32_t));
+#pragma omp for schedule(dynamic, 16)
+    for (int j = 0; j < n_scope; ++j) {
+      const col_t* c = &o->C[j];
+      for (int32_t t = 0; t < c->n; ++t)
+        if (c->val[t] != 0.0) { fl += (double)x_row_nnz(o, X, c->row[t]); nc += 1.0; }
+      const int32_t nt = spmv_col(o, X, c, y, mark, list);
+      for (int32_t t = 0; t < nt; ++t) ny += y[list[t]] != 0.0;
+      clear_touched(y, mark, list, nt);
+    }
+    free(y); free(mark); free(list);
+  }
+  o->work.flops[ORC_W_PRODUCT] += 2.0 * fl;
+  o->work.bytes[ORC_W_PRODUCT] += 8.0 * ((double)nnz_x + nc + ny);
+  o->work.passes[ORC_W_PRODUCT] += 1;
+}
+
+/* |supp C_i ∩ supp y| for a dense y */
+static int64_t support_meet(const col_t* c, const double* y) {
+  int64_t k = 0;
+  for (int32_t t = 0; t < c->n; ++t) k += c->val[t] != 0.0 && y[c->row[t]] != 0.0;
+  return k;
+}
+
+/* C^T S C pairs (only_occ: occupied MOs): for neighbouring groups g <= h, i in g and j in h,
+ * with local(i) <= local(j) when g == h */
+static void work_overlap(orc_t* o, int n_scope) {
+  double fl = 0.0, nc = 0.0, ny = 0.0, np = 0.0;
+#pragma omp parallel reduction(+ : fl, nc, ny, np)
+  {
+    double* y = xcalloc(o->n_ao, sizeof(double));
+    uint8_t* mark = xcalloc(o->n_ao, 1);
+    int32_t* list = xcalloc(o->n_ao, sizeof(int32_t));
+#pragma omp for schedule(dynamic, 4)
+    for (int j = 0; j < n_scope; ++j) {
+      nc += (double)col_nnz(&o->C[j]);
+      const int32_t nt = spmv_col(o, o->S, &o->C[j], y, mark, list);
+      for (int32_t t = 0; t < nt; ++t) ny += y[list[t]] != 0.0;
+      const int h = o->mo_group[j], jl = o->mo_local[j];
+      for (int k = o->gn_ptr[h]; k < o->gn_ptr[h + 1]; ++k) {
+        const int g = o->gn[k];
+        if (g > h) continue;
+        for (int il = 0; il < n_in_group(o, g); ++il) {
+          const int i = o->gm[o->gm_ptr[g] + il];
+          if (i >= n_scope || (g == h && il > jl)) continue;
+          fl += (double)support_meet(&o->C[i], y);
+          np += 1.0;
+        }
+      }
+      clear_touched(y, mark, list, nt);
+    }
+    free(y); free(mark); free(list);
+  }
+  o->work.flops[ORC_W_OVERLAP] += 2.0 * fl;
+  o->work.bytes[ORC_W_OVERLAP] += 8.0 * (nc + ny + np);
+  o->work.passes[ORC_W_OVERLAP] += 1;
+}
+
+/* occupied-virtual C_i^T (H C)_a of the Jacobi blocks */
+static void work_fock_blocks(orc_t* o) {
+  const int G = o->n_groups;
+  double fl = 0.0, nc = 0.0, ny = 0.0, np = 0.0;
+  for (int i = 0; i < o->n_occ; ++i) nc += (double)col_nnz(&o->C[i]);
+#pragma omp parallel reduction(+ : fl, ny, np)
+  {
+    double* y = xcalloc(o->n_ao, sizeof(double));
+    uint8_t* mark = xcalloc(o->n_ao, 1);
+    int32_t* list = xcalloc(o->n_ao, sizeof(int32_t));
+#pragma omp for schedule(dynamic, 4)
+    for (int a = o->n_occ; a < o->n_mo; ++a) {
+      const int32_t nt = spmv_col(o, o->H, &o->C[a], y, mark, list);
+      for (int32_t t = 0; t < nt; ++t) ny += y[list[t]] != 0.0;
+      const int h = o->mo_group[a];
+      for (int k = o->gn_ptr[h]; k < o->gn_ptr[h + 1]; ++k) {
+        const int g = o->gn[k];
+        if (o->jb_of[(size_t)g * G + h] < 0) continue;
+        for (int il = 0; il < o->g_nocc[g]; ++il) {
+          fl += (double)support_meet(&o->C[o->gm[o->gm_ptr[g] + il]], y);
+          np += 1.0;
+        }
+      }
+      clear_touched(y, mark, list, nt);
+    }
+    free(y); free(mark); free(list);
+  }
+  o->work.flops[ORC_W_FOCK_BLOCKS] += 2.0 * fl;
+  o->work.bytes[ORC_W_FOCK_BLOCKS] += 8.0 * (nc + ny + np);
+  o->work.passes[ORC_W_FOCK_BLOCKS] += 1;
+}
+
+static int64_t nnz_scope(const orc_t* o, int n_scope) {
+  int64_t n = 0;
+  for (int j = 0; j < n_scope; ++j) n += col_nnz(&o->C[j]);
+  return n;
+}
+
+/* the selected pairs of a combination sweep, before it runs (D in o->O, threshold thr);
+ * with the trace on, C entering and the pair list are kept */
+static void work_combine_begin(orc_t* o, int n_scope, double thr, double eta) {
+  double fl = 0.0, ns = 0.0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : fl, ns)
+  for (int j = 0; j < n_scope; ++j) {
+    const int h = o->mo_group[j], jl = o->mo_local[j], nh = n_in_group(o, h);
+    for (int k = o->gn_ptr[h]; k < o->gn_ptr[h + 1]; ++k) {
+      const int g = o->gn[k];
+      const double* Dgh = oblk(o, g, h);
+      for (int il = 0; il < n_in_group(o, g); ++il) {
+        const int i = o->gm[o->gm_ptr[g] + il];
+        if (i >= n_scope || i == j) continue;
+        if (fabs(Dgh[(size_t)il * nh + jl]) < thr) continue;
+        ns += 1.0;
+        fl += (double)col_nnz(&o->C[i]);
+      }
+    }
+  }
+  const int64_t nin = nnz_scope(o, n_scope);
+  o->work.flops[ORC_W_COMBINE] += 2.0 * fl;
+  o->work.bytes[ORC_W_COMBINE] += 8.0 * ((double)nin + ns);
+  o->work.passes[ORC_W_COMBINE] += 1;
+  const int k = o->work.n_sweeps;
+  if (k < ORC_W_MAX_SWEEPS) {
+    o->work.sweep_sel[k] = (int64_t)ns;
+    o->work.sweep_nnz_in[k] = nin;
+    o->work.sweep_flops[k] = 2.0 * fl;
+  }
+  if (o->trace_on) {
+    if (o->n_trace == o->cap_trace) {
+      o->cap_trace = o->cap_trace ? 2 * o->cap_trace : 8;
+      o->trace = realloc(o->trace, sizeof(struct trace_sweep) * o->cap_trace);
+    }
+    struct trace_sweep* t = &o->trace[o->n_trace++];
+    memset(t, 0, sizeof(*t));
+    t->n_scope = n_scope;
+    t->eta = eta;
+    t->colptr = xcalloc(n_scope + 1, sizeof(int64_t));
+    for (int j = 0; j < n_scope; ++j) t->colptr[j + 1] = t->colptr[j] + o->C[j].n;
+    t->nnz = t->colptr[n_scope];
+    t->row = xcalloc(t->nnz, sizeof(int32_t));
+    t->val = xcalloc(t->nnz, sizeof(double));
+    for (int j = 0; j < n_scope; ++j) {
+      memcpy(t->row + t->colptr[j], o->C[j].row, sizeof(int32_t) * o->C[j].n);
+      memcpy(t->val + t->colptr[j], o->C[j].val, sizeof(double) * o->C[j].n);
+    }
+    t->n_sel = (int64_t)ns;
+    t->si = xcalloc(t->n_sel, sizeof(int32_t));
+    t->sj = xcalloc(t->n_sel, sizeof(int32_t));
+    t->sd = xcalloc(t->n_sel, sizeof(double));
+    int64_t w = 0;
+    for (int j = 0; j < n_scope; ++j) {
+      const int h = o->mo_group[j], jl = o->mo_local[j], nh = n_in_group(o, h);
+      for (int k2 = o->gn_ptr[h]; k2 < o->gn_ptr[h + 1]; ++k2) {
+        const int g = o->gn[k2];
+        const double* Dgh = oblk(o, g, h);
+        for (int il = 0; il < n_in_group(o, g); ++il) {
+          const int i = o->gm[o->gm_ptr[g] + il];
+          const double d = Dgh[(size_t)il * nh + jl];
+          if (i >= n_scope || i == j || fabs(d) < thr) continue;
+          t->si[w] = i; t->sj[w] = j; t->sd[w] = d; ++w;
+        }
+      }
+    }
+  }
+}
+
+static void work_combine_end(orc_t* o, int n_scope) {
+  const int64_t nout = nnz_scope(o, n_scope);
+  o->work.bytes[ORC_W_COMBINE] += 8.0 * (double)nout;
+  if (o->work.n_sweeps < ORC_W_MAX_SWEEPS) o->work.sweep_nnz_out[o->work.n_sweeps] = nout;
+  o->work.n_sweeps += 1;
+}
+
+static void trace_clear(orc_t* o) {
+  for (int k = 0; k < o->n_trace; ++k) {
+    struct trace_sweep* t = &o->trace[k];
+    free(t->colptr); free(t->row); free(t->val); free(t->si); free(t->sj); free(t->sd);
+  }
+  o->n_trace = 0;
+}
+
+static void work_reset(orc_t* o) {
+  memset(&o->work, 0, sizeof(o->work));
+  trace_clear(o);
+}
+
 /* Orthonormalization loop (section 3.4; thresholds of section 4.1).
  * Returns ORC_OK, ORC_E_NOT_SPD; *converged tells whether eta < eps/100 was reached. */
 /* The section's combination taken literally: every selected pair (i, j), i < j, in
@@ -445,6 +668,10 @@ static int orthonormalize(orc_t* o, int only_occ, int max_sweeps, int* sweeps_ou
   double eta = 0.0;
   *converged = 0;
   for (;;) {
+    if (o->count_on) {
+      work_product(o, o->S, n_scope);
+      work_overlap(o, n_scope);
+    }
     overlap_mo(o, only_occ);
     /* normalize with the diagonal */
     int bad = 0;
@@ -485,6 +712,7 @@ static int orthonormalize(orc_t* o, int only_occ, int max_sweeps, int* sweeps_ou
       ++sweeps;
       continue;
     }
+    if (o->count_on || o->trace_on) work_combine_begin(o, n_scope, thr, eta);
 #pragma omp parallel
     {
       double* y = xcalloc(o->n_ao, sizeof(double));
@@ -535,6 +763,7 @@ static int orthonormalize(orc_t* o, int only_occ, int max_sweeps, int* sweeps_ou
       free(y); free(mark); free(list);
     }
     for (int j = 0; j < n_scope; ++j) { col_free(&o->C[j]); o->C[j] = Cn[j]; Cn[j].row = NULL; Cn[j].val = NULL; Cn[j].n = 0; }
+    if (o->count_on || o->trace_on) work_combine_end(o, n_scope);
     ++sweeps;
   }
   free(sc); free(Cn);
@@ -703,6 +932,7 @@ static void apply_rotations(orc_t* o) {
     rb1[b] = t + 1;
   }
   int32_t* blist = xcalloc(o->n_blocks, sizeof(int32_t));
+  double w_flops = 0.0, w_bytes = 0.0;      /* work accounting (orc_set_count) */
   for (int r = 0; r < o->n_rounds; ++r) {
     int nbl = 0;
     for (int b = 0; b < o->n_blocks; ++b)
@@ -732,6 +962,14 @@ static void apply_rotations(orc_t* o) {
         }
         qsort(U, nu, sizeof(int32_t), cmp_i32);
         for (int32_t k = 0; k < nu; ++k) pos[U[k]] = k;
+        if (o->count_on) {
+          int64_t nz = 0;
+          for (int t = 0; t < nc; ++t) nz += col_nnz(&o->C[cols[t]]);
+#pragma omp atomic
+          w_bytes += 16.0 * (double)nz;
+#pragma omp atomic
+          w_flops += 6.0 * (double)(rb1[b] - rb0[b]) * (double)nu;
+        }
         double* v = xcalloc((size_t)nc * (nu ? nu : 1), sizeof(double));
         for (int t = 0; t < nc; ++t) {
           const col_t* c = &o->C[cols[t]];
@@ -774,6 +1012,11 @@ static void apply_rotations(orc_t* o) {
     }
   }
   free(rb0); free(rb1); free(blist);
+  if (o->count_on) {
+    o->work.flops[ORC_W_ROTATE] += w_flops;
+    o->work.bytes[ORC_W_ROTATE] += w_bytes;
+    o->work.passes[ORC_W_ROTATE] += 1;
+  }
 }
 
 /* ----------------------------------------------------------------------------------- */
@@ -825,6 +1068,7 @@ static void density_charges(orc_t* o) {
 }
 
 static void energy(orc_t* o) {
+  if (o->count_on) work_product(o, o->fock_full ? o->Fuser : o->H0, o->n_occ);
   coulomb_q(o);
   double* rs = xcalloc(o->n_ao, sizeof(double));
   const double* X = o->fock_full ? o->Fuser : o->H0;
@@ -960,6 +1204,8 @@ static int64_t nnz_c(const orc_t* o) {
 
 void orc_destroy(orc_t* o) {
   if (!o) return;
+  trace_clear(o);
+  free(o->trace);
   if (o->C) for (int j = 0; j < o->n_mo; ++j) col_free(&o->C[j]);
   void* ptrs[] = {o->atom_nao, o->ao_off, o->ao_atom, o->xyz, o->U, o->q0, o->atom_group,
                   o->blk_rowptr, o->blk_col, o->blk_off, o->rp, o->ci, o->ao2blk, o->S, o->H0,
@@ -1114,9 +1360,14 @@ int orc_step(orc_t* o, orc_step_info* info) {
   orc_step_info s;
   memset(&s, 0, sizeof(s));
   const double E_prev = o->E;
+  if (o->count_on || o->trace_on) work_reset(o);
   double t = now_s(), t2;
   fock_build(o);                                   /* step IV: Fock matrix */
   t2 = now_s(); s.t_fock = t2 - t; t = t2;
+  if (o->count_on) {
+    work_product(o, o->H, o->n_mo);
+    work_fock_blocks(o);
+  }
   s.max_abs_fov = fmo(o);                          /* C^T H C */
   t2 = now_s(); s.t_fmo = t2 - t; t = t2;
   s.n_candidates = select_rotations(o);            /* step V */
@@ -1179,6 +1430,7 @@ int orc_set_control(orc_t* o, double eps, double e_conv, double dq_conv, int32_t
 int orc_orthonormalize(orc_t* o, int32_t only_occ, orc_step_info* info) {
   orc_step_info s;
   memset(&s, 0, sizeof(s));
+  if (o->count_on || o->trace_on) work_reset(o);
   int sweeps = 0, conv = 0;
   double eta = 0.0;
   int rc = orthonormalize(o, only_occ ? 1 : 0, o->max_sweeps_init, &sweeps, &eta, &conv);
@@ -1232,4 +1484,43 @@ int orc_n_rot(const orc_t* o) { return o->n_rot; }
 int orc_rotations(const orc_t* o, int32_t* i, int32_t* a, double* c, double* s) {
   for (int t = 0; t < o->n_rot; ++t) { i[t] = o->rot_i[t]; a[t] = o->rot_a[t]; c[t] = o->rot_c[t]; s[t] = o->rot_s[t]; }
   return o->n_rot;
+}
+
+/* ---- measurement only ---------------------------------------------------------------- */
+
+int orc_set_count(orc_t* o, int32_t on) { o->count_on = on != 0; return ORC_OK; }
+int orc_work_get(const orc_t* o, orc_work* out) { *out = o->work; return ORC_OK; }
+int orc_set_trace(orc_t* o, int32_t on) { o->trace_on = on != 0; return ORC_OK; }
+int orc_trace_sweeps(const orc_t* o) { return o->n_trace; }
+
+int orc_trace_sizes(const orc_t* o, int32_t k, int32_t* n_scope, int64_t* nnz, int64_t* n_sel, double* eta) {
+  if (k < 0 || k >= o->n_trace) return ORC_E_ARG;
+  const struct trace_sweep* t = &o->trace[k];
+  *n_scope = t->n_scope; *nnz = t->nnz; *n_sel = t->n_sel; *eta = t->eta;
+  return ORC_OK;
+}
+
+int orc_trace_get(const orc_t* o, int32_t k, int64_t* colptr, int32_t* row, double* val, int32_t* sel_i,
+                  int32_t* sel_j, double* sel_d) {
+  if (k < 0 || k >= o->n_trace) return ORC_E_ARG;
+  const struct trace_sweep* t = &o->trace[k];
+  memcpy(colptr, t->colptr, sizeof(int64_t) * (t->n_scope + 1));
+  memcpy(row, t->row, sizeof(int32_t) * t->nnz);
+  memcpy(val, t->val, sizeof(double) * t->nnz);
+  memcpy(sel_i, t->si, sizeof(int32_t) * t->n_sel);
+  memcpy(sel_j, t->sj, sizeof(int32_t) * t->n_sel);
+  memcpy(sel_d, t->sd, sizeof(double) * t->n_sel);
+  return ORC_OK;
+}
+
+int orc_fov(const orc_t* o, double* out, int64_t* n) {
+  *n = o->jb_foff[o->n_blocks];
+  if (out) memcpy(out, o->F, sizeof(double) * (size_t)*n);
+  return ORC_OK;
+}
+
+int orc_fock(const orc_t* o, double* out) {
+  memset(out, 0, sizeof(double) * o->nblkval);
+  for (int64_t k = 0; k < o->rp[o->n_ao]; ++k) out[o->ao2blk[k]] = o->H[k];
+  return ORC_OK;
 }

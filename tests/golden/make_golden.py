@@ -1,8 +1,11 @@
 """Write the stored oracle values for the 12,288-atom water box (4096 molecules, one seed).
 
 Calls only the FP64 oracle (oracle/) on inputs from the seeded generator.  The GPU
-test compares the library's set-up and first steps with these values because the
-oracle needs minutes per step at this size.
+tests compare the library's set-up and steps with these values, and the benchmark
+states its energy error against them, because the oracle needs half a minute or
+more per step at this size.  Each step also records the oracle's count of the
+algorithmic work of its passes (orc_work), which the library's own counters are
+checked against.
 
     python tests/golden/make_golden.py [n_steps] [seed]
 """
@@ -20,10 +23,11 @@ from oracle.oracle import Oracle  # noqa: E402
 from paper_1402_2880_amd import synth  # noqa: E402
 
 
-def main(n_steps: int = 4, seed: int = 1):
+def main(n_steps: int = 25, seed: int = 1):
     s = synth.make_config("water4096", seed)
     t = time.time()
     o = Oracle(s, eps=1e-5, e_conv=1e-6)
+    o.set_count(True)
     init = o.init_info()
     sample = np.arange(0, s.n_atoms, 97)
     rec = dict(config="water4096", seed=seed, eps=1e-5, e_conv=1e-6, n_atoms=s.n_atoms, n_ao=s.n_ao,
@@ -37,14 +41,17 @@ def main(n_steps: int = 4, seed: int = 1):
         rec["steps"].append(dict(energy=si["energy"], delta_e=si["delta_e"], dq_max=si["dq_max"],
                                  n_candidates=si["n_candidates"], n_rotations=si["n_rotations"],
                                  n_ortho_sweeps=si["n_ortho_sweeps"], converged=si["converged"],
-                                 max_abs_fov=si["max_abs_fov"],
+                                 post_ortho=si["post_ortho"], max_abs_fov=si["max_abs_fov"],
+                                 nnz_c=si["nnz_c"], work=o.work(),
                                  charges_sample=o.charges()[sample].tolist()))
         print("step", k + 1, round(time.time() - t, 1), si["energy"], flush=True)
-    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"water4096_seed{seed}.json")
-    with open(out, "w") as f:
-        json.dump(rec, f, indent=1)
+        # written after every step, so that an interrupted run keeps what it has
+        out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"water4096_seed{seed}.json")
+        with open(out + ".tmp", "w") as f:
+            json.dump(rec, f, indent=1)
+        os.replace(out + ".tmp", out)
     print("wrote", out)
 
 
 if __name__ == "__main__":
-    main(int(sys.argv[1]) if len(sys.argv) > 1 else 4, int(sys.argv[2]) if len(sys.argv) > 2 else 1)
+    main(int(sys.argv[1]) if len(sys.argv) > 1 else 25, int(sys.argv[2]) if len(sys.argv) > 2 else 1)
