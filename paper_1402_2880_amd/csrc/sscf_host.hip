@@ -123,7 +123,8 @@ struct sscf_ctx {
   double* Dt = nullptr;                 // transposes of the off-diagonal D blocks
   double* sc = nullptr;
   uint8_t *upd = nullptr, *pair_sel = nullptr;
-  unsigned int* fmask = nullptr;
+  uint8_t* rmask = nullptr;             // per pair and orientation: selected 16-column slices of each D row
+  uint8_t *pcidx = nullptr, *pncol = nullptr;   // packed nonzero columns of the C tiles (values in Y)
   double* part = nullptr;               // partial sums of the split reductions (coldot, coulomb)
   // energy gradient (allocated on first use)
   double *foo_a = nullptr, *foo_b = nullptr, *wblk = nullptr, *wval = nullptr;
@@ -287,13 +288,15 @@ struct sscf_ctx {
       // pair combinations C <- C - 1/2 C D_sel into the other buffer
       const int nx = 1 - cur;
       HIPC(hipMemsetAsync(upd, 0, (size_t)v.G * W, stream));
-      launch_mark_selected(v, n_pairs, pg, ph, O, sd, pair_sel, upd, fmask, stream);
+      launch_mark_selected(v, n_pairs, pg, ph, O, sd, pair_sel, upd, rmask, nullptr, stream);
       launch_update_support(v, actC[cur], gn_ptr, gn, pair_of, pair_sel, act_tmp, stream);
       launch_list(v, act_tmp, list_tmp, cnt_tmp, stream);
       launch_clear_tiles(v, C[nx], actC[nx], cmask[nx], listC[nx], cntC[nx], stream);
+      // the combination reads the nonzero columns of C packed into Y (free until the next product)
       const int pu = pbegin(KC_UPDATE);
-      launch_ortho_update(v, C[cur], actC[cur], gn_ptr, gn, pair_of, pair_sel, O, Dt, fmask, sd, upd, cut, list_tmp, cnt_tmp,
-                          C[nx], actC[nx], cmask[cur], cmask[nx], ctr(KC_UPDATE), stream);
+      launch_pack_cols(v, C[cur], listC[cur], cntC[cur], occ_only ? v.OW : v.W, Y, pcidx, pncol, stream);
+      launch_ortho_update(v, C[cur], actC[cur], Y, pcidx, pncol, gn_ptr, gn, pair_of, pair_sel, O, Dt, rmask, sd, upd,
+                          cut, list_tmp, cnt_tmp, C[nx], actC[nx], cmask[nx], ctr(KC_UPDATE), stream);
       pend(pu);
       rebuild_list(nx);
       cur = nx;
@@ -674,7 +677,9 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
   x->sc = x->dalloc<double>((size_t)G * v.W);
   x->upd = x->dalloc<uint8_t>((size_t)G * v.W);
   x->pair_sel = x->dalloc<uint8_t>(x->n_pairs);
-  x->fmask = x->dalloc<unsigned int>((size_t)x->n_pairs * 16);
+  x->rmask = x->dalloc<uint8_t>((size_t)x->n_pairs * 2 * v.W);
+  x->pcidx = x->dalloc<uint8_t>(ntiles * v.W);
+  x->pncol = x->dalloc<uint8_t>(ntiles);
   {
     double* z = x->dalloc<double>(ZERO_DOUBLES);
     launch_fill(z, ZERO_DOUBLES, 0.0, s);
@@ -840,6 +845,9 @@ static void step(sscf_ctx* x, sscf_step_info* out) {
                     x->roff, x->rmeta, s);
   launch_givens_rb(v, x->n_rounds, x->roff, x->rmeta, x->tcol, x->Rrot, x->R32, x->eps, x->C[x->cur],
                    x->actC[x->cur], x->cmask[x->cur], x->ctr(KC_GIVENS), s);
+  // the cut |C| < eps can empty a tile or a slice: flags exact again before the products
+  x->rebuild_list(x->cur);
+  launch_tile_flags(v, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur], x->actC[x->cur], x->cmask[x->cur], s);
   x->pend(pi);
   x->rebuild_list(x->cur);
   HIPC(hipEventRecord(x->ev[4], s));

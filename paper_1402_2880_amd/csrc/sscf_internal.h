@@ -101,17 +101,22 @@ void launch_normalize_d(const View& v, int n_pairs, const int* pg, const int* ph
 void launch_scale_c(const View& v, double* C, const int* listC, const int* cntC, const double* sc,
                     hipStream_t s);
 void launch_mark_selected(const View& v, int n_pairs, const int* pg, const int* ph, const double* D,
-                          const Scalars* sd, uint8_t* pair_sel, uint8_t* upd, unsigned int* fmask, hipStream_t s);
+                          const Scalars* sd, uint8_t* pair_sel, uint8_t* upd, uint8_t* rmask, int* nsel,
+                          hipStream_t s);
 void launch_update_support(const View& v, const uint8_t* actC, const int* gn_ptr, const int* gn,
                            const int* pair_of, const uint8_t* pair_sel, uint8_t* act_new,
                            hipStream_t s);
 void launch_clear_tiles(const View& v, double* C, uint8_t* act, unsigned int* cmask,
                         const int* list, const int* cnt, hipStream_t s);
-void launch_ortho_update(const View& v, const double* C, const uint8_t* actC, const int* gn_ptr,
-                         const int* gn, const int* pair_of, const uint8_t* pair_sel, const double* D,
-                         const double* Dt, const unsigned int* fmask, const Scalars* sd, const uint8_t* upd,
-                         double cut, const int* listN, const int* cntN, double* Cn, uint8_t* actN,
-                         const unsigned int* cmask, unsigned int* cmaskN, unsigned long long* ctr, hipStream_t s);
+void launch_tile_flags(const View& v, const double* C, const int* list, const int* cnt, uint8_t* act,
+                       unsigned int* cmask, hipStream_t s);
+void launch_pack_cols(const View& v, const double* C, const int* list, const int* cnt, int col_end, double* P,
+                      uint8_t* cidx, uint8_t* ncol, hipStream_t s);
+void launch_ortho_update(const View& v, const double* C, const uint8_t* actC, const double* P, const uint8_t* cidx,
+                         const uint8_t* ncol, const int* gn_ptr, const int* gn, const int* pair_of,
+                         const uint8_t* pair_sel, const double* D, const double* Dt, const uint8_t* rmask,
+                         const Scalars* sd, const uint8_t* upd, double cut, const int* listN, const int* cntN,
+                         double* Cn, uint8_t* actN, unsigned int* cmaskN, unsigned long long* ctr, hipStream_t s);
 void launch_coulomb(const View& v, int scc, const double* dq, double* part, double* Q, hipStream_t s);
 void launch_fock(const View& v, const double* S, const double* H0, const double* Hfull,
                  const double* Q, double eps, double* H, float* H32, hipStream_t s);

@@ -429,16 +429,19 @@ void launch_scale_c(const View& v, double* C, const int* listC, const int* cntC,
   hipLaunchKernelGGL(k_scale_c, dim3(v.n_rb, v.G), dim3(256), 0, s, v.n_rb, v.W, C, listC, cntC, sc);
 }
 
-// Per pair: flag it when any |D| >= 1e-3 eta, flag the MOs that take part, and record which
-// 4 x 16 MFMA fragments of D (words 0..7) and of its transpose (words 8..15) hold such an entry.
+// Per pair: flag it when any |D| >= 1e-3 eta, flag the MOs that take part, and record for
+// every row of D (orientation 0: rows = MOs of pg[p], rmask[(2p) W + i]) and of its transpose
+// (orientation 1: rows = MOs of ph[p], rmask[(2p + 1) W + j]) the 16-column slices of the other
+// group that hold a selected entry (bit n = slice n).  nsel (work counting, may be NULL): the
+// selected ordered pairs (i, j), i != j, per MO i, added over the pairs.
 __global__ void __launch_bounds__(256) k_mark_selected(int W, const int* pg, const int* ph, const double* D,
                                                        const Scalars* sd, uint8_t* pair_sel, uint8_t* upd,
-                                                       unsigned int* fmask) {
+                                                       uint8_t* rmask, int* nsel) {
   const int p = blockIdx.x;
   const int g = pg[p], h = ph[p];
-  const int NT = W / 16;
-  __shared__ unsigned int fm[16];
-  if (threadIdx.x < 16) fm[threadIdx.x] = 0u;
+  __shared__ unsigned int r0[MAX_W], r1[MAX_W];
+  __shared__ int n0[MAX_W], n1[MAX_W];
+  for (int c = threadIdx.x; c < MAX_W; c += 256) { r0[c] = 0u; r1[c] = 0u; n0[c] = 0; n1[c] = 0; }
   __syncthreads();
   const double thr = 1e-3 * __longlong_as_double((long long)sd->eta_bits);
   const double* Dp = D + (size_t)p * W * W;
@@ -449,19 +452,30 @@ __global__ void __launch_bounds__(256) k_mark_selected(int W, const int* pg, con
       any = 1;
       upd[(size_t)g * W + i] = 1;
       upd[(size_t)h * W + j] = 1;
-      const int bd = (i / 4) * NT + j / 16, bt = (j / 4) * NT + i / 16;
-      atomicOr(&fm[bd >> 5], 1u << (bd & 31));
-      atomicOr(&fm[8 + (bt >> 5)], 1u << (bt & 31));
+      atomicOr(&r0[i], 1u << (j >> 4));
+      atomicOr(&r1[j], 1u << (i >> 4));
+      if (nsel) { atomicAdd(&n0[i], 1); atomicAdd(&n1[j], 1); }
     }
   }
   any = __syncthreads_or(any);
-  if (threadIdx.x < 16) fmask[(size_t)p * 16 + threadIdx.x] = fm[threadIdx.x];
+  uint8_t* rm = rmask + (size_t)p * 2 * W;
+  for (int c = threadIdx.x; c < W; c += 256) {
+    rm[c] = (uint8_t)r0[c];
+    rm[W + c] = (uint8_t)r1[c];
+    if (nsel) {
+      // a self pair holds both (i, j) and (j, i); another pair only (i, j) with i of g
+      if (n0[c]) atomicAdd(&nsel[(size_t)g * W + c], n0[c]);
+      if (g != h && n1[c]) atomicAdd(&nsel[(size_t)h * W + c], n1[c]);
+    }
+  }
   if (threadIdx.x == 0) pair_sel[p] = (uint8_t)(any ? 1 : 0);
 }
 void launch_mark_selected(const View& v, int n_pairs, const int* pg, const int* ph, const double* D,
-                          const Scalars* sd, uint8_t* pair_sel, uint8_t* upd, unsigned int* fmask, hipStream_t s) {
+                          const Scalars* sd, uint8_t* pair_sel, uint8_t* upd, uint8_t* rmask, int* nsel,
+                          hipStream_t s) {
   if (n_pairs > 0)
-    hipLaunchKernelGGL(k_mark_selected, dim3(n_pairs), dim3(256), 0, s, v.W, pg, ph, D, sd, pair_sel, upd, fmask);
+    hipLaunchKernelGGL(k_mark_selected, dim3(n_pairs), dim3(256), 0, s, v.W, pg, ph, D, sd, pair_sel, upd, rmask,
+                       nsel);
 }
 
 __global__ void k_update_support(int G, int n_rb, const uint8_t* actC, const int* gn_ptr, const int* gn,
@@ -497,37 +511,152 @@ void launch_clear_tiles(const View& v, double* C, uint8_t* act, unsigned int* cm
   hipLaunchKernelGGL(k_clear_tiles, dim3(v.n_rb, v.G), dim3(256), 0, s, v.n_rb, v.W, C, act, cmask, list, cnt);
 }
 
+// ---------------------------------------------------------------------------------------
+// Column scans of C tiles (one wave per listed tile; lane l owns columns l and l + 64).
+//  * k_tile_flags: the activity byte and 16-column slice mask of each tile, exactly from its
+//    values (after the rotation cut a tile or slice may have lost all its nonzeros).
+//  * k_pack_cols: the nonzero columns of each tile packed to the front of its slot in P,
+//    column-major (packed column k = the 16 rows of the tile's k-th nonzero column, one
+//    128-byte line), with cidx[tile W + k] its column and ncol[tile] their number.  Only
+//    columns below col_end are packed (the occupied ones in an occupied-only sweep).
+// ---------------------------------------------------------------------------------------
+
+template <int NT>
+__device__ __forceinline__ void tile_columns(const double* __restrict__ T, int col_end, double (&v0)[RB],
+                                             double (&v1)[RB], bool& nz0, bool& nz1) {
+  constexpr int W = NT * 16;
+  const int lane = threadIdx.x & 63;
+  const bool in0 = lane < W && lane < col_end, in1 = lane + 64 < W && lane + 64 < col_end;
+  nz0 = nz1 = false;
+#pragma unroll
+  for (int k = 0; k < RB; ++k) {
+    v0[k] = in0 ? T[k * W + lane] : 0.0;
+    nz0 |= v0[k] != 0.0;
+    if constexpr (W > 64) {
+      v1[k] = in1 ? T[k * W + lane + 64] : 0.0;
+      nz1 |= v1[k] != 0.0;
+    } else {
+      v1[k] = 0.0;
+    }
+  }
+}
+
+template <int NT>
+__global__ void __launch_bounds__(256) k_tile_flags(int G, int n_rb, int nchunk, const double* __restrict__ C,
+                                                    const int* __restrict__ list, const int* __restrict__ cnt,
+                                                    uint8_t* __restrict__ act, unsigned int* __restrict__ cmask) {
+  constexpr int W = NT * 16;
+  int chunk;
+  const int g = xcd_group_chunk(nchunk, chunk);
+  if (g >= G) return;
+  const int t = chunk * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (t >= cnt[g]) return;
+  const size_t tile = (size_t)g * n_rb + list[(size_t)g * n_rb + t];
+  double v0[RB], v1[RB];
+  bool nz0, nz1;
+  tile_columns<NT>(C + tile * (RB * W), W, v0, v1, nz0, nz1);
+  const unsigned long long b0 = __ballot(nz0), b1 = __ballot(nz1);
+  unsigned int cm = 0u;
+#pragma unroll
+  for (int n = 0; n < NT; ++n) {
+    const unsigned long long b = n < 4 ? b0 : b1;
+    if ((b >> (16 * (n & 3))) & 0xffffull) cm |= 1u << n;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    cmask[tile] = cm;
+    act[tile] = (uint8_t)(cm != 0u);
+  }
+}
+
+template <int NT>
+__global__ void __launch_bounds__(256) k_pack_cols(int G, int n_rb, int nchunk, const double* __restrict__ C,
+                                                   const int* __restrict__ list, const int* __restrict__ cnt,
+                                                   int col_end, double* __restrict__ P, uint8_t* __restrict__ cidx,
+                                                   uint8_t* __restrict__ ncol) {
+  constexpr int W = NT * 16;
+  int chunk;
+  const int g = xcd_group_chunk(nchunk, chunk);
+  if (g >= G) return;
+  const int t = chunk * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (t >= cnt[g]) return;
+  const int lane = threadIdx.x & 63;
+  const size_t tile = (size_t)g * n_rb + list[(size_t)g * n_rb + t];
+  double v0[RB], v1[RB];
+  bool nz0, nz1;
+  tile_columns<NT>(C + tile * (RB * W), col_end, v0, v1, nz0, nz1);
+  const unsigned long long b0 = __ballot(nz0), b1 = __ballot(nz1);
+  const unsigned long long below = (1ull << lane) - 1ull;
+  const int c0 = __popcll(b0);
+  double* Pt = P + tile * (RB * W);
+  uint8_t* ct = cidx + tile * W;
+  if (nz0) {
+    const int k = __popcll(b0 & below);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) Pt[k * RB + r] = v0[r];
+    ct[k] = (uint8_t)lane;
+  }
+  if (nz1) {
+    const int k = c0 + __popcll(b1 & below);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) Pt[k * RB + r] = v1[r];
+    ct[k] = (uint8_t)(lane + 64);
+  }
+  if (lane == 0) ncol[tile] = (uint8_t)(c0 + __popcll(b1));
+}
+
+void launch_tile_flags(const View& v, const double* C, const int* list, const int* cnt, uint8_t* act,
+                       unsigned int* cmask, hipStream_t s) {
+  const int nchunk = (v.n_rb + 3) / 4;
+  dim3 grid(xcd_grid(v.G, nchunk)), blk(256);
+  switch (v.W / 16) {
+#define SSCF_TF(NT) case NT: hipLaunchKernelGGL(k_tile_flags<NT>, grid, blk, 0, s, v.G, v.n_rb, nchunk, C, list, cnt, act, cmask); break;
+    SSCF_TF(1) SSCF_TF(2) SSCF_TF(3) SSCF_TF(4) SSCF_TF(5) SSCF_TF(6) SSCF_TF(7) SSCF_TF(8)
+#undef SSCF_TF
+  }
+}
+
+void launch_pack_cols(const View& v, const double* C, const int* list, const int* cnt, int col_end, double* P,
+                      uint8_t* cidx, uint8_t* ncol, hipStream_t s) {
+  const int nchunk = (v.n_rb + 3) / 4;
+  dim3 grid(xcd_grid(v.G, nchunk)), blk(256);
+  switch (v.W / 16) {
+#define SSCF_PK(NT) case NT: hipLaunchKernelGGL(k_pack_cols<NT>, grid, blk, 0, s, v.G, v.n_rb, nchunk, C, list, cnt, col_end, P, cidx, ncol); break;
+    SSCF_PK(1) SSCF_PK(2) SSCF_PK(3) SSCF_PK(4) SSCF_PK(5) SSCF_PK(6) SSCF_PK(7) SSCF_PK(8)
+#undef SSCF_PK
+  }
+}
+
 // Cn[g][r] = C[g][r] - 1/2 sum_{h ~ g} C[h][r] D_sel(h, g), then |v| < cut -> 0 in the
 // columns that took part in a combination.  D is stored per unordered pair (a <= b) with
 // rows = MOs of a, columns = MOs of b; Dt holds the transposes, so D_sel(h, g) (rows = MOs
 // of h) is read row-contiguously in both orientations.
 //
 // One wave per output tile (g, r), no workgroup synchronization.  A ballot over g's
-// neighbours finds, 64 at a time, those h whose pair is selected and whose C_h is active at
-// row block r, with its 16-column slice mask.  Per such h the wave walks the k-steps four at
-// a time: the four C_h elements (A operand) and the D fragments that hold a selected entry
-// (B operand, thresholded at 1e-3 eta) are loaded together, straight from L2, then multiplied
-// on the matrix cores.  Fragments without a selected entry and k-steps in zero slices of
-// C_h[r] are skipped (adding zero would leave the sum unchanged).  The sum runs over h in
-// neighbour order and over k-steps in order, so the result does not depend on the launch.
-// (A form that staged each D block in LDS for 8 row blocks at a time spent a third of its
-// time in staging and barriers, with 39% of its waves idle per block: 16.8 against 14.0 ms
-// per launch over the same SCF steps of water4096.)
+// neighbours finds, 64 at a time, those h whose pair is selected and whose tile (h, r) has a
+// nonzero column.  Per such h only the tile's nonzero columns enter the product: they come
+// packed (k_pack_cols), four per k-step of the 16 x 16 x 4 matrix-core product, each as one
+// 128-byte line; the B operand is the matching rows of D_sel(h, g) (thresholded at 1e-3
+// eta), and a 16-column slice of the output is skipped for a k-step when none of its four
+// rows holds a selected entry there (rmask).  Adding the skipped terms would add exact
+// zeros.  The sum runs over h in neighbour order and over the packed columns in increasing
+// column order, so the result does not depend on the launch.
 template <int NT>
 __global__ void __launch_bounds__(256) k_ortho_update(int G, int n_rb, int nchunk, const double* __restrict__ C,
                                                       const uint8_t* __restrict__ actC,
-                                                      const unsigned int* __restrict__ cmask,
+                                                      const double* __restrict__ P, const uint8_t* __restrict__ cidx,
+                                                      const uint8_t* __restrict__ ncol,
                                                       const int* __restrict__ gn_ptr, const int* __restrict__ gn,
                                                       const int* __restrict__ pair_of,
                                                       const uint8_t* __restrict__ pair_sel,
                                                       const double* __restrict__ D, const double* __restrict__ Dt,
-                                                      const unsigned int* __restrict__ fmask,
+                                                      const uint8_t* __restrict__ rmask,
                                                       const Scalars* __restrict__ sd,
                                                       const uint8_t* __restrict__ upd, double cut,
                                                       const int* __restrict__ listN, const int* __restrict__ cntN,
                                                       double* __restrict__ Cn, uint8_t* __restrict__ actN,
                                                       unsigned int* __restrict__ cmaskN, unsigned long long* ctr) {
-  constexpr int W = NT * 16, KS = W / 4;
+  constexpr int W = NT * 16;
+  constexpr int KB = 2;                       // k-steps whose loads go out together
   int chunk;
   const int g = xcd_group_chunk(nchunk, chunk);
   if (g >= G) return;
@@ -545,47 +674,61 @@ __global__ void __launch_bounds__(256) k_ortho_update(int G, int n_rb, int nchun
   const int k_end = gn_ptr[g + 1];
   for (int kb = gn_ptr[g]; kb < k_end; kb += 64) {
     const int k = kb + lane;
-    int h = 0;
-    unsigned int am = 0u;
+    int h = 0, nz = 0;
     if (k < k_end) {
       h = gn[k];
       const size_t th = (size_t)h * n_rb + r;
-      if (pair_sel[pair_of[(size_t)g * G + h]] && actC[th]) am = cmask[th];
+      if (pair_sel[pair_of[(size_t)g * G + h]] && actC[th]) nz = ncol[th];
     }
-    unsigned long long M = __ballot(am != 0u);
+    unsigned long long M = __ballot(nz != 0);
     while (M) {
       const int j = __ffsll((long long)M) - 1;
       M &= M - 1ull;
       const int hc = __shfl(h, j);
-      const unsigned int amj = __builtin_amdgcn_readfirstlane(__shfl((int)am, j));
+      const int nzj = __builtin_amdgcn_readfirstlane(__shfl(nz, j));
       const int p = pair_of[(size_t)g * G + hc];
       const bool tr = hc > g;
-      const double* Dp = (tr ? Dt : D) + (size_t)p * W * W + lk * W + lr;
-      const unsigned int* fm = fmask + (size_t)p * 16 + (tr ? 8 : 0);
-      const double* Ch = C + ((size_t)hc * n_rb + r) * (RB * W) + lr * W + lk;
-      for (int s0 = 0; s0 < KS; s0 += 4) {
-        if (!(amj & (1u << (s0 >> 2)))) continue;        // the 4 k-steps share one slice
-        double a[4], b[4][NT];
-        unsigned int fb[4];
+      const size_t th = (size_t)hc * n_rb + r;
+      const double* Dp = (tr ? Dt : D) + (size_t)p * W * W + lr;
+      const uint8_t* rm = rmask + ((size_t)p * 2 + (tr ? 1 : 0)) * W;
+      const double* A = P + th * (RB * W) + lr;
+      // packed column k's index and slice mask live in lane k (k < 64) or lane k - 64
+      const uint8_t* ci = cidx + th * W;
+      const int col0 = lane < nzj ? ci[lane] : 0;
+      const int col1 = (W > 64 && lane + 64 < nzj) ? ci[lane + 64] : 0;
+      int m0 = lane < nzj ? rm[col0] : 0;
+      int m1 = (W > 64 && lane + 64 < nzj) ? rm[col1] : 0;
+      // OR over the four columns of each k-step (aligned groups of four lanes)
+      m0 |= __shfl_xor(m0, 1);
+      m0 |= __shfl_xor(m0, 2);
+      m1 |= __shfl_xor(m1, 1);
+      m1 |= __shfl_xor(m1, 2);
+      for (int s0 = 0; s0 < nzj; s0 += 4 * KB) {
+        double a[KB];
+        int col[KB];
+        unsigned int nm[KB];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int st = s0 + u;
-          a[u] = Ch[4 * st];
-          unsigned int f = 0u;
-#pragma unroll
-          for (int n = 0; n < NT; ++n) {
-            const int bit = st * NT + n;
-            const bool on = (fm[bit >> 5] >> (bit & 31)) & 1u;
-            f |= on ? (1u << n) : 0u;
-            b[u][n] = on ? Dp[st * 4 * W + n * 16] : 0.0;
-          }
-          fb[u] = f;
+        for (int u = 0; u < KB; ++u) {
+          const int q0 = s0 + 4 * u;           // first packed column of this k-step
+          const int kk = q0 + lk;
+          a[u] = kk < nzj ? A[kk * RB] : 0.0;
+          const int c0 = __shfl(col0, kk & 63), c1 = __shfl(col1, kk & 63);
+          col[u] = q0 < 64 ? c0 : c1;
+          unsigned int mm = 0u;
+          if (q0 < nzj) mm = (unsigned int)(q0 < 64 ? __builtin_amdgcn_readlane(m0, q0 & 63)
+                                                     : __builtin_amdgcn_readlane(m1, q0 & 63));
+          nm[u] = mm;
         }
+        double b[KB][NT];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < KB; ++u)
+#pragma unroll
+          for (int n = 0; n < NT; ++n) b[u][n] = ((nm[u] >> n) & 1u) ? Dp[(size_t)col[u] * W + n * 16] : 0.0;
+#pragma unroll
+        for (int u = 0; u < KB; ++u)
 #pragma unroll
           for (int n = 0; n < NT; ++n)
-            if (fb[u] & (1u << n)) {
+            if ((nm[u] >> n) & 1u) {
               const double bv = (fabs(b[u][n]) >= thr) ? b[u][n] : 0.0;
               acc[n] = mfma64(a[u], bv, acc[n]);
               ++n_mfma;
@@ -620,15 +763,15 @@ __global__ void __launch_bounds__(256) k_ortho_update(int G, int n_rb, int nchun
   }
 }
 
-void launch_ortho_update(const View& v, const double* C, const uint8_t* actC, const int* gn_ptr, const int* gn,
-                         const int* pair_of, const uint8_t* pair_sel, const double* D, const double* Dt,
-                         const unsigned int* fmask, const Scalars* sd, const uint8_t* upd, double cut,
-                         const int* listN, const int* cntN, double* Cn, uint8_t* actN, const unsigned int* cmask,
-                         unsigned int* cmaskN, unsigned long long* ctr, hipStream_t s) {
+void launch_ortho_update(const View& v, const double* C, const uint8_t* actC, const double* P, const uint8_t* cidx,
+                         const uint8_t* ncol, const int* gn_ptr, const int* gn, const int* pair_of,
+                         const uint8_t* pair_sel, const double* D, const double* Dt, const uint8_t* rmask,
+                         const Scalars* sd, const uint8_t* upd, double cut, const int* listN, const int* cntN,
+                         double* Cn, uint8_t* actN, unsigned int* cmaskN, unsigned long long* ctr, hipStream_t s) {
   const int nchunk = (v.n_rb + 3) / 4;
   dim3 grid(xcd_grid(v.G, nchunk)), blk(256);
   switch (v.W / 16) {
-#define SSCF_UPD(NT) case NT: hipLaunchKernelGGL(k_ortho_update<NT>, grid, blk, 0, s, v.G, v.n_rb, nchunk, C, actC, cmask, gn_ptr, gn, pair_of, pair_sel, D, Dt, fmask, sd, upd, cut, listN, cntN, Cn, actN, cmaskN, ctr); break;
+#define SSCF_UPD(NT) case NT: hipLaunchKernelGGL(k_ortho_update<NT>, grid, blk, 0, s, v.G, v.n_rb, nchunk, C, actC, P, cidx, ncol, gn_ptr, gn, pair_of, pair_sel, D, Dt, rmask, sd, upd, cut, listN, cntN, Cn, actN, cmaskN, ctr); break;
     SSCF_UPD(1) SSCF_UPD(2) SSCF_UPD(3) SSCF_UPD(4) SSCF_UPD(5) SSCF_UPD(6) SSCF_UPD(7) SSCF_UPD(8)
 #undef SSCF_UPD
   }
