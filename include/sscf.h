@@ -50,7 +50,11 @@ enum { SSCF_FP64 = 0, SSCF_FP32_MIXED = 1 };
 enum { SSCF_FOCK_H0 = 0, SSCF_FOCK_FULL = 1 };
 
 /* bits of sscf_system_desc.flags */
-enum { SSCF_FLAG_PROFILE = 1 };  /* time kernel classes with HIP events; count their work */
+enum {
+  SSCF_FLAG_PROFILE = 1,     /* time the kernel classes with HIP events; count executed matrix-core products */
+  SSCF_FLAG_COUNT_WORK = 2   /* count the algorithmic work of each pass (sscf_get_kernel_stats); adds counting
+                                kernels and host synchronizations between the passes: for measurement runs */
+};
 
 /* Convergence criterion of sscf_control (section 4.1 uses the charge criterion). */
 enum { SSCF_CONV_ENERGY = 0, SSCF_CONV_CHARGE = 1 };
@@ -142,6 +146,8 @@ typedef struct {
   int32_t ortho_converged;     /* eta < eps/100 was reached                                     */
   int32_t post_ortho;          /* occupied-only orthonormalization was run (once converged)     */
   int64_t nnz_tiles;           /* active 16-row tiles of C                                      */
+  int64_t nnz_c;               /* nonzero coefficients of C after the step (with
+                                  SSCF_FLAG_COUNT_WORK; -1 without)                             */
   float ms_fock, ms_cfc, ms_select, ms_rot, ms_ortho, ms_sums, ms_total;
 } sscf_step_info;
 
@@ -310,21 +316,39 @@ sscf_status sscf_init_info(const sscf_ctx* ctx, sscf_step_info* info);
 sscf_status sscf_get_schedule(const sscf_ctx* ctx, int32_t* g, int32_t* h, int32_t* round,
                               int32_t* n_blocks);
 
-/* Work and time of the main kernel classes, accumulated over the calls since
- * initialization (or the last reset) when the context was created with
- * SSCF_FLAG_PROFILE.  Classes: spmm_tiles (S C, H C, H0 C), pair_overlap
- * (C^T S C), pair_fock (occupied-virtual C^T H C), ortho_update (C - 1/2 C D),
- * rotations (composition of each block's rotations and one pass over the row
- * blocks), select, fock.  `flops`
- * counts the FP64 MFMA tile products of the class (2048 flops each) and `bytes`
- * the algorithmic traffic of the rotation pass (each rotated element of an active
- * row read and written once).  Call with out == NULL to get *n. */
+/* Work and time of the main kernel classes, accumulated over the steps, set-up and step III
+ * calls since initialization (or the last reset).  Classes: spmm_tiles (the products Y = X C:
+ * H C of C^T H C, S C of each orthonormalization sweep, H0 C_occ of the band energy),
+ * pair_overlap (C^T S C over neighbouring groups, section 3.4), pair_fock (occupied-virtual
+ * C^T H C of the Jacobi blocks, section 3.5), ortho_update (the pair combinations C - 1/2 C D_sel,
+ * section 3.4, with the packing of C's nonzero columns it reads), rotations (composition of each
+ * Jacobi block's rotations and the pass over the row blocks, section 3.5, with the recount of
+ * the tile flags after the cut), select, fock.
+ *  launches, ms: with SSCF_FLAG_PROFILE, the launches of the class and their summed HIP-event time.
+ *  mfma_flops:   with SSCF_FLAG_PROFILE, 2048 flops per executed 16 x 16 x 4 matrix-core product
+ *                of the class (zero operands and padding included: the tiled execution).
+ *  alg_flops, alg_bytes: with SSCF_FLAG_COUNT_WORK (else -1), the algorithmic work of the
+ *                class, counted on the library's state at each pass; nnz counts nonzero values,
+ *                a flop is one multiplication or addition of the sparse operation itself, each
+ *                nonzero FP64 value read or written counts 8 bytes (4 in FP32), once:
+ *     spmm_tiles:   2 sum_{nu, j} [C_nu,j != 0] nnz(X row nu);  8 (nnz X + nnz C + nnz Y)
+ *     pair_overlap: 2 sum |supp C_i ∩ supp (S C)_j| over each unordered pair of MOs of
+ *                   neighbouring groups once (i of the lower group; i <= j inside a group);
+ *                   8 (nnz C + nnz S C + pairs)
+ *     pair_fock:    the same over the occupied i and virtual a of the Jacobi blocks
+ *     ortho_update: 2 sum_{(i, j) selected, i != j} nnz C_i;  8 (nnz C before + selected
+ *                   pairs + nnz C after)
+ *     rotations:    6 n_rot(b) |U(b)| per Jacobi block b, U(b) the rows where one of the block's
+ *                   columns is nonzero when the block starts; 16 bytes per nonzero of those columns
+ *   The same definitions, counted by the test oracle on its own state, pin these counts.
+ * Call with out == NULL to get *n. */
 typedef struct {
   char name[32];
   int64_t launches;
   double ms;                   /* summed HIP-event time of the launches                         */
-  double flops;
-  double bytes;
+  double mfma_flops;
+  double alg_flops;
+  double alg_bytes;
 } sscf_kernel_stat;
 
 sscf_status sscf_get_kernel_stats(const sscf_ctx* ctx, sscf_kernel_stat* out, int32_t* n);

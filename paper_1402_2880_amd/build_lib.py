@@ -8,7 +8,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsscf.so")
-SOURCES = ["sscf_kernels.hip", "sscf_setup.hip", "sscf_host.hip"]
+SOURCES = ["sscf_kernels.hip", "sscf_setup.hip", "sscf_count.hip", "sscf_host.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions stay off (hipcc would otherwise form them from float code)

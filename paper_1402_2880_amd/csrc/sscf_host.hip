@@ -63,9 +63,8 @@ int round16(int x) { return ((x + 15) / 16) * 16; }
 enum { KC_SPMM, KC_PAIR_O, KC_PAIR_F, KC_UPDATE, KC_GIVENS, KC_SELECT, KC_FOCK };
 const char* const KC_NAME[SSCF_N_KERNEL_CLASSES] = {
     "spmm_tiles", "pair_overlap", "pair_fock", "ortho_update", "rotations", "select", "fock"};
-// MFMA tile products count 16 x 16 x 4 multiply-adds; the Givens counter holds bytes
-const double KC_FLOP_PER_UNIT[SSCF_N_KERNEL_CLASSES] = {2048.0, 2048.0, 2048.0, 2048.0, 0.0, 0.0, 0.0};
-const double KC_BYTE_PER_UNIT[SSCF_N_KERNEL_CLASSES] = {0.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0};
+// executed FP64/FP32 16 x 16 x 4 matrix-core products: 2048 flops each
+const double KC_FLOP_PER_MFMA = 2048.0;
 
 }  // namespace
 
@@ -90,6 +89,7 @@ struct sscf_ctx {
   int pair_maxc = 0, jb_maxc = 0;
 
   // host copies needed after set-up
+  std::vector<int> h_pg, h_ph;        // unordered neighbour pairs g <= h
   std::vector<int64_t> h_blk_rowptr, h_blk_off;
   std::vector<int32_t> h_blk_col, h_atom_nao;
   std::vector<int32_t> h_mo_of;      // [G * W] MO index of a panel column, -1 if none
@@ -159,6 +159,85 @@ struct sscf_ctx {
   double pms[SSCF_N_KERNEL_CLASSES] = {};
   long long plaunch[SSCF_N_KERNEL_CLASSES] = {};
   unsigned long long* pctr = nullptr;
+
+  // optional work counting (SSCF_FLAG_COUNT_WORK): the algorithmic flops and bytes of each
+  // pass, counted on the current state by the kernels of sscf_count.hip between the passes
+  bool count = false, counting = false;     // counting: inside a step, set-up or step III call
+  double wfl[SSCF_N_KERNEL_CLASSES] = {}, wby[SSCF_N_KERNEL_CLASSES] = {};
+  unsigned long long* wdev = nullptr;       // 8 scratch counters
+  int *w_xrow = nullptr, *w_colnnz = nullptr, *w_nsel = nullptr;
+  ulonglong2 *w_mC = nullptr, *w_mY = nullptr;
+  bool wc() const { return count && counting; }
+  void wzero() { HIPC(hipMemsetAsync(wdev, 0, 8 * sizeof(unsigned long long), stream)); }
+  std::array<unsigned long long, 8> wread() {
+    std::array<unsigned long long, 8> h{};
+    HIPC(hipMemcpyAsync(h.data(), wdev, sizeof(h), hipMemcpyDeviceToHost, stream));
+    sync();
+    return h;
+  }
+  // Y = X C over the columns [0, c1) of every panel (X, C, Y in FP32 when fp32)
+  void count_product(const void* X, const void* Cp, const void* Yp, bool fp32, bool occ_only) {
+    const int c1 = occ_only ? v.OW : v.W;
+    wzero();
+    launch_fill_i32(w_xrow, (size_t)v.n_rb * RB, 0, stream);
+    launch_cnt_xrow(v, X, fp32, w_xrow, wdev + 0, stream);
+    launch_cnt_tiles(v, Cp, fp32, listC[cur], cntC[cur], 0, c1, w_xrow, nullptr, wdev + 1, wdev + 2, stream);
+    launch_cnt_tiles(v, Yp, fp32, listY, cntY, 0, c1, nullptr, nullptr, wdev + 3, nullptr, stream);
+    const auto w = wread();
+    wfl[KC_SPMM] += 2.0 * (double)w[2];
+    wby[KC_SPMM] += (fp32 ? 4.0 : 8.0) * ((double)w[0] + (double)w[1] + (double)w[3]);
+  }
+  // C_g^T Y_h over the items (g, h): columns [a0, a1) of g against [b0, b1) of h
+  void count_pairs(int cls, int n_items, const int* ig, const int* ih, const void* Cp, const void* Yp, bool fp32,
+                   int a0, int a1, int b0, int b1, int tri, double n_out) {
+    wzero();
+    launch_row_masks(v, Cp, fp32, listC[cur], cntC[cur], w_mC, stream);
+    launch_row_masks(v, Yp, fp32, listY, cntY, w_mY, stream);
+    launch_cnt_pairs(v, n_items, ig, ih, listC[cur], cntC[cur], actY, w_mC, w_mY, a0, a1, b0, b1, tri, wdev + 0,
+                     stream);
+    launch_cnt_tiles(v, Cp, fp32, listC[cur], cntC[cur], a0, a1, nullptr, nullptr, wdev + 1, nullptr, stream);
+    launch_cnt_tiles(v, Yp, fp32, listY, cntY, b0, b1, nullptr, nullptr, wdev + 2, nullptr, stream);
+    const auto w = wread();
+    wfl[cls] += 2.0 * (double)w[0];
+    wby[cls] += (fp32 ? 4.0 : 8.0) * ((double)w[1] + (double)w[2]) + 8.0 * n_out;   // outputs are FP64
+  }
+  // unordered MO pairs of C^T S C in scope: i of the lower group, i <= j inside a group
+  double overlap_pairs(bool occ_only) const {
+    double n = 0.0;
+    for (size_t p = 0; p < h_pg.size(); ++p) {
+      const double ng = h_pnocc[h_pg[p]] + (occ_only ? 0 : h_pnvirt[h_pg[p]]);
+      const double nh = h_pnocc[h_ph[p]] + (occ_only ? 0 : h_pnvirt[h_ph[p]]);
+      n += (h_pg[p] == h_ph[p]) ? ng * (ng + 1.0) / 2.0 : ng * nh;
+    }
+    return n;
+  }
+  double fock_pairs() const {
+    double n = 0.0;
+    for (int b = 0; b < n_blocks; ++b) n += (double)h_pnocc[h_jb_g[b]] * (double)h_pnvirt[h_jb_h[b]];
+    return n;
+  }
+  // the combination: 2 nnz(C_i) per selected (i, j); C read, D_sel read (nsel from the marking)
+  void count_update_begin(bool occ_only) {
+    const int c1 = occ_only ? v.OW : v.W;
+    wzero();
+    launch_fill_i32(w_colnnz, (size_t)v.G * v.W, 0, stream);
+    launch_cnt_tiles(v, C[cur], false, listC[cur], cntC[cur], 0, c1, nullptr, w_colnnz, wdev + 0, nullptr, stream);
+    launch_cnt_dot((size_t)v.G * v.W, w_colnnz, w_nsel, wdev + 1, wdev + 2, stream);
+    const auto w = wread();
+    wfl[KC_UPDATE] += 2.0 * (double)w[1];
+    wby[KC_UPDATE] += 8.0 * ((double)w[0] + (double)w[2]);
+  }
+  void count_update_end(int b, bool occ_only) {          // C written: buffer b, listed
+    wzero();
+    launch_cnt_tiles(v, C[b], false, listC[b], cntC[b], 0, occ_only ? v.OW : v.W, nullptr, nullptr, wdev + 0, nullptr,
+                     stream);
+    wby[KC_UPDATE] += 8.0 * (double)wread()[0];
+  }
+  int64_t count_nnz_c() {
+    wzero();
+    launch_cnt_tiles(v, C[cur], false, listC[cur], cntC[cur], 0, v.W, nullptr, nullptr, wdev + 0, nullptr, stream);
+    return (int64_t)wread()[0];
+  }
 
   int pbegin(int c) {
     if (!prof) return -1;
@@ -258,6 +337,7 @@ struct sscf_ctx {
     const int pi = pbegin(KC_SPMM);
     launch_spmm(v, X, C[cur], actC[cur], cmask[cur], listY, cntY, Y, ymask, smask, ctr(KC_SPMM), stream);
     pend(pi);
+    if (wc()) count_product(X, C[cur], Y, false, occ_only);
   }
 
   // orthonormalization loop (section 3.4); returns the number of combination sweeps
@@ -273,6 +353,8 @@ struct sscf_ctx {
       launch_pair(v, n_pairs, pair_perm, pair_maxc, pg, ph, C[cur], listC[cur], cntC[cur], cmask[cur], Y, actY, ymask, 0, nt, 0, nt, O, W,
                   (size_t)W * W, ctr(KC_PAIR_O), stream);
       pend(pi);
+      if (wc()) count_pairs(KC_PAIR_O, n_pairs, pg, ph, C[cur], Y, false, 0, 16 * nt, 0, 16 * nt, 1,
+                            overlap_pairs(occ_only != 0));
       HIPC(hipMemsetAsync(&sd->eta_bits, 0, sizeof(unsigned long long), stream));
       HIPC(hipMemsetAsync(&sd->err, 0, sizeof(int), stream));
       launch_ortho_scale(v, v.G, self_pair, O, pnocc, pnvirt, occ_only, sc, sd, stream);
@@ -288,10 +370,12 @@ struct sscf_ctx {
       // pair combinations C <- C - 1/2 C D_sel into the other buffer
       const int nx = 1 - cur;
       HIPC(hipMemsetAsync(upd, 0, (size_t)v.G * W, stream));
-      launch_mark_selected(v, n_pairs, pg, ph, O, sd, pair_sel, upd, rmask, nullptr, stream);
+      if (wc()) launch_fill_i32(w_nsel, (size_t)v.G * W, 0, stream);
+      launch_mark_selected(v, n_pairs, pg, ph, O, sd, pair_sel, upd, rmask, wc() ? w_nsel : nullptr, stream);
       launch_update_support(v, actC[cur], gn_ptr, gn, pair_of, pair_sel, act_tmp, stream);
       launch_list(v, act_tmp, list_tmp, cnt_tmp, stream);
       launch_clear_tiles(v, C[nx], actC[nx], cmask[nx], listC[nx], cntC[nx], stream);
+      if (wc()) count_update_begin(occ_only != 0);
       // the combination reads the nonzero columns of C packed into Y (free until the next product)
       const int pu = pbegin(KC_UPDATE);
       launch_pack_cols(v, C[cur], listC[cur], cntC[cur], occ_only ? v.OW : v.W, Y, pcidx, pncol, stream);
@@ -299,6 +383,7 @@ struct sscf_ctx {
                           cut, list_tmp, cnt_tmp, C[nx], actC[nx], cmask[nx], ctr(KC_UPDATE), stream);
       pend(pu);
       rebuild_list(nx);
+      if (wc()) count_update_end(nx, occ_only != 0);
       cur = nx;
       ++sweeps;
     }
@@ -367,7 +452,7 @@ void validate(const sscf_system_desc* d) {
       !(d->rot_cap_factor >= 0.0) || d->max_sweeps_init < 0 || d->max_sweeps_step < 0)
     fail(SSCF_E_INVALID_ARG, "bad thresholds");
   if (d->precision != SSCF_FP64 && d->precision != SSCF_FP32_MIXED) fail(SSCF_E_INVALID_ARG, "bad precision");
-  if (d->flags & ~(uint64_t)SSCF_FLAG_PROFILE) fail(SSCF_E_INVALID_ARG, "unknown bits in flags");
+  if (d->flags & ~(uint64_t)(SSCF_FLAG_PROFILE | SSCF_FLAG_COUNT_WORK)) fail(SSCF_E_INVALID_ARG, "unknown bits in flags");
   for (int a = 0; a < d->n_atoms; ++a) {
     if (d->atom_nao[a] < 1 || d->atom_nao[a] > 4) fail(SSCF_E_INVALID_ARG, "atom %d: atom_nao must be 1..4", a);
     if (d->atom_group[a] < 0 || d->atom_group[a] >= d->n_groups) fail(SSCF_E_INVALID_ARG, "atom %d: bad group", a);
@@ -394,6 +479,7 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
   x->alloc = d->alloc;
   x->n_val = d->n_val;
   x->prof = (d->flags & SSCF_FLAG_PROFILE) != 0;
+  x->count = (d->flags & SSCF_FLAG_COUNT_WORK) != 0;
   View& v = x->v;
   const int na = d->n_atoms;
   v.n_atoms = na;
@@ -566,6 +652,8 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
         ph.push_back(h);
       }
   x->n_pairs = (int)pg.size();
+  x->h_pg = pg;
+  x->h_ph = ph;
   // Jacobi blocks (g occupied, h virtual), greedy rounds in (g, h) order (section 3.5)
   {
     int maxdeg = 0;
@@ -729,6 +817,14 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
   HIPC(hipMemsetAsync(x->sd, 0, sizeof(Scalars), s));
   x->pctr = x->dalloc<unsigned long long>(SSCF_N_KERNEL_CLASSES);
   HIPC(hipMemsetAsync(x->pctr, 0, sizeof(unsigned long long) * SSCF_N_KERNEL_CLASSES, s));
+  if (x->count) {
+    x->wdev = x->dalloc<unsigned long long>(8);
+    x->w_xrow = x->dalloc<int>((size_t)v.n_rb * RB);
+    x->w_colnnz = x->dalloc<int>((size_t)G * v.W);
+    x->w_nsel = x->dalloc<int>((size_t)G * v.W);
+    x->w_mC = x->dalloc<ulonglong2>(ntiles * RB);
+    x->w_mY = x->dalloc<ulonglong2>(ntiles * RB);
+  }
 
   // C0 into the tiles
   {
@@ -748,6 +844,7 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
   x->sync();
 
   // initial orthonormalization (section 3.4), charges and energy
+  x->counting = true;
   HIPC(hipEventRecord(x->ev[0], s));
   double eta = 0.0;
   int conv = 0;
@@ -768,6 +865,8 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
   ii.n_ortho_sweeps = sweeps;
   ii.ortho_converged = conv;
   ii.nnz_tiles = x->active_tiles();
+  ii.nnz_c = x->count ? x->count_nnz_c() : -1;
+  x->counting = false;
   float ms = 0.f;
   HIPC(hipEventElapsedTime(&ms, x->ev[0], x->ev[1]));
   ii.ms_ortho = ms;
@@ -781,6 +880,7 @@ static void step(sscf_ctx* x, sscf_step_info* out) {
   hipStream_t s = x->stream;
   sscf_step_info info;
   std::memset(&info, 0, sizeof(info));
+  x->counting = true;
   const double E_prev = x->E;
   HIPC(hipMemsetAsync(x->sd, 0, offsetof(Scalars, e_band), s));
   HIPC(hipEventRecord(x->ev[0], s));
@@ -798,11 +898,15 @@ static void step(sscf_ctx* x, sscf_step_info* out) {
     launch_spmm32(v, x->H32, x->C32, x->actC[x->cur], x->cmask[x->cur], x->listY, x->cntY, x->Y32, x->ymask,
                   x->ctr(KC_SPMM), s);
     x->pend(pi);
+    if (x->wc()) x->count_product(x->H32, x->C32, x->Y32, true, false);
     pi = x->pbegin(KC_PAIR_F);
     launch_pair32(v, x->n_blocks, x->jb_perm, x->jb_maxc, x->jb_g, x->jb_h, x->C32, x->listC[x->cur], x->cntC[x->cur],
                   x->cmask[x->cur], x->Y32, x->actY, x->ymask, 0, v.OW / 16, v.OW, v.VW / 16, x->F, v.VW,
                   (size_t)v.OW * v.VW, x->ctr(KC_PAIR_F), s);
     x->pend(pi);
+    if (x->wc())
+      x->count_pairs(KC_PAIR_F, x->n_blocks, x->jb_g, x->jb_h, x->C32, x->Y32, true, 0, v.OW, v.OW, v.W, 0,
+                     x->fock_pairs());
     launch_coldot32(v, x->C32, x->listC[x->cur], x->cntC[x->cur], x->Y32, x->actY, x->Fdiag, s);
   } else {
     x->product(x->H, true);
@@ -811,6 +915,9 @@ static void step(sscf_ctx* x, sscf_step_info* out) {
                 x->cmask[x->cur], x->Y, x->actY, x->ymask, 0, v.OW / 16, v.OW, v.VW / 16, x->F, v.VW,
                 (size_t)v.OW * v.VW, x->ctr(KC_PAIR_F), s);
     x->pend(pi);
+    if (x->wc())
+      x->count_pairs(KC_PAIR_F, x->n_blocks, x->jb_g, x->jb_h, x->C[x->cur], x->Y, false, 0, v.OW, v.OW, v.W, 0,
+                     x->fock_pairs());
     launch_coldot(v, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur], x->Y, x->actY, x->part, x->Fdiag, s);
   }
   HIPC(hipEventRecord(x->ev[2], s));
@@ -843,13 +950,19 @@ static void step(sscf_ctx* x, sscf_step_info* out) {
   launch_compose_rot(v, x->n_blocks, x->rot_cnt, x->rot_slot, x->rot_cs, x->tcnt, x->Rrot, x->R32, s);
   launch_round_meta(x->n_rounds, x->round_ptr, x->round_list, x->rot_cnt, x->jb_g, x->jb_h, x->tcnt, x->rcnt,
                     x->roff, x->rmeta, s);
+  if (x->wc()) x->wzero();
   launch_givens_rb(v, x->n_rounds, x->roff, x->rmeta, x->tcol, x->Rrot, x->R32, x->eps, x->C[x->cur],
-                   x->actC[x->cur], x->cmask[x->cur], x->ctr(KC_GIVENS), s);
+                   x->actC[x->cur], x->cmask[x->cur], x->rot_cnt, x->wc() ? x->wdev : nullptr, s);
   // the cut |C| < eps can empty a tile or a slice: flags exact again before the products
   x->rebuild_list(x->cur);
   launch_tile_flags(v, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur], x->actC[x->cur], x->cmask[x->cur], s);
   x->pend(pi);
   x->rebuild_list(x->cur);
+  if (x->wc()) {
+    const auto w = x->wread();
+    x->wfl[KC_GIVENS] += (double)w[0];
+    x->wby[KC_GIVENS] += (double)w[1];
+  }
   HIPC(hipEventRecord(x->ev[4], s));
   // step III: re-orthonormalization
   double eta = 0.0;
@@ -895,6 +1008,8 @@ static void step(sscf_ctx* x, sscf_step_info* out) {
   info.e_band = h.e_band;
   info.e_coul = h.e_coul;
   info.nnz_tiles = x->active_tiles();
+  info.nnz_c = x->count ? x->count_nnz_c() : -1;
+  x->counting = false;
   float t[7];
   for (int i = 0; i < 7; ++i) HIPC(hipEventElapsedTime(&t[i], x->ev[i], x->ev[i + 1]));
   info.ms_fock = t[0];
@@ -918,6 +1033,7 @@ static sscf_status guarded(sscf_ctx* x, Fn&& fn) {
   try {
     fn();
   } catch (const Fail& f) {
+    x->counting = false;
     x->err = f.msg;
     if (f.code == SSCF_E_HIP) x->failed = true;
     return f.code;
@@ -1322,10 +1438,12 @@ sscf_status sscf_orthonormalize(sscf_ctx* x, int32_t occ_only, sscf_step_info* o
     std::memset(&info, 0, sizeof(info));
     double eta = 0.0;
     int conv = 0;
+    x->counting = true;
     const int sweeps = x->orthonormalize(occ_only, x->max_sweeps_init, &eta, &conv);
     if (!conv) fail(SSCF_E_ORTHO, "orthonormalization did not reach eps/100 in %d sweeps (eta %.3e)", sweeps, eta);
     x->charges(0);
     x->energy_terms();
+    x->counting = false;
     const Scalars h = x->read_scalars();
     x->E = h.e_band + h.e_coul;
     info.energy = x->E;
@@ -1335,6 +1453,7 @@ sscf_status sscf_orthonormalize(sscf_ctx* x, int32_t occ_only, sscf_step_info* o
     info.ortho_eta = eta;
     info.ortho_converged = conv;
     info.nnz_tiles = x->active_tiles();
+    info.nnz_c = x->count ? x->count_nnz_c() : -1;
     x->pcollect();
     if (out) *out = info;
   });
@@ -1484,7 +1603,8 @@ sscf_status sscf_get_kernel_stats(const sscf_ctx* cx, sscf_kernel_stat* out, int
   if (!out) { *n = SSCF_N_KERNEL_CLASSES; return SSCF_OK; }
   if (*n < SSCF_N_KERNEL_CLASSES) return SSCF_E_INVALID_ARG;
   return guarded(x, [&] {
-    if (!x->prof) fail(SSCF_E_STATE, "profiling was not requested (SSCF_FLAG_PROFILE)");
+    if (!x->prof && !x->count)
+      fail(SSCF_E_STATE, "neither profiling (SSCF_FLAG_PROFILE) nor work counting (SSCF_FLAG_COUNT_WORK) was requested");
     unsigned long long c[SSCF_N_KERNEL_CLASSES];
     HIPC(hipMemcpyAsync(c, x->pctr, sizeof(c), hipMemcpyDeviceToHost, x->stream));
     x->sync();
@@ -1493,8 +1613,9 @@ sscf_status sscf_get_kernel_stats(const sscf_ctx* cx, sscf_kernel_stat* out, int
       std::strncpy(out[k].name, KC_NAME[k], sizeof(out[k].name) - 1);
       out[k].launches = x->plaunch[k];
       out[k].ms = x->pms[k];
-      out[k].flops = KC_FLOP_PER_UNIT[k] * (double)c[k];
-      out[k].bytes = KC_BYTE_PER_UNIT[k] * (double)c[k];
+      out[k].mfma_flops = KC_FLOP_PER_MFMA * (double)c[k];
+      out[k].alg_flops = x->count ? x->wfl[k] : -1.0;
+      out[k].alg_bytes = x->count ? x->wby[k] : -1.0;
     }
     *n = SSCF_N_KERNEL_CLASSES;
   });
@@ -1503,9 +1624,10 @@ sscf_status sscf_get_kernel_stats(const sscf_ctx* cx, sscf_kernel_stat* out, int
 sscf_status sscf_reset_kernel_stats(sscf_ctx* x) {
   if (!x) return SSCF_E_INVALID_ARG;
   return guarded(x, [&] {
-    if (!x->prof) fail(SSCF_E_STATE, "profiling was not requested (SSCF_FLAG_PROFILE)");
+    if (!x->prof && !x->count)
+      fail(SSCF_E_STATE, "neither profiling (SSCF_FLAG_PROFILE) nor work counting (SSCF_FLAG_COUNT_WORK) was requested");
     x->pcollect();
-    for (int k = 0; k < SSCF_N_KERNEL_CLASSES; ++k) { x->pms[k] = 0.0; x->plaunch[k] = 0; }
+    for (int k = 0; k < SSCF_N_KERNEL_CLASSES; ++k) { x->pms[k] = 0.0; x->plaunch[k] = 0; x->wfl[k] = 0.0; x->wby[k] = 0.0; }
     HIPC(hipMemsetAsync(x->pctr, 0, sizeof(unsigned long long) * SSCF_N_KERNEL_CLASSES, x->stream));
     x->sync();
   });

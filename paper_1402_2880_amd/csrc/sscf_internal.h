@@ -158,7 +158,7 @@ void launch_km_move(int n, int m, const double* pts, const int* assign, const do
                     double* disp, hipStream_t s);
 void launch_givens_rb(const View& v, int n_rounds, const int* roff, const int4* meta, const int* tcol,
                       const double* R, const float* R32, double eps, double* C, uint8_t* actC,
-                      unsigned int* cmask, unsigned long long* ctr, hipStream_t s);
+                      unsigned int* cmask, const int* rot_cnt, unsigned long long* wcnt, hipStream_t s);
 void launch_spmm32(const View& v, const float* X, const float* C, const uint8_t* actC,
                    const unsigned int* cmask, const int* listY, const int* cntY, float* Y,
                    unsigned int* ymask, unsigned long long* ctr, hipStream_t s);
@@ -183,6 +183,18 @@ void launch_density_blocks(const View& v, const double* A, const uint8_t* actA, 
 void launch_apply_occ(const View& v, const double* C, const uint8_t* actC, const int* gn_ptr, const int* gn,
                       const int* pair_of, const int* pg, const double* FA, const double* FB, const int* listZ,
                       const int* cntZ, double* Z, hipStream_t s);
+// ---- work counting (sscf_count.hip) --------------------------------------------------------
+void launch_cnt_xrow(const View& v, const void* X, bool fp32, int* xrow, unsigned long long* tot, hipStream_t s);
+void launch_cnt_tiles(const View& v, const void* T, bool fp32, const int* list, const int* cnt, int c0, int c1,
+                      const int* weight, int* colnnz, unsigned long long* nnz, unsigned long long* wsum,
+                      hipStream_t s);
+void launch_row_masks(const View& v, const void* T, bool fp32, const int* list, const int* cnt, ulonglong2* masks,
+                      hipStream_t s);
+void launch_cnt_pairs(const View& v, int n_items, const int* ig, const int* ih, const int* listC, const int* cntC,
+                      const uint8_t* actY, const ulonglong2* mC, const ulonglong2* mY, int a0, int a1, int b0,
+                      int b1, int tri, unsigned long long* out, hipStream_t s);
+void launch_cnt_dot(size_t n, const int* a, const int* b, unsigned long long* dot, unsigned long long* sumb,
+                    hipStream_t s);
 void launch_gather(const int64_t* map, int64_t n, const double* src, double* dst, hipStream_t s);
 void launch_scatter(const int64_t* map, int64_t n, const double* src, double* dst, hipStream_t s);
 

@@ -1260,7 +1260,8 @@ __global__ void __launch_bounds__(256) k_givens_rb(int G, int n_rb, int W, int O
                                                    const int* __restrict__ roff, const int4* __restrict__ meta,
                                                    const int* __restrict__ tcol,
                                                    const Real* __restrict__ R, double eps, double* C,
-                                                   uint8_t* actC, unsigned int* cmask, unsigned long long* ctr) {
+                                                   uint8_t* actC, unsigned int* cmask, const int* __restrict__ rot_cnt,
+                                                   unsigned long long* wcnt) {
   typedef typename Mfma<Real>::acc_t acc_t;
   extern __shared__ int4 gv_smem[];
   int4* list_l = gv_smem;                                    // relevant blocks of the round
@@ -1271,7 +1272,10 @@ __global__ void __launch_bounds__(256) k_givens_rb(int G, int n_rb, int W, int O
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   for (int g = threadIdx.x; g < G; g += blockDim.x) act_l[g] = actC[(size_t)g * n_rb + rb];
-  unsigned long long bytes = 0;
+  // work counting (wcnt != NULL): per block and row block, the nonzeros of the touched columns
+  // before the block (read and written: 16 bytes each) and 6 flops per rotation and row of
+  // their union
+  unsigned long long w_flops = 0, w_bytes = 0;
   // the first 256 rotating blocks of round r + 1 are fetched while round r is applied
   auto fetch_round = [&](int r) {
     return (int)threadIdx.x < roff[r + 1] - roff[r] ? meta[roff[r] + threadIdx.x] : make_int4(-1, 0, 0, 0);
@@ -1311,6 +1315,7 @@ __global__ void __launch_bounds__(256) k_givens_rb(int G, int n_rb, int W, int O
         acc_t acc[NTMAX];
 #pragma unroll
         for (int n = 0; n < NTMAX; ++n) acc[n] = acc_t{0, 0, 0, 0};
+        unsigned int w_rows = 0u, w_nnz = 0u;
         for (int s0 = 0; s0 < ns; s0 += 8) {
           // gathers, all in flight together (a lane past T reads the zero page)
           Real a[8];
@@ -1321,6 +1326,14 @@ __global__ void __launch_bounds__(256) k_givens_rb(int G, int n_rb, int W, int O
             const bool in = s0 + u < ns && k < T;
             const int col = (k < 64) ? c0 : c1;
             a[u] = (Real)ld_or_zero(in, (col < OW ? Cg : Ch) + lr * W + col, zl(zp, rb * 8 + u));
+          }
+          if (wcnt) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const unsigned long long b = __ballot(a[u] != Real(0));      // bit = 16 lk + row
+              w_nnz += __popcll(b);
+              w_rows |= (unsigned int)((b | (b >> 16) | (b >> 32) | (b >> 48)) & 0xffffull);
+            }
           }
 #pragma unroll
           for (int n = 0; n < NTMAX; ++n) {
@@ -1362,23 +1375,29 @@ __global__ void __launch_bounds__(256) k_givens_rb(int G, int n_rb, int W, int O
           if (anyg && !act_l[g]) { act_l[g] = 1; actC[(size_t)g * n_rb + rb] = 1; }
           if (anyh && !act_l[h]) { act_l[h] = 1; actC[(size_t)h * n_rb + rb] = 1; }
         }
-        bytes += (unsigned long long)T * RB * 16ULL;
+        if (wcnt) {
+          w_bytes += 16ull * w_nnz;
+          w_flops += 6ull * (unsigned long long)rot_cnt[b] * (unsigned long long)__popc(w_rows);
+        }
       }
       __syncthreads();
     }
   }
-  if (ctr && lane == 0 && bytes) atomicAdd(ctr, bytes);
+  if (wcnt && lane == 0) {
+    if (w_flops) atomicAdd(wcnt, w_flops);
+    if (w_bytes) atomicAdd(wcnt + 1, w_bytes);
+  }
 }
 
 void launch_givens_rb(const View& v, int n_rounds, const int* roff, const int4* meta, const int* tcol, const double* R,
-                      const float* R32, double eps, double* C, uint8_t* actC, unsigned int* cmask,
-                      unsigned long long* ctr, hipStream_t s) {
+                      const float* R32, double eps, double* C, uint8_t* actC, unsigned int* cmask, const int* rot_cnt,
+                      unsigned long long* wcnt, hipStream_t s) {
   if (n_rounds <= 0) return;
   const size_t lds = 256 * sizeof(int4) + 4 * sizeof(int) + (size_t)v.G;
   switch ((v.W + 15) / 16) {
 #define SSCF_GIV(N) case N: \
-    if (R32) hipLaunchKernelGGL((k_givens_rb<N, float>), dim3(v.n_rb), dim3(256), lds, s, v.G, v.n_rb, v.W, v.OW, n_rounds, v.zeros, roff, meta, tcol, R32, eps, C, actC, cmask, ctr); \
-    else hipLaunchKernelGGL((k_givens_rb<N, double>), dim3(v.n_rb), dim3(256), lds, s, v.G, v.n_rb, v.W, v.OW, n_rounds, v.zeros, roff, meta, tcol, R, eps, C, actC, cmask, ctr); \
+    if (R32) hipLaunchKernelGGL((k_givens_rb<N, float>), dim3(v.n_rb), dim3(256), lds, s, v.G, v.n_rb, v.W, v.OW, n_rounds, v.zeros, roff, meta, tcol, R32, eps, C, actC, cmask, rot_cnt, wcnt); \
+    else hipLaunchKernelGGL((k_givens_rb<N, double>), dim3(v.n_rb), dim3(256), lds, s, v.G, v.n_rb, v.W, v.OW, n_rounds, v.zeros, roff, meta, tcol, R, eps, C, actC, cmask, rot_cnt, wcnt); \
     break;
     SSCF_GIV(1) SSCF_GIV(2) SSCF_GIV(3) SSCF_GIV(4) SSCF_GIV(5) SSCF_GIV(6) SSCF_GIV(7) SSCF_GIV(8)
 #undef SSCF_GIV

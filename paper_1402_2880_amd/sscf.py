@@ -24,6 +24,7 @@ STATUS = {0: "SSCF_OK", -1: "SSCF_E_INVALID_ARG", -2: "SSCF_E_NOT_SPD", -3: "SSC
 FP64, FP32_MIXED = 0, 1
 FOCK_H0, FOCK_FULL = 0, 1
 FLAG_PROFILE = 1
+FLAG_COUNT_WORK = 2
 N_KERNEL_CLASSES = 7
 
 ALLOC_FN = ct.CFUNCTYPE(ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p)
@@ -56,7 +57,7 @@ class StepInfo(ct.Structure):
         ("max_abs_fov", ct.c_double), ("ortho_eta", ct.c_double), ("e_band", ct.c_double),
         ("e_coul", ct.c_double), ("n_candidates", ct.c_int32), ("n_rotations", ct.c_int32),
         ("n_ortho_sweeps", ct.c_int32), ("converged", ct.c_int32), ("ortho_converged", ct.c_int32),
-        ("post_ortho", ct.c_int32), ("nnz_tiles", ct.c_int64), ("ms_fock", ct.c_float),
+        ("post_ortho", ct.c_int32), ("nnz_tiles", ct.c_int64), ("nnz_c", ct.c_int64), ("ms_fock", ct.c_float),
         ("ms_cfc", ct.c_float), ("ms_select", ct.c_float), ("ms_rot", ct.c_float),
         ("ms_ortho", ct.c_float), ("ms_sums", ct.c_float), ("ms_total", ct.c_float),
     ]
@@ -93,7 +94,7 @@ CONV_ENERGY, CONV_CHARGE = 0, 1
 
 class KernelStat(ct.Structure):
     _fields_ = [("name", ct.c_char * 32), ("launches", ct.c_int64), ("ms", ct.c_double),
-                ("flops", ct.c_double), ("bytes", ct.c_double)]
+                ("mfma_flops", ct.c_double), ("alg_flops", ct.c_double), ("alg_bytes", ct.c_double)]
 
 
 EXPORTS = ["sscf_get_kernel_stats", "sscf_reset_kernel_stats", "sscf_init_system", "sscf_set_fock", "sscf_scf_step", "sscf_get_energy",
@@ -180,7 +181,7 @@ class SparseSCF:
     def __init__(self, system, eps: float = 1e-5, e_conv: float = 1e-6, group_nbr_bohr: float = 20.0,
                  rot_cap_factor: float = 10.0, max_sweeps_init: int = 200, max_sweeps_step: int = 50,
                  scc: bool = True, precision: int = FP64, stream=None, use_torch_allocator: bool = True,
-                 profile: bool = False):
+                 profile: bool = False, count_work: bool = False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("the sparse SCF library needs a GPU")
@@ -218,7 +219,7 @@ class SparseSCF:
             group_nbr_bohr=group_nbr_bohr, rot_cap_factor=rot_cap_factor,
             max_sweeps_init=max_sweeps_init, max_sweeps_step=max_sweeps_step, scc=1 if scc else 0,
             precision=precision, hip_stream=self._stream.cuda_stream, alloc=alloc,
-            flags=FLAG_PROFILE if profile else 0)
+            flags=(FLAG_PROFILE if profile else 0) | (FLAG_COUNT_WORK if count_work else 0))
         h = ct.c_void_p()
         rc = lib().sscf_init_system(ct.byref(d), ct.byref(h))
         if rc != SSCF_OK:
@@ -314,7 +315,8 @@ class SparseSCF:
         arr = (KernelStat * N_KERNEL_CLASSES)()
         n = ct.c_int32(N_KERNEL_CLASSES)
         self._check(lib().sscf_get_kernel_stats(self._h, arr, ct.byref(n)))
-        return {a.name.decode(): dict(launches=a.launches, ms=a.ms, flops=a.flops, bytes=a.bytes)
+        return {a.name.decode(): dict(launches=a.launches, ms=a.ms, mfma_flops=a.mfma_flops,
+                                      alg_flops=a.alg_flops, alg_bytes=a.alg_bytes)
                 for a in arr[:n.value]}
 
     def reset_kernel_stats(self) -> None:
