@@ -6,12 +6,28 @@ selection and application, re-orthonormalization, charges, energy) on the
 MOs), inputs resident in HBM.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--config water4096] [--precision fp64]
+
+What one invocation measures:
+  * the timed run: W untimed steps, then K steps between two device
+    synchronizations (value = K / wall time), every kernel class bracketed by HIP
+    events on the library stream;
+  * a replay of the same steps from the same inputs with the algorithmic work
+    counters on (SSCF_FLAG_COUNT_WORK; the path is deterministic, the replay's
+    energies are checked equal to the timed run's): the roofline fields price each
+    kernel class by the work of the method itself, not by the tiles it executes;
+  * the other precision form on the same system and window (FP32 form next to the
+    FP64 one), timed the same way;
+  * the energy error of every timed step against the stored FP64 oracle values of
+    this workload (tests/golden), when they cover the window;
+  * the FP64 oracle on the host cores (cpu_baseline), on a bounded sample.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -19,90 +35,218 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "SCF steps/sec + HBM GB/s at 12k atoms; FP32 vs FP64 form at 1e-6 Ha"
-PEAK = {"hbm": 8000.0, "fp64": 78.6, "fp32": 157.3}   # GB/s, TFLOP/s (MI355X, dense)
+PEAK_HBM = 8000.0                         # GB/s, MI355X HBM3E
+PEAK = {"fp64": 78.6, "fp32": 157.3}      # TFLOP/s, MI355X dense FP64 / FP32 (vector = matrix)
+CLASSES = ("spmm_tiles", "pair_overlap", "pair_fock", "ortho_update", "rotations")
 # Measured HBM traffic per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a copy kernel);
-# it is reported only while the kernel source is the one the counters were taken from.
+# reported only while the kernel source is the one the counters were taken from.
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic_water4096_fp64.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1402_2880_amd", "csrc", "sscf_kernels.hip")
-KERNEL_OF_CLASS = {"ortho_update": "sscf::k_ortho_update<6>", "spmm_tiles": "sscf::k_spmm_row<6, double>",
-                   "pair_overlap": "sscf::k_pair<3, 3>", "pair_fock": "sscf::k_pair<2, 2>",
-                   "rotations": "sscf::k_givens_rb<6, double>"}
+GOLDEN = os.path.join(ROOT, "tests", "golden", "water4096_seed{}.json")
+# The paper's own numbers for this path (context only: other hardware, no steps/s or GB/s printed)
+PAPER_CONTEXT = {
+    "note": "the paper prints no SCF steps/s, GB/s or seconds per step for this path; shares of its "
+            "whole-program wall time on 2x Xeon E5-2670 (16 cores) and an SGI Altix UV (384 cores), "
+            "C^T H C in FP32, orthonormalization in FP64",
+    "ctc_h_plus_rotations_share": "33-40% (rotations alone 3-6%)",
+    "orthonormalization_share": "40-50% (half C^T S C, half pair combinations)",
+    "coulomb_share": "<20% (10% at 33,120 molecules, 18% at 504,896)",
+    "ctxc_speedup_16_cores": "about 16 for small boxes, about 11 for large ones",
+    "energy_error_vs_lapack": "relative 8.0e-11 to 1.2e-10 at dq_max 1e-5 (184-3,312 molecules)",
+}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(system, budget_s: float, eps: float, e_conv: float):
-    """The FP64 oracle on the host cores: set-up untimed, then SCF steps until the budget."""
-    from oracle.oracle import Oracle
-    threads = os.cpu_count() or 1
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads() -> int:
+    n = os.cpu_count() or 1
     omp = os.environ.get("OMP_NUM_THREADS")
     if omp and omp.isdigit():
-        threads = min(threads, int(omp))
+        n = min(n, int(omp))
+    return n
+
+
+def cpu_baseline(system, budget_s: float, eps: float, e_conv: float, gpu_window: str):
+    """The FP64 oracle on the host cores: set-up untimed, then SCF steps from the initial guess until
+    the budget; and one step of the 512-molecule box on one thread and on all threads (the thread
+    scaling of the oracle)."""
+    from oracle.oracle import Oracle
+    from paper_1402_2880_amd import synth
+    threads = host_threads()
     o = Oracle(system, eps=eps, e_conv=e_conv, n_threads=threads)
-    n, t_sum = 0, 0.0
-    while t_sum < budget_s and n < 20:
-        t = time.time()
+    times = []
+    while sum(times) < budget_s and len(times) < 25:
+        t = time.perf_counter()
         o.step()
-        t_sum += time.time() - t
-        n += 1
-    return dict(value=n / t_sum, unit="SCF steps/s", cores=threads, kind="oracle",
-                sample=f"oracle SCF steps 1..{n} of the same {system.name} system (set-up not timed), "
-                       f"{t_sum:.1f} s")
+        times.append(time.perf_counter() - t)
+    del o
+    med = statistics.median(times)
+    small = synth.make_config("water512", 1)
+    one = {}
+    for th in (1, threads):
+        ob = Oracle(small, eps=eps, e_conv=e_conv, n_threads=th)
+        t = time.perf_counter()
+        ob.step()
+        one[th] = time.perf_counter() - t
+        del ob
+    return dict(value=round(1.0 / med, 5), unit="SCF steps/s", cores=threads, kind="oracle",
+                cpu_model=cpu_model(), host_cpus=os.cpu_count(),
+                sample=f"oracle (FP64, OpenMP, {threads} threads) SCF steps 1..{len(times)} of the same "
+                       f"{system.name} system from the initial guess (set-up not timed), {sum(times):.1f} s; "
+                       f"value = 1 / median s per step; the GPU window is {gpu_window}: the oracle needs tens "
+                       "of seconds per step here, so the bounded sample cannot reach it",
+                s_per_step=[round(x, 2) for x in times], median_s_per_step=round(med, 3),
+                one_thread=dict(workload="water512 seed 1 (1,536 atoms), SCF step 1",
+                                s_1_thread=round(one[1], 3), s_all_threads=round(one[threads], 3),
+                                speedup=round(one[1] / one[threads], 2)))
 
 
-def step_traffic(kstats, elapsed_s: float, steps: int, config: str, precision: str, seed: int):
-    """HBM traffic of the timed steps: each profiled kernel's measured bytes per launch times its
-    launches in the timed window (the five MFMA / gather kernels; the rest move < 5% of the
-    bytes), or None when the counter summary does not match the kernel source."""
-    if kstats is None:
-        return None
-    per = {k: measured_traffic(k, config, precision, seed) for k in KERNEL_OF_CLASS}
-    if any(v is None for v in per.values()):
-        return None
-    total = sum(per[k] * kstats[k]["launches"] for k in per if k in kstats)
-    return dict(gb_per_step=round(total / steps, 2), gb_per_s=round(total / elapsed_s, 1),
-                kernels=sorted(per), source="profiles/traffic_water4096_fp64.json")
+def setup_timing(system, args, prec):
+    """The GPU set-up calls on this system: atom neighbour map and constrained k-means (section 3.2),
+    per-fragment initial guess (section 3.3), and the library set-up with the initial
+    orthonormalization."""
+    import numpy as np
+    import torch
+    from paper_1402_2880_amd import synth
+    from paper_1402_2880_amd.sscf import SparseSCF, atom_neighbours, constrained_kmeans, fragment_guess
+    n_mol = int(system.atom_mol.max()) + 1
+    first = np.searchsorted(system.atom_mol, np.arange(n_mol))
+    last = np.searchsorted(system.atom_mol, np.arange(n_mol), side="right")
+    nocc = np.array([int(round(system.q0[a:b].sum())) // 2 for a, b in zip(first, last)], dtype=np.int32)
+    aoo = system.ao_offset()
+    if int((aoo[last] - aoo[first]).max()) <= 8:
+        fragment_guess(system, system.atom_mol, nocc, system.atom_group[first])      # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fragment_guess(system, system.atom_mol, nocc, system.atom_group[first], drop=1e-13)
+        setup = dict(guess_ms=round(1e3 * (time.perf_counter() - t), 2), fragments=n_mol)
+    else:
+        setup = dict(guess_ms=None, fragments=n_mol,
+                     guess_note="molecules of more than 8 AOs: the GPU guess takes fragments of at most 8")
+    cut = synth.SK_CUTOFF * synth.BOHR_PER_ANGSTROM
+    atom_neighbours(system.xyz_bohr, cut)                                                # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    nrp, _ = atom_neighbours(system.xyz_bohr, cut)
+    setup.update(atom_map_ms=round(1e3 * (time.perf_counter() - t), 2), atom_map_nnz=int(nrp[-1]))
+    pts = system.xyz_bohr[first]
+    m0 = synth.initial_means(np.random.default_rng(args.seed), pts, -(-n_mol // synth.N_LINK))
+    constrained_kmeans(pts, m0, synth.N_LINK, max_iter=2)                                # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, _, kinfo = constrained_kmeans(pts, m0, synth.N_LINK, max_iter=100, tol=1e-4)
+    setup.update(kmeans_ms=round(1e3 * (time.perf_counter() - t), 2), kmeans_iterations=kinfo["iterations"],
+                 kmeans_rounds=kinfo["rounds"], kmeans_means=int(m0.shape[0]))
+    t = time.perf_counter()
+    g = SparseSCF(system, eps=args.eps, e_conv=args.e_conv, precision=prec)
+    torch.cuda.synchronize()
+    setup["init_ms"] = round(1e3 * (time.perf_counter() - t), 1)
+    g.close()
+    setup["includes"] = ("atom map: copy, count pass, scan, fill pass, copy back (two calls: size, then map); "
+                         "kmeans: copies, up to 100 iterations of attribution rounds + centroid move, copy back; "
+                         "guess: host-to-device copies, one thread per fragment, copy back, CSC assembly; "
+                         "init: validation, neighbour map (GPU), pairs, rounds, uploads, initial orthonormalization")
+    return setup
 
 
-def measured_traffic(kclass: str, config: str, precision: str, seed: int):
-    """HBM bytes per launch of the kernel class from the committed counter summary, or None."""
-    import hashlib
-    # the counters were taken on water4096 seed 1 in the FP64 form: no other workload uses them
+def measured_traffic(kernel: str, config: str, precision: str, seed: int):
+    """HBM bytes per launch of the kernel from the committed counter summary, or None."""
     if config != "water4096" or precision != "fp64" or seed != 1 or not os.path.exists(TRAFFIC):
         return None
     rec = json.load(open(TRAFFIC))
     if hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest() != rec.get("kernel_source_sha256"):
         return None
-    k = rec["kernels"].get(KERNEL_OF_CLASS.get(kclass, ""))
-    return None if k is None else round(k["hbm_bytes_per_launch"] / 1e9, 3)
+    k = rec["kernels"].get(rec.get("class_kernel", {}).get(kernel, ""))
+    return None if k is None else round(k["hbm_bytes_per_launch"] / 1e9, 4)
+
+
+def load_golden(config: str, seed: int, eps: float, e_conv: float):
+    path = GOLDEN.format(seed)
+    if config != "water4096" or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("seed") != seed or rec.get("eps") != eps or rec.get("e_conv") != e_conv:
+        return None
+    return rec
+
+
+def run_form(system, prec, args, profile: bool, count: bool, adjoint: bool = False):
+    """Warm-up and timed steps of one precision form; returns (infos, elapsed s, kernel stats)."""
+    import torch
+    from paper_1402_2880_amd.sscf import CONV_CHARGE, SparseSCF
+    g = SparseSCF(system, eps=args.eps, e_conv=args.e_conv, precision=prec, profile=profile, count_work=count)
+    if args.schedule == "paper":
+        g.set_control(args.eps, dq_conv=10 * args.eps, criterion=CONV_CHARGE, step_ortho=False)
+    warm = []
+    for _ in range(args.warmup):
+        warm.append(g.step())
+        if adjoint:
+            g.energy_gradient(device=True)
+    if profile or count:
+        g.reset_kernel_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        infos.append(g.step())
+        if adjoint:
+            g.energy_gradient(device=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ks = g.kernel_stats() if (profile or count) else None
+    init = g.init_info()
+    g.close()
+    return warm, infos, elapsed, ks, init
+
+
+def energy_errors(infos, golden, first_step: int):
+    """|E_gpu - E_oracle| of each step covered by the stored oracle values (steps are 1-based)."""
+    if golden is None:
+        return None
+    out = []
+    for k, si in enumerate(infos):
+        n = first_step + k
+        if n <= len(golden["steps"]):
+            out.append(abs(si["energy"] - golden["steps"][n - 1]["energy"]))
+    return out or None
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=18)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="water4096")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--eps", type=float, default=1e-5)
     ap.add_argument("--e-conv", type=float, default=1e-6)
-    ap.add_argument("--cpu-budget", type=float, default=25.0)
+    ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-profile", action="store_true", help="time without per-kernel HIP events")
+    ap.add_argument("--no-other-form", action="store_true", help="skip the other precision form's timed run")
+    ap.add_argument("--no-count", action="store_true", help="skip the work-counting replay (no roofline)")
     ap.add_argument("--schedule", default="step", choices=["step", "paper"],
                     help="step: step III after every step, |dE| < e-conv (default); paper: step III only at "
                          "set-up and after convergence, dq_max < 10 eps (section 4.1)")
-    ap.add_argument("--setup-timing", action="store_true",
-                    help="time the GPU atom neighbour map and constrained k-means (section 3.2), initial guess (section 3.3) and the library set-up (neighbour maps, "
-                         "schedule, initial orthonormalization)")
     ap.add_argument("--adjoint", action="store_true",
-                    help="a step is the forward SCF step plus the energy gradient (dE/dH0, dE/dS) at its MOs, "
-                         "both inside the timed region")
-    ap.add_argument("--gradient", action="store_true",
-                    help="after the timed steps, time one energy-gradient evaluation (dE/dH0, dE/dS)")
+                    help="a step is the forward SCF step plus the energy gradient (dE/dH0, dE/dS, dE/d onsite) "
+                         "at its MOs into device memory, both inside the timed region")
+    ap.add_argument("--setup-timing", action="store_true",
+                    help="also time the GPU atom neighbour map and constrained k-means (section 3.2), the initial "
+                         "guess (section 3.3) and the library set-up (neighbour maps, schedule, initial "
+                         "orthonormalization)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="before the SCF, copy a buffer of this size three times: a kernel of known "
                          "traffic against which hardware byte counters are scaled")
@@ -115,7 +259,7 @@ def main():
 
     import torch
     from paper_1402_2880_amd import synth
-    from paper_1402_2880_amd.sscf import FP32_MIXED, FP64, SparseSCF
+    from paper_1402_2880_amd.sscf import FP32_MIXED, FP64
 
     torch.cuda.set_device(0)
     if args.copy_calibration > 0:
@@ -125,131 +269,104 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        log(f"[bench] copy calibration: 3 copies of {args.copy_calibration} MiB "
-            f"({args.copy_calibration * 1024} KiB read and written each)")
+        log(f"[bench] copy calibration: 3 copies of {args.copy_calibration} MiB")
         del src, dst
     t = time.time()
     system = synth.make_config(args.config, args.seed)
     log(f"[bench] {args.config}: {system.n_atoms} atoms, {system.n_ao} AOs, {system.n_mo} MOs "
         f"(generated in {time.time() - t:.1f} s)")
     prec = FP64 if args.precision == "fp64" else FP32_MIXED
-    setup = None
-    if args.setup_timing:
-        import numpy as np
-        from paper_1402_2880_amd.sscf import fragment_guess
-        n_mol = int(system.atom_mol.max()) + 1
-        first = np.searchsorted(system.atom_mol, np.arange(n_mol))
-        last = np.searchsorted(system.atom_mol, np.arange(n_mol), side="right")
-        nocc = np.array([int(round(system.q0[a:b].sum())) // 2 for a, b in zip(first, last)], dtype=np.int32)
-        aoo = system.ao_offset()
-        if int((aoo[last] - aoo[first]).max()) <= 8:
-            fragment_guess(system, system.atom_mol, nocc, system.atom_group[first])      # warm-up
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            fragment_guess(system, system.atom_mol, nocc, system.atom_group[first], drop=1e-13)
-            setup = dict(guess_ms=round(1e3 * (time.perf_counter() - t), 2), fragments=n_mol)
-        else:
-            setup = dict(guess_ms=None, fragments=n_mol,
-                         guess_note="molecules of more than 8 AOs: the GPU guess takes fragments of at most 8")
-        # atom neighbour map (section 3.2): the pattern S and H are given on
-        from paper_1402_2880_amd.sscf import atom_neighbours
-        cut = synth.SK_CUTOFF * synth.BOHR_PER_ANGSTROM
-        atom_neighbours(system.xyz_bohr, cut)                                            # warm-up
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        nrp, _ = atom_neighbours(system.xyz_bohr, cut)
-        setup.update(atom_map_ms=round(1e3 * (time.perf_counter() - t), 2), atom_map_nnz=int(nrp[-1]))
-        # constrained k-means (section 3.2) on the molecules' first atoms, N_link per group
-        from paper_1402_2880_amd.sscf import constrained_kmeans
-        pts = system.xyz_bohr[first]
-        m0 = synth.initial_means(np.random.default_rng(args.seed), pts, -(-n_mol // synth.N_LINK))
-        constrained_kmeans(pts, m0, synth.N_LINK, max_iter=2)                            # warm-up
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        _, _, kinfo = constrained_kmeans(pts, m0, synth.N_LINK, max_iter=100, tol=1e-4)
-        setup.update(kmeans_ms=round(1e3 * (time.perf_counter() - t), 2), kmeans_iterations=kinfo["iterations"],
-                     kmeans_rounds=kinfo["rounds"], kmeans_means=int(m0.shape[0]))
-    t = time.time()
-    g = SparseSCF(system, eps=args.eps, e_conv=args.e_conv, precision=prec, profile=not args.no_profile)
-    if setup is not None:
-        setup["init_ms"] = round(1e3 * (time.time() - t), 1)
-        setup["includes"] = ("atom map: copy, count pass, scan, fill pass, copy back (two calls: size, then map); "
-                             "kmeans: copies, up to 100 iterations of attribution rounds + centroid move, copy back; "
-                             "guess: host-to-device copies, one thread per fragment, copy back, CSC assembly; "
-                             "init: validation, neighbour map (GPU), pairs, rounds, uploads, initial orthonormalization")
-    if args.schedule == "paper":
-        from paper_1402_2880_amd.sscf import CONV_CHARGE
-        g.set_control(args.eps, dq_conv=10 * args.eps, criterion=CONV_CHARGE, step_ortho=False)
-    log(f"[bench] set-up + initial orthonormalization {time.time() - t:.1f} s "
-        f"({g.init_info()['n_ortho_sweeps']} sweeps)")
-    for k in range(args.warmup):
-        si = g.step()
-        if args.adjoint:
-            g.energy_gradient()
-        log(f"[bench] warmup {k + 1}: E {si['energy']:.10f} rot {si['n_rotations']} "
-            f"{si['ms_total']:.1f} ms")
-    if not args.no_profile:
-        g.reset_kernel_stats()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = []
-    for k in range(args.steps):
-        infos.append(g.step())
-        if args.adjoint:
-            g.energy_gradient()      # includes the copy of dE/dH0 and dE/dS to host memory
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    for k, si in enumerate(infos):
-        log(f"[bench] step {args.warmup + k + 1}: E {si['energy']:.10f} dE {si['delta_e']:.2e} "
-            f"rot {si['n_rotations']} sweeps {si['n_ortho_sweeps']} {si['ms_total']:.1f} ms "
-            f"(fock {si['ms_fock']:.2f} cfc {si['ms_cfc']:.2f} sel {si['ms_select']:.2f} "
-            f"rot {si['ms_rot']:.2f} ortho {si['ms_ortho']:.2f} sums {si['ms_sums']:.2f})")
+    golden = load_golden(args.config, args.seed, args.eps, args.e_conv) if args.schedule == "step" else None
+    first = args.warmup + 1
+    window = f"SCF steps {first}..{args.warmup + args.steps}"
+
+    # 1. the timed run
+    warm, infos, elapsed, kstats, init = run_form(system, prec, args, profile=True, count=False,
+                                                  adjoint=args.adjoint)
+    for k, si in enumerate(warm + infos):
+        log(f"[bench] step {k + 1}: E {si['energy']:.10f} dE {si['delta_e']:.2e} rot {si['n_rotations']} "
+            f"sweeps {si['n_ortho_sweeps']} {si['ms_total']:.1f} ms (fock {si['ms_fock']:.2f} cfc "
+            f"{si['ms_cfc']:.2f} sel {si['ms_select']:.2f} rot {si['ms_rot']:.2f} ortho {si['ms_ortho']:.2f} "
+            f"sums {si['ms_sums']:.2f})")
     value = args.steps / elapsed
+    ms_step = 1e3 * elapsed / args.steps
+
+    # 2. the replay with the work counters
+    counts = None
+    if not args.no_count:
+        _, cinfos, _, cks, _ = run_form(system, prec, args, profile=False, count=True, adjoint=False)
+        same = all(a["energy"] == b["energy"] for a, b in zip(cinfos, infos))
+        counts = dict(stats=cks, replay_energies_identical=same,
+                      nnz_c=[si["nnz_c"] for si in cinfos])
+        log(f"[bench] count replay: energies identical to the timed run: {same}")
+
+    # 3. roofline per kernel class (algorithmic work / measured time), step level t_roof
+    peak_c = PEAK["fp64"] if args.precision == "fp64" else PEAK["fp32"]
+    classes = {}
+    t_roof_ms = 0.0
+    for name in CLASSES:
+        st = kstats[name]
+        if not st["launches"]:
+            continue
+        ms = st["ms"]
+        rec = dict(launches=st["launches"], ms=round(ms, 3), avg_launch_ms=round(ms / st["launches"], 4),
+                   mfma_tflops_executed=round(st["mfma_flops"] / max(ms, 1e-9) / 1e9, 3))
+        if counts is not None:
+            c = counts["stats"][name]
+            # FP32 form: the C^T H C products run at the FP32 peak, the rest stays FP64
+            pk = PEAK["fp32"] if (args.precision == "fp32" and name == "pair_fock") else PEAK["fp64"]
+            tf = c["alg_flops"] / max(ms, 1e-9) / 1e9
+            gb = c["alg_bytes"] / max(ms, 1e-9) / 1e6
+            t_c = c["alg_flops"] / (pk * 1e12) * 1e3            # ms at the compute peak
+            t_m = c["alg_bytes"] / (PEAK_HBM * 1e9) * 1e3        # ms at the HBM peak
+            t_roof_ms += max(t_c, t_m)
+            bound = "mfma" if t_c >= t_m else "hbm"
+            rec.update(alg_gflop_per_launch=round(c["alg_flops"] / st["launches"] / 1e9, 4),
+                       alg_gb_per_launch=round(c["alg_bytes"] / st["launches"] / 1e9, 4),
+                       alg_tflops=round(tf, 4), alg_gbs=round(gb, 1), bound=bound,
+                       peak=pk if bound == "mfma" else PEAK_HBM,
+                       frac=round(max(t_c, t_m) / ms, 5))
+        classes[name] = rec
+    dom = max(classes, key=lambda k: classes[k]["ms"])
+    d = classes[dom]
     roofline = None
-    kstats = None
-    if not args.no_profile:
-        kstats = g.kernel_stats()
-        for name, st in kstats.items():
-            if st["launches"]:
-                log(f"[bench] kernel {name}: {st['launches']} launches, {st['ms']:.2f} ms, "
-                    f"{st['flops'] / max(st['ms'], 1e-9) / 1e9:.1f} TFLOP/s, "
-                    f"{st['bytes'] / max(st['ms'], 1e-9) / 1e6:.1f} GB/s")
-        # the dominant kernel by time
-        name, st = max(kstats.items(), key=lambda kv: kv[1]["ms"])
-        per_launch_ms = st["ms"] / max(st["launches"], 1)
-        if st["flops"] > 0:
-            achieved = st["flops"] / st["launches"] / (per_launch_ms * 1e-3) / 1e12
-            # each class at the peak of the arithmetic it runs: FP64 matrix cores, except in the
-            # FP32 form the C^T H C blocks and the products (whose H C launches are FP32; priced at
-            # the FP32 peak, the lower fraction, although their S C launches stay FP64)
-            fp32_class = args.precision == "fp32" and name in ("pair_fock", "spmm_tiles")
-            peak = PEAK["fp32"] if fp32_class else PEAK["fp64"]
-            roofline = dict(kernel=name, bound="mfma", achieved=round(achieved, 3), peak=peak,
-                            unit="TFLOP/s", frac=round(achieved / peak, 4),
-                            traffic=measured_traffic(name, args.config, args.precision, args.seed),
-                            traffic_unit="GB per launch",
-                            avg_launch_ms=round(per_launch_ms, 4), launches=st["launches"])
-        else:
-            achieved = st["bytes"] / st["launches"] / (per_launch_ms * 1e-3) / 1e9
-            roofline = dict(kernel=name, bound="hbm", achieved=round(achieved, 1), peak=PEAK["hbm"],
-                            unit="GB/s", frac=round(achieved / PEAK["hbm"], 4),
-                            traffic=measured_traffic(name, args.config, args.precision, args.seed),
-                            traffic_unit="GB per launch",
-                            avg_launch_ms=round(per_launch_ms, 4), launches=st["launches"])
-    grad = None
-    if args.gradient:
-        g.energy_gradient()                     # first call allocates its buffers
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        gx, gs = g.energy_gradient()
-        grad = dict(ms=round(1e3 * (time.perf_counter() - t), 3), n_val=int(gx.shape[0]),
-                    includes="device kernels (untruncated Fock, H C, occupied-occupied pair blocks, "
-                             "C_occ F, P and W on the pattern) + device-to-host copy of P and W + host assembly")
-        log(f"[bench] gradient {grad}")
+    if counts is not None:
+        mfma = d["bound"] == "mfma"
+        roofline = dict(kernel=dom, bound=d["bound"],
+                        achieved=d["alg_tflops"] if mfma else d["alg_gbs"],
+                        peak=d["peak"], unit="TFLOP/s" if mfma else "GB/s", frac=d["frac"],
+                        traffic=measured_traffic(dom, args.config, args.precision, args.seed),
+                        traffic_unit="GB per launch", avg_launch_ms=d["avg_launch_ms"], launches=d["launches"],
+                        alg_gflop_per_launch=d["alg_gflop_per_launch"], alg_gb_per_launch=d["alg_gb_per_launch"],
+                        work="algorithmic (SSCF_FLAG_COUNT_WORK replay of the same steps), not executed tiles",
+                        mfma_tflops_executed=d["mfma_tflops_executed"])
+    step_roof = None if counts is None else dict(
+        t_roof_ms_per_step=round(t_roof_ms / args.steps, 4), t_step_ms=round(ms_step, 3),
+        frac=round(t_roof_ms / args.steps / ms_step, 5),
+        note="t_roof = sum over the five main kernel classes of max(alg bytes / 8 TB/s, alg flops / peak)")
+
+    # 4. energy error against the stored FP64 oracle values
+    errs = energy_errors(infos, golden, first)
+    err = None if errs is None else dict(max_abs_ha=max(errs), steps_compared=len(errs),
+                                         reference=f"stored FP64 oracle values, tests/golden/water4096_seed{args.seed}.json")
+
+    # 5. the other precision form on the same window
+    other = None
+    if not args.no_other_form:
+        oprec, oname = (FP32_MIXED, "fp32") if prec == FP64 else (FP64, "fp64")
+        _, oinfos, oel, _, _ = run_form(system, oprec, args, profile=False, count=False)
+        oerrs = energy_errors(oinfos, golden, first)
+        other = dict(precision=oname, value=round(args.steps / oel, 4), unit="SCF steps/s",
+                     ms_per_step=round(1e3 * oel / args.steps, 3),
+                     energy_error_vs_fp64_oracle_max_ha=None if oerrs is None else max(oerrs),
+                     energy_last=oinfos[-1]["energy"], converged_last=bool(oinfos[-1]["converged"]))
+        log(f"[bench] {oname} form: {other}")
+
+    setup = setup_timing(system, args, prec) if args.setup_timing else None
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle) ...")
-        cpu = cpu_baseline(system, args.cpu_budget, args.eps, args.e_conv)
+        cpu = cpu_baseline(system, args.cpu_budget, args.eps, args.e_conv, window)
         log(f"[bench] CPU baseline {cpu}")
     last = infos[-1]
     out = {
@@ -259,7 +376,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "ms_per_step": round(ms_step, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -270,27 +387,24 @@ def main():
                                + (f"eps {args.eps}, e_conv {args.e_conv}" if args.schedule == "step" else
                                   f"paper schedule: eps {args.eps}, dq_max < {10 * args.eps}, step III at set-up "
                                   "and after convergence only")
-                               + "; SCF steps "
-                               f"{args.warmup + 1}..{args.warmup + args.steps}"
-                               + ("; each step forward + adjoint (energy gradient, copied to the host)"
+                               + f"; {window}"
+                               + ("; each step forward + adjoint (dE/dH0, dE/dS, dE/d onsite into device memory)"
                                   if args.adjoint else ""),
                    "precision": args.precision, "schedule": args.schedule, "energy_last": last["energy"],
-                   "converged_last": bool(last["converged"])},
+                   "converged_last": bool(last["converged"]), "setup_energy": init["energy"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "energy_error_vs_oracle": err,
+        "other_form": other,
+        "step_roofline": step_roof,
+        "kernels": classes,
+        "paper_context": PAPER_CONTEXT,
     }
-    hbm = step_traffic(kstats, elapsed, args.steps, args.config, args.precision, args.seed)
-    if hbm is not None:
-        out["hbm"] = hbm
-    if grad is not None:
-        out["gradient"] = grad
     if setup is not None:
         out["setup"] = setup
-    if kstats is not None:
-        out["kernels"] = {k: dict(launches=v["launches"], ms=round(v["ms"], 3),
-                                  tflops=round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 3),
-                                  gbs=round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1))
-                          for k, v in kstats.items() if v["launches"]}
+    if counts is not None:
+        out["work_counts"] = dict(replay_energies_identical=counts["replay_energies_identical"],
+                                  nnz_c_first=counts["nnz_c"][0], nnz_c_last=counts["nnz_c"][-1])
     print(json.dumps(out), flush=True)
 
 

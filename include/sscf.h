@@ -276,11 +276,15 @@ sscf_status sscf_orthonormalize(sscf_ctx* ctx, int32_t occ_only, sscf_step_info*
  * `info` may be NULL.  Non-convergence is not an error. */
 sscf_status sscf_scf_step(sscf_ctx* ctx, sscf_step_info* info);
 
-/* Total energy (Ha) of the current MOs. */
+/* Total energy (Ha) of the current MOs.  The paper does not write the total energy out; the
+ * SCC-DFTB energy of section 3.7 without the repulsive term (a constant here) is used:
+ * E = sum_uv P_uv H0_uv + 1/2 sum_ab dq_a gamma_ab dq_b, with dq the Mulliken charges of
+ * eq. pop minus q0; after sscf_set_fock(SSCF_FOCK_FULL), E = sum_uv P_uv F_uv. */
 sscf_status sscf_get_energy(const sscf_ctx* ctx, double* e_total);
 
-/* Density P = 2 C_occ C_occ^T on the atom-block pattern of S, written to the
- * caller's host buffer p_val of n_val >= desc.n_val doubles (layout of S_val). */
+/* Density P = 2 C_occ C_occ^T (section 3.7, eq. pop, closed shell: n_i = 2) on the
+ * atom-block pattern of S, written to the caller's host buffer p_val of n_val >= desc.n_val
+ * doubles (layout of S_val); the Mulliken charges of eq. pop are sums of P S over it. */
 sscf_status sscf_get_density(const sscf_ctx* ctx, double* p_val, size_t n_val);
 
 /* Energy gradient at the current MOs (differentiation form).  The energy of
@@ -297,6 +301,18 @@ sscf_status sscf_get_density(const sscf_ctx* ctx, double* p_val, size_t n_val);
  * occupied-virtual coupling small); before that they are the same expressions at
  * the current MOs.  SSCF_E_INVALID_ARG for NULL buffers or a short n_val. */
 sscf_status sscf_get_energy_gradient(sscf_ctx* ctx, double* dE_dX, double* dE_dS, size_t n_val);
+
+/* The same gradient into DEVICE memory of the context's GPU, plus the derivatives with
+ * respect to the onsite energies of each atom shell: the onsite energy of a shell sits on
+ * the diagonal of H0 (section 3.7), so dE/d(eps_shell) = sum of P_uu over the shell's AOs.
+ * dE_dX, dE_dS: n_val >= desc.n_val doubles each (layout of S_val).  dE_donsite: NULL, or
+ * n_onsite >= 2 n_atoms doubles: [2a] the atom's s shell (its first AO), [2a + 1] its p shell
+ * (its other AOs; 0 for an atom with one AO).  The buffers stay owned by the caller.  The work
+ * is enqueued on the context's stream and the call returns without waiting for it: the
+ * values are ready for later work on that stream, or after synchronizing it.  Nothing is
+ * copied to or from the host.  SSCF_E_INVALID_ARG for NULL or host buffers or short sizes. */
+sscf_status sscf_get_energy_gradient_device(sscf_ctx* ctx, double* dE_dX, double* dE_dS, size_t n_val,
+                                            double* dE_donsite, size_t n_onsite);
 
 /* Mulliken populations q_a (section 3.7, eq. pop) into q[n_atoms] (host). */
 sscf_status sscf_get_charges(const sscf_ctx* ctx, double* q, size_t n);

@@ -103,6 +103,7 @@ struct sscf_ctx {
   int* ao_atom = nullptr;
   int64_t* ao_off = nullptr;
   int *xs_ptr = nullptr, *xs_col = nullptr, *xs_row = nullptr;
+  int* xs_diag = nullptr;            // index of the diagonal block (r, r) of each row block
   int64_t* val_map = nullptr;        // atom-block value index -> row-block element index
   double *S = nullptr, *H0 = nullptr, *H = nullptr, *Hfull = nullptr;
   double* C[2] = {nullptr, nullptr};
@@ -127,7 +128,8 @@ struct sscf_ctx {
   uint8_t *pcidx = nullptr, *pncol = nullptr;   // packed nonzero columns of the C tiles (values in Y)
   double* part = nullptr;               // partial sums of the split reductions (coldot, coulomb)
   // energy gradient (allocated on first use)
-  double *foo_a = nullptr, *foo_b = nullptr, *wblk = nullptr, *wval = nullptr;
+  double *foo_a = nullptr, *foo_b = nullptr, *wblk = nullptr;
+  double *gx = nullptr, *gs = nullptr;  // device copies for the host-buffer gradient call
   uint8_t* pair_all = nullptr;        // per pair: nonzero-fragment masks of D_sel and its transpose
   int *jb_g = nullptr, *jb_h = nullptr, *jb_nocc = nullptr, *jb_nvirt = nullptr, *round_list = nullptr;
   double *F = nullptr, *Fdiag = nullptr, *dvec = nullptr;
@@ -405,6 +407,42 @@ struct sscf_ctx {
     product(fock_full ? Hfull : H0, false, true);   // support of C unchanged since the last dilation
     launch_coldot(v, C[cur], listC[cur], cntC[cur], Y, actY, part, dvec, stream);
     launch_sum_band(v, dvec, pnocc, sd, stream);
+  }
+
+  // Energy gradient at the current MOs into device buffers (n_val values each; don: 2 per atom,
+  // may be NULL), enqueued on the stream.  The charge term of dE/dS only with H0 and SCC.
+  void gradient(double* dX, double* dS, double* don) {
+    hipStream_t s = stream;
+    const size_t fo = (size_t)v.OW * v.OW;
+    if (!foo_a) {
+      foo_a = dalloc<double>((size_t)n_pairs * fo);
+      foo_b = dalloc<double>((size_t)n_pairs * fo);
+      wblk = dalloc<double>((size_t)v.nbx * 256);
+      pair_all = dalloc<uint8_t>(n_pairs);
+      launch_fill_u8(pair_all, n_pairs, 1, s);
+    }
+    if (!pblk) pblk = dalloc<double>((size_t)v.nbx * 256);
+    // the Fock matrix of the current charges, not truncated, and Y = H C_occ
+    launch_fock(v, S, H0, fock_full ? Hfull : nullptr, Q, 0.0, H, nullptr, s);
+    const bool was = counting;
+    counting = false;
+    product(H, true, true);
+    counting = was;
+    // occupied-occupied blocks C_g^T H C_h of every neighbouring pair, in both orientations
+    const int no = v.OW / 16;
+    launch_pair(v, n_pairs, pair_perm, pair_maxc, pg, ph, C[cur], listC[cur], cntC[cur], cmask[cur], Y, actY, ymask,
+                0, no, 0, no, foo_a, v.OW, fo, nullptr, s);
+    launch_pair(v, n_pairs, pair_perm, pair_maxc, ph, pg, C[cur], listC[cur], cntC[cur], cmask[cur], Y, actY, ymask,
+                0, no, 0, no, foo_b, v.OW, fo, nullptr, s);
+    // Z = C_occ F on the row blocks where a neighbouring group is active (Z overwrites Y)
+    launch_update_support(v, actC[cur], gn_ptr, gn, pair_of, pair_all, act_tmp, s);
+    launch_list(v, act_tmp, list_tmp, cnt_tmp, s);
+    launch_apply_occ(v, C[cur], actC[cur], gn_ptr, gn, pair_of, pg, foo_a, foo_b, list_tmp, cnt_tmp, Y, s);
+    // P = 2 C_occ C_occ^T and W = 2 C_occ Z^T on the pattern of S, then the layout of S_val
+    launch_density_blocks(v, C[cur], actC[cur], C[cur], actC[cur], pblk, s);
+    launch_density_blocks(v, C[cur], actC[cur], Y, act_tmp, wblk, s);
+    launch_grad_assemble(v, n_val, val_map, pblk, wblk, Q, scc && !fock_full, dX, dS, s);
+    if (don) launch_grad_onsite(v, ao_off, xs_diag, pblk, don, s);
   }
 
   int64_t active_tiles() {
@@ -700,6 +738,11 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
   x->xs_ptr = x->upload(xs_ptr.data(), xs_ptr.size());
   x->xs_col = x->upload(xs_col.data(), xs_col.size());
   x->xs_row = x->upload(xs_row.data(), xs_row.size());
+  {
+    std::vector<int> diag(v.n_rb);
+    for (int r = 0; r < v.n_rb; ++r) diag[r] = (int)xs_find(r, r);
+    x->xs_diag = x->upload(diag.data(), diag.size());
+  }
   x->val_map = x->upload(val_map.data(), val_map.size());
   v.xyz = x->xyz;
   v.U = x->U;
@@ -1496,54 +1539,31 @@ sscf_status sscf_get_density(const sscf_ctx* cx, double* p_val, size_t n_val) {
 sscf_status sscf_get_energy_gradient(sscf_ctx* x, double* dE_dX, double* dE_dS, size_t n_val) {
   if (!x || !dE_dX || !dE_dS || n_val < (size_t)x->n_val) return SSCF_E_INVALID_ARG;
   return guarded(x, [&] {
-    const View& v = x->v;
-    hipStream_t s = x->stream;
-    const size_t fo = (size_t)v.OW * v.OW;
-    if (!x->foo_a) {
-      x->foo_a = x->dalloc<double>((size_t)x->n_pairs * fo);
-      x->foo_b = x->dalloc<double>((size_t)x->n_pairs * fo);
-      x->wblk = x->dalloc<double>((size_t)v.nbx * 256);
-      x->wval = x->dalloc<double>(x->n_val);
-      x->pair_all = x->dalloc<uint8_t>(x->n_pairs);
-      launch_fill_u8(x->pair_all, x->n_pairs, 1, s);
-    }
-    if (!x->pblk) x->pblk = x->dalloc<double>((size_t)v.nbx * 256);
-    if (!x->pval) x->pval = x->dalloc<double>(x->n_val);
-    // the Fock matrix of the current charges, not truncated, and Y = H C_occ
-    launch_fock(v, x->S, x->H0, x->fock_full ? x->Hfull : nullptr, x->Q, 0.0, x->H, nullptr, s);
-    x->product(x->H, true, true);
-    // occupied-occupied blocks C_g^T H C_h of every neighbouring pair, in both orientations
-    const int no = v.OW / 16;
-    launch_pair(v, x->n_pairs, x->pair_perm, x->pair_maxc, x->pg, x->ph, x->C[x->cur], x->listC[x->cur],
-                x->cntC[x->cur], x->cmask[x->cur], x->Y, x->actY, x->ymask, 0, no, 0, no, x->foo_a, v.OW, fo,
-                nullptr, s);
-    launch_pair(v, x->n_pairs, x->pair_perm, x->pair_maxc, x->ph, x->pg, x->C[x->cur], x->listC[x->cur],
-                x->cntC[x->cur], x->cmask[x->cur], x->Y, x->actY, x->ymask, 0, no, 0, no, x->foo_b, v.OW, fo,
-                nullptr, s);
-    // Z = C_occ F on the row blocks where a neighbouring group is active (Z overwrites Y)
-    launch_update_support(v, x->actC[x->cur], x->gn_ptr, x->gn, x->pair_of, x->pair_all, x->act_tmp, s);
-    launch_list(v, x->act_tmp, x->list_tmp, x->cnt_tmp, s);
-    launch_apply_occ(v, x->C[x->cur], x->actC[x->cur], x->gn_ptr, x->gn, x->pair_of, x->pg, x->foo_a, x->foo_b,
-                     x->list_tmp, x->cnt_tmp, x->Y, s);
-    // P = 2 C_occ C_occ^T and W = 2 C_occ Z^T on the pattern of S
-    launch_density_blocks(v, x->C[x->cur], x->actC[x->cur], x->C[x->cur], x->actC[x->cur], x->pblk, s);
-    launch_density_blocks(v, x->C[x->cur], x->actC[x->cur], x->Y, x->act_tmp, x->wblk, s);
-    launch_gather(x->val_map, x->n_val, x->pblk, x->pval, s);
-    launch_gather(x->val_map, x->n_val, x->wblk, x->wval, s);
-    std::vector<double> w(x->n_val), q(v.n_atoms);
-    HIPC(hipMemcpyAsync(dE_dX, x->pval, sizeof(double) * x->n_val, hipMemcpyDeviceToHost, s));
-    HIPC(hipMemcpyAsync(w.data(), x->wval, sizeof(double) * x->n_val, hipMemcpyDeviceToHost, s));
-    HIPC(hipMemcpyAsync(q.data(), x->Q, sizeof(double) * v.n_atoms, hipMemcpyDeviceToHost, s));
+    if (x->failed) fail(SSCF_E_STATE, "context failed earlier: %s", x->err.c_str());
+    if (!x->gx) x->gx = x->dalloc<double>(x->n_val);
+    if (!x->gs) x->gs = x->dalloc<double>(x->n_val);
+    x->gradient(x->gx, x->gs, nullptr);
+    HIPC(hipMemcpyAsync(dE_dX, x->gx, sizeof(double) * x->n_val, hipMemcpyDeviceToHost, x->stream));
+    HIPC(hipMemcpyAsync(dE_dS, x->gs, sizeof(double) * x->n_val, hipMemcpyDeviceToHost, x->stream));
     x->sync();
-    // dE/dS = -W + 1/2 P (Q_a + Q_b); the charge term only with H0 (the Mulliken charges' S)
-    const bool qterm = x->scc && !x->fock_full;
-    for (int a = 0; a < v.n_atoms; ++a)
-      for (int64_t k = x->h_blk_rowptr[a]; k < x->h_blk_rowptr[a + 1]; ++k) {
-        const int b = x->h_blk_col[k];
-        const int64_t n = (int64_t)x->h_atom_nao[a] * x->h_atom_nao[b];
-        const double qs = qterm ? 0.5 * (q[a] + q[b]) : 0.0;
-        for (int64_t e = x->h_blk_off[k]; e < x->h_blk_off[k] + n; ++e) dE_dS[e] = -w[e] + dE_dX[e] * qs;
+  });
+}
+
+sscf_status sscf_get_energy_gradient_device(sscf_ctx* x, double* dE_dX, double* dE_dS, size_t n_val,
+                                            double* dE_donsite, size_t n_onsite) {
+  if (!x || !dE_dX || !dE_dS || n_val < (size_t)x->n_val) return SSCF_E_INVALID_ARG;
+  if (dE_donsite && n_onsite < 2 * (size_t)x->v.n_atoms) return SSCF_E_INVALID_ARG;
+  return guarded(x, [&] {
+    if (x->failed) fail(SSCF_E_STATE, "context failed earlier: %s", x->err.c_str());
+    hipPointerAttribute_t at;
+    for (double* p : {dE_dX, dE_dS, dE_donsite}) {
+      if (!p) continue;
+      if (hipPointerGetAttributes(&at, p) != hipSuccess || at.type != hipMemoryTypeDevice) {
+        (void)hipGetLastError();
+        fail(SSCF_E_INVALID_ARG, "gradient outputs must be device memory");
       }
+    }
+    x->gradient(dE_dX, dE_dS, dE_donsite);
   });
 }
 

@@ -180,6 +180,10 @@ void launch_sum_coul(const View& v, int scc, const double* dq, const double* Q, 
                      hipStream_t s);
 void launch_density_blocks(const View& v, const double* A, const uint8_t* actA, const double* B,
                            const uint8_t* actB, double* P, hipStream_t s);
+void launch_grad_assemble(const View& v, int64_t n_val, const int64_t* map, const double* P, const double* Wb,
+                          const double* Q, int qterm, double* dX, double* dS, hipStream_t s);
+void launch_grad_onsite(const View& v, const int64_t* ao_off, const int* xs_diag, const double* P, double* out,
+                        hipStream_t s);
 void launch_apply_occ(const View& v, const double* C, const uint8_t* actC, const int* gn_ptr, const int* gn,
                       const int* pair_of, const int* pg, const double* FA, const double* FB, const int* listZ,
                       const int* cntZ, double* Z, hipStream_t s);

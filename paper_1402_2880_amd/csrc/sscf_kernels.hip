@@ -1536,6 +1536,49 @@ void launch_density_blocks(const View& v, const double* A, const uint8_t* actA, 
 }
 
 // ---------------------------------------------------------------------------------------
+// Energy gradient on the pattern of S (atom-block layout of S_val): dE/dX = P and
+// dE/dS = -W + 1/2 P (Q_a + Q_b) (the second term only with the charge term of H0), read from
+// the 16 x 16 row-block forms of P and W; and dE/d(onsite energy) per atom shell, the sum of
+// P over the shell's diagonal (s: the atom's first AO; p: its other AOs).
+// ---------------------------------------------------------------------------------------
+__global__ void k_grad_assemble(int64_t n, const int64_t* __restrict__ map, const int* __restrict__ xs_row,
+                                const int* __restrict__ xs_col, const int* __restrict__ ao_atom,
+                                const double* __restrict__ P, const double* __restrict__ Wb,
+                                const double* __restrict__ Q, int qterm, double* __restrict__ dX,
+                                double* __restrict__ dS) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int64_t e = map[t];
+  const int64_t b = e >> 8;
+  const int mu = xs_row[b] * RB + (int)((e >> 4) & 15), nu = xs_col[b] * RB + (int)(e & 15);
+  const double p = P[e];
+  const double qs = qterm ? 0.5 * (Q[ao_atom[mu]] + Q[ao_atom[nu]]) : 0.0;
+  dX[t] = p;
+  dS[t] = -Wb[e] + p * qs;
+}
+void launch_grad_assemble(const View& v, int64_t n_val, const int64_t* map, const double* P, const double* Wb,
+                          const double* Q, int qterm, double* dX, double* dS, hipStream_t s) {
+  if (n_val)
+    hipLaunchKernelGGL(k_grad_assemble, dim3(nblk((size_t)n_val, 256)), dim3(256), 0, s, n_val, map, v.xs_row,
+                       v.xs_col, v.ao_atom, P, Wb, Q, qterm, dX, dS);
+}
+
+__global__ void k_grad_onsite(int n_atoms, const int64_t* __restrict__ ao_off, const int* __restrict__ xs_diag,
+                              const double* __restrict__ P, double* __restrict__ out) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n_atoms) return;
+  const int64_t mu0 = ao_off[a];
+  double ps = P[(size_t)xs_diag[mu0 / RB] * 256 + (mu0 % RB) * 17], pp = 0.0;
+  for (int64_t mu = mu0 + 1; mu < ao_off[a + 1]; ++mu) pp += P[(size_t)xs_diag[mu / RB] * 256 + (mu % RB) * 17];
+  out[2 * a] = ps;
+  out[2 * a + 1] = pp;
+}
+void launch_grad_onsite(const View& v, const int64_t* ao_off, const int* xs_diag, const double* P, double* out,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_onsite, dim3(nblk(v.n_atoms, 256)), dim3(256), 0, s, v.n_atoms, ao_off, xs_diag, P, out);
+}
+
+// ---------------------------------------------------------------------------------------
 // Energy gradient (differentiation form): Z_g[r] = sum_{h ~ g} C_h,occ[r] F(h, g) with
 // F(h, g) = C_h,occ^T H C_g,occ (OW x OW; FA holds the blocks with rows = MOs of pg[p],
 // FB those with rows = MOs of ph[p]).  One wave per output tile, occupied columns only.

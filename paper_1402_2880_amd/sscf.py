@@ -99,7 +99,8 @@ class KernelStat(ct.Structure):
 
 EXPORTS = ["sscf_get_kernel_stats", "sscf_reset_kernel_stats", "sscf_init_system", "sscf_set_fock", "sscf_scf_step", "sscf_get_energy",
            "sscf_get_density", "sscf_get_charges", "sscf_get_mo_coefficients", "sscf_init_info",
-           "sscf_get_schedule", "sscf_get_energy_gradient", "sscf_set_control", "sscf_get_control",
+           "sscf_get_schedule", "sscf_get_energy_gradient", "sscf_get_energy_gradient_device",
+           "sscf_set_control", "sscf_get_control",
            "sscf_orthonormalize", "sscf_fragment_guess", "sscf_constrained_kmeans", "sscf_atom_neighbours",
            "sscf_destroy",
            "sscf_last_error"]
@@ -122,6 +123,7 @@ def lib():
         L.sscf_get_energy.argtypes = [vp, ct.POINTER(ct.c_double)]
         L.sscf_get_density.argtypes = [vp, vp, sz]
         L.sscf_get_energy_gradient.argtypes = [vp, vp, vp, sz]
+        L.sscf_get_energy_gradient_device.argtypes = [vp, vp, vp, sz, vp, sz]
         L.sscf_set_control.argtypes = [vp, ct.POINTER(Control)]
         L.sscf_get_control.argtypes = [vp, ct.POINTER(Control)]
         L.sscf_orthonormalize.argtypes = [vp, i32, ct.POINTER(StepInfo)]
@@ -282,13 +284,28 @@ class SparseSCF:
         self._check(lib().sscf_orthonormalize(self._h, 1 if occ_only else 0, ct.byref(si)))
         return si.as_dict()
 
-    def energy_gradient(self):
+    def energy_gradient(self, device: bool = False):
         """(dE/dH0, dE/dS) at the current MOs on the atom-block pattern (dE/dF in complete-Fock
-        mode): P and -W + 1/2 P (Q_a + Q_b).  Derivatives of E once the SCF has converged."""
-        gx = np.zeros(self.system.S_val.shape[0])
-        gs = np.zeros(self.system.S_val.shape[0])
-        self._check(lib().sscf_get_energy_gradient(self._h, _p(gx), _p(gs), gx.shape[0]))
-        return gx, gs
+        mode): P and -W + 1/2 P (Q_a + Q_b).  Derivatives of E once the SCF has converged.
+
+        device=False: two host numpy arrays.  device=True: three float64 tensors on the context's
+        GPU, written by the library on its stream with no host transfer: dE/dH0, dE/dS and
+        dE/d(onsite energy) per atom shell ([2a] s shell, [2a + 1] p shell)."""
+        n = self.system.S_val.shape[0]
+        if not device:
+            gx = np.zeros(n)
+            gs = np.zeros(n)
+            self._check(lib().sscf_get_energy_gradient(self._h, _p(gx), _p(gs), n))
+            return gx, gs
+        import torch
+        dev = torch.device("cuda", self._device)
+        with torch.cuda.stream(self._stream):
+            gx = torch.empty(n, dtype=torch.float64, device=dev)
+            gs = torch.empty(n, dtype=torch.float64, device=dev)
+            gon = torch.empty(2 * self.system.n_atoms, dtype=torch.float64, device=dev)
+        self._check(lib().sscf_get_energy_gradient_device(self._h, gx.data_ptr(), gs.data_ptr(), n,
+                                                          gon.data_ptr(), gon.numel()))
+        return gx, gs, gon
 
     def charges(self) -> np.ndarray:
         out = np.zeros(self.system.n_atoms)
@@ -332,49 +349,75 @@ class SparseSCF:
         return g[:n.value], h[:n.value], r[:n.value]
 
 
+def _converged(system, H0_val, S_val, opts):
+    """A context on the given H0 and S values, run to self-consistency."""
+    s = dataclasses.replace(system, H0_val=H0_val.detach().cpu().double().numpy().copy(),
+                            S_val=S_val.detach().cpu().double().numpy().copy())
+    g = SparseSCF(s, **opts.get("scf", {}))
+    fov_tol = opts.get("fov_tol", 0.0)
+    try:
+        for _ in range(opts.get("max_steps", 200)):
+            info = g.step()
+            if info["converged"] and (fov_tol <= 0.0 or info["max_abs_fov"] < fov_tol):
+                return g
+        raise RuntimeError("sparse SCF did not converge within max_steps")
+    except Exception:
+        g.close()
+        raise
+
+
 def _torch_function():
     import torch
 
     class SCFEnergy(torch.autograd.Function):
         """Self-consistent energy E(H0_val, S_val) of the sparse SCF, differentiable.
 
-        forward runs the library to convergence from the system's initial guess and evaluates
-        dE/dH0 = P and dE/dS = -W + 1/2 P (Q_a + Q_b) once there; only these two vectors are
-        kept for backward (no MO state).  Inputs are float64 tensors in the layout of S_val.
+        forward runs the library to convergence from the system's initial guess and keeps no MO
+        state.  backward recomputes the converged MOs from the saved inputs and evaluates the
+        adjoint on the GPU: dE/dH0 = P and dE/dS = -W + 1/2 P (Q_a + Q_b), written to device
+        memory (opts["recompute"] False: evaluated in forward instead and the two vectors kept).
+        Inputs are float64 tensors in the layout of S_val; the inputs still reach the library
+        through host memory, since a context is set up from host arrays.
         """
 
         @staticmethod
         def forward(ctx, H0_val, S_val, system, opts):
-            s = dataclasses.replace(system, H0_val=H0_val.detach().cpu().double().numpy().copy(),
-                                    S_val=S_val.detach().cpu().double().numpy().copy())
-            g = SparseSCF(s, **opts.get("scf", {}))
-            fov_tol = opts.get("fov_tol", 0.0)
+            g = _converged(system, H0_val, S_val, opts)
             try:
-                for _ in range(opts.get("max_steps", 200)):
-                    info = g.step()
-                    if info["converged"] and (fov_tol <= 0.0 or info["max_abs_fov"] < fov_tol):
-                        break
-                else:
-                    raise RuntimeError("sparse SCF did not converge within max_steps")
                 E = g.energy()
-                gx, gs = g.energy_gradient()
+                if not opts.get("recompute", True):
+                    gx, gs, _ = g.energy_gradient(device=True)
+                    torch.cuda.synchronize(g._device)
+                    ctx.save_for_backward(gx.to(H0_val.device), gs.to(S_val.device))
+                else:
+                    ctx.save_for_backward(H0_val.detach(), S_val.detach())
             finally:
                 g.close()
-            ctx.save_for_backward(torch.from_numpy(gx).to(H0_val.device), torch.from_numpy(gs).to(S_val.device))
+            ctx.system, ctx.opts = system, opts
             return torch.tensor(E, dtype=torch.float64, device=H0_val.device)
 
         @staticmethod
         def backward(ctx, gE):
-            gx, gs = ctx.saved_tensors
-            return gE * gx, gE * gs, None, None
+            a, b = ctx.saved_tensors
+            if not ctx.opts.get("recompute", True):
+                return gE * a, gE * b, None, None
+            g = _converged(ctx.system, a, b, ctx.opts)
+            try:
+                gx, gs, _ = g.energy_gradient(device=True)
+                torch.cuda.synchronize(g._device)
+            finally:
+                g.close()
+            return gE * gx.to(a.device), gE * gs.to(b.device), None, None
 
     return SCFEnergy
 
 
-def scf_energy(system, H0_val, S_val, max_steps: int = 200, fov_tol: float = 0.0, **scf_kw):
-    """Differentiable self-consistent energy (torch float64 scalar) for H0_val and S_val tensors."""
+def scf_energy(system, H0_val, S_val, max_steps: int = 200, fov_tol: float = 0.0, recompute: bool = True,
+               **scf_kw):
+    """Differentiable self-consistent energy (torch float64 scalar) for H0_val and S_val tensors.
+    recompute: the backward pass recomputes the converged MOs instead of keeping the gradient."""
     return _torch_function().apply(H0_val, S_val, system,
-                                   dict(max_steps=max_steps, fov_tol=fov_tol, scf=scf_kw))
+                                   dict(max_steps=max_steps, fov_tol=fov_tol, recompute=recompute, scf=scf_kw))
 
 
 def fragment_guess(system, atom_frag, frag_nocc, frag_group, drop: float = 0.0, stream=None):

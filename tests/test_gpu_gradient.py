@@ -179,3 +179,56 @@ def test_onsite_gradient_water512_finite_differences():
 
 def test_gradient_maximum_panel_width():
     compare(synth.water_box(60, 12.5, 7, n_link=20), "panel width 128", steps=4)
+
+
+def test_device_gradient_equals_host_and_onsite_is_the_shell_diagonal(water128):
+    """The device-output call gives the host call's values bit for bit, and dE/d(onsite) per shell is
+    the sum of P over the shell's diagonal (here from the oracle's P: the oracle's density on the
+    pattern, an independent computation)."""
+    import torch
+    o, g = Oracle(water128), gpu(water128)
+    run(o), run(g)
+    hx, hs = g.energy_gradient()
+    dx, ds, don = g.energy_gradient(device=True)
+    torch.cuda.synchronize()
+    assert dx.is_cuda and ds.is_cuda and don.is_cuda
+    assert np.array_equal(dx.cpu().numpy(), hx) and np.array_equal(ds.cpu().numpy(), hs)
+    P = o.density()
+    s = water128
+    aoo = s.ao_offset()
+    want = np.zeros(2 * s.n_atoms)
+    for a in range(s.n_atoms):
+        k = s.blk_rowptr[a] + np.searchsorted(s.blk_col[s.blk_rowptr[a]:s.blk_rowptr[a + 1]], a)
+        na = s.atom_nao[a]
+        d = [P[s.blk_off[k] + i * na + i] for i in range(na)]
+        want[2 * a] = d[0]
+        want[2 * a + 1] = sum(d[1:])
+    assert np.abs(don.cpu().numpy() - want).max() < 1e-9
+
+
+def test_device_gradient_refuses_host_buffers(water128):
+    import ctypes as ct
+    from paper_1402_2880_amd.sscf import lib
+    g = gpu(water128)
+    n = water128.S_val.shape[0]
+    a = np.zeros(n)
+    b = np.zeros(n)
+    rc = lib().sscf_get_energy_gradient_device(g._h, a.ctypes.data, b.ctypes.data, n, None, 0)
+    assert rc == -1
+    g.close()
+
+
+@pytest.mark.parametrize("recompute", [True, False])
+def test_autograd_recompute_and_kept_gradient_agree(recompute):
+    import torch
+    from paper_1402_2880_amd.sscf import scf_energy
+    s = synth.water_box(8, 7.0, 2, n_link=4)
+    kw = dict(fov_tol=1e-10, **TIGHT, group_nbr_bohr=1e6)
+    H0 = torch.tensor(s.H0_val, dtype=torch.float64, requires_grad=True)
+    S = torch.tensor(s.S_val, dtype=torch.float64, requires_grad=True)
+    E = scf_energy(s, H0, S, recompute=recompute, **kw)
+    E.backward()
+    g = gpu(s, **TIGHT, group_nbr_bohr=1e6)
+    run(g, fov_tol=1e-10)
+    gx, gs = g.energy_gradient()
+    assert np.array_equal(H0.grad.numpy(), gx) and np.array_equal(S.grad.numpy(), gs)
