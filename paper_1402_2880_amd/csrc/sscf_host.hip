@@ -134,6 +134,8 @@ struct sscf_ctx {
   int *jb_g = nullptr, *jb_h = nullptr, *jb_nocc = nullptr, *jb_nvirt = nullptr, *round_list = nullptr;
   double *F = nullptr, *Fdiag = nullptr, *dvec = nullptr;
   int *rot_cnt = nullptr, *tcnt = nullptr, *tcol = nullptr, *round_ptr = nullptr;
+  ulonglong2* tmask = nullptr;          // per Jacobi block: its touched panel columns
+  ulonglong2* colm = nullptr;           // per tile: nonzero columns (exact during the rotation pass)
   int *rcnt = nullptr, *roff = nullptr;
   int4* rmeta = nullptr;                // blocks with rotations, packed in round order
   int2* rot_slot = nullptr;
@@ -689,6 +691,8 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
         pg.push_back(g);
         ph.push_back(h);
       }
+  // the rotation pass keeps two 64-bit column masks per group in LDS (64 KB per workgroup)
+  if (256 * 16 + 16 * (size_t)G + 4 * 128 + 16 > 65536) fail(SSCF_E_CAPACITY, "%d MO groups: at most 3800", G);
   x->n_pairs = (int)pg.size();
   x->h_pg = pg;
   x->h_ph = ph;
@@ -847,6 +851,8 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
   x->rot_cs = x->dalloc<double2>((size_t)x->n_blocks * per);
   x->tcnt = x->dalloc<int>(x->n_blocks);
   x->tcol = x->dalloc<int>((size_t)x->n_blocks * v.W);
+  x->tmask = x->dalloc<ulonglong2>(x->n_blocks);
+  x->colm = x->dalloc<ulonglong2>(ntiles);
   x->hist = x->dalloc<unsigned int>(256);
   HIPC(hipMemsetAsync(x->hist, 0, 256 * sizeof(unsigned int), s));
   x->ties = x->dalloc<long long>(MAX_TIES);
@@ -984,7 +990,7 @@ static void step(sscf_ctx* x, sscf_step_info* out) {
                    x->eps, x->sd, x->ties, s);
   }
   launch_block_select(v, x->n_blocks, x->jb_g, x->jb_h, x->jb_nocc, x->jb_nvirt, x->F, x->Fdiag, x->mo_of, x->eps,
-                      x->sd, x->rot_cnt, x->rot_slot, x->rot_cs, x->tcnt, x->tcol,
+                      x->sd, x->rot_cnt, x->rot_slot, x->rot_cs, x->tcnt, x->tcol, x->tmask,
                       x->precision == SSCF_FP32_MIXED, s);
   x->pend(pi);
   HIPC(hipEventRecord(x->ev[3], s));
@@ -994,11 +1000,11 @@ static void step(sscf_ctx* x, sscf_step_info* out) {
   launch_round_meta(x->n_rounds, x->round_ptr, x->round_list, x->rot_cnt, x->jb_g, x->jb_h, x->tcnt, x->rcnt,
                     x->roff, x->rmeta, s);
   if (x->wc()) x->wzero();
-  launch_givens_rb(v, x->n_rounds, x->roff, x->rmeta, x->tcol, x->Rrot, x->R32, x->eps, x->C[x->cur],
-                   x->actC[x->cur], x->cmask[x->cur], x->rot_cnt, x->wc() ? x->wdev : nullptr, s);
-  // the cut |C| < eps can empty a tile or a slice: flags exact again before the products
-  x->rebuild_list(x->cur);
-  launch_tile_flags(v, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur], x->actC[x->cur], x->cmask[x->cur], s);
+  // the nonzero columns of every active tile, kept exact by the pass (which also leaves exact
+  // tile flags: the cut |C| < eps can empty a tile or a slice)
+  launch_tile_flags(v, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur], x->actC[x->cur], x->cmask[x->cur], x->colm, s);
+  launch_givens_rb(v, x->n_rounds, x->roff, x->rmeta, x->tmask, x->tcol, x->Rrot, x->R32, x->eps, x->C[x->cur],
+                   x->actC[x->cur], x->cmask[x->cur], x->colm, x->rot_cnt, x->wc() ? x->wdev : nullptr, s);
   x->pend(pi);
   x->rebuild_list(x->cur);
   if (x->wc()) {

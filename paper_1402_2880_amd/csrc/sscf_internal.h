@@ -109,7 +109,7 @@ void launch_update_support(const View& v, const uint8_t* actC, const int* gn_ptr
 void launch_clear_tiles(const View& v, double* C, uint8_t* act, unsigned int* cmask,
                         const int* list, const int* cnt, hipStream_t s);
 void launch_tile_flags(const View& v, const double* C, const int* list, const int* cnt, uint8_t* act,
-                       unsigned int* cmask, hipStream_t s);
+                       unsigned int* cmask, ulonglong2* colm, hipStream_t s);
 void launch_pack_cols(const View& v, const double* C, const int* list, const int* cnt, int col_end, double* P,
                       uint8_t* cidx, uint8_t* ncol, hipStream_t s);
 void launch_ortho_update(const View& v, const double* C, const uint8_t* actC, const double* P, const uint8_t* cidx,
@@ -133,7 +133,7 @@ void launch_tie_cut(int nb, int OW, int VW, const int* jb_g, const int* jb_h, co
 void launch_block_select(const View& v, int nb, const int* jb_g, const int* jb_h, const int* jb_nocc,
                          const int* jb_nvirt, const double* F, const double* Fdiag, const int* mo_of,
                          double tau, Scalars* sd, int* rot_cnt, int2* rot_slot, double2* rot_cs,
-                         int* tcnt, int* tcol, int fp32, hipStream_t s);
+                         int* tcnt, int* tcol, ulonglong2* tmask, int fp32, hipStream_t s);
 void launch_compose_rot(const View& v, int nb, const int* rot_cnt, const int2* rot_slot,
                         const double2* rot_cs, const int* tcnt, double* R, float* R32, hipStream_t s);
 void launch_round_meta(int n_rounds, const int* round_ptr, const int* round_list, const int* rot_cnt,
@@ -156,9 +156,10 @@ void launch_km_round(int n, int m, int n_link, const double* pts, const double* 
                      hipStream_t s);
 void launch_km_move(int n, int m, const double* pts, const int* assign, const double* means, double* out,
                     double* disp, hipStream_t s);
-void launch_givens_rb(const View& v, int n_rounds, const int* roff, const int4* meta, const int* tcol,
-                      const double* R, const float* R32, double eps, double* C, uint8_t* actC,
-                      unsigned int* cmask, const int* rot_cnt, unsigned long long* wcnt, hipStream_t s);
+void launch_givens_rb(const View& v, int n_rounds, const int* roff, const int4* meta, const ulonglong2* tmask,
+                      const int* tcol, const double* R, const float* R32, double eps, double* C, uint8_t* actC,
+                      unsigned int* cmask, ulonglong2* colm, const int* rot_cnt, unsigned long long* wcnt,
+                      hipStream_t s);
 void launch_spmm32(const View& v, const float* X, const float* C, const uint8_t* actC,
                    const unsigned int* cmask, const int* listY, const int* cntY, float* Y,
                    unsigned int* ymask, unsigned long long* ctr, hipStream_t s);

@@ -513,8 +513,8 @@ void launch_clear_tiles(const View& v, double* C, uint8_t* act, unsigned int* cm
 
 // ---------------------------------------------------------------------------------------
 // Column scans of C tiles (one wave per listed tile; lane l owns columns l and l + 64).
-//  * k_tile_flags: the activity byte and 16-column slice mask of each tile, exactly from its
-//    values (after the rotation cut a tile or slice may have lost all its nonzeros).
+//  * k_tile_flags: the activity byte, the 16-column slice mask and (colm, may be NULL) the
+//    nonzero columns of each tile, exactly from its values.
 //  * k_pack_cols: the nonzero columns of each tile packed to the front of its slot in P,
 //    column-major (packed column k = the 16 rows of the tile's k-th nonzero column, one
 //    128-byte line), with cidx[tile W + k] its column and ncol[tile] their number.  Only
@@ -544,7 +544,8 @@ __device__ __forceinline__ void tile_columns(const double* __restrict__ T, int c
 template <int NT>
 __global__ void __launch_bounds__(256) k_tile_flags(int G, int n_rb, int nchunk, const double* __restrict__ C,
                                                     const int* __restrict__ list, const int* __restrict__ cnt,
-                                                    uint8_t* __restrict__ act, unsigned int* __restrict__ cmask) {
+                                                    uint8_t* __restrict__ act, unsigned int* __restrict__ cmask,
+                                                    ulonglong2* __restrict__ colm) {
   constexpr int W = NT * 16;
   int chunk;
   const int g = xcd_group_chunk(nchunk, chunk);
@@ -565,6 +566,7 @@ __global__ void __launch_bounds__(256) k_tile_flags(int G, int n_rb, int nchunk,
   if ((threadIdx.x & 63) == 0) {
     cmask[tile] = cm;
     act[tile] = (uint8_t)(cm != 0u);
+    if (colm) colm[tile] = make_ulonglong2(b0, b1);
   }
 }
 
@@ -605,11 +607,11 @@ __global__ void __launch_bounds__(256) k_pack_cols(int G, int n_rb, int nchunk, 
 }
 
 void launch_tile_flags(const View& v, const double* C, const int* list, const int* cnt, uint8_t* act,
-                       unsigned int* cmask, hipStream_t s) {
+                       unsigned int* cmask, ulonglong2* colm, hipStream_t s) {
   const int nchunk = (v.n_rb + 3) / 4;
   dim3 grid(xcd_grid(v.G, nchunk)), blk(256);
   switch (v.W / 16) {
-#define SSCF_TF(NT) case NT: hipLaunchKernelGGL(k_tile_flags<NT>, grid, blk, 0, s, v.G, v.n_rb, nchunk, C, list, cnt, act, cmask); break;
+#define SSCF_TF(NT) case NT: hipLaunchKernelGGL(k_tile_flags<NT>, grid, blk, 0, s, v.G, v.n_rb, nchunk, C, list, cnt, act, cmask, colm); break;
     SSCF_TF(1) SSCF_TF(2) SSCF_TF(3) SSCF_TF(4) SSCF_TF(5) SSCF_TF(6) SSCF_TF(7) SSCF_TF(8)
 #undef SSCF_TF
   }
@@ -1036,7 +1038,8 @@ __global__ void __launch_bounds__(256) k_block_select(int W, int OW, int VW, con
                                                       const int* jb_nocc, const int* jb_nvirt, const double* F,
                                                       const double* Fdiag, const int* mo_of, long long n_mo,
                                                       double tau, Scalars* sd, int* rot_cnt, int2* rot_slot,
-                                                      double2* rot_cs, int* tcnt, int* tcol, int fp32) {
+                                                      double2* rot_cs, int* tcnt, int* tcol, ulonglong2* tmask,
+                                                      int fp32) {
   __shared__ unsigned long long khi[SEL_MAX];
   __shared__ unsigned int klo[SEL_MAX];
   __shared__ int n_sel;
@@ -1096,9 +1099,17 @@ __global__ void __launch_bounds__(256) k_block_select(int W, int OW, int VW, con
   __syncthreads();
   if (threadIdx.x == 0) {
     int u = 0;
+    unsigned long long t0 = 0ull, t1 = 0ull;
     for (int c = 0; c < W; ++c)
-      if (used[c]) { upos[c] = u; tcol[(size_t)b * W + u] = c; ++u; }
+      if (used[c]) {
+        upos[c] = u;
+        tcol[(size_t)b * W + u] = c;
+        ++u;
+        if (c < 64) t0 |= 1ull << c;
+        else t1 |= 1ull << (c - 64);
+      }
     tcnt[b] = u;
+    tmask[b] = make_ulonglong2(t0, t1);
     rot_cnt[b] = n;
     atomicAdd(&sd->n_rot, n);
   }
@@ -1130,11 +1141,11 @@ __global__ void __launch_bounds__(256) k_block_select(int W, int OW, int VW, con
 
 void launch_block_select(const View& v, int nb, const int* jb_g, const int* jb_h, const int* jb_nocc, const int* jb_nvirt,
                          const double* F, const double* Fdiag, const int* mo_of, double tau, Scalars* sd,
-                         int* rot_cnt, int2* rot_slot, double2* rot_cs, int* tcnt, int* tcol, int fp32,
-                         hipStream_t s) {
+                         int* rot_cnt, int2* rot_slot, double2* rot_cs, int* tcnt, int* tcol, ulonglong2* tmask,
+                         int fp32, hipStream_t s) {
   if (nb > 0)
     hipLaunchKernelGGL(k_block_select, dim3(nb), dim3(256), 0, s, v.W, v.OW, v.VW, jb_g, jb_h, jb_nocc, jb_nvirt, F,
-                       Fdiag, mo_of, (long long)v.n_mo, tau, sd, rot_cnt, rot_slot, rot_cs, tcnt, tcol, fp32);
+                       Fdiag, mo_of, (long long)v.n_mo, tau, sd, rot_cnt, rot_slot, rot_cs, tcnt, tcol, tmask, fp32);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1254,44 +1265,59 @@ void launch_round_meta(int n_rounds, const int* round_ptr, const int* round_list
                      roff, meta);
 }
 
+// One workgroup per row block rb walks the rounds in order (a barrier between rounds, the
+// blocks of a round spread over its waves).  The nonzero columns of every tile (g, rb) are kept
+// exact in LDS (cm_l, initialized from colm): a block is applied at rb only when one of its
+// touched columns is nonzero there, and only those columns enter the product (the K dimension
+// of x R_b packs them), so rows and columns the rotations cannot reach cost nothing.  After
+// each block the written columns' bits are recomputed from the truncated values.  At the end
+// the workgroup writes the exact activity, slice mask and column mask of each tile (g, rb).
 template <int NTMAX, typename Real>
 __global__ void __launch_bounds__(256) k_givens_rb(int G, int n_rb, int W, int OW, int n_rounds,
-                                                   const double* __restrict__ zp,
                                                    const int* __restrict__ roff, const int4* __restrict__ meta,
+                                                   const ulonglong2* __restrict__ tmask,
                                                    const int* __restrict__ tcol,
                                                    const Real* __restrict__ R, double eps, double* C,
-                                                   uint8_t* actC, unsigned int* cmask, const int* __restrict__ rot_cnt,
-                                                   unsigned long long* wcnt) {
+                                                   uint8_t* actC, unsigned int* cmask, ulonglong2* colm,
+                                                   const int* __restrict__ rot_cnt, unsigned long long* wcnt) {
   typedef typename Mfma<Real>::acc_t acc_t;
   extern __shared__ int4 gv_smem[];
-  int4* list_l = gv_smem;                                    // relevant blocks of the round
-  int* cnt_l = reinterpret_cast<int*>(gv_smem + 256);
-  uint8_t* act_l = reinterpret_cast<uint8_t*>(cnt_l + 4);   // activity of row block rb, per group
+  int4* list_l = gv_smem;                                                   // relevant blocks of the round
+  unsigned long long* cm_l = reinterpret_cast<unsigned long long*>(gv_smem + 256);   // 2 words per group
+  uint8_t* pos_all = reinterpret_cast<uint8_t*>(cm_l + 2 * G);              // 128 slots per wave
+  int* cnt_l = reinterpret_cast<int*>(pos_all + 4 * 128);
   const int rb = blockIdx.x;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  for (int g = threadIdx.x; g < G; g += blockDim.x) act_l[g] = actC[(size_t)g * n_rb + rb];
+  uint8_t* pos_l = pos_all + wv * 128;
+  // occupied columns [0, OW) and virtual columns [OW, W) of a panel, as 128-bit masks
+  const unsigned long long occ0 = OW >= 64 ? ~0ull : ((1ull << OW) - 1ull);
+  const unsigned long long occ1 = OW > 64 ? ((OW >= 128) ? ~0ull : ((1ull << (OW - 64)) - 1ull)) : 0ull;
+  for (int g = threadIdx.x; g < G; g += blockDim.x) {
+    const size_t t = (size_t)g * n_rb + rb;
+    const ulonglong2 m = actC[t] ? colm[t] : make_ulonglong2(0ull, 0ull);
+    cm_l[2 * g] = m.x;
+    cm_l[2 * g + 1] = m.y;
+  }
   // work counting (wcnt != NULL): per block and row block, the nonzeros of the touched columns
   // before the block (read and written: 16 bytes each) and 6 flops per rotation and row of
   // their union
   unsigned long long w_flops = 0, w_bytes = 0;
-  // the first 256 rotating blocks of round r + 1 are fetched while round r is applied
-  auto fetch_round = [&](int r) {
-    return (int)threadIdx.x < roff[r + 1] - roff[r] ? meta[roff[r] + threadIdx.x] : make_int4(-1, 0, 0, 0);
-  };
-  int4 nxt = fetch_round(0);
+  __syncthreads();
   for (int r = 0; r < n_rounds; ++r) {
     const int b0 = roff[r], b1 = roff[r + 1];
-    const int4 cur = nxt;
-    if (r + 1 < n_rounds) nxt = fetch_round(r + 1);
     for (int c0 = b0; c0 < b1; c0 += 256) {
       // every thread checks one rotating block of the round; the relevant ones go to LDS
-      int4 mt = cur;
-      if (c0 != b0) mt = (c0 + (int)threadIdx.x < b1) ? meta[c0 + threadIdx.x] : make_int4(-1, 0, 0, 0);
+      const int4 mt = (c0 + (int)threadIdx.x < b1) ? meta[c0 + threadIdx.x] : make_int4(-1, 0, 0, 0);
       if (threadIdx.x == 0) cnt_l[0] = 0;
       __syncthreads();
-      const bool rel = mt.x >= 0 && (act_l[mt.y] || act_l[mt.z]);
+      bool rel = false;
+      if (mt.x >= 0) {
+        const ulonglong2 tm = tmask[mt.x];
+        rel = ((cm_l[2 * mt.y] & tm.x & occ0) | (cm_l[2 * mt.y + 1] & tm.y & occ1) |
+               (cm_l[2 * mt.z] & tm.x & ~occ0) | (cm_l[2 * mt.z + 1] & tm.y & ~occ1)) != 0ull;
+      }
       const unsigned long long m = __ballot(rel);
       int off = 0;
       if (lane == 0 && m) off = atomicAdd(cnt_l, __popcll(m));
@@ -1307,73 +1333,106 @@ __global__ void __launch_bounds__(256) k_givens_rb(int G, int n_rb, int W, int O
         const Real* Rb = R + (size_t)b * W * W;
         double* Cg = C + ((size_t)g * n_rb + rb) * RB * W;
         double* Ch = C + ((size_t)h * n_rb + rb) * RB * W;
-        // the touched-column list is read once (two entries per lane) and shuffled to the
-        // lanes that gather; gathers go out 8 k-steps at a time
+        // touched columns (two per lane) and whether each is nonzero at rb; the nonzero ones'
+        // positions, packed in order, form the K dimension
         const int tcl0 = (lane < T) ? tc[lane] : 0;
         const int tcl1 = (lane + 64 < T) ? tc[lane + 64] : 0;
-        const int ns = 4 * nt_n;
+        auto col_nz = [&](int col) {
+          const int grp = col < OW ? g : h;
+          return (cm_l[2 * grp + (col >> 6)] >> (col & 63)) & 1ull;
+        };
+        const bool nz0 = lane < T && col_nz(tcl0);
+        const bool nz1 = lane + 64 < T && col_nz(tcl1);
+        const unsigned long long q0 = __ballot(nz0), q1 = __ballot(nz1);
+        const unsigned long long below = (1ull << lane) - 1ull;
+        const int n0 = __popcll(q0);
+        if (nz0) pos_l[__popcll(q0 & below)] = (uint8_t)lane;
+        if (nz1) pos_l[n0 + __popcll(q1 & below)] = (uint8_t)(lane + 64);
+        const int nzk = n0 + __popcll(q1);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         acc_t acc[NTMAX];
 #pragma unroll
         for (int n = 0; n < NTMAX; ++n) acc[n] = acc_t{0, 0, 0, 0};
         unsigned int w_rows = 0u, w_nnz = 0u;
-        for (int s0 = 0; s0 < ns; s0 += 8) {
-          // gathers, all in flight together (a lane past T reads the zero page)
-          Real a[8];
+        for (int s0 = 0; s0 < nzk; s0 += 16) {
+          // four k-steps: packed slots s0 + 4 u + lk, gathers all in flight together
+          Real a[4];
+          int kp[4];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int k = 4 * (s0 + u) + lk;
+          for (int u = 0; u < 4; ++u) {
+            const int slot = s0 + 4 * u + lk;
+            const bool in = slot < nzk;
+            const int k = in ? pos_l[slot] : 0;
             const int c0 = __shfl(tcl0, k & 63), c1 = __shfl(tcl1, k & 63);
-            const bool in = s0 + u < ns && k < T;
             const int col = (k < 64) ? c0 : c1;
-            a[u] = (Real)ld_or_zero(in, (col < OW ? Cg : Ch) + lr * W + col, zl(zp, rb * 8 + u));
+            kp[u] = k;
+            a[u] = in ? (Real)((col < OW ? Cg : Ch)[lr * W + col]) : Real(0);
           }
           if (wcnt) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              const unsigned long long b = __ballot(a[u] != Real(0));      // bit = 16 lk + row
-              w_nnz += __popcll(b);
-              w_rows |= (unsigned int)((b | (b >> 16) | (b >> 32) | (b >> 48)) & 0xffffull);
+            for (int u = 0; u < 4; ++u) {
+              const unsigned long long bb = __ballot(a[u] != Real(0));      // bit = 16 lk + row
+              w_nnz += __popcll(bb);
+              w_rows |= (unsigned int)((bb | (bb >> 16) | (bb >> 32) | (bb >> 48)) & 0xffffull);
             }
           }
 #pragma unroll
           for (int n = 0; n < NTMAX; ++n) {
             if (n >= nt_n) break;
-            Real rv[8];
+            Real rv[4];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) rv[u] = Rb[(size_t)min(4 * (s0 + u) + lk, W - 1) * W + n * 16 + lr];
+            for (int u = 0; u < 4; ++u) rv[u] = Rb[(size_t)kp[u] * W + n * 16 + lr];
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-              if (s0 + u < ns) acc[n] = Mfma<Real>::op(a[u], rv[u], acc[n]);
+            for (int u = 0; u < 4; ++u)
+              if (s0 + 4 * u < nzk) acc[n] = Mfma<Real>::op(a[u], rv[u], acc[n]);
           }
         }
-        int nzg = 0, nzh = 0;
-        unsigned int bg = 0, bh = 0;
+        // write back with the cut |C| < eps; the written columns' new nonzero bits
+        unsigned long long ng0 = 0, ng1 = 0, nh0 = 0, nh1 = 0;
 #pragma unroll
         for (int n = 0; n < NTMAX; ++n) {
           const int j = n * 16 + lr;
           const int c0 = __shfl(tcl0, j & 63), c1 = __shfl(tcl1, j & 63);
+          int nzc = 0;
+          const int col = (j < 64) ? c0 : c1;
           if (n < nt_n && j < T) {
-            const int col = (j < 64) ? c0 : c1;
             double* base = (col < OW) ? Cg : Ch;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
               double x = (double)acc[n][q];
               if (fabs(x) < eps) x = 0.0;
               base[Mfma<Real>::row(lk, q) * W + col] = x;
-              if (x != 0.0) {
-                if (col < OW) { nzg = 1; bg |= 1u << (col >> 4); }
-                else { nzh = 1; bh |= 1u << (col >> 4); }
-              }
+              nzc |= x != 0.0;
             }
           }
+          nzc |= __shfl_xor(nzc, 16);
+          nzc |= __shfl_xor(nzc, 32);
+          if (nzc && lk == 0) {
+            const unsigned long long bit = 1ull << (col & 63);
+            if (col < OW) { if (col < 64) ng0 |= bit; else ng1 |= bit; }
+            else { if (col < 64) nh0 |= bit; else nh1 |= bit; }
+          }
         }
-        const bool anyg = __ballot(nzg) != 0ULL, anyh = __ballot(nzh) != 0ULL;
-        for (int o = 32; o > 0; o >>= 1) { bg |= __shfl_xor(bg, o); bh |= __shfl_xor(bh, o); }
+        for (int o = 32; o > 0; o >>= 1) {
+          ng0 |= __shfl_xor(ng0, o);
+          ng1 |= __shfl_xor(ng1, o);
+          nh0 |= __shfl_xor(nh0, o);
+          nh1 |= __shfl_xor(nh1, o);
+        }
         if (lane == 0) {
-          if (bg) atomicOr(&cmask[(size_t)g * n_rb + rb], bg);
-          if (bh) atomicOr(&cmask[(size_t)h * n_rb + rb], bh);
-          if (anyg && !act_l[g]) { act_l[g] = 1; actC[(size_t)g * n_rb + rb] = 1; }
-          if (anyh && !act_l[h]) { act_l[h] = 1; actC[(size_t)h * n_rb + rb] = 1; }
+          // another block of the round may change the other half (virtual / occupied) of the
+          // same group's bits: disjoint bits, atomic updates
+          const ulonglong2 tm = tmask[b];
+          atomicAnd(&cm_l[2 * g], ~(tm.x & occ0));
+          atomicAnd(&cm_l[2 * g + 1], ~(tm.y & occ1));
+          if (ng0) atomicOr(&cm_l[2 * g], ng0);
+          if (ng1) atomicOr(&cm_l[2 * g + 1], ng1);
+          atomicAnd(&cm_l[2 * h], ~(tm.x & ~occ0));
+          atomicAnd(&cm_l[2 * h + 1], ~(tm.y & ~occ1));
+          if (nh0) atomicOr(&cm_l[2 * h], nh0);
+          if (nh1) atomicOr(&cm_l[2 * h + 1], nh1);
         }
         if (wcnt) {
           w_bytes += 16ull * w_nnz;
@@ -1383,21 +1442,33 @@ __global__ void __launch_bounds__(256) k_givens_rb(int G, int n_rb, int W, int O
       __syncthreads();
     }
   }
+  // exact flags of the row block's tiles
+  for (int g = threadIdx.x; g < G; g += blockDim.x) {
+    const size_t t = (size_t)g * n_rb + rb;
+    const unsigned long long m0 = cm_l[2 * g], m1 = cm_l[2 * g + 1];
+    unsigned int sl = 0u;
+    for (int n = 0; n < 8; ++n)
+      if (((n < 4 ? m0 : m1) >> (16 * (n & 3))) & 0xffffull) sl |= 1u << n;
+    actC[t] = (uint8_t)(sl != 0u);
+    cmask[t] = sl;
+    colm[t] = make_ulonglong2(m0, m1);
+  }
   if (wcnt && lane == 0) {
     if (w_flops) atomicAdd(wcnt, w_flops);
     if (w_bytes) atomicAdd(wcnt + 1, w_bytes);
   }
 }
 
-void launch_givens_rb(const View& v, int n_rounds, const int* roff, const int4* meta, const int* tcol, const double* R,
-                      const float* R32, double eps, double* C, uint8_t* actC, unsigned int* cmask, const int* rot_cnt,
-                      unsigned long long* wcnt, hipStream_t s) {
+void launch_givens_rb(const View& v, int n_rounds, const int* roff, const int4* meta, const ulonglong2* tmask,
+                      const int* tcol, const double* R, const float* R32, double eps, double* C, uint8_t* actC,
+                      unsigned int* cmask, ulonglong2* colm, const int* rot_cnt, unsigned long long* wcnt,
+                      hipStream_t s) {
   if (n_rounds <= 0) return;
-  const size_t lds = 256 * sizeof(int4) + 4 * sizeof(int) + (size_t)v.G;
+  const size_t lds = 256 * sizeof(int4) + 2 * sizeof(unsigned long long) * (size_t)v.G + 4 * 128 + 16;
   switch ((v.W + 15) / 16) {
 #define SSCF_GIV(N) case N: \
-    if (R32) hipLaunchKernelGGL((k_givens_rb<N, float>), dim3(v.n_rb), dim3(256), lds, s, v.G, v.n_rb, v.W, v.OW, n_rounds, v.zeros, roff, meta, tcol, R32, eps, C, actC, cmask, rot_cnt, wcnt); \
-    else hipLaunchKernelGGL((k_givens_rb<N, double>), dim3(v.n_rb), dim3(256), lds, s, v.G, v.n_rb, v.W, v.OW, n_rounds, v.zeros, roff, meta, tcol, R, eps, C, actC, cmask, rot_cnt, wcnt); \
+    if (R32) hipLaunchKernelGGL((k_givens_rb<N, float>), dim3(v.n_rb), dim3(256), lds, s, v.G, v.n_rb, v.W, v.OW, n_rounds, roff, meta, tmask, tcol, R32, eps, C, actC, cmask, colm, rot_cnt, wcnt); \
+    else hipLaunchKernelGGL((k_givens_rb<N, double>), dim3(v.n_rb), dim3(256), lds, s, v.G, v.n_rb, v.W, v.OW, n_rounds, roff, meta, tmask, tcol, R, eps, C, actC, cmask, colm, rot_cnt, wcnt); \
     break;
     SSCF_GIV(1) SSCF_GIV(2) SSCF_GIV(3) SSCF_GIV(4) SSCF_GIV(5) SSCF_GIV(6) SSCF_GIV(7) SSCF_GIV(8)
 #undef SSCF_GIV
