@@ -217,6 +217,23 @@ sscf_status sscf_fragment_guess(const sscf_guess_desc* d, int64_t* c0_colptr, in
 sscf_status sscf_atom_neighbours(int32_t n_atoms, const double* xyz, double cutoff, void* hip_stream,
                                  int64_t* rowptr, int32_t* col, int64_t cap, int64_t* nnz);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the atom neighbour map of sscf_atom_neighbours with
+ * every array in DEVICE memory owned by the caller and no allocation of any kind on the device.
+ * xyz: n_atoms x 3 doubles; rowptr: n_atoms + 1 int64, always written; col: cap int32, written
+ * when the map fits (col may be NULL to ask for the size).  *nnz (host) receives the number of
+ * entries.  The map is the one sscf_atom_neighbours returns, entry for entry.  The call's
+ * scratch (tile bounding boxes, per-atom counts, an error flag; about 1.2 MB) is a fixed array
+ * that each GPU the library runs on holds until the process ends; every call on a GPU uses that
+ * GPU's copy, so calls that overlap on one GPU (from several threads or streams) race: order
+ * them.  The call synchronizes the stream twice (to read the size, and before returning, when
+ * the scratch is free again).  Errors: SSCF_E_CAPACITY for n_atoms > SSCF_NOALLOC_MAX_ATOMS or
+ * cap too small (rowptr and *nnz are then written, col is not); SSCF_E_INVALID_ARG as for
+ * sscf_atom_neighbours, or for host pointers.  Error text: sscf_last_error(NULL). */
+#define SSCF_NOALLOC_MAX_ATOMS 262144
+sscf_status sscf_atom_neighbours_noalloc(int32_t n_atoms, const double* xyz, double cutoff, void* hip_stream,
+                                         int64_t* rowptr, int32_t* col, int64_t cap, int64_t* nnz);
+
 /* Inputs of the constrained k-means of section 3.2 (host memory, read during the call). */
 typedef struct {
   int32_t n_points;

@@ -25,6 +25,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -1325,6 +1326,95 @@ sscf_status sscf_atom_neighbours(int32_t n_atoms, const double* xyz, double cuto
     return f.code;
   } catch (const std::exception& e) {
     freeall();
+    g_init_error = e.what();
+    return SSCF_E_NOMEM;
+  }
+}
+
+// ---- the atom neighbour map without allocation -------------------------------------------
+// Its scratch lives in `scratch`, a fixed array of every GPU the library runs on: the bounding
+// boxes of the 64-atom tiles (6 doubles each), the neighbour count of every atom, and an error
+// flag.  Host code never passes `scratch` itself (that name is a host-side stand-in): the
+// device address of each GPU's copy comes from hipGetSymbolAddress, once per device.
+namespace {
+constexpr int NOALLOC_TILES = (SSCF_NOALLOC_MAX_ATOMS + NB_TILE_ATOMS - 1) / NB_TILE_ATOMS;
+constexpr size_t NOALLOC_BOX = 0;                                                   // doubles
+constexpr size_t NOALLOC_CNT = NOALLOC_BOX + sizeof(double) * 6 * NOALLOC_TILES;     // ints
+constexpr size_t NOALLOC_FLAG = NOALLOC_CNT + sizeof(int) * SSCF_NOALLOC_MAX_ATOMS;  // one int
+constexpr size_t NOALLOC_BYTES = NOALLOC_FLAG + 256;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+// device address of this device's scratch (looked up on the first call on the device)
+static unsigned char* scratch_of_current_device() {
+  int dev = 0;
+  HIPC(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) fail(SSCF_E_CAPACITY, "device %d: at most %d devices", dev, NOALLOC_MAX_DEVICES);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPC(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = static_cast<unsigned char*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+
+static bool is_device_memory(const void* p) {
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type == hipMemoryTypeDevice;
+}
+
+sscf_status sscf_atom_neighbours_noalloc(int32_t n_atoms, const double* xyz, double cutoff, void* hip_stream,
+                                         int64_t* rowptr, int32_t* col, int64_t cap, int64_t* nnz) {
+  if (!xyz || !rowptr || !nnz) {
+    g_init_error = "atom neighbours (no allocation): NULL argument";
+    return SSCF_E_INVALID_ARG;
+  }
+  try {
+    const int n = n_atoms;
+    if (n <= 0) fail(SSCF_E_INVALID_ARG, "atom neighbours (no allocation): n_atoms must be positive");
+    if (n > SSCF_NOALLOC_MAX_ATOMS)
+      fail(SSCF_E_CAPACITY, "atom neighbours (no allocation): %d atoms exceed the fixed scratch's %d", n,
+           SSCF_NOALLOC_MAX_ATOMS);
+    if (!(cutoff > 0.0) || !(cutoff <= 1e100))
+      fail(SSCF_E_INVALID_ARG, "atom neighbours (no allocation): cutoff must be in (0, 1e100]");
+    if (!is_device_memory(xyz) || !is_device_memory(rowptr) || (col && !is_device_memory(col)))
+      fail(SSCF_E_INVALID_ARG, "atom neighbours (no allocation): xyz, rowptr and col must be device memory");
+    hipStream_t s = (hipStream_t)hip_stream;
+    unsigned char* base = scratch_of_current_device();
+    double* box = reinterpret_cast<double*>(base + NOALLOC_BOX);
+    int* cnt = reinterpret_cast<int*>(base + NOALLOC_CNT);
+    int* flag = reinterpret_cast<int*>(base + NOALLOC_FLAG);
+    // the flag keeps the last call's value: cleared by a kernel (no memset node)
+    launch_fill_i32(flag, 1, 0, s);
+    launch_check_coords(3LL * n, xyz, flag, s);
+    launch_atom_nbr_count(n, xyz, cutoff, box, cnt, rowptr, s);
+    int bad = 0;
+    int64_t total = 0;
+    HIPC(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(&total, rowptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (bad) fail(SSCF_E_INVALID_ARG, "atom neighbours (no allocation): bad coordinate");
+    *nnz = total;
+    if (total > cap || !col)
+      fail(SSCF_E_CAPACITY, "atom neighbours (no allocation): %lld entries do not fit in cap %lld",
+           (long long)total, (long long)cap);
+    launch_atom_nbr_fill(n, xyz, cutoff, box, rowptr, col, s);
+    // the scratch is free again once the call returns
+    HIPC(hipStreamSynchronize(s));
+    return SSCF_OK;
+  } catch (const Fail& f) {
+    g_init_error = f.msg;
+    return f.code;
+  } catch (const std::exception& e) {
     g_init_error = e.what();
     return SSCF_E_NOMEM;
   }

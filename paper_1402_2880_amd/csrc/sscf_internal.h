@@ -35,7 +35,8 @@ constexpr int KM_MAX_LINK = 1024;      // largest n_link (a chunk scans KM_SLOTS
 constexpr int KM_MAX_MEANS = 4096;     // most means (the per-point sort of means lives in LDS)
 constexpr int KM_PCAP = 256;           // proposals listed per mean and round (more: a scan of all points)
 static_assert(KM_MAX_LINK + KM_PCAP <= KM_SLOTS, "listed proposals and kept points must fit in the LDS slots");
-constexpr int MAX_TIES = 4096;   // candidates sharing the cut-off |F| that can be ordered
+constexpr int MAX_TIES = 4096;
+constexpr int NB_TILE_ATOMS = 64;       // atoms per tile of the atom neighbour map   // candidates sharing the cut-off |F| that can be ordered
 
 // scalars shared between kernels and the host (one device copy per context)
 struct Scalars {
@@ -145,6 +146,7 @@ void launch_fragment_guess(int n_frag, const int* frag_atom0, const int64_t* ao_
                            const int* blk_col, const int64_t* blk_off, const int* atom_nao, const double* S,
                            const double* H, const int64_t* frag_coff, double* out, double* lam, int* err,
                            hipStream_t s);
+void launch_check_coords(int64_t n, const double* x, int* flag, hipStream_t s);
 void launch_atom_nbr_count(int n, const double* xyz, double cutoff, double* box, int* cnt, int64_t* rowptr,
                            hipStream_t s);
 void launch_atom_nbr_fill(int n, const double* xyz, double cutoff, const double* box, const int64_t* rowptr, int* col,

@@ -441,6 +441,7 @@ namespace sscf {
 // ---------------------------------------------------------------------------------------
 
 constexpr int NB_TILE = 64;
+static_assert(NB_TILE == NB_TILE_ATOMS, "tile size of the atom neighbour map");
 
 // lo/hi corners of each tile's atoms (exact: min and max round nothing)
 __global__ void __launch_bounds__(64) k_tile_bbox(int n, const double* __restrict__ xyz, double* __restrict__ box) {
@@ -523,6 +524,16 @@ __global__ void __launch_bounds__(1024) k_row_scan(int n, const int* __restrict_
     run += cnt[i];
     rowptr[i + 1] = run;
   }
+}
+
+// flag = 1 when a coordinate is not finite or exceeds 1e100 in magnitude (flag cleared by the caller)
+__global__ void k_check_coords(int64_t n, const double* __restrict__ x, int* flag) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (!(fabs(x[i]) <= 1e100)) *flag = 1;
+}
+void launch_check_coords(int64_t n, const double* x, int* flag, hipStream_t s) {
+  const int64_t g = (n + 255) / 256;
+  if (n) hipLaunchKernelGGL(k_check_coords, dim3((unsigned int)(g < 1024 ? g : 1024)), dim3(256), 0, s, n, x, flag);
 }
 
 void launch_atom_nbr_count(int n, const double* xyz, double cutoff, double* box, int* cnt, int64_t* rowptr,

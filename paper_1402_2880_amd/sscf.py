@@ -102,6 +102,7 @@ EXPORTS = ["sscf_get_kernel_stats", "sscf_reset_kernel_stats", "sscf_init_system
            "sscf_get_schedule", "sscf_get_energy_gradient", "sscf_get_energy_gradient_device",
            "sscf_set_control", "sscf_get_control",
            "sscf_orthonormalize", "sscf_fragment_guess", "sscf_constrained_kmeans", "sscf_atom_neighbours",
+           "sscf_atom_neighbours_noalloc",
            "sscf_destroy",
            "sscf_last_error"]
 
@@ -132,6 +133,7 @@ def lib():
         L.sscf_get_charges.argtypes = [vp, vp, sz]
         L.sscf_constrained_kmeans.argtypes = [ct.POINTER(KmeansDesc), vp, vp, ct.POINTER(KmeansInfo)]
         L.sscf_atom_neighbours.argtypes = [i32, vp, ct.c_double, vp, vp, vp, i64, ct.POINTER(i64)]
+        L.sscf_atom_neighbours_noalloc.argtypes = [i32, vp, ct.c_double, vp, vp, vp, i64, ct.POINTER(i64)]
         L.sscf_get_mo_coefficients.argtypes = [vp, vp, vp, vp, ct.POINTER(i64)]
         L.sscf_init_info.argtypes = [vp, ct.POINTER(StepInfo)]
         L.sscf_get_schedule.argtypes = [vp, vp, vp, vp, ct.POINTER(i32)]
