@@ -176,7 +176,8 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "wat
 @pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden values not generated")
 @pytest.mark.parametrize("seed", [1, 2])
 def test_water4096_against_stored_oracle(seed):
-    """The 12,288-atom box (two geometries): set-up and first steps against stored oracle values."""
+    """The 12,288-atom box (two geometries): set-up and every stored step (25 per geometry, the
+    benchmark's window included) against stored oracle values."""
     rec = json.load(open(GOLDEN.replace("seed1", f"seed{seed}")))
     assert rec["seed"] == seed
     s = synth.make_config("water4096", seed)
@@ -195,6 +196,8 @@ def test_water4096_against_stored_oracle(seed):
         assert gs["n_candidates"] == st["n_candidates"]
         assert gs["n_rotations"] == st["n_rotations"]
         assert gs["n_ortho_sweeps"] == st["n_ortho_sweeps"]
+        if "post_ortho" in st:
+            assert gs["converged"] == st["converged"] and gs["post_ortho"] == st["post_ortho"]
         assert np.abs(g.charges()[sample] - np.array(st["charges_sample"])).max() < Q_TOL
 
 
@@ -223,12 +226,16 @@ def test_fp32_form_water128(water128):
     assert conv_g and conv_o
 
 
-def test_fp32_form_water4096():
+@pytest.mark.parametrize("seed", [1, 2])
+def test_fp32_form_water4096(seed):
+    """Every stored step (25: through convergence and the occupied-only step III) within 1e-6 Ha
+    of the FP64 oracle."""
     from paper_1402_2880_amd.sscf import FP32_MIXED
-    if not os.path.exists(GOLDEN):
+    path = GOLDEN.replace("seed1", f"seed{seed}")
+    if not os.path.exists(path):
         pytest.skip("golden values not generated")
-    rec = json.load(open(GOLDEN))
-    s = synth.make_config("water4096", 1)
+    rec = json.load(open(path))
+    s = synth.make_config("water4096", seed)
     g = gpu(s, eps=rec["eps"], e_conv=rec["e_conv"], precision=FP32_MIXED)
     for k, st in enumerate(rec["steps"]):
         gs = g.step()
