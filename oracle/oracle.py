@@ -13,8 +13,18 @@ from typing import Dict, Optional
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# SSCF_ORACLE_LIB: another build of the same source (the sanitizer build of the tests)
+LIB_PATH = os.environ.get("SSCF_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 SOURCES = [os.path.join(HERE, "sscf_oracle.c")]
+SAN_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
+
+
+def build_sanitized(path: str) -> str:
+    """The oracle with AddressSanitizer and UndefinedBehaviorSanitizer (for the tests)."""
+    cmd = ["gcc", "-std=c11", "-D_POSIX_C_SOURCE=200809L", "-fopenmp", "-fPIC", "-shared", "-Wall",
+           "-Wno-unused-function"] + SAN_FLAGS + ["-o", path] + SOURCES + ["-lm"]
+    subprocess.run(cmd, check=True)
+    return path
 
 
 def build(force: bool = True) -> str:
