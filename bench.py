@@ -150,7 +150,7 @@ def setup_timing(system, args, prec):
     setup.update(kmeans_ms=round(1e3 * (time.perf_counter() - t), 2), kmeans_iterations=kinfo["iterations"],
                  kmeans_rounds=kinfo["rounds"], kmeans_means=int(m0.shape[0]))
     t = time.perf_counter()
-    g = SparseSCF(system, eps=args.eps, e_conv=args.e_conv, precision=prec)
+    g = SparseSCF(system, eps=args.eps, e_conv=args.e_conv, precision=prec, **synth.RUN_OPTIONS.get(args.config, {}))
     torch.cuda.synchronize()
     setup["init_ms"] = round(1e3 * (time.perf_counter() - t), 1)
     g.close()
@@ -183,32 +183,41 @@ def load_golden(config: str, seed: int, eps: float, e_conv: float):
 
 
 def run_form(system, prec, args, profile: bool, count: bool, adjoint: bool = False):
-    """Warm-up and timed steps of one precision form; returns (infos, elapsed s, kernel stats)."""
+    """Warm-up and timed steps of one precision form; returns (warm-up infos, timed infos, elapsed s,
+    kernel stats, set-up info, memory info)."""
     import torch
+    from paper_1402_2880_amd import synth
     from paper_1402_2880_amd.sscf import CONV_CHARGE, SparseSCF
-    g = SparseSCF(system, eps=args.eps, e_conv=args.e_conv, precision=prec, profile=profile, count_work=count)
+    g = SparseSCF(system, eps=args.eps, e_conv=args.e_conv, precision=prec, profile=profile, count_work=count,
+                  **synth.RUN_OPTIONS.get(args.config, {}))
     if args.schedule == "paper":
         g.set_control(args.eps, dq_conv=10 * args.eps, criterion=CONV_CHARGE, step_ortho=False)
+    log(f"[bench] {'fp64' if prec == 0 else 'fp32'} context ready (count={count}): "
+        f"set-up energy {g.init_info()['energy']:.8f}")
     warm = []
-    for _ in range(args.warmup):
+    for k in range(args.warmup):
         warm.append(g.step())
         if adjoint:
             g.energy_gradient(device=True)
+        log(f"[bench]   warm-up step {k + 1}: {warm[-1]['ms_total']:.1f} ms")
     if profile or count:
         g.reset_kernel_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
-    for _ in range(args.steps):
+    for k in range(args.steps):
         infos.append(g.step())
         if adjoint:
             g.energy_gradient(device=True)
+        if args.log_steps:
+            log(f"[bench]   step {args.warmup + k + 1}: {infos[-1]['ms_total']:.1f} ms")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ks = g.kernel_stats() if (profile or count) else None
     init = g.init_info()
+    mem = g.memory_info()
     g.close()
-    return warm, infos, elapsed, ks, init
+    return warm, infos, elapsed, ks, init, mem
 
 
 def energy_errors(infos, golden, first_step: int):
@@ -235,6 +244,7 @@ def main():
     ap.add_argument("--e-conv", type=float, default=1e-6)
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--log-steps", action="store_true", help="log every timed step as it ends (long steps)")
     ap.add_argument("--no-other-form", action="store_true", help="skip the other precision form's timed run")
     ap.add_argument("--no-count", action="store_true", help="skip the work-counting replay (no roofline)")
     ap.add_argument("--schedule", default="step", choices=["step", "paper"],
@@ -281,8 +291,8 @@ def main():
     window = f"SCF steps {first}..{args.warmup + args.steps}"
 
     # 1. the timed run
-    warm, infos, elapsed, kstats, init = run_form(system, prec, args, profile=True, count=False,
-                                                  adjoint=args.adjoint)
+    warm, infos, elapsed, kstats, init, mem = run_form(system, prec, args, profile=True, count=False,
+                                                       adjoint=args.adjoint)
     for k, si in enumerate(warm + infos):
         log(f"[bench] step {k + 1}: E {si['energy']:.10f} dE {si['delta_e']:.2e} rot {si['n_rotations']} "
             f"sweeps {si['n_ortho_sweeps']} {si['ms_total']:.1f} ms (fock {si['ms_fock']:.2f} cfc "
@@ -294,7 +304,7 @@ def main():
     # 2. the replay with the work counters
     counts = None
     if not args.no_count:
-        _, cinfos, _, cks, _ = run_form(system, prec, args, profile=False, count=True, adjoint=False)
+        _, cinfos, _, cks, _, _ = run_form(system, prec, args, profile=False, count=True, adjoint=False)
         same = all(a["energy"] == b["energy"] for a, b in zip(cinfos, infos))
         counts = dict(stats=cks, replay_energies_identical=same,
                       nnz_c=[si["nnz_c"] for si in cinfos])
@@ -347,18 +357,25 @@ def main():
 
     # 4. energy error against the stored FP64 oracle values
     errs = energy_errors(infos, golden, first)
-    err = None if errs is None else dict(max_abs_ha=max(errs), steps_compared=len(errs),
-                                         reference=f"stored FP64 oracle values, tests/golden/water4096_seed{args.seed}.json")
+    err = (dict(max_abs_ha=None, note=f"no stored oracle values for {args.config}: parity at this size is "
+                "unpinned; the same generator at small size is compared with the oracle step by step in the tests, "
+                "and other_form gives the FP64/FP32 gap on this window")
+           if errs is None else
+           dict(max_abs_ha=max(errs), steps_compared=len(errs),
+                reference=f"stored FP64 oracle values, tests/golden/{args.config}_seed{args.seed}.json"))
 
     # 5. the other precision form on the same window
     other = None
     if not args.no_other_form:
         oprec, oname = (FP32_MIXED, "fp32") if prec == FP64 else (FP64, "fp64")
-        _, oinfos, oel, _, _ = run_form(system, oprec, args, profile=False, count=False)
+        _, oinfos, oel, _, _, _ = run_form(system, oprec, args, profile=False, count=False,
+                                            adjoint=args.adjoint)
         oerrs = energy_errors(oinfos, golden, first)
         other = dict(precision=oname, value=round(args.steps / oel, 4), unit="SCF steps/s",
                      ms_per_step=round(1e3 * oel / args.steps, 3),
                      energy_error_vs_fp64_oracle_max_ha=None if oerrs is None else max(oerrs),
+                     energy_diff_vs_timed_form_max_ha=max(abs(a["energy"] - b["energy"])
+                                                          for a, b in zip(oinfos, infos)),
                      energy_last=oinfos[-1]["energy"], converged_last=bool(oinfos[-1]["converged"]))
         log(f"[bench] {oname} form: {other}")
 
@@ -400,6 +417,11 @@ def main():
         "kernels": classes,
         "paper_context": PAPER_CONTEXT,
     }
+    out["memory"] = dict(device_gb=round(mem["device_bytes"] / 1e9, 3), tile_slots=mem["tile_slots"],
+                         tile_slots_y=mem["tile_slots_y"],
+                         tiles=mem["tiles"], kib_per_atom=round(mem["device_bytes"] / 1024 / system.n_atoms, 1),
+                         options=synth.RUN_OPTIONS.get(args.config, {}),
+                         paper_context="982 GiB at 1.5 M atoms, about 680 KiB per atom (whole program, SGI UV)")
     if setup is not None:
         out["setup"] = setup
     if counts is not None:

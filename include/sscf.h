@@ -127,7 +127,17 @@ typedef struct {
                                   in FP32, everything else in FP64                              */
   void* hip_stream;            /* hipStream_t for all device work; NULL = default stream        */
   sscf_allocator alloc;        /* zero-filled = hipMalloc / hipFree                             */
-  uint64_t flags;              /* 0, or SSCF_FLAG_PROFILE                                       */
+  uint64_t flags;              /* 0, or SSCF_FLAG_PROFILE | SSCF_FLAG_COUNT_WORK                */
+  /* tile capacity of C (section 3.2: the MOs of a group stay near it).  <= 0: every 16-row
+     tile of every group has storage (dense capacity, 8 n_groups ceil(n_ao/16) 16 W bytes per
+     copy of C: quadratic in the size).  > 0: group g has storage for the row blocks within
+     reach_g + slot_margin_bohr of it, reach_g the farthest row block its initial MOs (C0)
+     touch; distances between bounding spheres (of the group's atoms, of the block's atoms),
+     in bohr.  Memory then grows linearly with the size.  The products Y = X C get the row
+     blocks that the pattern of S links to those.  A coefficient of C that would be nonzero
+     outside (after the cuts of the method) is an error: SSCF_E_CAPACITY from the call that
+     produced it, the context is then failed.  Values the cuts leave zero there are no error. */
+  double slot_margin_bohr;
 } sscf_system_desc;
 
 /* Per-step report.  Times are device time (HIP events) in milliseconds. */
@@ -330,6 +340,12 @@ sscf_status sscf_get_energy_gradient(sscf_ctx* ctx, double* dE_dX, double* dE_dS
  * copied to or from the host.  SSCF_E_INVALID_ARG for NULL or host buffers or short sizes. */
 sscf_status sscf_get_energy_gradient_device(sscf_ctx* ctx, double* dE_dX, double* dE_dS, size_t n_val,
                                             double* dE_donsite, size_t n_onsite);
+
+/* Device memory the context holds now (bytes, its own allocations), the tile slots of each
+ * pool of C and of each pool of the products Y = X C (see slot_margin_bohr), and the number
+ * of (group, 16-row block) tiles.  All pointers must be non-NULL (else SSCF_E_INVALID_ARG). */
+sscf_status sscf_memory_info(const sscf_ctx* ctx, size_t* device_bytes, int64_t* tile_slots, int64_t* tile_slots_y,
+                             int64_t* tiles);
 
 /* Mulliken populations q_a (section 3.7, eq. pop) into q[n_atoms] (host). */
 sscf_status sscf_get_charges(const sscf_ctx* ctx, double* q, size_t n);

@@ -49,14 +49,14 @@ __global__ void __launch_bounds__(256) k_cnt_xrow(int nbx, const int* __restrict
 // weight[AO row] over those nonzeros into *wsum; with colnnz, the nonzeros of each column
 // (added to colnnz[g W + c]).
 template <typename Real>
-__global__ void __launch_bounds__(256) k_cnt_tiles(int n_rb, int W, const Real* __restrict__ T,
+__global__ void __launch_bounds__(256) k_cnt_tiles(int n_rb, int W, const int* __restrict__ slot, const Real* __restrict__ T,
                                                    const int* __restrict__ list, const int* __restrict__ cnt, int c0,
                                                    int c1, const int* __restrict__ weight, int* __restrict__ colnnz,
                                                    unsigned long long* nnz, unsigned long long* wsum) {
   const int g = blockIdx.y, t = blockIdx.x;
   if (t >= cnt[g]) return;
   const int r = list[(size_t)g * n_rb + t];
-  const Real* Tt = T + ((size_t)g * n_rb + r) * (size_t)(RB * W);
+  const Real* Tt = T + (size_t)slot[(size_t)g * n_rb + r] * (size_t)(RB * W);
   unsigned long long n = 0, w = 0;
   for (int e = threadIdx.x; e < RB * W; e += 256) {
     const int c = e % W, k = e / W;
@@ -69,21 +69,22 @@ __global__ void __launch_bounds__(256) k_cnt_tiles(int n_rb, int W, const Real* 
   if (wsum) block_add(w, wsum);
 }
 
-// Row masks of the listed tiles: masks[(tile * 16 + k)] = the nonzero columns of row k
+// Row masks of the listed tiles: masks[(slot * 16 + k)] = the nonzero columns of row k (slot of
+// the pool T lives in)
 // (bit c of .x for c < 64, bit c - 64 of .y).  One wave per tile.
 template <typename Real>
-__global__ void __launch_bounds__(64) k_row_masks(int n_rb, int W, const Real* __restrict__ T,
+__global__ void __launch_bounds__(64) k_row_masks(int n_rb, int W, const int* __restrict__ slot, const Real* __restrict__ T,
                                                   const int* __restrict__ list, const int* __restrict__ cnt,
                                                   ulonglong2* __restrict__ masks) {
   const int g = blockIdx.y, t = blockIdx.x;
   if (t >= cnt[g]) return;
-  const size_t tile = (size_t)g * n_rb + list[(size_t)g * n_rb + t];
-  const Real* Tt = T + tile * (size_t)(RB * W);
+  const size_t sl = (size_t)slot[(size_t)g * n_rb + list[(size_t)g * n_rb + t]];
+  const Real* Tt = T + sl * (size_t)(RB * W);
   const int lane = threadIdx.x;
   for (int k = 0; k < RB; ++k) {
     const unsigned long long lo = __ballot(lane < W && Tt[k * W + lane] != Real(0));
     const unsigned long long hi = __ballot(lane + 64 < W && Tt[k * W + lane + 64] != Real(0));
-    if (lane == 0) masks[tile * RB + k] = make_ulonglong2(lo, hi);
+    if (lane == 0) masks[sl * RB + k] = make_ulonglong2(lo, hi);
   }
 }
 
@@ -98,7 +99,8 @@ __device__ __forceinline__ unsigned long long range_bits(int lo, int hi, int wor
 // Pair products C_g^T Y_h: for every item (g = ig[i], h = ih[i]) and every row active in both,
 // the number of (column a of g in [a0, a1), column b of h in [b0, b1)) with both entries
 // nonzero; with tri (self pairs of C^T S C) only a <= b.  Sum into *out.  One wave per item.
-__global__ void __launch_bounds__(64) k_cnt_pairs(int n_items, int n_rb, const int* __restrict__ ig,
+__global__ void __launch_bounds__(64) k_cnt_pairs(int n_items, int n_rb, const int* __restrict__ slot,
+                                                  const int* __restrict__ slotY, const int* __restrict__ ig,
                                                   const int* __restrict__ ih, const int* __restrict__ listC,
                                                   const int* __restrict__ cntC, const uint8_t* __restrict__ actY,
                                                   const ulonglong2* __restrict__ mC, const ulonglong2* __restrict__ mY,
@@ -113,8 +115,8 @@ __global__ void __launch_bounds__(64) k_cnt_pairs(int n_items, int n_rb, const i
   for (int t = threadIdx.x; t < cntC[g]; t += 64) {
     const int r = listC[(size_t)g * n_rb + t];
     if (!actY[(size_t)h * n_rb + r]) continue;
-    const ulonglong2* pc = mC + ((size_t)g * n_rb + r) * RB;
-    const ulonglong2* py = mY + ((size_t)h * n_rb + r) * RB;
+    const ulonglong2* pc = mC + (size_t)slot[(size_t)g * n_rb + r] * RB;
+    const ulonglong2* py = mY + (size_t)slotY[(size_t)h * n_rb + r] * RB;
     for (int k = 0; k < RB; ++k) {
       const unsigned long long c0 = pc[k].x & ra0, c1 = pc[k].y & ra1;
       const unsigned long long y0 = py[k].x & rb0, y1 = py[k].y & rb1;
@@ -160,24 +162,26 @@ void launch_cnt_xrow(const View& v, const void* X, bool fp32, int* xrow, unsigne
                        xrow, tot);
 }
 
-void launch_cnt_tiles(const View& v, const void* T, bool fp32, const int* list, const int* cnt, int c0, int c1,
-                      const int* weight, int* colnnz, unsigned long long* nnz, unsigned long long* wsum,
+void launch_cnt_tiles(const View& v, const void* T, bool fp32, bool is_y, const int* list, const int* cnt, int c0,
+                      int c1, const int* weight, int* colnnz, unsigned long long* nnz, unsigned long long* wsum,
                       hipStream_t s) {
+  const int* sl = is_y ? v.slotY : v.slot;
   if (fp32)
-    hipLaunchKernelGGL(k_cnt_tiles<float>, dim3(v.n_rb, v.G), dim3(256), 0, s, v.n_rb, v.W, (const float*)T, list,
+    hipLaunchKernelGGL(k_cnt_tiles<float>, dim3(v.n_rb, v.G), dim3(256), 0, s, v.n_rb, v.W, sl, (const float*)T, list,
                        cnt, c0, c1, weight, colnnz, nnz, wsum);
   else
-    hipLaunchKernelGGL(k_cnt_tiles<double>, dim3(v.n_rb, v.G), dim3(256), 0, s, v.n_rb, v.W, (const double*)T, list,
+    hipLaunchKernelGGL(k_cnt_tiles<double>, dim3(v.n_rb, v.G), dim3(256), 0, s, v.n_rb, v.W, sl, (const double*)T, list,
                        cnt, c0, c1, weight, colnnz, nnz, wsum);
 }
 
-void launch_row_masks(const View& v, const void* T, bool fp32, const int* list, const int* cnt, ulonglong2* masks,
-                      hipStream_t s) {
+void launch_row_masks(const View& v, const void* T, bool fp32, bool is_y, const int* list, const int* cnt,
+                      ulonglong2* masks, hipStream_t s) {
+  const int* sl = is_y ? v.slotY : v.slot;
   if (fp32)
-    hipLaunchKernelGGL(k_row_masks<float>, dim3(v.n_rb, v.G), dim3(64), 0, s, v.n_rb, v.W, (const float*)T, list,
+    hipLaunchKernelGGL(k_row_masks<float>, dim3(v.n_rb, v.G), dim3(64), 0, s, v.n_rb, v.W, sl, (const float*)T, list,
                        cnt, masks);
   else
-    hipLaunchKernelGGL(k_row_masks<double>, dim3(v.n_rb, v.G), dim3(64), 0, s, v.n_rb, v.W, (const double*)T, list,
+    hipLaunchKernelGGL(k_row_masks<double>, dim3(v.n_rb, v.G), dim3(64), 0, s, v.n_rb, v.W, sl, (const double*)T, list,
                        cnt, masks);
 }
 
@@ -185,8 +189,8 @@ void launch_cnt_pairs(const View& v, int n_items, const int* ig, const int* ih, 
                       const uint8_t* actY, const ulonglong2* mC, const ulonglong2* mY, int a0, int a1, int b0,
                       int b1, int tri, unsigned long long* out, hipStream_t s) {
   if (n_items > 0)
-    hipLaunchKernelGGL(k_cnt_pairs, dim3(n_items), dim3(64), 0, s, n_items, v.n_rb, ig, ih, listC, cntC, actY, mC,
-                       mY, a0, a1, b0, b1, tri, out);
+    hipLaunchKernelGGL(k_cnt_pairs, dim3(n_items), dim3(64), 0, s, n_items, v.n_rb, v.slot, v.slotY, ig, ih, listC, cntC,
+                       actY, mC, mY, a0, a1, b0, b1, tri, out);
 }
 
 void launch_cnt_dot(size_t n, const int* a, const int* b, unsigned long long* dot, unsigned long long* sumb,

@@ -79,6 +79,7 @@ struct sscf_ctx {
   hipStream_t stream = nullptr;
   sscf_allocator alloc{};
   std::vector<void*> owned;
+  std::vector<size_t> owned_bytes;
   std::string err;
   bool failed = false;
 
@@ -137,6 +138,9 @@ struct sscf_ctx {
   int *rot_cnt = nullptr, *tcnt = nullptr, *tcol = nullptr, *round_ptr = nullptr;
   ulonglong2* tmask = nullptr;          // per Jacobi block: its touched panel columns
   ulonglong2* colm = nullptr;           // per tile: nonzero columns (exact during the rotation pass)
+  int* slot = nullptr;                  // tile -> slot of the pools of C (-1: none)
+  int* slotY = nullptr;                 // tile -> slot of the pools of Y (-1: none)
+  size_t n_slots = 0, n_slots_y = 0;
   int *rcnt = nullptr, *roff = nullptr;
   int4* rmeta = nullptr;                // blocks with rotations, packed in round order
   int2* rot_slot = nullptr;
@@ -186,8 +190,8 @@ struct sscf_ctx {
     wzero();
     launch_fill_i32(w_xrow, (size_t)v.n_rb * RB, 0, stream);
     launch_cnt_xrow(v, X, fp32, w_xrow, wdev + 0, stream);
-    launch_cnt_tiles(v, Cp, fp32, listC[cur], cntC[cur], 0, c1, w_xrow, nullptr, wdev + 1, wdev + 2, stream);
-    launch_cnt_tiles(v, Yp, fp32, listY, cntY, 0, c1, nullptr, nullptr, wdev + 3, nullptr, stream);
+    launch_cnt_tiles(v, Cp, fp32, false, listC[cur], cntC[cur], 0, c1, w_xrow, nullptr, wdev + 1, wdev + 2, stream);
+    launch_cnt_tiles(v, Yp, fp32, true, listY, cntY, 0, c1, nullptr, nullptr, wdev + 3, nullptr, stream);
     const auto w = wread();
     wfl[KC_SPMM] += 2.0 * (double)w[2];
     wby[KC_SPMM] += (fp32 ? 4.0 : 8.0) * ((double)w[0] + (double)w[1] + (double)w[3]);
@@ -196,12 +200,12 @@ struct sscf_ctx {
   void count_pairs(int cls, int n_items, const int* ig, const int* ih, const void* Cp, const void* Yp, bool fp32,
                    int a0, int a1, int b0, int b1, int tri, double n_out) {
     wzero();
-    launch_row_masks(v, Cp, fp32, listC[cur], cntC[cur], w_mC, stream);
-    launch_row_masks(v, Yp, fp32, listY, cntY, w_mY, stream);
+    launch_row_masks(v, Cp, fp32, false, listC[cur], cntC[cur], w_mC, stream);
+    launch_row_masks(v, Yp, fp32, true, listY, cntY, w_mY, stream);
     launch_cnt_pairs(v, n_items, ig, ih, listC[cur], cntC[cur], actY, w_mC, w_mY, a0, a1, b0, b1, tri, wdev + 0,
                      stream);
-    launch_cnt_tiles(v, Cp, fp32, listC[cur], cntC[cur], a0, a1, nullptr, nullptr, wdev + 1, nullptr, stream);
-    launch_cnt_tiles(v, Yp, fp32, listY, cntY, b0, b1, nullptr, nullptr, wdev + 2, nullptr, stream);
+    launch_cnt_tiles(v, Cp, fp32, false, listC[cur], cntC[cur], a0, a1, nullptr, nullptr, wdev + 1, nullptr, stream);
+    launch_cnt_tiles(v, Yp, fp32, true, listY, cntY, b0, b1, nullptr, nullptr, wdev + 2, nullptr, stream);
     const auto w = wread();
     wfl[cls] += 2.0 * (double)w[0];
     wby[cls] += (fp32 ? 4.0 : 8.0) * ((double)w[1] + (double)w[2]) + 8.0 * n_out;   // outputs are FP64
@@ -226,7 +230,7 @@ struct sscf_ctx {
     const int c1 = occ_only ? v.OW : v.W;
     wzero();
     launch_fill_i32(w_colnnz, (size_t)v.G * v.W, 0, stream);
-    launch_cnt_tiles(v, C[cur], false, listC[cur], cntC[cur], 0, c1, nullptr, w_colnnz, wdev + 0, nullptr, stream);
+    launch_cnt_tiles(v, C[cur], false, false, listC[cur], cntC[cur], 0, c1, nullptr, w_colnnz, wdev + 0, nullptr, stream);
     launch_cnt_dot((size_t)v.G * v.W, w_colnnz, w_nsel, wdev + 1, wdev + 2, stream);
     const auto w = wread();
     wfl[KC_UPDATE] += 2.0 * (double)w[1];
@@ -234,13 +238,13 @@ struct sscf_ctx {
   }
   void count_update_end(int b, bool occ_only) {          // C written: buffer b, listed
     wzero();
-    launch_cnt_tiles(v, C[b], false, listC[b], cntC[b], 0, occ_only ? v.OW : v.W, nullptr, nullptr, wdev + 0, nullptr,
+    launch_cnt_tiles(v, C[b], false, false, listC[b], cntC[b], 0, occ_only ? v.OW : v.W, nullptr, nullptr, wdev + 0, nullptr,
                      stream);
     wby[KC_UPDATE] += 8.0 * (double)wread()[0];
   }
   int64_t count_nnz_c() {
     wzero();
-    launch_cnt_tiles(v, C[cur], false, listC[cur], cntC[cur], 0, v.W, nullptr, nullptr, wdev + 0, nullptr, stream);
+    launch_cnt_tiles(v, C[cur], false, false, listC[cur], cntC[cur], 0, v.W, nullptr, nullptr, wdev + 0, nullptr, stream);
     return (int64_t)wread()[0];
   }
 
@@ -286,6 +290,7 @@ struct sscf_ctx {
       if (e != hipSuccess) fail(SSCF_E_NOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
     }
     owned.push_back(p);
+    owned_bytes.push_back(bytes);
     return static_cast<T*>(p);
   }
 
@@ -296,6 +301,7 @@ struct sscf_ctx {
     if (stream) hipStreamSynchronize(stream);
     if (alloc.free) alloc.free(alloc.self, p, (void*)stream);
     else hipFree(p);
+    owned_bytes.erase(owned_bytes.begin() + (it - owned.begin()));
     owned.erase(it);
   }
 
@@ -313,6 +319,7 @@ struct sscf_ctx {
       else hipFree(p);
     }
     owned.clear();
+    owned_bytes.clear();
     for (auto& e : ev)
       if (e) { hipEventDestroy(e); e = nullptr; }
     for (auto& e : pev) hipEventDestroy(e);
@@ -325,6 +332,9 @@ struct sscf_ctx {
     Scalars h{};
     HIPC(hipMemcpyAsync(&h, sd, sizeof(Scalars), hipMemcpyDeviceToHost, stream));
     sync();
+    if (h.cap_err)
+      fail(SSCF_E_CAPACITY,
+           "a nonzero fell on a tile without a slot (an MO reached beyond its initial reach + slot_margin_bohr)");
     return h;
   }
 
@@ -377,7 +387,7 @@ struct sscf_ctx {
       HIPC(hipMemsetAsync(upd, 0, (size_t)v.G * W, stream));
       if (wc()) launch_fill_i32(w_nsel, (size_t)v.G * W, 0, stream);
       launch_mark_selected(v, n_pairs, pg, ph, O, sd, pair_sel, upd, rmask, wc() ? w_nsel : nullptr, stream);
-      launch_update_support(v, actC[cur], gn_ptr, gn, pair_of, pair_sel, act_tmp, stream);
+      launch_update_support(v, actC[cur], gn_ptr, gn, pair_of, pair_sel, nullptr, act_tmp, stream);
       launch_list(v, act_tmp, list_tmp, cnt_tmp, stream);
       launch_clear_tiles(v, C[nx], actC[nx], cmask[nx], listC[nx], cntC[nx], stream);
       if (wc()) count_update_begin(occ_only != 0);
@@ -437,13 +447,14 @@ struct sscf_ctx {
                 0, no, 0, no, foo_a, v.OW, fo, nullptr, s);
     launch_pair(v, n_pairs, pair_perm, pair_maxc, ph, pg, C[cur], listC[cur], cntC[cur], cmask[cur], Y, actY, ymask,
                 0, no, 0, no, foo_b, v.OW, fo, nullptr, s);
-    // Z = C_occ F on the row blocks where a neighbouring group is active (Z overwrites Y)
-    launch_update_support(v, actC[cur], gn_ptr, gn, pair_of, pair_all, act_tmp, s);
+    // Z = C_occ F on the row blocks where a neighbouring group is active and that S links to an
+    // active row block of the group (W needs no other; Z overwrites Y, in Y's pool)
+    launch_update_support(v, actC[cur], gn_ptr, gn, pair_of, pair_all, actY, act_tmp, s);
     launch_list(v, act_tmp, list_tmp, cnt_tmp, s);
     launch_apply_occ(v, C[cur], actC[cur], gn_ptr, gn, pair_of, pg, foo_a, foo_b, list_tmp, cnt_tmp, Y, s);
     // P = 2 C_occ C_occ^T and W = 2 C_occ Z^T on the pattern of S, then the layout of S_val
-    launch_density_blocks(v, C[cur], actC[cur], C[cur], actC[cur], pblk, s);
-    launch_density_blocks(v, C[cur], actC[cur], Y, act_tmp, wblk, s);
+    launch_density_blocks(v, C[cur], actC[cur], C[cur], actC[cur], false, pblk, s);
+    launch_density_blocks(v, C[cur], actC[cur], Y, act_tmp, true, wblk, s);
     launch_grad_assemble(v, n_val, val_map, pblk, wblk, Q, scc && !fock_full, dX, dS, s);
     if (don) launch_grad_onsite(v, ao_off, xs_diag, pblk, don, s);
   }
@@ -776,9 +787,100 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
   x->h_atom_nao.assign(d->atom_nao, d->atom_nao + na);
   const size_t ntiles = (size_t)G * v.n_rb;
   const size_t tile_elems = (size_t)RB * v.W;
+  // Tile capacity.  Without a margin every tile (g, r) has a slot (dense capacity,
+  // 8 G n_rb 16 W bytes per copy of C).  With one, group g gets the row blocks within
+  // R_g = reach_g + margin of it, reach_g the farthest row block that g's initial MOs touch
+  // (section 3.2: the MOs of a group stay near it).  Distances are taken between bounding
+  // spheres (of the group's atoms, of the block's atoms), a superset of the atom-to-atom test;
+  // memory then grows with the number of atoms instead of its square.
+  {
+    std::vector<int> slot(ntiles, -1);
+    int64_t ns = 0;
+    if (!(d->slot_margin_bohr > 0.0)) {
+      for (size_t t = 0; t < ntiles; ++t) slot[t] = (int)t;
+      ns = (int64_t)ntiles;
+    } else {
+      auto sphere = [&](const std::vector<int>& atoms, double* c) {
+        c[0] = c[1] = c[2] = 0.0;
+        for (int a : atoms)
+          for (int k = 0; k < 3; ++k) c[k] += d->xyz_bohr[3 * a + k];
+        for (int k = 0; k < 3; ++k) c[k] /= (double)atoms.size();
+        double r2 = 0.0;
+        for (int a : atoms) {
+          double q = 0.0;
+          for (int k = 0; k < 3; ++k) q += (d->xyz_bohr[3 * a + k] - c[k]) * (d->xyz_bohr[3 * a + k] - c[k]);
+          r2 = std::max(r2, q);
+        }
+        c[3] = std::sqrt(r2);
+      };
+      std::vector<std::vector<int>> gat(G), rat(v.n_rb);
+      for (int a = 0; a < na; ++a) {
+        gat[d->atom_group[a]].push_back(a);
+        for (int64_t r = ao_off[a] / RB; r <= (ao_off[a + 1] - 1) / RB; ++r) rat[r].push_back(a);
+      }
+      std::vector<double> gs((size_t)G * 4, 0.0), rs((size_t)v.n_rb * 4, 0.0);
+      for (int g = 0; g < G; ++g)
+        if (!gat[g].empty()) sphere(gat[g], &gs[4 * (size_t)g]);
+      for (int r = 0; r < v.n_rb; ++r) sphere(rat[r], &rs[4 * (size_t)r]);
+      auto gap = [&](int g, int r) {
+        const double* a = &gs[4 * (size_t)g];
+        const double* b = &rs[4 * (size_t)r];
+        const double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+        return std::sqrt(dx * dx + dy * dy + dz * dz) - a[3] - b[3];
+      };
+      std::vector<double> reach(G, 0.0);
+      for (int j = 0; j < v.n_mo; ++j) {
+        const int g = d->mo_group[j];
+        int last = -1;
+        for (int64_t t = cp[j]; t < cp[j + 1]; ++t) {
+          const int r = d->c0_row[t] / RB;
+          if (r == last || d->c0_val[t] == 0.0) continue;
+          last = r;
+          reach[g] = std::max(reach[g], gap(g, r));
+        }
+      }
+      for (int g = 0; g < G; ++g) {
+        if (gat[g].empty()) continue;
+        const double R = reach[g] + d->slot_margin_bohr;
+        for (int r = 0; r < v.n_rb; ++r) {
+          if (gap(g, r) < R) {
+            if (ns >= INT32_MAX) fail(SSCF_E_CAPACITY, "more than 2^31 tile slots");
+            slot[(size_t)g * v.n_rb + r] = (int)ns++;
+          }
+        }
+      }
+    }
+    x->n_slots = (size_t)std::max<int64_t>(ns, 1);
+    x->slot = x->upload(slot.data(), slot.size());
+    v.slot = x->slot;
+    // the pools of Y = X C: every row block that X's pattern links to a row block where C has
+    // a slot (Y never has a nonzero elsewhere)
+    std::vector<int> slotY(ntiles, -1);
+    int64_t nsy = 0;
+    if (!(d->slot_margin_bohr > 0.0)) {
+      slotY = slot;
+      nsy = ns;
+    } else {
+      for (int g = 0; g < G; ++g) {
+        const int* sg = &slot[(size_t)g * v.n_rb];
+        for (int r = 0; r < v.n_rb; ++r) {
+          bool need = false;
+          for (int k = xs_ptr[r]; k < xs_ptr[r + 1] && !need; ++k) need = sg[xs_col[k]] >= 0;
+          if (need) {
+            if (nsy >= INT32_MAX) fail(SSCF_E_CAPACITY, "more than 2^31 tile slots");
+            slotY[(size_t)g * v.n_rb + r] = (int)nsy++;
+          }
+        }
+      }
+    }
+    x->n_slots_y = (size_t)std::max<int64_t>(nsy, 1);
+    x->slotY = x->upload(slotY.data(), slotY.size());
+    v.slotY = x->slotY;
+  }
+  const size_t nslot = x->n_slots, nslot_y = x->n_slots_y;
   for (int b = 0; b < 2; ++b) {
-    x->C[b] = x->dalloc<double>(ntiles * tile_elems);
-    HIPC(hipMemsetAsync(x->C[b], 0, ntiles * tile_elems * sizeof(double), s));
+    x->C[b] = x->dalloc<double>(nslot * tile_elems);
+    HIPC(hipMemsetAsync(x->C[b], 0, nslot * tile_elems * sizeof(double), s));
     x->actC[b] = x->dalloc<uint8_t>(ntiles);
     HIPC(hipMemsetAsync(x->actC[b], 0, ntiles, s));
     x->listC[b] = x->dalloc<int>(ntiles);
@@ -787,7 +889,7 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
     x->cntC[b] = x->dalloc<int>(G);
     HIPC(hipMemsetAsync(x->cntC[b], 0, sizeof(int) * G, s));
   }
-  x->Y = x->dalloc<double>(ntiles * tile_elems);
+  x->Y = x->dalloc<double>(nslot_y * tile_elems);
   x->actY = x->dalloc<uint8_t>(ntiles);
   x->ymask = x->dalloc<unsigned int>(ntiles);
   x->listY = x->dalloc<int>(ntiles);
@@ -814,7 +916,7 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
   x->upd = x->dalloc<uint8_t>((size_t)G * v.W);
   x->pair_sel = x->dalloc<uint8_t>(x->n_pairs);
   x->rmask = x->dalloc<uint8_t>((size_t)x->n_pairs * 2 * v.W);
-  x->pcidx = x->dalloc<uint8_t>(ntiles * v.W);
+  x->pcidx = x->dalloc<uint8_t>(nslot_y * v.W);
   x->pncol = x->dalloc<uint8_t>(ntiles);
   {
     double* z = x->dalloc<double>(ZERO_DOUBLES);
@@ -839,8 +941,8 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
   x->rot_slot = x->dalloc<int2>((size_t)x->n_blocks * per);
   if (x->precision == SSCF_FP32_MIXED) {
     x->H32 = x->dalloc<float>(nxe);
-    x->Y32 = x->dalloc<float>(ntiles * tile_elems);
-    x->C32 = x->dalloc<float>(ntiles * tile_elems);
+    x->Y32 = x->dalloc<float>(nslot_y * tile_elems);
+    x->C32 = x->dalloc<float>(nslot * tile_elems);
     x->R32 = x->dalloc<float>((size_t)x->n_blocks * v.W * v.W);
   } else {
     x->Rrot = x->dalloc<double>((size_t)x->n_blocks * v.W * v.W);
@@ -865,6 +967,7 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
   x->rowq = x->dalloc<double>(v.n_ao);
   x->sd = x->dalloc<Scalars>(1);
   HIPC(hipMemsetAsync(x->sd, 0, sizeof(Scalars), s));
+  v.cap_err = &x->sd->cap_err;
   x->pctr = x->dalloc<unsigned long long>(SSCF_N_KERNEL_CLASSES);
   HIPC(hipMemsetAsync(x->pctr, 0, sizeof(unsigned long long) * SSCF_N_KERNEL_CLASSES, s));
   if (x->count) {
@@ -872,8 +975,8 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
     x->w_xrow = x->dalloc<int>((size_t)v.n_rb * RB);
     x->w_colnnz = x->dalloc<int>((size_t)G * v.W);
     x->w_nsel = x->dalloc<int>((size_t)G * v.W);
-    x->w_mC = x->dalloc<ulonglong2>(ntiles * RB);
-    x->w_mY = x->dalloc<ulonglong2>(ntiles * RB);
+    x->w_mC = x->dalloc<ulonglong2>(nslot * RB);
+    x->w_mY = x->dalloc<ulonglong2>(nslot_y * RB);
   }
 
   // C0 into the tiles
@@ -886,7 +989,7 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
     double* dval = x->upload(d->c0_val, nnz0);
     int* dpanel = x->upload(mo_panel.data(), v.n_mo);
     int* dcolm = x->upload(mo_col.data(), v.n_mo);
-    launch_scatter_c0(v, (int)nnz0, dcol, drow, dval, dpanel, dcolm, x->C[0], x->actC[0], x->cmask[0], s);
+    launch_scatter_c0(v, (int)nnz0, dcol, drow, dval, dpanel, dcolm, x->C[0], x->actC[0], x->cmask[0], v.cap_err, s);
     x->cur = 0;
     x->rebuild_list(0);
     x->dfree(dcol); x->dfree(drow); x->dfree(dval); x->dfree(dpanel); x->dfree(dcolm);
@@ -1085,7 +1188,8 @@ static sscf_status guarded(sscf_ctx* x, Fn&& fn) {
   } catch (const Fail& f) {
     x->counting = false;
     x->err = f.msg;
-    if (f.code == SSCF_E_HIP) x->failed = true;
+    // the state is not a complete step any more after a runtime or capacity failure
+    if (f.code == SSCF_E_HIP || f.code == SSCF_E_CAPACITY) x->failed = true;
     return f.code;
   } catch (const std::exception& e) {
     x->err = e.what();
@@ -1598,6 +1702,18 @@ sscf_status sscf_orthonormalize(sscf_ctx* x, int32_t occ_only, sscf_step_info* o
   });
 }
 
+sscf_status sscf_memory_info(const sscf_ctx* x, size_t* device_bytes, int64_t* tile_slots, int64_t* tile_slots_y,
+                             int64_t* tiles) {
+  if (!x || !device_bytes || !tile_slots || !tile_slots_y || !tiles) return SSCF_E_INVALID_ARG;
+  size_t b = 0;
+  for (size_t n : x->owned_bytes) b += n;
+  *device_bytes = b;
+  *tile_slots = (int64_t)x->n_slots;
+  *tile_slots_y = (int64_t)x->n_slots_y;
+  *tiles = (int64_t)x->v.G * x->v.n_rb;
+  return SSCF_OK;
+}
+
 sscf_status sscf_get_energy(const sscf_ctx* x, double* e) {
   if (!x || !e) return SSCF_E_INVALID_ARG;
   *e = x->E;
@@ -1625,7 +1741,7 @@ sscf_status sscf_get_density(const sscf_ctx* cx, double* p_val, size_t n_val) {
   return guarded(x, [&] {
     if (!x->pblk) x->pblk = x->dalloc<double>((size_t)x->v.nbx * 256);
     if (!x->pval) x->pval = x->dalloc<double>(x->n_val);
-    launch_density_blocks(x->v, x->C[x->cur], x->actC[x->cur], x->C[x->cur], x->actC[x->cur], x->pblk, x->stream);
+    launch_density_blocks(x->v, x->C[x->cur], x->actC[x->cur], x->C[x->cur], x->actC[x->cur], false, x->pblk, x->stream);
     launch_gather(x->val_map, x->n_val, x->pblk, x->pval, x->stream);
     HIPC(hipMemcpyAsync(p_val, x->pval, sizeof(double) * x->n_val, hipMemcpyDeviceToHost, x->stream));
     x->sync();
@@ -1670,7 +1786,9 @@ sscf_status sscf_get_mo_coefficients(const sscf_ctx* cx, int64_t* colptr, int32_
     const View& v = x->v;
     const size_t ntiles = (size_t)v.G * v.n_rb;
     std::vector<uint8_t> act(ntiles);
+    std::vector<int> hslot(ntiles);
     HIPC(hipMemcpyAsync(act.data(), x->actC[x->cur], ntiles, hipMemcpyDeviceToHost, x->stream));
+    HIPC(hipMemcpyAsync(hslot.data(), x->slot, sizeof(int) * ntiles, hipMemcpyDeviceToHost, x->stream));
     x->sync();
     std::vector<std::vector<std::pair<int32_t, double>>> cols(v.n_mo);
     std::vector<double> tile((size_t)RB * v.W);
@@ -1678,7 +1796,7 @@ sscf_status sscf_get_mo_coefficients(const sscf_ctx* cx, int64_t* colptr, int32_
       for (int r = 0; r < v.n_rb; ++r) {
         const size_t t = (size_t)g * v.n_rb + r;
         if (!act[t]) continue;
-        HIPC(hipMemcpyAsync(tile.data(), x->C[x->cur] + t * RB * v.W, sizeof(double) * RB * v.W,
+        HIPC(hipMemcpyAsync(tile.data(), x->C[x->cur] + (size_t)hslot[t] * RB * v.W, sizeof(double) * RB * v.W,
                             hipMemcpyDeviceToHost, x->stream));
         x->sync();
         for (int k = 0; k < RB; ++k)

@@ -6,8 +6,9 @@
 //  * The MOs of MO group g (section 3.2) form panel g of W columns: occupied
 //    MOs in columns [0, OW), virtual MOs in [OW, OW + VW) = [OW, W); unused
 //    columns are zero.  W, OW, VW are multiples of 16.
-//  * C is stored with dense capacity: tile (g, r) holds rows 16 r .. 16 r + 15
-//    of panel g as a row-major 16 x W block at C + (g * n_rb + r) * 16 W.
+//  * C is stored as a pool of tiles: tile (g, r) holds rows 16 r .. 16 r + 15 of
+//    panel g as a row-major 16 x W block at C + slot[g * n_rb + r] * 16 W; the slot
+//    table gives every tile a slot (dense capacity) or only those near the group.
 //    act[g * n_rb + r] tells whether the tile may hold nonzeros; an inactive C
 //    tile is all zeros.  list[g * n_rb + t], t < cnt[g], are the active row
 //    blocks of panel g in increasing order.
@@ -54,6 +55,7 @@ struct Scalars {
   int tie_n;                        // tie keys collected
   double e_band, e_coul;
   double eta;
+  int cap_err;                      // a nonzero fell on a tile without a slot (sticky)
 };
 
 struct View {
@@ -71,6 +73,14 @@ struct View {
   const int* xs_row;
   // ZERO_DOUBLES zero doubles: the target of loads that are known to give zero
   const double* zeros;
+  // tile capacity: slot[g * n_rb + r] is the slot of tile (g, r) in the pools of C and its FP32
+  // copy (n_slots tiles of 16 x W each), -1 when the tile has no slot (then it is zero and must
+  // stay so: a nonzero landing there sets *cap_err).  slotY does the same for the products
+  // Y = X C (and what shares their pools): its tiles are the row blocks that X's pattern links
+  // to a tile of C with a slot, so a product never falls outside it.
+  const int* slot;
+  const int* slotY;
+  int* cap_err;
 };
 
 // ---- launchers (sscf_kernels.hip) ------------------------------------------------------
@@ -79,7 +89,7 @@ void launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t s);
 void launch_fill_i32(int* p, size_t n, int v, hipStream_t s);
 void launch_scatter_c0(const View& v, int nnz, const int64_t* colptr_expanded_col, const int* row,
                        const double* val, const int* mo_panel, const int* mo_col, double* C,
-                       uint8_t* act, unsigned int* cmask, hipStream_t s);
+                       uint8_t* act, unsigned int* cmask, int* cap_err, hipStream_t s);
 void launch_dilate(const View& v, const uint8_t* actC, uint8_t* actY, hipStream_t s);
 void launch_list(const View& v, const uint8_t* act, int* list, int* cnt, hipStream_t s);
 void launch_spmm(const View& v, const double* X, const double* C, const uint8_t* actC,
@@ -104,8 +114,11 @@ void launch_scale_c(const View& v, double* C, const int* listC, const int* cntC,
 void launch_mark_selected(const View& v, int n_pairs, const int* pg, const int* ph, const double* D,
                           const Scalars* sd, uint8_t* pair_sel, uint8_t* upd, uint8_t* rmask, int* nsel,
                           hipStream_t s);
+// act_new = support of C after the combinations of the selected pairs.  With mask, only the tiles
+// where mask is set (no capacity test); without, a tile with no slot is marked 2 (a tile the
+// combination computes only to check that it stays zero).
 void launch_update_support(const View& v, const uint8_t* actC, const int* gn_ptr, const int* gn,
-                           const int* pair_of, const uint8_t* pair_sel, uint8_t* act_new,
+                           const int* pair_of, const uint8_t* pair_sel, const uint8_t* mask, uint8_t* act_new,
                            hipStream_t s);
 void launch_clear_tiles(const View& v, double* C, uint8_t* act, unsigned int* cmask,
                         const int* list, const int* cnt, hipStream_t s);
@@ -181,8 +194,9 @@ void launch_atom_charges(const View& v, const int64_t* ao_off, const double* row
 void launch_sum_band(const View& v, const double* d, const int* pnocc, Scalars* sd, hipStream_t s);
 void launch_sum_coul(const View& v, int scc, const double* dq, const double* Q, Scalars* sd,
                      hipStream_t s);
+// B_is_y: B lives in the pool of Y (slotY), else in that of C
 void launch_density_blocks(const View& v, const double* A, const uint8_t* actA, const double* B,
-                           const uint8_t* actB, double* P, hipStream_t s);
+                           const uint8_t* actB, bool B_is_y, double* P, hipStream_t s);
 void launch_grad_assemble(const View& v, int64_t n_val, const int64_t* map, const double* P, const double* Wb,
                           const double* Q, int qterm, double* dX, double* dS, hipStream_t s);
 void launch_grad_onsite(const View& v, const int64_t* ao_off, const int* xs_diag, const double* P, double* out,
@@ -192,11 +206,12 @@ void launch_apply_occ(const View& v, const double* C, const uint8_t* actC, const
                       const int* cntZ, double* Z, hipStream_t s);
 // ---- work counting (sscf_count.hip) --------------------------------------------------------
 void launch_cnt_xrow(const View& v, const void* X, bool fp32, int* xrow, unsigned long long* tot, hipStream_t s);
-void launch_cnt_tiles(const View& v, const void* T, bool fp32, const int* list, const int* cnt, int c0, int c1,
-                      const int* weight, int* colnnz, unsigned long long* nnz, unsigned long long* wsum,
+// is_y: T lives in the pool of Y (slotY), else in that of C
+void launch_cnt_tiles(const View& v, const void* T, bool fp32, bool is_y, const int* list, const int* cnt, int c0,
+                      int c1, const int* weight, int* colnnz, unsigned long long* nnz, unsigned long long* wsum,
                       hipStream_t s);
-void launch_row_masks(const View& v, const void* T, bool fp32, const int* list, const int* cnt, ulonglong2* masks,
-                      hipStream_t s);
+void launch_row_masks(const View& v, const void* T, bool fp32, bool is_y, const int* list, const int* cnt,
+                      ulonglong2* masks, hipStream_t s);
 void launch_cnt_pairs(const View& v, int n_items, const int* ig, const int* ih, const int* listC, const int* cntC,
                       const uint8_t* actY, const ulonglong2* mC, const ulonglong2* mY, int a0, int a1, int b0,
                       int b1, int tri, unsigned long long* out, hipStream_t s);

@@ -98,23 +98,28 @@ void launch_scatter(const int64_t* map, int64_t n, const double* src, double* ds
 
 // C0 (one entry per thread) into the tiles
 __global__ void k_scatter_c0(int nnz, const int64_t* col_of, const int* row, const double* val,
-                             const int* mo_panel, const int* mo_col, int n_rb, int W, double* C,
-                             uint8_t* act, unsigned int* cmask) {
+                             const int* mo_panel, const int* mo_col, int n_rb, int W, const int* slot, double* C,
+                             uint8_t* act, unsigned int* cmask, int* cap_err) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nnz) return;
   const int j = (int)col_of[e];
   const int mu = row[e];
   const int g = mo_panel[j];
   const size_t tile = (size_t)g * n_rb + mu / RB;
-  C[(tile * RB + (mu % RB)) * W + mo_col[j]] = val[e];
+  const int sl = slot[tile];
+  if (sl < 0) {                                 // outside the tile capacity
+    *cap_err = 1;
+    return;
+  }
+  C[((size_t)sl * RB + (mu % RB)) * W + mo_col[j]] = val[e];
   act[tile] = 1;
   if (val[e] != 0.0) atomicOr(&cmask[tile], 1u << (mo_col[j] >> 4));
 }
 void launch_scatter_c0(const View& v, int nnz, const int64_t* col_of, const int* row, const double* val,
                        const int* mo_panel, const int* mo_col, double* C, uint8_t* act, unsigned int* cmask,
-                       hipStream_t s) {
+                       int* cap_err, hipStream_t s) {
   if (nnz) hipLaunchKernelGGL(k_scatter_c0, dim3(nblk(nnz, 256)), dim3(256), 0, s, nnz, col_of, row, val,
-                              mo_panel, mo_col, v.n_rb, v.W, C, act, cmask);
+                              mo_panel, mo_col, v.n_rb, v.W, v.slot, C, act, cmask, cap_err);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -122,8 +127,8 @@ void launch_scatter_c0(const View& v, int nnz, const int64_t* col_of, const int*
 // sorted lists of active row blocks
 // ---------------------------------------------------------------------------------------
 
-__global__ void k_dilate(int G, int n_rb, const int* xs_ptr, const int* xs_col, const uint8_t* actC,
-                         uint8_t* actY) {
+__global__ void k_dilate(int G, int n_rb, const int* xs_ptr, const int* xs_col, const int* slotY, const uint8_t* actC,
+                         uint8_t* actY, int* cap_err) {
   const size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   if (idx >= (size_t)G * n_rb) return;
   const int g = (int)(idx / n_rb), r = (int)(idx % n_rb);
@@ -131,11 +136,16 @@ __global__ void k_dilate(int G, int n_rb, const int* xs_ptr, const int* xs_col, 
   uint8_t any = 0;
   for (int k = xs_ptr[r]; k < xs_ptr[r + 1]; ++k)
     if (a[xs_col[k]]) { any = 1; break; }
+  if (any && slotY[idx] < 0) {                  // cannot happen while C keeps to its slots
+    *cap_err = 1;
+    any = 0;
+  }
   actY[idx] = any;
 }
 void launch_dilate(const View& v, const uint8_t* actC, uint8_t* actY, hipStream_t s) {
   const size_t n = (size_t)v.G * v.n_rb;
-  hipLaunchKernelGGL(k_dilate, dim3(nblk(n, 256)), dim3(256), 0, s, v.G, v.n_rb, v.xs_ptr, v.xs_col, actC, actY);
+  hipLaunchKernelGGL(k_dilate, dim3(nblk(n, 256)), dim3(256), 0, s, v.G, v.n_rb, v.xs_ptr, v.xs_col, v.slotY, actC,
+                     actY, v.cap_err);
 }
 
 __global__ void __launch_bounds__(256) k_list(int n_rb, const uint8_t* act, int* list, int* cnt) {
@@ -206,7 +216,9 @@ __device__ __forceinline__ double ld_or_zero(bool on, const double* p, const dou
 // ---------------------------------------------------------------------------------------
 
 template <int MW, int NW>
-__global__ void __launch_bounds__(256) k_pair(int n_rb, int W, const int* __restrict__ perm, int maxc,
+__global__ void __launch_bounds__(256) k_pair(int n_rb, int W, const int* __restrict__ slot,
+                                              const int* __restrict__ slotY,
+                                              const int* __restrict__ perm, int maxc,
                                               const int* __restrict__ pg,
                                               const int* __restrict__ ph, const double* __restrict__ C,
                                               const int* __restrict__ listC, const int* __restrict__ cntC,
@@ -254,8 +266,8 @@ __global__ void __launch_bounds__(256) k_pair(int n_rb, int W, const int* __rest
         const int r = __shfl(rr, j);
         const unsigned int mj = __builtin_amdgcn_readfirstlane(__shfl((int)mab, j));
         const unsigned int ma = mj & 0xffffu, mb = mj >> 16;
-        const double* Ct = C + (gb + r) * (size_t)(RB * W) + row_off + mt0 * 16 + lr;
-        const double* Yt = Y + (hb + r) * (size_t)(RB * W) + col_off + nt0 * 16 + lr;
+        const double* Ct = C + (size_t)slot[gb + r] * (RB * W) + row_off + mt0 * 16 + lr;
+        const double* Yt = Y + (size_t)slotY[hb + r] * (RB * W) + col_off + nt0 * 16 + lr;
         double a[4][MW], b[4][NW];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -300,21 +312,21 @@ void launch_pair(const View& v, int n_pairs, const int* perm, int maxc, const in
   const int m = mw > nw ? mw : nw;
   dim3 grid(N_XCD * maxc), blk(256);
   if (m <= 1)
-    hipLaunchKernelGGL((k_pair<1, 1>), grid, blk, 0, s, v.n_rb, v.W, perm, maxc, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+    hipLaunchKernelGGL((k_pair<1, 1>), grid, blk, 0, s, v.n_rb, v.W, v.slot, v.slotY, perm, maxc, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
   else if (m <= 2)
-    hipLaunchKernelGGL((k_pair<2, 2>), grid, blk, 0, s, v.n_rb, v.W, perm, maxc, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+    hipLaunchKernelGGL((k_pair<2, 2>), grid, blk, 0, s, v.n_rb, v.W, v.slot, v.slotY, perm, maxc, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
   else if (m <= 3)
-    hipLaunchKernelGGL((k_pair<3, 3>), grid, blk, 0, s, v.n_rb, v.W, perm, maxc, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+    hipLaunchKernelGGL((k_pair<3, 3>), grid, blk, 0, s, v.n_rb, v.W, v.slot, v.slotY, perm, maxc, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
   else
-    hipLaunchKernelGGL((k_pair<4, 4>), grid, blk, 0, s, v.n_rb, v.W, perm, maxc, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+    hipLaunchKernelGGL((k_pair<4, 4>), grid, blk, 0, s, v.n_rb, v.W, v.slot, v.slotY, perm, maxc, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
 }
 
 // per-column dot products d[g][c] = sum_r sum_k C[g][r][k][c] Y[g][r][k][c]
 // The active row blocks of panel g are split into CD_SPLIT strided parts, one workgroup each;
 // the parts' sums are added in a fixed order by k_coldot_sum.
 
-__global__ void k_coldot(int n_rb, int W, const double* C, const int* listC, const int* cntC, const double* Y,
-                         const uint8_t* actY, double* part) {
+__global__ void k_coldot(int n_rb, int W, const int* slot, const int* slotY, const double* C, const int* listC,
+                         const int* cntC, const double* Y, const uint8_t* actY, double* part) {
   const int g = blockIdx.x, sp = blockIdx.y, c = threadIdx.x;
   if (c >= W) return;
   const size_t gb = (size_t)g * n_rb;
@@ -322,8 +334,8 @@ __global__ void k_coldot(int n_rb, int W, const double* C, const int* listC, con
   for (int t = sp; t < cntC[g]; t += CD_SPLIT) {
     const int r = listC[gb + t];
     if (!actY[gb + r]) continue;
-    const double* Ct = C + (gb + r) * (size_t)(RB * W) + c;
-    const double* Yt = Y + (gb + r) * (size_t)(RB * W) + c;
+    const double* Ct = C + (size_t)slot[gb + r] * (RB * W) + c;
+    const double* Yt = Y + (size_t)slotY[gb + r] * (RB * W) + c;
 #pragma unroll
     for (int k = 0; k < RB; ++k) s += Ct[k * W] * Yt[k * W];
   }
@@ -339,7 +351,7 @@ __global__ void k_coldot_sum(size_t n, const double* part, double* out) {
 void launch_coldot(const View& v, const double* C, const int* listC, const int* cntC, const double* Y,
                    const uint8_t* actY, double* part, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_coldot, dim3(v.G, CD_SPLIT), dim3(v.W <= 64 ? 64 : (v.W <= 128 ? 128 : 256)), 0, s, v.n_rb,
-                     v.W, C, listC, cntC, Y, actY, part);
+                     v.W, v.slot, v.slotY, C, listC, cntC, Y, actY, part);
   const size_t n = (size_t)v.G * v.W;
   hipLaunchKernelGGL(k_coldot_sum, dim3(nblk(n, 256)), dim3(256), 0, s, n, part, out);
 }
@@ -416,17 +428,17 @@ void launch_normalize_d(const View& v, int n_pairs, const int* pg, const int* ph
                        occ_only, sd);
 }
 
-__global__ void __launch_bounds__(256) k_scale_c(int n_rb, int W, double* C, const int* listC, const int* cntC,
-                                                 const double* sc) {
+__global__ void __launch_bounds__(256) k_scale_c(int n_rb, int W, const int* slot, double* C, const int* listC,
+                                                 const int* cntC, const double* sc) {
   const int g = blockIdx.y, t = blockIdx.x;
   if (t >= cntC[g]) return;
   const size_t tile = (size_t)g * n_rb + listC[(size_t)g * n_rb + t];
-  double* Ct = C + tile * (size_t)(RB * W);
+  double* Ct = C + (size_t)slot[tile] * (RB * W);
   const double* s = sc + (size_t)g * W;
   for (int e = threadIdx.x; e < RB * W; e += 256) Ct[e] = Ct[e] / s[e % W];
 }
 void launch_scale_c(const View& v, double* C, const int* listC, const int* cntC, const double* sc, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_c, dim3(v.n_rb, v.G), dim3(256), 0, s, v.n_rb, v.W, C, listC, cntC, sc);
+  hipLaunchKernelGGL(k_scale_c, dim3(v.n_rb, v.G), dim3(256), 0, s, v.n_rb, v.W, v.slot, C, listC, cntC, sc);
 }
 
 // Per pair: flag it when any |D| >= 1e-3 eta, flag the MOs that take part, and record for
@@ -478,44 +490,52 @@ void launch_mark_selected(const View& v, int n_pairs, const int* pg, const int* 
                        nsel);
 }
 
-__global__ void k_update_support(int G, int n_rb, const uint8_t* actC, const int* gn_ptr, const int* gn,
-                                 const int* pair_of, const uint8_t* pair_sel, uint8_t* act_new) {
+__global__ void k_update_support(int G, int n_rb, const int* slot, const uint8_t* actC, const int* gn_ptr, const int* gn,
+                                 const int* pair_of, const uint8_t* pair_sel, const uint8_t* mask, uint8_t* act_new) {
   const size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   if (idx >= (size_t)G * n_rb) return;
   const int g = (int)(idx / n_rb), r = (int)(idx % n_rb);
   uint8_t a = actC[idx];
+  if (mask && !mask[idx]) {
+    act_new[idx] = 0;
+    return;
+  }
   for (int k = gn_ptr[g]; k < gn_ptr[g + 1] && !a; ++k) {
     const int h = gn[k];
     if (pair_sel[pair_of[(size_t)g * G + h]] && actC[(size_t)h * n_rb + r]) a = 1;
   }
+  // no slot: the combination there is computed and must come out zero (its values are the
+  // neighbours' tails times D_sel, mostly below the cut)
+  if (a && !mask && slot[idx] < 0) a = 2;
   act_new[idx] = a;
 }
 void launch_update_support(const View& v, const uint8_t* actC, const int* gn_ptr, const int* gn, const int* pair_of,
-                           const uint8_t* pair_sel, uint8_t* act_new, hipStream_t s) {
+                           const uint8_t* pair_sel, const uint8_t* mask, uint8_t* act_new, hipStream_t s) {
   const size_t n = (size_t)v.G * v.n_rb;
-  hipLaunchKernelGGL(k_update_support, dim3(nblk(n, 256)), dim3(256), 0, s, v.G, v.n_rb, actC, gn_ptr, gn, pair_of,
-                     pair_sel, act_new);
+  hipLaunchKernelGGL(k_update_support, dim3(nblk(n, 256)), dim3(256), 0, s, v.G, v.n_rb, v.slot, actC, gn_ptr, gn,
+                     pair_of, pair_sel, mask, act_new);
 }
 
-__global__ void __launch_bounds__(256) k_clear_tiles(int n_rb, int W, double* C, uint8_t* act, unsigned int* cmask,
-                                                     const int* list, const int* cnt) {
+__global__ void __launch_bounds__(256) k_clear_tiles(int n_rb, int W, const int* slot, double* C, uint8_t* act,
+                                                     unsigned int* cmask, const int* list, const int* cnt) {
   const int g = blockIdx.y, t = blockIdx.x;
   if (t >= cnt[g]) return;
   const size_t tile = (size_t)g * n_rb + list[(size_t)g * n_rb + t];
-  double* Ct = C + tile * (size_t)(RB * W);
+  double* Ct = C + (size_t)slot[tile] * (RB * W);
   for (int e = threadIdx.x; e < RB * W; e += 256) Ct[e] = 0.0;
   if (threadIdx.x == 0) { act[tile] = 0; cmask[tile] = 0u; }
 }
 void launch_clear_tiles(const View& v, double* C, uint8_t* act, unsigned int* cmask, const int* list, const int* cnt,
                         hipStream_t s) {
-  hipLaunchKernelGGL(k_clear_tiles, dim3(v.n_rb, v.G), dim3(256), 0, s, v.n_rb, v.W, C, act, cmask, list, cnt);
+  hipLaunchKernelGGL(k_clear_tiles, dim3(v.n_rb, v.G), dim3(256), 0, s, v.n_rb, v.W, v.slot, C, act, cmask, list, cnt);
 }
 
 // ---------------------------------------------------------------------------------------
 // Column scans of C tiles (one wave per listed tile; lane l owns columns l and l + 64).
 //  * k_tile_flags: the activity byte, the 16-column slice mask and (colm, may be NULL) the
 //    nonzero columns of each tile, exactly from its values.
-//  * k_pack_cols: the nonzero columns of each tile packed to the front of its slot in P,
+//  * k_pack_cols: the nonzero columns of each tile packed to the front of its slot in P (a
+//    buffer of the pool of Y, addressed with slotY, whose tiles include all of C's),
 //    column-major (packed column k = the 16 rows of the tile's k-th nonzero column, one
 //    128-byte line), with cidx[tile W + k] its column and ncol[tile] their number.  Only
 //    columns below col_end are packed (the occupied ones in an occupied-only sweep).
@@ -542,7 +562,8 @@ __device__ __forceinline__ void tile_columns(const double* __restrict__ T, int c
 }
 
 template <int NT>
-__global__ void __launch_bounds__(256) k_tile_flags(int G, int n_rb, int nchunk, const double* __restrict__ C,
+__global__ void __launch_bounds__(256) k_tile_flags(int G, int n_rb, int nchunk, const int* __restrict__ slot,
+                                                    const double* __restrict__ C,
                                                     const int* __restrict__ list, const int* __restrict__ cnt,
                                                     uint8_t* __restrict__ act, unsigned int* __restrict__ cmask,
                                                     ulonglong2* __restrict__ colm) {
@@ -555,7 +576,7 @@ __global__ void __launch_bounds__(256) k_tile_flags(int G, int n_rb, int nchunk,
   const size_t tile = (size_t)g * n_rb + list[(size_t)g * n_rb + t];
   double v0[RB], v1[RB];
   bool nz0, nz1;
-  tile_columns<NT>(C + tile * (RB * W), W, v0, v1, nz0, nz1);
+  tile_columns<NT>(C + (size_t)slot[tile] * (RB * W), W, v0, v1, nz0, nz1);
   const unsigned long long b0 = __ballot(nz0), b1 = __ballot(nz1);
   unsigned int cm = 0u;
 #pragma unroll
@@ -571,7 +592,8 @@ __global__ void __launch_bounds__(256) k_tile_flags(int G, int n_rb, int nchunk,
 }
 
 template <int NT>
-__global__ void __launch_bounds__(256) k_pack_cols(int G, int n_rb, int nchunk, const double* __restrict__ C,
+__global__ void __launch_bounds__(256) k_pack_cols(int G, int n_rb, int nchunk, const int* __restrict__ slot,
+                                                   const int* __restrict__ slotP, const double* __restrict__ C,
                                                    const int* __restrict__ list, const int* __restrict__ cnt,
                                                    int col_end, double* __restrict__ P, uint8_t* __restrict__ cidx,
                                                    uint8_t* __restrict__ ncol) {
@@ -585,12 +607,13 @@ __global__ void __launch_bounds__(256) k_pack_cols(int G, int n_rb, int nchunk, 
   const size_t tile = (size_t)g * n_rb + list[(size_t)g * n_rb + t];
   double v0[RB], v1[RB];
   bool nz0, nz1;
-  tile_columns<NT>(C + tile * (RB * W), col_end, v0, v1, nz0, nz1);
+  tile_columns<NT>(C + (size_t)slot[tile] * (RB * W), col_end, v0, v1, nz0, nz1);
   const unsigned long long b0 = __ballot(nz0), b1 = __ballot(nz1);
   const unsigned long long below = (1ull << lane) - 1ull;
   const int c0 = __popcll(b0);
-  double* Pt = P + tile * (RB * W);
-  uint8_t* ct = cidx + tile * W;
+  const size_t sp = (size_t)slotP[tile];
+  double* Pt = P + sp * (RB * W);
+  uint8_t* ct = cidx + sp * W;
   if (nz0) {
     const int k = __popcll(b0 & below);
 #pragma unroll
@@ -611,7 +634,7 @@ void launch_tile_flags(const View& v, const double* C, const int* list, const in
   const int nchunk = (v.n_rb + 3) / 4;
   dim3 grid(xcd_grid(v.G, nchunk)), blk(256);
   switch (v.W / 16) {
-#define SSCF_TF(NT) case NT: hipLaunchKernelGGL(k_tile_flags<NT>, grid, blk, 0, s, v.G, v.n_rb, nchunk, C, list, cnt, act, cmask, colm); break;
+#define SSCF_TF(NT) case NT: hipLaunchKernelGGL(k_tile_flags<NT>, grid, blk, 0, s, v.G, v.n_rb, nchunk, v.slot, C, list, cnt, act, cmask, colm); break;
     SSCF_TF(1) SSCF_TF(2) SSCF_TF(3) SSCF_TF(4) SSCF_TF(5) SSCF_TF(6) SSCF_TF(7) SSCF_TF(8)
 #undef SSCF_TF
   }
@@ -622,7 +645,7 @@ void launch_pack_cols(const View& v, const double* C, const int* list, const int
   const int nchunk = (v.n_rb + 3) / 4;
   dim3 grid(xcd_grid(v.G, nchunk)), blk(256);
   switch (v.W / 16) {
-#define SSCF_PK(NT) case NT: hipLaunchKernelGGL(k_pack_cols<NT>, grid, blk, 0, s, v.G, v.n_rb, nchunk, C, list, cnt, col_end, P, cidx, ncol); break;
+#define SSCF_PK(NT) case NT: hipLaunchKernelGGL(k_pack_cols<NT>, grid, blk, 0, s, v.G, v.n_rb, nchunk, v.slot, v.slotY, C, list, cnt, col_end, P, cidx, ncol); break;
     SSCF_PK(1) SSCF_PK(2) SSCF_PK(3) SSCF_PK(4) SSCF_PK(5) SSCF_PK(6) SSCF_PK(7) SSCF_PK(8)
 #undef SSCF_PK
   }
@@ -643,7 +666,8 @@ void launch_pack_cols(const View& v, const double* C, const int* list, const int
 // zeros.  The sum runs over h in neighbour order and over the packed columns in increasing
 // column order, so the result does not depend on the launch.
 template <int NT>
-__global__ void __launch_bounds__(256) k_ortho_update(int G, int n_rb, int nchunk, const double* __restrict__ C,
+__global__ void __launch_bounds__(256) k_ortho_update(int G, int n_rb, int nchunk, const int* __restrict__ slot,
+                                                      const int* __restrict__ slotP, const double* __restrict__ C,
                                                       const uint8_t* __restrict__ actC,
                                                       const double* __restrict__ P, const uint8_t* __restrict__ cidx,
                                                       const uint8_t* __restrict__ ncol,
@@ -656,7 +680,8 @@ __global__ void __launch_bounds__(256) k_ortho_update(int G, int n_rb, int nchun
                                                       const uint8_t* __restrict__ upd, double cut,
                                                       const int* __restrict__ listN, const int* __restrict__ cntN,
                                                       double* __restrict__ Cn, uint8_t* __restrict__ actN,
-                                                      unsigned int* __restrict__ cmaskN, unsigned long long* ctr) {
+                                                      unsigned int* __restrict__ cmaskN, int* __restrict__ cap_err,
+                                                      unsigned long long* ctr) {
   constexpr int W = NT * 16;
   constexpr int KB = 2;                       // k-steps whose loads go out together
   int chunk;
@@ -693,9 +718,10 @@ __global__ void __launch_bounds__(256) k_ortho_update(int G, int n_rb, int nchun
       const size_t th = (size_t)hc * n_rb + r;
       const double* Dp = (tr ? Dt : D) + (size_t)p * W * W + lr;
       const uint8_t* rm = rmask + ((size_t)p * 2 + (tr ? 1 : 0)) * W;
-      const double* A = P + th * (RB * W) + lr;
+      const size_t sh = (size_t)slotP[th];
+      const double* A = P + sh * (RB * W) + lr;
       // packed column k's index and slice mask live in lane k (k < 64) or lane k - 64
-      const uint8_t* ci = cidx + th * W;
+      const uint8_t* ci = cidx + sh * W;
       const int col0 = lane < nzj ? ci[lane] : 0;
       const int col1 = (W > 64 && lane + 64 < nzj) ? ci[lane + 64] : 0;
       int m0 = lane < nzj ? rm[col0] : 0;
@@ -739,9 +765,32 @@ __global__ void __launch_bounds__(256) k_ortho_update(int G, int n_rb, int nchun
     }
   }
   const size_t tile = (size_t)g * n_rb + r;
+  const int so_i = slot[tile];
+  if (so_i < 0) {
+    // a tile with no slot (listed with activity 2): C is zero there; the combination must
+    // leave it so after the cut, else C has outgrown its capacity
+    int bad = 0;
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+      const bool u = upd[(size_t)g * W + n * 16 + lr] != 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double v = -0.5 * acc[n][q];
+        bad |= (u ? fabs(v) >= cut : v != 0.0);
+      }
+    }
+    if (__ballot(bad) && lane == 0) *cap_err = 1;
+    if (lane == 0) {
+      actN[tile] = 0;
+      cmaskN[tile] = 0u;
+      if (ctr && n_mfma) atomicAdd(ctr, (unsigned long long)n_mfma);
+    }
+    return;
+  }
   const bool own = actC[tile] != 0;
-  const double* Cg = C + tile * (RB * W);
-  double* Co = Cn + tile * (RB * W);
+  const size_t so = (size_t)so_i;
+  const double* Cg = C + so * (RB * W);
+  double* Co = Cn + so * (RB * W);
   unsigned int cm = 0;
 #pragma unroll
   for (int n = 0; n < NT; ++n) {
@@ -773,7 +822,7 @@ void launch_ortho_update(const View& v, const double* C, const uint8_t* actC, co
   const int nchunk = (v.n_rb + 3) / 4;
   dim3 grid(xcd_grid(v.G, nchunk)), blk(256);
   switch (v.W / 16) {
-#define SSCF_UPD(NT) case NT: hipLaunchKernelGGL(k_ortho_update<NT>, grid, blk, 0, s, v.G, v.n_rb, nchunk, C, actC, P, cidx, ncol, gn_ptr, gn, pair_of, pair_sel, D, Dt, rmask, sd, upd, cut, listN, cntN, Cn, actN, cmaskN, ctr); break;
+#define SSCF_UPD(NT) case NT: hipLaunchKernelGGL(k_ortho_update<NT>, grid, blk, 0, s, v.G, v.n_rb, nchunk, v.slot, v.slotY, C, actC, P, cidx, ncol, gn_ptr, gn, pair_of, pair_sel, D, Dt, rmask, sd, upd, cut, listN, cntN, Cn, actN, cmaskN, v.cap_err, ctr); break;
     SSCF_UPD(1) SSCF_UPD(2) SSCF_UPD(3) SSCF_UPD(4) SSCF_UPD(5) SSCF_UPD(6) SSCF_UPD(7) SSCF_UPD(8)
 #undef SSCF_UPD
   }
@@ -1277,9 +1326,10 @@ __global__ void __launch_bounds__(256) k_givens_rb(int G, int n_rb, int W, int O
                                                    const int* __restrict__ roff, const int4* __restrict__ meta,
                                                    const ulonglong2* __restrict__ tmask,
                                                    const int* __restrict__ tcol,
-                                                   const Real* __restrict__ R, double eps, double* C,
-                                                   uint8_t* actC, unsigned int* cmask, ulonglong2* colm,
-                                                   const int* __restrict__ rot_cnt, unsigned long long* wcnt) {
+                                                   const Real* __restrict__ R, double eps, const int* __restrict__ slot,
+                                                   double* C, uint8_t* actC, unsigned int* cmask, ulonglong2* colm,
+                                                   const int* __restrict__ rot_cnt, int* cap_err,
+                                                   unsigned long long* wcnt) {
   typedef typename Mfma<Real>::acc_t acc_t;
   extern __shared__ int4 gv_smem[];
   int4* list_l = gv_smem;                                                   // relevant blocks of the round
@@ -1331,8 +1381,11 @@ __global__ void __launch_bounds__(256) k_givens_rb(int G, int n_rb, int W, int O
         const int nt_n = (T + 15) >> 4;
         const int* tc = tcol + (size_t)b * W;
         const Real* Rb = R + (size_t)b * W * W;
-        double* Cg = C + ((size_t)g * n_rb + rb) * RB * W;
-        double* Ch = C + ((size_t)h * n_rb + rb) * RB * W;
+        // a tile without a slot is all zero and stays so: its columns are never nonzero in
+        // cm_l, so nothing is gathered from it; a nonzero written to it is a capacity error
+        const int sgi = slot[(size_t)g * n_rb + rb], shi = slot[(size_t)h * n_rb + rb];
+        double* Cg = C + (size_t)(sgi < 0 ? 0 : sgi) * RB * W;
+        double* Ch = C + (size_t)(shi < 0 ? 0 : shi) * RB * W;
         // touched columns (two per lane) and whether each is nonzero at rb; the nonzero ones'
         // positions, packed in order, form the K dimension
         const int tcl0 = (lane < T) ? tc[lane] : 0;
@@ -1399,12 +1452,17 @@ __global__ void __launch_bounds__(256) k_givens_rb(int G, int n_rb, int W, int O
           const int col = (j < 64) ? c0 : c1;
           if (n < nt_n && j < T) {
             double* base = (col < OW) ? Cg : Ch;
+            const bool has = (col < OW) ? sgi >= 0 : shi >= 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
               double x = (double)acc[n][q];
               if (fabs(x) < eps) x = 0.0;
-              base[Mfma<Real>::row(lk, q) * W + col] = x;
-              nzc |= x != 0.0;
+              if (has) {
+                base[Mfma<Real>::row(lk, q) * W + col] = x;
+                nzc |= x != 0.0;
+              } else if (x != 0.0) {
+                *cap_err = 1;
+              }
             }
           }
           nzc |= __shfl_xor(nzc, 16);
@@ -1467,8 +1525,8 @@ void launch_givens_rb(const View& v, int n_rounds, const int* roff, const int4* 
   const size_t lds = 256 * sizeof(int4) + 2 * sizeof(unsigned long long) * (size_t)v.G + 4 * 128 + 16;
   switch ((v.W + 15) / 16) {
 #define SSCF_GIV(N) case N: \
-    if (R32) hipLaunchKernelGGL((k_givens_rb<N, float>), dim3(v.n_rb), dim3(256), lds, s, v.G, v.n_rb, v.W, v.OW, n_rounds, roff, meta, tmask, tcol, R32, eps, C, actC, cmask, colm, rot_cnt, wcnt); \
-    else hipLaunchKernelGGL((k_givens_rb<N, double>), dim3(v.n_rb), dim3(256), lds, s, v.G, v.n_rb, v.W, v.OW, n_rounds, roff, meta, tmask, tcol, R, eps, C, actC, cmask, colm, rot_cnt, wcnt); \
+    if (R32) hipLaunchKernelGGL((k_givens_rb<N, float>), dim3(v.n_rb), dim3(256), lds, s, v.G, v.n_rb, v.W, v.OW, n_rounds, roff, meta, tmask, tcol, R32, eps, v.slot, C, actC, cmask, colm, rot_cnt, v.cap_err, wcnt); \
+    else hipLaunchKernelGGL((k_givens_rb<N, double>), dim3(v.n_rb), dim3(256), lds, s, v.G, v.n_rb, v.W, v.OW, n_rounds, roff, meta, tmask, tcol, R, eps, v.slot, C, actC, cmask, colm, rot_cnt, v.cap_err, wcnt); \
     break;
     SSCF_GIV(1) SSCF_GIV(2) SSCF_GIV(3) SSCF_GIV(4) SSCF_GIV(5) SSCF_GIV(6) SSCF_GIV(7) SSCF_GIV(8)
 #undef SSCF_GIV
@@ -1481,7 +1539,8 @@ void launch_givens_rb(const View& v, int n_rounds, const int* roff, const int4* 
 // Row sums are formed panel by panel in increasing order (fixed order).
 // ---------------------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) k_charges_rows(int G, int n_rb, int n_ao, int W, const double* C,
+__global__ void __launch_bounds__(256) k_charges_rows(int G, int n_rb, int n_ao, int W, const int* slot,
+                                                      const int* slotY, const double* C,
                                                       const uint8_t* actC, const double* Y, const uint8_t* actY,
                                                       const double* sc, const int* pnocc, double* rowq) {
   const int rb = blockIdx.x;
@@ -1491,8 +1550,8 @@ __global__ void __launch_bounds__(256) k_charges_rows(int G, int n_rb, int n_ao,
     const size_t tile = (size_t)g * n_rb + rb;
     if (!actC[tile] || !actY[tile]) continue;
     const int no = pnocc[g];
-    const double* Cr = C + (tile * RB + k) * W;
-    const double* Yr = Y + (tile * RB + k) * W;
+    const double* Cr = C + ((size_t)slot[tile] * RB + k) * W;
+    const double* Yr = Y + ((size_t)slotY[tile] * RB + k) * W;
     const double* s = sc + (size_t)g * W;
     double part = 0.0;
     for (int c = l; c < no; c += 16) part += Cr[c] * Yr[c] / s[c];
@@ -1504,8 +1563,8 @@ __global__ void __launch_bounds__(256) k_charges_rows(int G, int n_rb, int n_ao,
 }
 void launch_charges_rows(const View& v, const double* C, const uint8_t* actC, const double* Y, const uint8_t* actY,
                          const double* sc, const int* pnocc, double* rowq, hipStream_t s) {
-  hipLaunchKernelGGL(k_charges_rows, dim3(v.n_rb), dim3(256), 0, s, v.G, v.n_rb, v.n_ao, v.W, C, actC, Y, actY, sc,
-                     pnocc, rowq);
+  hipLaunchKernelGGL(k_charges_rows, dim3(v.n_rb), dim3(256), 0, s, v.G, v.n_rb, v.n_ao, v.W, v.slot, v.slotY, C, actC, Y, actY,
+                     sc, pnocc, rowq);
 }
 
 __global__ void k_atom_charges(int n_atoms, const int64_t* ao_off, const double* rowq, const double* q0, double* q,
@@ -1580,7 +1639,9 @@ void launch_sum_coul(const View& v, int scc, const double* dq, const double* Q, 
 // per 16 x 16 block; MFMA over the occupied columns)
 // ---------------------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) k_density_blocks(int nbx, int G, int n_rb, int W, int OW, const int* xs_row,
+__global__ void __launch_bounds__(256) k_density_blocks(int nbx, int G, int n_rb, int W, int OW, const int* slot,
+                                                        const int* slotB,
+                                                        const int* xs_row,
                                                         const int* xs_col, const double* A, const uint8_t* actA,
                                                         const double* B, const uint8_t* actB, double* P) {
   const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -1591,8 +1652,8 @@ __global__ void __launch_bounds__(256) k_density_blocks(int nbx, int G, int n_rb
   for (int g = 0; g < G; ++g) {
     const size_t tr = (size_t)g * n_rb + r, tc = (size_t)g * n_rb + c;
     if (!actA[tr] || !actB[tc]) continue;
-    const double* At = A + tr * (RB * W);
-    const double* Bt = B + tc * (RB * W);
+    const double* At = A + (size_t)slot[tr] * (RB * W);
+    const double* Bt = B + (size_t)slotB[tc] * (RB * W);
     for (int s = 0; s < OW / 4; ++s) acc = mfma64(At[lr * W + 4 * s + lk], Bt[lr * W + 4 * s + lk], acc);
   }
 #pragma unroll
@@ -1601,9 +1662,9 @@ __global__ void __launch_bounds__(256) k_density_blocks(int nbx, int G, int n_rb
 // 2 A_occ B_occ^T on the 16 x 16 blocks of the S pattern: the density P (A = B = C) or
 // W = 2 C_occ Z_occ^T (B = Z) of the energy gradient
 void launch_density_blocks(const View& v, const double* A, const uint8_t* actA, const double* B, const uint8_t* actB,
-                           double* P, hipStream_t s) {
+                           bool B_is_y, double* P, hipStream_t s) {
   hipLaunchKernelGGL(k_density_blocks, dim3((v.nbx + 3) / 4), dim3(256), 0, s, v.nbx, v.G, v.n_rb, v.W, v.OW,
-                     v.xs_row, v.xs_col, A, actA, B, actB, P);
+                     v.slot, B_is_y ? v.slotY : v.slot, v.xs_row, v.xs_col, A, actA, B, actB, P);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1652,10 +1713,12 @@ void launch_grad_onsite(const View& v, const int64_t* ao_off, const int* xs_diag
 // ---------------------------------------------------------------------------------------
 // Energy gradient (differentiation form): Z_g[r] = sum_{h ~ g} C_h,occ[r] F(h, g) with
 // F(h, g) = C_h,occ^T H C_g,occ (OW x OW; FA holds the blocks with rows = MOs of pg[p],
-// FB those with rows = MOs of ph[p]).  One wave per output tile, occupied columns only.
+// FB those with rows = MOs of ph[p]).  One wave per output tile, occupied columns only; Z lives
+// in the pool of Y.
 // ---------------------------------------------------------------------------------------
 template <int NO>
-__global__ void __launch_bounds__(256) k_apply_occ(int G, int n_rb, int W, int nchunk, const double* __restrict__ C,
+__global__ void __launch_bounds__(256) k_apply_occ(int G, int n_rb, int W, int nchunk, const int* __restrict__ slot,
+                                                   const int* __restrict__ slotZ, const double* __restrict__ C,
                                                    const uint8_t* __restrict__ actC, const int* __restrict__ gn_ptr,
                                                    const int* __restrict__ gn, const int* __restrict__ pair_of,
                                                    const int* __restrict__ pg, const double* __restrict__ FA,
@@ -1679,7 +1742,7 @@ __global__ void __launch_bounds__(256) k_apply_occ(int G, int n_rb, int W, int n
     if (!actC[th]) continue;
     const int p = pair_of[(size_t)g * G + h];
     const double* Fp = ((pg[p] == h) ? FA : FB) + (size_t)p * OW * OW + lr;
-    const double* Ch = C + th * (RB * W) + lr * W + lk;
+    const double* Ch = C + (size_t)slot[th] * (RB * W) + lr * W + lk;
 #pragma unroll 4
     for (int s = 0; s < OW / 4; ++s) {
       const double a = Ch[4 * s];
@@ -1687,7 +1750,7 @@ __global__ void __launch_bounds__(256) k_apply_occ(int G, int n_rb, int W, int n
       for (int n = 0; n < NO; ++n) acc[n] = mfma64(a, Fp[(4 * s + lk) * OW + n * 16], acc[n]);
     }
   }
-  double* Zt = Z + ((size_t)g * n_rb + r) * (RB * W);
+  double* Zt = Z + (size_t)slotZ[(size_t)g * n_rb + r] * (RB * W);
 #pragma unroll
   for (int n = 0; n < NO; ++n)
 #pragma unroll
@@ -1700,7 +1763,7 @@ void launch_apply_occ(const View& v, const double* C, const uint8_t* actC, const
   const int nchunk = (v.n_rb + 3) / 4;
   dim3 grid(xcd_grid(v.G, nchunk)), blk(256);
   switch (v.OW / 16) {
-#define SSCF_APO(NO) case NO: hipLaunchKernelGGL(k_apply_occ<NO>, grid, blk, 0, s, v.G, v.n_rb, v.W, nchunk, C, actC, gn_ptr, gn, pair_of, pg, FA, FB, listZ, cntZ, Z); break;
+#define SSCF_APO(NO) case NO: hipLaunchKernelGGL(k_apply_occ<NO>, grid, blk, 0, s, v.G, v.n_rb, v.W, nchunk, v.slot, v.slotY, C, actC, gn_ptr, gn, pair_of, pg, FA, FB, listZ, cntZ, Z); break;
     SSCF_APO(1) SSCF_APO(2) SSCF_APO(3) SSCF_APO(4) SSCF_APO(5) SSCF_APO(6) SSCF_APO(7) SSCF_APO(8)
 #undef SSCF_APO
     default: break;
@@ -1714,20 +1777,23 @@ void launch_apply_occ(const View& v, const double* C, const uint8_t* actC, const
 // step for the active tiles (k_round_c32), so every product reads half the bytes.
 // ---------------------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) k_round_c32(int n_rb, int W, const double* __restrict__ C,
+__global__ void __launch_bounds__(256) k_round_c32(int n_rb, int W, const int* __restrict__ slot,
+                                                   const double* __restrict__ C,
                                                    const int* __restrict__ list, const int* __restrict__ cnt,
                                                    float* __restrict__ C32) {
   const int g = blockIdx.y, t = blockIdx.x;
   if (t >= cnt[g]) return;
-  const size_t base = ((size_t)g * n_rb + list[(size_t)g * n_rb + t]) * (size_t)(RB * W);
+  const size_t base = (size_t)slot[(size_t)g * n_rb + list[(size_t)g * n_rb + t]] * (size_t)(RB * W);
   for (int e = threadIdx.x; e < RB * W; e += 256) C32[base + e] = (float)C[base + e];
 }
 void launch_round_c32(const View& v, const double* C, const int* list, const int* cnt, float* C32, hipStream_t s) {
-  hipLaunchKernelGGL(k_round_c32, dim3(v.n_rb, v.G), dim3(256), 0, s, v.n_rb, v.W, C, list, cnt, C32);
+  hipLaunchKernelGGL(k_round_c32, dim3(v.n_rb, v.G), dim3(256), 0, s, v.n_rb, v.W, v.slot, C, list, cnt, C32);
 }
 
 template <int MW, int NW>
-__global__ void __launch_bounds__(256) k_pair32(int n_rb, int W, const int* __restrict__ perm, int maxc,
+__global__ void __launch_bounds__(256) k_pair32(int n_rb, int W, const int* __restrict__ slot,
+                                                const int* __restrict__ slotY,
+                                                const int* __restrict__ perm, int maxc,
                                                 const int* __restrict__ pg, const int* __restrict__ ph,
                                                 const float* __restrict__ C, const int* __restrict__ listC,
                                                 const int* __restrict__ cntC, const unsigned int* __restrict__ cmask,
@@ -1773,8 +1839,8 @@ __global__ void __launch_bounds__(256) k_pair32(int n_rb, int W, const int* __re
         const int r = __shfl(rr, j);
         const unsigned int mj = __builtin_amdgcn_readfirstlane(__shfl((int)mab, j));
         const unsigned int ma = mj & 0xffffu, mb = mj >> 16;
-        const float* Ct = C + (gb + r) * (size_t)(RB * W) + row_off + mt0 * 16 + lr;
-        const float* Yt = Y + (hb + r) * (size_t)(RB * W) + col_off + nt0 * 16 + lr;
+        const float* Ct = C + (size_t)slot[gb + r] * (RB * W) + row_off + mt0 * 16 + lr;
+        const float* Yt = Y + (size_t)slotY[hb + r] * (RB * W) + col_off + nt0 * 16 + lr;
         float a[4][MW], b[4][NW];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -1819,17 +1885,17 @@ void launch_pair32(const View& v, int n_pairs, const int* perm, int maxc, const 
   const int m = mw > nw ? mw : nw;
   dim3 grid(N_XCD * maxc), blk(256);
   if (m <= 1)
-    hipLaunchKernelGGL((k_pair32<1, 1>), grid, blk, 0, s, v.n_rb, v.W, perm, maxc, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+    hipLaunchKernelGGL((k_pair32<1, 1>), grid, blk, 0, s, v.n_rb, v.W, v.slot, v.slotY, perm, maxc, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
   else if (m <= 2)
-    hipLaunchKernelGGL((k_pair32<2, 2>), grid, blk, 0, s, v.n_rb, v.W, perm, maxc, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+    hipLaunchKernelGGL((k_pair32<2, 2>), grid, blk, 0, s, v.n_rb, v.W, v.slot, v.slotY, perm, maxc, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
   else if (m <= 3)
-    hipLaunchKernelGGL((k_pair32<3, 3>), grid, blk, 0, s, v.n_rb, v.W, perm, maxc, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+    hipLaunchKernelGGL((k_pair32<3, 3>), grid, blk, 0, s, v.n_rb, v.W, v.slot, v.slotY, perm, maxc, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
   else
-    hipLaunchKernelGGL((k_pair32<4, 4>), grid, blk, 0, s, v.n_rb, v.W, perm, maxc, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
+    hipLaunchKernelGGL((k_pair32<4, 4>), grid, blk, 0, s, v.n_rb, v.W, v.slot, v.slotY, perm, maxc, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
 }
 
-__global__ void k_coldot32(int n_rb, int W, const float* C, const int* listC, const int* cntC, const float* Y,
-                           const uint8_t* actY, double* out) {
+__global__ void k_coldot32(int n_rb, int W, const int* slot, const int* slotY, const float* C, const int* listC,
+                           const int* cntC, const float* Y, const uint8_t* actY, double* out) {
   const int g = blockIdx.x, c = threadIdx.x;
   if (c >= W) return;
   const size_t gb = (size_t)g * n_rb;
@@ -1837,8 +1903,8 @@ __global__ void k_coldot32(int n_rb, int W, const float* C, const int* listC, co
   for (int t = 0; t < cntC[g]; ++t) {
     const int r = listC[gb + t];
     if (!actY[gb + r]) continue;
-    const float* Ct = C + (gb + r) * (size_t)(RB * W) + c;
-    const float* Yt = Y + (gb + r) * (size_t)(RB * W) + c;
+    const float* Ct = C + (size_t)slot[gb + r] * (RB * W) + c;
+    const float* Yt = Y + (size_t)slotY[gb + r] * (RB * W) + c;
 #pragma unroll
     for (int k = 0; k < RB; ++k) s += Ct[k * W] * Yt[k * W];
   }
@@ -1846,8 +1912,8 @@ __global__ void k_coldot32(int n_rb, int W, const float* C, const int* listC, co
 }
 void launch_coldot32(const View& v, const float* C, const int* listC, const int* cntC, const float* Y,
                      const uint8_t* actY, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_coldot32, dim3(v.G), dim3(v.W <= 64 ? 64 : (v.W <= 128 ? 128 : 256)), 0, s, v.n_rb, v.W, C,
-                     listC, cntC, Y, actY, out);
+  hipLaunchKernelGGL(k_coldot32, dim3(v.G), dim3(v.W <= 64 ? 64 : (v.W <= 128 ? 128 : 256)), 0, s, v.n_rb, v.W,
+                     v.slot, v.slotY, C, listC, cntC, Y, actY, out);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1859,7 +1925,8 @@ void launch_coldot32(const View& v, const float* C, const int* listC, const int*
 // of a product's loads issued together.  Real as above.
 // ---------------------------------------------------------------------------------------
 template <int NT, typename Real>
-__global__ void __launch_bounds__(256) k_spmm_row(int G, int n_rb, int nchunk, const int* __restrict__ xs_ptr,
+__global__ void __launch_bounds__(256) k_spmm_row(int G, int n_rb, int nchunk, const int* __restrict__ slot,
+                                                  const int* __restrict__ slotY, const int* __restrict__ xs_ptr,
                                                   const int* __restrict__ xs_col, const Real* __restrict__ X,
                                                   const Real* __restrict__ C, const uint8_t* __restrict__ actC,
                                                   const unsigned int* __restrict__ cmask,
@@ -1898,7 +1965,7 @@ __global__ void __launch_bounds__(256) k_spmm_row(int G, int n_rb, int nchunk, c
       const int cj = __shfl(c, j);
       const unsigned int mj = __builtin_amdgcn_readfirstlane(__shfl((int)mk, j));
       const Real* Xb = X + (size_t)(base + j) * 256 + lr * 16 + lk;
-      const Real* Ct = C + (pb + cj) * (RB * W) + lk * W + lr;
+      const Real* Ct = C + (size_t)slot[pb + cj] * (RB * W) + lk * W + lr;
       Real xa[4], cb[4][NT];
 #pragma unroll
       for (int s = 0; s < 4; ++s) xa[s] = Xb[4 * s];
@@ -1926,7 +1993,7 @@ __global__ void __launch_bounds__(256) k_spmm_row(int G, int n_rb, int nchunk, c
       }
     }
   }
-  Real* Yt = Y + (pb + r) * (RB * W);
+  Real* Yt = Y + (size_t)slotY[pb + r] * (RB * W);
   unsigned int ym = 0;
 #pragma unroll
   for (int n = 0; n < NT; ++n) {
@@ -1951,7 +2018,7 @@ static void launch_spmm_row(const View& v, const Real* X, const Real* C, const u
   const int nchunk = (v.n_rb + 3) / 4;
   dim3 grid(xcd_grid(v.G, nchunk)), blk(256);
   switch (v.W / 16) {
-#define SSCF_SPR(NT) case NT: hipLaunchKernelGGL((k_spmm_row<NT, Real>), grid, blk, 0, s, v.G, v.n_rb, nchunk, v.xs_ptr, v.xs_col, X, C, actC, cmask, listY, cntY, Y, ymask, smask, ctr); break;
+#define SSCF_SPR(NT) case NT: hipLaunchKernelGGL((k_spmm_row<NT, Real>), grid, blk, 0, s, v.G, v.n_rb, nchunk, v.slot, v.slotY, v.xs_ptr, v.xs_col, X, C, actC, cmask, listY, cntY, Y, ymask, smask, ctr); break;
     SSCF_SPR(1) SSCF_SPR(2) SSCF_SPR(3) SSCF_SPR(4) SSCF_SPR(5) SSCF_SPR(6) SSCF_SPR(7) SSCF_SPR(8)
 #undef SSCF_SPR
   }

@@ -47,7 +47,7 @@ class SystemDesc(ct.Structure):
         ("group_nbr_bohr", ct.c_double), ("rot_cap_factor", ct.c_double),
         ("max_sweeps_init", ct.c_int32), ("max_sweeps_step", ct.c_int32), ("scc", ct.c_int32),
         ("precision", ct.c_int32), ("hip_stream", ct.c_void_p), ("alloc", Allocator),
-        ("flags", ct.c_uint64),
+        ("flags", ct.c_uint64), ("slot_margin_bohr", ct.c_double),
     ]
 
 
@@ -102,7 +102,7 @@ EXPORTS = ["sscf_get_kernel_stats", "sscf_reset_kernel_stats", "sscf_init_system
            "sscf_get_schedule", "sscf_get_energy_gradient", "sscf_get_energy_gradient_device",
            "sscf_set_control", "sscf_get_control",
            "sscf_orthonormalize", "sscf_fragment_guess", "sscf_constrained_kmeans", "sscf_atom_neighbours",
-           "sscf_atom_neighbours_noalloc",
+           "sscf_atom_neighbours_noalloc", "sscf_memory_info",
            "sscf_destroy",
            "sscf_last_error"]
 
@@ -131,6 +131,7 @@ def lib():
         L.sscf_fragment_guess.argtypes = [ct.POINTER(GuessDesc), vp, vp, vp, i64, vp, ct.POINTER(i64),
                                           ct.POINTER(i32)]
         L.sscf_get_charges.argtypes = [vp, vp, sz]
+        L.sscf_memory_info.argtypes = [vp, ct.POINTER(sz), ct.POINTER(i64), ct.POINTER(i64), ct.POINTER(i64)]
         L.sscf_constrained_kmeans.argtypes = [ct.POINTER(KmeansDesc), vp, vp, ct.POINTER(KmeansInfo)]
         L.sscf_atom_neighbours.argtypes = [i32, vp, ct.c_double, vp, vp, vp, i64, ct.POINTER(i64)]
         L.sscf_atom_neighbours_noalloc.argtypes = [i32, vp, ct.c_double, vp, vp, vp, i64, ct.POINTER(i64)]
@@ -185,7 +186,7 @@ class SparseSCF:
     def __init__(self, system, eps: float = 1e-5, e_conv: float = 1e-6, group_nbr_bohr: float = 20.0,
                  rot_cap_factor: float = 10.0, max_sweeps_init: int = 200, max_sweeps_step: int = 50,
                  scc: bool = True, precision: int = FP64, stream=None, use_torch_allocator: bool = True,
-                 profile: bool = False, count_work: bool = False):
+                 profile: bool = False, count_work: bool = False, slot_margin_bohr: float = 0.0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("the sparse SCF library needs a GPU")
@@ -223,7 +224,8 @@ class SparseSCF:
             group_nbr_bohr=group_nbr_bohr, rot_cap_factor=rot_cap_factor,
             max_sweeps_init=max_sweeps_init, max_sweeps_step=max_sweeps_step, scc=1 if scc else 0,
             precision=precision, hip_stream=self._stream.cuda_stream, alloc=alloc,
-            flags=(FLAG_PROFILE if profile else 0) | (FLAG_COUNT_WORK if count_work else 0))
+            flags=(FLAG_PROFILE if profile else 0) | (FLAG_COUNT_WORK if count_work else 0),
+            slot_margin_bohr=slot_margin_bohr)
         h = ct.c_void_p()
         rc = lib().sscf_init_system(ct.byref(d), ct.byref(h))
         if rc != SSCF_OK:
@@ -308,6 +310,11 @@ class SparseSCF:
         self._check(lib().sscf_get_energy_gradient_device(self._h, gx.data_ptr(), gs.data_ptr(), n,
                                                           gon.data_ptr(), gon.numel()))
         return gx, gs, gon
+
+    def memory_info(self) -> Dict:
+        b, sl, sy, t = ct.c_size_t(), ct.c_int64(), ct.c_int64(), ct.c_int64()
+        self._check(lib().sscf_memory_info(self._h, ct.byref(b), ct.byref(sl), ct.byref(sy), ct.byref(t)))
+        return dict(device_bytes=b.value, tile_slots=sl.value, tile_slots_y=sy.value, tiles=t.value)
 
     def charges(self) -> np.ndarray:
         out = np.zeros(self.system.n_atoms)

@@ -35,6 +35,7 @@ import math
 from typing import Dict, List, Optional
 
 import numpy as np
+from scipy.linalg import eigh
 
 BOHR_PER_ANGSTROM = 1.0 / 0.529177210903
 
@@ -441,7 +442,6 @@ def build_matrices(xyz_ang: np.ndarray, el: np.ndarray):
 
 def molecular_guess(Hm: np.ndarray, Sm: np.ndarray, n_occ_m: int):
     """Lowest-first solutions of Hm c = lambda Sm c; the largest |c| entry is made positive."""
-    from scipy.linalg import eigh
     w, V = eigh(Hm, Sm)
     for j in range(V.shape[1]):
         k = int(np.argmax(np.abs(V[:, j])))
@@ -450,8 +450,35 @@ def molecular_guess(Hm: np.ndarray, Sm: np.ndarray, n_occ_m: int):
     return w, V[:, :n_occ_m], V[:, n_occ_m:]
 
 
-def assemble(name, seed, box, xyz_ang, el, atom_mol, mol_group, n_groups, c0_drop=1e-13):
-    """System from explicit geometry (Angstrom), molecule ids and MO group per molecule."""
+def cholesky_local(M: np.ndarray, rank: int, tol: float = 1e-12):
+    """Pivoted Cholesky factor of a positive semi-definite matrix of the given rank: M = L L^T
+    with L's columns in pivot order, and the pivot (row) of each column.  For the density of a
+    gapped system its columns are local (Cholesky MOs)."""
+    from scipy.linalg.lapack import dpstrf
+    A = np.array(M, dtype=np.float64, order="F", copy=True)
+    L, piv, r, info = dpstrf(A, lower=1, tol=tol)
+    if info < 0:
+        raise RuntimeError(f"dpstrf failed ({info})")
+    L = np.tril(L)
+    r = min(int(r), rank)
+    piv = piv - 1                                   # LAPACK pivots are 1-based
+    out = np.zeros((M.shape[0], r))
+    out[piv, :] = L[:, :r]
+    return out, piv[:r]
+
+
+def assemble(name, seed, box, xyz_ang, el, atom_mol, mol_group, n_groups, c0_drop=1e-13, mol_nocc=None,
+             unit_group=None, atom_unit=None):
+    """System from explicit geometry (Angstrom), molecule ids and MO group per molecule.
+
+    The guess of section 3.3 is solved per molecule (atom_mol: contiguous runs of atoms), its
+    doubly occupied count in mol_nocc (default: half the reference electrons of its atoms).
+    With unit_group and atom_unit (a long molecule split into units, each in an MO group), the
+    molecule's own occupied and virtual spaces are spanned by local MOs instead: the columns of
+    pivoted Cholesky factors of C_occ C_occ^T and C_virt C_virt^T (Cholesky MOs: the density of
+    a gapped molecule decays with distance, and so do they, away from their pivot AO).  Each
+    goes to the group of the unit of its pivot.  They are not orthonormal (the library's first
+    orthonormalization makes them so)."""
     n_atoms = xyz_ang.shape[0]
     nao, rowptr, col, off, S, H = build_matrices(xyz_ang, el)
     aoo = np.zeros(n_atoms + 1, dtype=np.int64)
@@ -480,14 +507,27 @@ def assemble(name, seed, box, xyz_ang, el, atom_mol, mol_group, n_groups, c0_dro
                 Sm[aoo[a] - lo:aoo[a] - lo + na, aoo[b] - lo:aoo[b] - lo + nb] = blkS
                 Hm[aoo[a] - lo:aoo[a] - lo + na, aoo[b] - lo:aoo[b] - lo + nb] = blkH
         n_el_m = q0[a0:a1].sum()
-        n_occ_m = int(round(n_el_m)) // 2
+        n_occ_m = int(round(n_el_m)) // 2 if mol_nocc is None else int(mol_nocc[m])
         _, Vo, Vv = molecular_guess(Hm, Sm, n_occ_m)
-        g = mol_group[m]
         rows = np.arange(lo, hi, dtype=np.int32)
-        for j in range(Vo.shape[1]):
-            occ_cols[g].append((rows, Vo[:, j]))
-        for j in range(Vv.shape[1]):
-            virt_cols[g].append((rows, Vv[:, j]))
+        if unit_group is None:
+            g = mol_group[m]
+            for j in range(Vo.shape[1]):
+                occ_cols[g].append((rows, Vo[:, j]))
+            for j in range(Vv.shape[1]):
+                virt_cols[g].append((rows, Vv[:, j]))
+        else:
+            # local MOs: Cholesky factors of the molecule's occupied and virtual projectors, in
+            # the order of their pivots along the molecule
+            ao_unit = np.repeat(atom_unit[a0:a1], nao[a0:a1])
+            for V, dest in ((Vo, occ_cols), (Vv, virt_cols)):
+                L, piv = cholesky_local(V @ V.T, V.shape[1])
+                if L.shape[1] != V.shape[1]:
+                    raise RuntimeError("local guess: the Cholesky factor lost rank")
+                for j in np.argsort(piv, kind="stable"):      # along the molecule
+                    v = L[:, j] / np.sqrt(L[:, j] @ Sm @ L[:, j])
+                    k = int(np.argmax(np.abs(v)))
+                    dest[unit_group[ao_unit[piv[j]]]].append((rows, v if v[k] > 0 else -v))
     cols, groups = [], []
     for g in range(n_groups):
         cols += occ_cols[g]
@@ -503,7 +543,7 @@ def assemble(name, seed, box, xyz_ang, el, atom_mol, mol_group, n_groups, c0_dro
         rr.append(rows[keep])
         vv.append(v[keep])
         colptr[j + 1] = colptr[j] + int(keep.sum())
-    atom_group = mol_group[atom_mol].astype(np.int32)
+    atom_group = (mol_group[atom_mol] if unit_group is None else unit_group[atom_unit]).astype(np.int32)
     sysm = System(
         name=name, seed=seed, box_angstrom=box, n_atoms=n_atoms,
         atom_el=el.astype(np.int32), atom_nao=nao.astype(np.int32),
@@ -559,11 +599,24 @@ CONFIGS = {
     # alkane-like chains at about the headline size: 400 octanes (10,400 atoms, 20,000 AOs),
     # 60 A cube (about half the liquid density), groups of two chains
     "octane400": dict(n_chains=400, n_c=8, box=60.0),
+    # the large alkane form: 400 chains of C83H168 (100,400 atoms, 200,000 AOs), 160 A cube
+    # (half the octane400 density: the coils are long), local guess from each chain's own
+    # solution, MO groups of 10 carbons along a chain.  Without the charge term: the plain SCC iteration (no mixing)
+    # grows a charge oscillation on these long chains; the library options are in RUN_OPTIONS
+    "alkane400x83": dict(n_chains=400, n_c=83, box=160.0, seg=10),
 }
+
+
+# library options a workload needs besides its system (scc: the DFTB charge term; slot_margin_bohr:
+# storage only for the row blocks within that distance beyond the reach of each MO group's
+# initial MOs; on a 60-chain box of the same chains the MOs grew at most 46 bohr past it)
+RUN_OPTIONS = {"alkane400x83": dict(scc=False, slot_margin_bohr=55.0)}
 
 
 def make_config(name: str, seed: int = 1) -> System:
     c = CONFIGS[name]
+    if "seg" in c:
+        return alkane_segments_box(c["n_chains"], c["n_c"], c["box"], seed, seg=c["seg"], name=name)
     if "n_chains" in c:
         return alkane_box(c["n_chains"], c["n_c"], c["box"], seed, name=name)
     return water_box(c["n_mol"], c["box"], seed, name=name)
@@ -686,3 +739,71 @@ def alkane_box(n_chains: int, n_c: int, box: float, seed: int, n_link: int = 2, 
     el = np.concatenate([el_all[i] for i in order])
     atom_mol = np.repeat(np.arange(n_chains), per)
     return assemble(name or f"alkane{n_chains}x{n_c}", seed, box, xyz, el, atom_mol, ren[assign[order]], used.size)
+
+
+def alkane_segments_box(n_chains: int, n_c: int, box: float, seed: int, seg: int = 10, name: str = "") -> System:
+    """A seeded open box of long C_nH_(2n+2) chains with local MOs from the start.
+
+    Chains: seeded conformations (alkane_chain) with random centres in [0, box)^3 and random
+    orientations, no two atoms of different chains closer than 2.2 A; chains follow a Morton
+    order of their centres.  A chain is one molecule of the guess of section 3.3, but its
+    solution spreads over the whole chain, so it is made local before it enters C (see
+    assemble): the units are a carbon and its hydrogens, and each local MO goes to the group of
+    its pivot's unit.  The SCF starts from the chain's own solution, in a local basis.  MO groups
+    (section 3.2) are runs of `seg` consecutive units along a chain, spatially compact as the
+    constrained k-means would make them."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(seed)
+    placed, recent, chains, centres = [], [], [], []
+    tree = None
+    for ci in range(n_chains):
+        local, el = alkane_chain(rng, n_c)
+        local = local - local.mean(axis=0)
+        for attempt in range(20000):
+            R = _random_rotations(rng, 1)[0]
+            pos = rng.uniform(0.0, box, 3)
+            cand = local @ R.T + pos
+            ok = True
+            if tree is not None:
+                d, _ = tree.query(cand, k=1, distance_upper_bound=2.2)
+                ok = not np.isfinite(d).any()
+            if ok:
+                for x in recent:
+                    if np.min(((cand[:, None, :] - x[None, :, :]) ** 2).sum(-1)) < 2.2 ** 2:
+                        ok = False
+                        break
+            if ok:
+                break
+        else:
+            raise RuntimeError(f"alkane_segments_box: no room for chain {ci} (seed {seed})")
+        chains.append((cand, el))
+        centres.append(pos)
+        recent.append(cand)
+        if len(recent) >= 16:
+            placed.extend(recent)
+            recent = []
+            tree = cKDTree(np.concatenate(placed))
+    centres = np.array(centres)
+    lo = centres.min(axis=0)
+    span = float((centres.max(axis=0) - lo).max())
+    order = np.argsort(_morton_key(centres, lo, span), kind="stable")
+    xyz, els, atom_mol, atom_unit, unit_group = [], [], [], [], []
+    n_unit = n_grp = 0
+    for m, c in enumerate(order):
+        cx, cel = chains[c]
+        cpos = np.flatnonzero(cel == EL_C)
+        for u, a0 in enumerate(cpos):
+            a1 = cpos[u + 1] if u + 1 < len(cpos) else len(cel)
+            atom_unit += [n_unit] * (a1 - a0)
+            unit_group.append(n_grp + u // seg)
+            n_unit += 1
+        xyz.append(cx)
+        els.append(cel)
+        atom_mol += [m] * len(cel)
+        n_grp += -(-len(cpos) // seg)
+    # coefficients below 1e-5 (the rotation threshold eps of section 3.5) are left out: the guess
+    # only starts the iteration, and the slowly decaying tails of the Cholesky MOs along a chain
+    # would otherwise reach tens of Angstrom from their group
+    return assemble(name or f"alkanes{n_chains}x{n_c}", seed, box, np.concatenate(xyz), np.concatenate(els),
+                    np.array(atom_mol), np.zeros(n_chains, dtype=np.int64), n_grp, c0_drop=1e-5,
+                    unit_group=np.array(unit_group), atom_unit=np.array(atom_unit))

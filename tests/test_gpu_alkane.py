@@ -44,3 +44,41 @@ def test_octane_box_fp32_form(octanes):
 
 def test_octane_box_gradient(octanes):
     compare(octanes, "16 octanes")
+
+
+# ---------------------------------------------------------------------------------------
+# long chains (the large alkane form at small scale): six C20H42 chains, local guess from each
+# chain's own solution, groups of five carbons, no charge term (as the 100k-atom workload)
+# ---------------------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def chains():
+    return synth.alkane_segments_box(6, 20, 20.0, 1, seg=5)
+
+
+def test_long_chains_per_step(chains):
+    """FP64 against the oracle step by step through convergence, counts included."""
+    compare_steps(chains, 14, gkw=dict(scc=False), okw=dict(scc=False), label="6 x C20H42")
+
+
+def test_long_chains_fp32_form(chains):
+    """The FP32 form against the FP64 oracle.  The rotation cap binds at every step here (3,660 =
+    10 N_occ), so, as for the octanes, FP32 values of F_ia next to the top-K cut may select another
+    set; both runs must converge, to energies within the SCF criterion (1e-6 Ha)."""
+    from paper_1402_2880_amd.sscf import FP32_MIXED, SparseSCF
+    o, g = Oracle(chains, scc=False), SparseSCF(chains, precision=FP32_MIXED, scc=False)
+    done_o = done_g = False
+    for k in range(40):
+        if not done_o:
+            done_o = bool(o.step()["converged"])
+        if not done_g:
+            done_g = bool(g.step()["converged"])
+        print(f"[fp32] chains step {k + 1} |dE| vs FP64 oracle {abs(g.energy() - o.energy()):.2e}", flush=True)
+        if done_o and done_g:
+            break
+    assert done_o and done_g
+    assert abs(g.energy() - o.energy()) < FP32_TOL
+
+
+def test_long_chains_gradient(chains):
+    compare(chains, "6 x C20H42 non-SCC", scc=False)
