@@ -192,8 +192,10 @@ def run_form(system, prec, args, profile: bool, count: bool, adjoint: bool = Fal
                   **synth.RUN_OPTIONS.get(args.config, {}))
     if args.schedule == "paper":
         g.set_control(args.eps, dq_conv=10 * args.eps, criterion=CONV_CHARGE, step_ortho=False)
+    m = g.memory_info()
     log(f"[bench] {'fp64' if prec == 0 else 'fp32'} context ready (count={count}): "
-        f"set-up energy {g.init_info()['energy']:.8f}")
+        f"set-up energy {g.init_info()['energy']:.8f}, {m['device_bytes'] / 1e9:.1f} GB on the device, "
+        f"tile slots C {m['tile_slots']} Y {m['tile_slots_y']} of {m['tiles']}")
     warm = []
     for k in range(args.warmup):
         warm.append(g.step())
@@ -267,6 +269,7 @@ def main():
               "(how it would shard is described in the design notes)", file=sys.stderr)
         sys.exit(2)
 
+    log("[bench] importing torch")
     import torch
     from paper_1402_2880_amd import synth
     from paper_1402_2880_amd.sscf import FP32_MIXED, FP64
@@ -282,7 +285,8 @@ def main():
         log(f"[bench] copy calibration: 3 copies of {args.copy_calibration} MiB")
         del src, dst
     t = time.time()
-    system = synth.make_config(args.config, args.seed)
+    log(f"[bench] generating {args.config} seed {args.seed}")
+    system = synth.make_config(args.config, args.seed, log=log)
     log(f"[bench] {args.config}: {system.n_atoms} atoms, {system.n_ao} AOs, {system.n_mo} MOs "
         f"(generated in {time.time() - t:.1f} s)")
     prec = FP64 if args.precision == "fp64" else FP32_MIXED

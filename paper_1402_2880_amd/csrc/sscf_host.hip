@@ -141,6 +141,7 @@ struct sscf_ctx {
   int* slot = nullptr;                  // tile -> slot of the pools of C (-1: none)
   int* slotY = nullptr;                 // tile -> slot of the pools of Y (-1: none)
   size_t n_slots = 0, n_slots_y = 0;
+  std::vector<double> cap_gap_g, cap_gap_r, cap_R;   // spheres and radius of each group (report)
   int *rcnt = nullptr, *roff = nullptr;
   int4* rmeta = nullptr;                // blocks with rotations, packed in round order
   int2* rot_slot = nullptr;
@@ -332,9 +333,21 @@ struct sscf_ctx {
     Scalars h{};
     HIPC(hipMemcpyAsync(&h, sd, sizeof(Scalars), hipMemcpyDeviceToHost, stream));
     sync();
-    if (h.cap_err)
+    if (h.cap_err) {
+      const int64_t t = (int64_t)h.cap_err - 1;
+      const int g = (int)(t / v.n_rb), r = (int)(t % v.n_rb);
+      double gap = 0.0, R = 0.0;
+      if (!cap_R.empty() && g < v.G) {
+        const double* a = &cap_gap_g[4 * (size_t)g];
+        const double* b = &cap_gap_r[4 * (size_t)r];
+        gap = std::sqrt((a[0] - b[0]) * (a[0] - b[0]) + (a[1] - b[1]) * (a[1] - b[1]) + (a[2] - b[2]) * (a[2] - b[2])) -
+              a[3] - b[3];
+        R = cap_R[g];
+      }
       fail(SSCF_E_CAPACITY,
-           "a nonzero fell on a tile without a slot (an MO reached beyond its initial reach + slot_margin_bohr)");
+           "a nonzero of C fell on a tile without a slot: group %d, row block %d, %.1f bohr from the group, beyond "
+           "its capacity of %.1f bohr (initial reach + slot_margin_bohr)", g, r, gap, R);
+    }
     return h;
   }
 
@@ -382,14 +395,15 @@ struct sscf_ctx {
       *eta_out = eta;
       if (eta < tol) { *converged = 1; break; }
       if (sweeps >= max_sweeps) break;
-      // pair combinations C <- C - 1/2 C D_sel into the other buffer
+      // pair combinations C <- C - 1/2 C D_sel, in place: the combination reads the other
+      // groups' tiles from their packed copy, and only the activity flags are double-buffered
       const int nx = 1 - cur;
       HIPC(hipMemsetAsync(upd, 0, (size_t)v.G * W, stream));
       if (wc()) launch_fill_i32(w_nsel, (size_t)v.G * W, 0, stream);
       launch_mark_selected(v, n_pairs, pg, ph, O, sd, pair_sel, upd, rmask, wc() ? w_nsel : nullptr, stream);
       launch_update_support(v, actC[cur], gn_ptr, gn, pair_of, pair_sel, nullptr, act_tmp, stream);
       launch_list(v, act_tmp, list_tmp, cnt_tmp, stream);
-      launch_clear_tiles(v, C[nx], actC[nx], cmask[nx], listC[nx], cntC[nx], stream);
+      launch_clear_flags(v, actC[nx], cmask[nx], listC[nx], cntC[nx], stream);
       if (wc()) count_update_begin(occ_only != 0);
       // the combination reads the nonzero columns of C packed into Y (free until the next product)
       const int pu = pbegin(KC_UPDATE);
@@ -839,9 +853,13 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
           reach[g] = std::max(reach[g], gap(g, r));
         }
       }
+      x->cap_gap_g = gs;
+      x->cap_gap_r = rs;
+      x->cap_R.assign(G, 0.0);
       for (int g = 0; g < G; ++g) {
         if (gat[g].empty()) continue;
         const double R = reach[g] + d->slot_margin_bohr;
+        x->cap_R[g] = R;
         for (int r = 0; r < v.n_rb; ++r) {
           if (gap(g, r) < R) {
             if (ns >= INT32_MAX) fail(SSCF_E_CAPACITY, "more than 2^31 tile slots");
@@ -864,7 +882,7 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
       for (int g = 0; g < G; ++g) {
         const int* sg = &slot[(size_t)g * v.n_rb];
         for (int r = 0; r < v.n_rb; ++r) {
-          bool need = false;
+          bool need = sg[r] >= 0;
           for (int k = xs_ptr[r]; k < xs_ptr[r + 1] && !need; ++k) need = sg[xs_col[k]] >= 0;
           if (need) {
             if (nsy >= INT32_MAX) fail(SSCF_E_CAPACITY, "more than 2^31 tile slots");
@@ -878,9 +896,11 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
     v.slotY = x->slotY;
   }
   const size_t nslot = x->n_slots, nslot_y = x->n_slots_y;
+  // one pool of C values (C[0] and C[1] are the same memory: see orthonormalize), two sets of
+  // activity flags and lists
+  x->C[0] = x->C[1] = x->dalloc<double>(nslot * tile_elems);
+  HIPC(hipMemsetAsync(x->C[0], 0, nslot * tile_elems * sizeof(double), s));
   for (int b = 0; b < 2; ++b) {
-    x->C[b] = x->dalloc<double>(nslot * tile_elems);
-    HIPC(hipMemsetAsync(x->C[b], 0, nslot * tile_elems * sizeof(double), s));
     x->actC[b] = x->dalloc<uint8_t>(ntiles);
     HIPC(hipMemsetAsync(x->actC[b], 0, ntiles, s));
     x->listC[b] = x->dalloc<int>(ntiles);
@@ -941,8 +961,11 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
   x->rot_slot = x->dalloc<int2>((size_t)x->n_blocks * per);
   if (x->precision == SSCF_FP32_MIXED) {
     x->H32 = x->dalloc<float>(nxe);
-    x->Y32 = x->dalloc<float>(nslot_y * tile_elems);
-    x->C32 = x->dalloc<float>(nslot * tile_elems);
+    // C32 and Y32 live only inside the C^T H C pass, when Y holds nothing that is read later
+    // (every later reader of Y recomputes it first): they share Y's memory, nslot + nslot_y FP32
+    // tiles within its nslot_y FP64 tiles (nslot <= nslot_y)
+    x->C32 = reinterpret_cast<float*>(x->Y);
+    x->Y32 = reinterpret_cast<float*>(x->Y) + nslot_y * tile_elems;
     x->R32 = x->dalloc<float>((size_t)x->n_blocks * v.W * v.W);
   } else {
     x->Rrot = x->dalloc<double>((size_t)x->n_blocks * v.W * v.W);

@@ -55,7 +55,7 @@ struct Scalars {
   int tie_n;                        // tie keys collected
   double e_band, e_coul;
   double eta;
-  int cap_err;                      // a nonzero fell on a tile without a slot (sticky)
+  int cap_err;                      // 1 + the first tile where a nonzero fell without a slot (sticky)
 };
 
 struct View {
@@ -75,7 +75,7 @@ struct View {
   const double* zeros;
   // tile capacity: slot[g * n_rb + r] is the slot of tile (g, r) in the pools of C and its FP32
   // copy (n_slots tiles of 16 x W each), -1 when the tile has no slot (then it is zero and must
-  // stay so: a nonzero landing there sets *cap_err).  slotY does the same for the products
+  // stay so: a nonzero landing there records the tile in *cap_err).  slotY does the same for the products
   // Y = X C (and what shares their pools): its tiles are the row blocks that X's pattern links
   // to a tile of C with a slot, so a product never falls outside it.
   const int* slot;
@@ -120,8 +120,8 @@ void launch_mark_selected(const View& v, int n_pairs, const int* pg, const int* 
 void launch_update_support(const View& v, const uint8_t* actC, const int* gn_ptr, const int* gn,
                            const int* pair_of, const uint8_t* pair_sel, const uint8_t* mask, uint8_t* act_new,
                            hipStream_t s);
-void launch_clear_tiles(const View& v, double* C, uint8_t* act, unsigned int* cmask,
-                        const int* list, const int* cnt, hipStream_t s);
+void launch_clear_flags(const View& v, uint8_t* act, unsigned int* cmask, const int* list, const int* cnt,
+                        hipStream_t s);
 void launch_tile_flags(const View& v, const double* C, const int* list, const int* cnt, uint8_t* act,
                        unsigned int* cmask, ulonglong2* colm, hipStream_t s);
 void launch_pack_cols(const View& v, const double* C, const int* list, const int* cnt, int col_end, double* P,

@@ -96,6 +96,12 @@ void launch_scatter(const int64_t* map, int64_t n, const double* src, double* ds
   if (n) hipLaunchKernelGGL(k_scatter, dim3(nblk(n, 256)), dim3(256), 0, s, map, n, src, dst);
 }
 
+// a nonzero of C fell on tile (g, r) = tile, which has no slot: the first such tile (+ 1) is
+// kept for the error report
+__device__ __forceinline__ void note_capacity(int* cap_err, size_t tile) {
+  atomicCAS(cap_err, 0, tile < (size_t)INT32_MAX - 1 ? (int)tile + 1 : INT32_MAX);
+}
+
 // C0 (one entry per thread) into the tiles
 __global__ void k_scatter_c0(int nnz, const int64_t* col_of, const int* row, const double* val,
                              const int* mo_panel, const int* mo_col, int n_rb, int W, const int* slot, double* C,
@@ -108,7 +114,7 @@ __global__ void k_scatter_c0(int nnz, const int64_t* col_of, const int* row, con
   const size_t tile = (size_t)g * n_rb + mu / RB;
   const int sl = slot[tile];
   if (sl < 0) {                                 // outside the tile capacity
-    *cap_err = 1;
+    note_capacity(cap_err, tile);
     return;
   }
   C[((size_t)sl * RB + (mu % RB)) * W + mo_col[j]] = val[e];
@@ -137,7 +143,7 @@ __global__ void k_dilate(int G, int n_rb, const int* xs_ptr, const int* xs_col, 
   for (int k = xs_ptr[r]; k < xs_ptr[r + 1]; ++k)
     if (a[xs_col[k]]) { any = 1; break; }
   if (any && slotY[idx] < 0) {                  // cannot happen while C keeps to its slots
-    *cap_err = 1;
+    note_capacity(cap_err, idx);
     any = 0;
   }
   actY[idx] = any;
@@ -516,18 +522,19 @@ void launch_update_support(const View& v, const uint8_t* actC, const int* gn_ptr
                      pair_of, pair_sel, mask, act_new);
 }
 
-__global__ void __launch_bounds__(256) k_clear_tiles(int n_rb, int W, const int* slot, double* C, uint8_t* act,
-                                                     unsigned int* cmask, const int* list, const int* cnt) {
-  const int g = blockIdx.y, t = blockIdx.x;
+// activity flags and slice masks of the listed tiles back to zero (the values are not touched)
+__global__ void __launch_bounds__(256) k_clear_flags(int n_rb, uint8_t* act, unsigned int* cmask, const int* list,
+                                                     const int* cnt) {
+  const int g = blockIdx.y;
+  const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= cnt[g]) return;
   const size_t tile = (size_t)g * n_rb + list[(size_t)g * n_rb + t];
-  double* Ct = C + (size_t)slot[tile] * (RB * W);
-  for (int e = threadIdx.x; e < RB * W; e += 256) Ct[e] = 0.0;
-  if (threadIdx.x == 0) { act[tile] = 0; cmask[tile] = 0u; }
+  act[tile] = 0;
+  cmask[tile] = 0u;
 }
-void launch_clear_tiles(const View& v, double* C, uint8_t* act, unsigned int* cmask, const int* list, const int* cnt,
+void launch_clear_flags(const View& v, uint8_t* act, unsigned int* cmask, const int* list, const int* cnt,
                         hipStream_t s) {
-  hipLaunchKernelGGL(k_clear_tiles, dim3(v.n_rb, v.G), dim3(256), 0, s, v.n_rb, v.W, v.slot, C, act, cmask, list, cnt);
+  hipLaunchKernelGGL(k_clear_flags, dim3((v.n_rb + 255) / 256, v.G), dim3(256), 0, s, v.n_rb, act, cmask, list, cnt);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -656,6 +663,8 @@ void launch_pack_cols(const View& v, const double* C, const int* list, const int
 // rows = MOs of a, columns = MOs of b; Dt holds the transposes, so D_sel(h, g) (rows = MOs
 // of h) is read row-contiguously in both orientations.
 //
+// Cn may be C itself (the update runs in place): the wave of tile (g, r) is the only one that
+// reads or writes C's tile (g, r); the other groups' tiles come from their packed copy.
 // One wave per output tile (g, r), no workgroup synchronization.  A ballot over g's
 // neighbours finds, 64 at a time, those h whose pair is selected and whose tile (h, r) has a
 // nonzero column.  Per such h only the tile's nonzero columns enter the product: they come
@@ -667,7 +676,7 @@ void launch_pack_cols(const View& v, const double* C, const int* list, const int
 // column order, so the result does not depend on the launch.
 template <int NT>
 __global__ void __launch_bounds__(256) k_ortho_update(int G, int n_rb, int nchunk, const int* __restrict__ slot,
-                                                      const int* __restrict__ slotP, const double* __restrict__ C,
+                                                      const int* __restrict__ slotP, const double* C,
                                                       const uint8_t* __restrict__ actC,
                                                       const double* __restrict__ P, const uint8_t* __restrict__ cidx,
                                                       const uint8_t* __restrict__ ncol,
@@ -679,7 +688,7 @@ __global__ void __launch_bounds__(256) k_ortho_update(int G, int n_rb, int nchun
                                                       const Scalars* __restrict__ sd,
                                                       const uint8_t* __restrict__ upd, double cut,
                                                       const int* __restrict__ listN, const int* __restrict__ cntN,
-                                                      double* __restrict__ Cn, uint8_t* __restrict__ actN,
+                                                      double* Cn, uint8_t* __restrict__ actN,
                                                       unsigned int* __restrict__ cmaskN, int* __restrict__ cap_err,
                                                       unsigned long long* ctr) {
   constexpr int W = NT * 16;
@@ -779,7 +788,7 @@ __global__ void __launch_bounds__(256) k_ortho_update(int G, int n_rb, int nchun
         bad |= (u ? fabs(v) >= cut : v != 0.0);
       }
     }
-    if (__ballot(bad) && lane == 0) *cap_err = 1;
+    if (__ballot(bad) && lane == 0) note_capacity(cap_err, tile);
     if (lane == 0) {
       actN[tile] = 0;
       cmaskN[tile] = 0u;
@@ -1461,7 +1470,7 @@ __global__ void __launch_bounds__(256) k_givens_rb(int G, int n_rb, int W, int O
                 base[Mfma<Real>::row(lk, q) * W + col] = x;
                 nzc |= x != 0.0;
               } else if (x != 0.0) {
-                *cap_err = 1;
+                note_capacity(cap_err, (size_t)((col < OW) ? g : h) * n_rb + rb);
               }
             }
           }

@@ -468,7 +468,7 @@ def cholesky_local(M: np.ndarray, rank: int, tol: float = 1e-12):
 
 
 def assemble(name, seed, box, xyz_ang, el, atom_mol, mol_group, n_groups, c0_drop=1e-13, mol_nocc=None,
-             unit_group=None, atom_unit=None):
+             unit_group=None, atom_unit=None, log=None):
     """System from explicit geometry (Angstrom), molecule ids and MO group per molecule.
 
     The guess of section 3.3 is solved per molecule (atom_mol: contiguous runs of atoms), its
@@ -478,7 +478,7 @@ def assemble(name, seed, box, xyz_ang, el, atom_mol, mol_group, n_groups, c0_dro
     pivoted Cholesky factors of C_occ C_occ^T and C_virt C_virt^T (Cholesky MOs: the density of
     a gapped molecule decays with distance, and so do they, away from their pivot AO).  Each
     goes to the group of the unit of its pivot.  They are not orthonormal (the library's first
-    orthonormalization makes them so)."""
+    orthonormalization makes them so).  log: optional callable for progress lines."""
     n_atoms = xyz_ang.shape[0]
     nao, rowptr, col, off, S, H = build_matrices(xyz_ang, el)
     aoo = np.zeros(n_atoms + 1, dtype=np.int64)
@@ -524,10 +524,12 @@ def assemble(name, seed, box, xyz_ang, el, atom_mol, mol_group, n_groups, c0_dro
                 L, piv = cholesky_local(V @ V.T, V.shape[1])
                 if L.shape[1] != V.shape[1]:
                     raise RuntimeError("local guess: the Cholesky factor lost rank")
+                L = L / np.sqrt(np.einsum("ij,ij->j", L, Sm @ L))            # S-normalized
+                L = L * np.sign(L[np.argmax(np.abs(L), axis=0), np.arange(L.shape[1])])
                 for j in np.argsort(piv, kind="stable"):      # along the molecule
-                    v = L[:, j] / np.sqrt(L[:, j] @ Sm @ L[:, j])
-                    k = int(np.argmax(np.abs(v)))
-                    dest[unit_group[ao_unit[piv[j]]]].append((rows, v if v[k] > 0 else -v))
+                    dest[unit_group[ao_unit[piv[j]]]].append((rows, L[:, j]))
+        if log is not None and (m + 1) % 100 == 0:
+            log(f"[synth] {name}: guess of {m + 1} of {n_mol} molecules")
     cols, groups = [], []
     for g in range(n_groups):
         cols += occ_cols[g]
@@ -610,13 +612,14 @@ CONFIGS = {
 # library options a workload needs besides its system (scc: the DFTB charge term; slot_margin_bohr:
 # storage only for the row blocks within that distance beyond the reach of each MO group's
 # initial MOs; on a 60-chain box of the same chains the MOs grew at most 46 bohr past it)
-RUN_OPTIONS = {"alkane400x83": dict(scc=False, slot_margin_bohr=55.0)}
+RUN_OPTIONS = {"alkane400x83": dict(scc=False, slot_margin_bohr=90.0)}
 
 
-def make_config(name: str, seed: int = 1) -> System:
+def make_config(name: str, seed: int = 1, log=None) -> System:
+    """A named workload; log: optional callable for progress lines of long generations."""
     c = CONFIGS[name]
     if "seg" in c:
-        return alkane_segments_box(c["n_chains"], c["n_c"], c["box"], seed, seg=c["seg"], name=name)
+        return alkane_segments_box(c["n_chains"], c["n_c"], c["box"], seed, seg=c["seg"], name=name, log=log)
     if "n_chains" in c:
         return alkane_box(c["n_chains"], c["n_c"], c["box"], seed, name=name)
     return water_box(c["n_mol"], c["box"], seed, name=name)
@@ -741,7 +744,8 @@ def alkane_box(n_chains: int, n_c: int, box: float, seed: int, n_link: int = 2, 
     return assemble(name or f"alkane{n_chains}x{n_c}", seed, box, xyz, el, atom_mol, ren[assign[order]], used.size)
 
 
-def alkane_segments_box(n_chains: int, n_c: int, box: float, seed: int, seg: int = 10, name: str = "") -> System:
+def alkane_segments_box(n_chains: int, n_c: int, box: float, seed: int, seg: int = 10, name: str = "",
+                        log=None) -> System:
     """A seeded open box of long C_nH_(2n+2) chains with local MOs from the start.
 
     Chains: seeded conformations (alkane_chain) with random centres in [0, box)^3 and random
@@ -783,6 +787,8 @@ def alkane_segments_box(n_chains: int, n_c: int, box: float, seed: int, seg: int
             placed.extend(recent)
             recent = []
             tree = cKDTree(np.concatenate(placed))
+        if log is not None and (ci + 1) % 100 == 0:
+            log(f"[synth] {name}: placed {ci + 1} of {n_chains} chains")
     centres = np.array(centres)
     lo = centres.min(axis=0)
     span = float((centres.max(axis=0) - lo).max())
@@ -806,4 +812,4 @@ def alkane_segments_box(n_chains: int, n_c: int, box: float, seed: int, seg: int
     # would otherwise reach tens of Angstrom from their group
     return assemble(name or f"alkanes{n_chains}x{n_c}", seed, box, np.concatenate(xyz), np.concatenate(els),
                     np.array(atom_mol), np.zeros(n_chains, dtype=np.int64), n_grp, c0_drop=1e-5,
-                    unit_group=np.array(unit_group), atom_unit=np.array(atom_unit))
+                    unit_group=np.array(unit_group), atom_unit=np.array(atom_unit), log=log)
