@@ -24,7 +24,6 @@ What one invocation measures:
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import statistics
@@ -41,7 +40,6 @@ CLASSES = ("spmm_tiles", "pair_overlap", "pair_fock", "ortho_update", "rotations
 # Measured HBM traffic per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a copy kernel);
 # reported only while the kernel source is the one the counters were taken from.
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic_water4096_fp64.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1402_2880_amd", "csrc", "sscf_kernels.hip")
 GOLDEN = os.path.join(ROOT, "tests", "golden", "water4096_seed{}.json")
 # The paper's own numbers for this path (context only: other hardware, no steps/s or GB/s printed)
 PAPER_CONTEXT = {
@@ -165,8 +163,9 @@ def measured_traffic(kernel: str, config: str, precision: str, seed: int):
     """HBM bytes per launch of the kernel from the committed counter summary, or None."""
     if config != "water4096" or precision != "fp64" or seed != 1 or not os.path.exists(TRAFFIC):
         return None
+    from paper_1402_2880_amd.prof_summary import source_sha256
     rec = json.load(open(TRAFFIC))
-    if hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest() != rec.get("kernel_source_sha256"):
+    if source_sha256() != rec.get("kernel_source_sha256"):
         return None
     k = rec["kernels"].get(rec.get("class_kernel", {}).get(kernel, ""))
     return None if k is None else round(k["hbm_bytes_per_launch"] / 1e9, 4)
