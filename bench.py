@@ -33,6 +33,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_1402_2880_amd.prof_summary import source_sha256  # noqa: E402  (hashing only, no GPU)
+
 METRIC = "SCF steps/sec + HBM GB/s at 12k atoms; FP32 vs FP64 form at 1e-6 Ha"
 PEAK_HBM = 8000.0                         # GB/s, MI355X HBM3E
 PEAK = {"fp64": 78.6, "fp32": 157.3}      # TFLOP/s, MI355X dense FP64 / FP32 (vector = matrix)
@@ -163,7 +165,6 @@ def measured_traffic(kernel: str, config: str, precision: str, seed: int):
     """HBM bytes per launch of the kernel from the committed counter summary, or None."""
     if config != "water4096" or precision != "fp64" or seed != 1 or not os.path.exists(TRAFFIC):
         return None
-    from paper_1402_2880_amd.prof_summary import source_sha256
     rec = json.load(open(TRAFFIC))
     if source_sha256() != rec.get("kernel_source_sha256"):
         return None
@@ -419,6 +420,7 @@ def main():
         "step_roofline": step_roof,
         "kernels": classes,
         "paper_context": PAPER_CONTEXT,
+        "kernel_source_sha256": source_sha256(),
     }
     out["memory"] = dict(device_gb=round(mem["device_bytes"] / 1e9, 3), tile_slots=mem["tile_slots"],
                          tile_slots_y=mem["tile_slots_y"],

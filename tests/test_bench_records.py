@@ -45,13 +45,14 @@ def test_contract_fields(path):
 
 
 def test_default_line_has_baseline_and_traffic():
+    """The default line carries the oracle baseline; it carries the counter-measured traffic
+    whenever it was taken on the kernel sources the counters were taken on."""
     d = load(os.path.join(ROOT, "profiles", "bench_water4096_fp64.json"))
     cpu = d["cpu_baseline"]
     assert cpu["kind"] == "oracle" and cpu["cores"] >= 1 and cpu["value"] > 0 and cpu["sample"]
-    assert d["roofline"]["traffic"] is not None and d["hbm"]["gb_per_step"] > 0
     traffic = json.load(open(os.path.join(ROOT, "profiles", "traffic_water4096_fp64.json")))
-    import hashlib
-    src = os.path.join(ROOT, "paper_1402_2880_amd", "csrc", "sscf_kernels.hip")
-    if traffic["kernel_source_sha256"] != hashlib.sha256(open(src, "rb").read()).hexdigest():
-        pytest.skip("kernel source changed since the counters were taken: bench reports traffic null "
-                    "until the counter runs are repeated")
+    assert traffic["class_kernel"][d["roofline"]["kernel"]] in traffic["kernels"]
+    if d.get("kernel_source_sha256") == traffic["kernel_source_sha256"]:
+        assert d["roofline"]["traffic"] is not None
+    else:
+        assert d["roofline"]["traffic"] is None
