@@ -365,6 +365,13 @@ sscf_status sscf_init_info(const sscf_ctx* ctx, sscf_step_info* info);
 sscf_status sscf_get_schedule(const sscf_ctx* ctx, int32_t* g, int32_t* h, int32_t* round,
                               int32_t* n_blocks);
 
+/* The rotations (section 3.5) the last step selected and applied, as (occupied MO, virtual MO)
+ * pairs in the order of application within each Jacobi block (decreasing |F_ia|), block by
+ * block in the order of sscf_get_schedule: occ[k], virt[k] for k < *n.  Call with occ == NULL
+ * to get *n (0 before the first step); with arrays, *n gives their room (SSCF_E_INVALID_ARG if
+ * too small).  Host arrays, caller-owned. */
+sscf_status sscf_get_rotations(const sscf_ctx* ctx, int32_t* occ, int32_t* virt, int64_t* n);
+
 /* Work and time of the main kernel classes, accumulated over the steps, set-up and step III
  * calls since initialization (or the last reset).  Classes: spmm_tiles (the products Y = X C:
  * H C of C^T H C, S C of each orthonormalization sweep, H0 C_occ of the band energy),

@@ -958,6 +958,7 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
   x->Fdiag = x->dalloc<double>((size_t)G * v.W);
   x->dvec = x->dalloc<double>((size_t)G * v.W);
   x->rot_cnt = x->dalloc<int>(x->n_blocks);
+  HIPC(hipMemsetAsync(x->rot_cnt, 0, sizeof(int) * x->n_blocks, s));
   x->rot_slot = x->dalloc<int2>((size_t)x->n_blocks * per);
   if (x->precision == SSCF_FP32_MIXED) {
     x->H32 = x->dalloc<float>(nxe);
@@ -1852,6 +1853,39 @@ sscf_status sscf_get_schedule(const sscf_ctx* x, int32_t* g, int32_t* h, int32_t
   }
   *n_blocks = x->n_blocks;
   return SSCF_OK;
+}
+
+sscf_status sscf_get_rotations(const sscf_ctx* cx, int32_t* occ, int32_t* virt, int64_t* n) {
+  sscf_ctx* x = const_cast<sscf_ctx*>(cx);
+  if (!x || !n) return SSCF_E_INVALID_ARG;
+  return guarded(x, [&] {
+    const View& v = x->v;
+    const size_t per = (size_t)v.OW * v.VW;
+    std::vector<int> cnt(x->n_blocks);
+    HIPC(hipMemcpyAsync(cnt.data(), x->rot_cnt, sizeof(int) * cnt.size(), hipMemcpyDeviceToHost, x->stream));
+    x->sync();
+    int64_t tot = 0;
+    for (int c : cnt) tot += c;
+    if (occ && virt) {
+      if (*n < tot) fail(SSCF_E_INVALID_ARG, "room for %lld rotations, %lld selected", (long long)*n, (long long)tot);
+      std::vector<int2> sl((size_t)x->n_blocks * per);
+      std::vector<int> tc((size_t)x->n_blocks * v.W);
+      HIPC(hipMemcpyAsync(sl.data(), x->rot_slot, sizeof(int2) * sl.size(), hipMemcpyDeviceToHost, x->stream));
+      HIPC(hipMemcpyAsync(tc.data(), x->tcol, sizeof(int) * tc.size(), hipMemcpyDeviceToHost, x->stream));
+      x->sync();
+      int64_t k = 0;
+      for (int b = 0; b < x->n_blocks; ++b) {
+        const int g = x->h_jb_g[b], h = x->h_jb_h[b];
+        for (int q = 0; q < cnt[b]; ++q) {
+          const int2 r = sl[(size_t)b * per + q];
+          occ[k] = x->h_mo_of[(size_t)g * v.W + tc[(size_t)b * v.W + r.x]];
+          virt[k] = x->h_mo_of[(size_t)h * v.W + tc[(size_t)b * v.W + r.y]];
+          ++k;
+        }
+      }
+    }
+    *n = tot;
+  });
 }
 
 sscf_status sscf_get_kernel_stats(const sscf_ctx* cx, sscf_kernel_stat* out, int32_t* n) {

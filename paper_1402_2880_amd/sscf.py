@@ -99,7 +99,7 @@ class KernelStat(ct.Structure):
 
 EXPORTS = ["sscf_get_kernel_stats", "sscf_reset_kernel_stats", "sscf_init_system", "sscf_set_fock", "sscf_scf_step", "sscf_get_energy",
            "sscf_get_density", "sscf_get_charges", "sscf_get_mo_coefficients", "sscf_init_info",
-           "sscf_get_schedule", "sscf_get_energy_gradient", "sscf_get_energy_gradient_device",
+           "sscf_get_schedule", "sscf_get_rotations", "sscf_get_energy_gradient", "sscf_get_energy_gradient_device",
            "sscf_set_control", "sscf_get_control",
            "sscf_orthonormalize", "sscf_fragment_guess", "sscf_constrained_kmeans", "sscf_atom_neighbours",
            "sscf_atom_neighbours_noalloc", "sscf_memory_info",
@@ -138,6 +138,7 @@ def lib():
         L.sscf_get_mo_coefficients.argtypes = [vp, vp, vp, vp, ct.POINTER(i64)]
         L.sscf_init_info.argtypes = [vp, ct.POINTER(StepInfo)]
         L.sscf_get_schedule.argtypes = [vp, vp, vp, vp, ct.POINTER(i32)]
+        L.sscf_get_rotations.argtypes = [vp, vp, vp, ct.POINTER(i64)]
         L.sscf_get_kernel_stats.argtypes = [vp, vp, ct.POINTER(i32)]
         L.sscf_reset_kernel_stats.argtypes = [vp]
         L.sscf_destroy.argtypes = [vp]
@@ -356,6 +357,15 @@ class SparseSCF:
         r = np.zeros_like(g)
         self._check(lib().sscf_get_schedule(self._h, _p(g), _p(h), _p(r), ct.byref(n)))
         return g[:n.value], h[:n.value], r[:n.value]
+
+    def rotations(self):
+        """(occupied MO, virtual MO) of each rotation the last step applied (see sscf_get_rotations)."""
+        n = ct.c_int64(0)
+        self._check(lib().sscf_get_rotations(self._h, None, None, ct.byref(n)))
+        i = np.zeros(max(n.value, 1), dtype=np.int32)
+        a = np.zeros_like(i)
+        self._check(lib().sscf_get_rotations(self._h, _p(i), _p(a), ct.byref(n)))
+        return i[:n.value], a[:n.value]
 
 
 def _converged(system, H0_val, S_val, opts):
