@@ -1968,26 +1968,53 @@ __global__ void __launch_bounds__(256) k_spmm_row(int G, int n_rb, int nchunk, c
       mk = actC[pb + c] ? (cmask[pb + c] & smask) : 0u;
     }
     unsigned long long m = __ballot(mk != 0u);
-    while (m) {
-      const int j = __ffsll((long long)m) - 1;
-      m &= m - 1ull;
+    if (!m) continue;
+    // X blocks are read once per group and mostly miss L2: the next product's X block is
+    // loaded while the current one's C slices load and multiply
+    int j = __ffsll((long long)m) - 1;
+    m &= m - 1ull;
+    Real xn[4];
+    {
+      const Real* Xb = X + (size_t)(base + j) * 256 + lr * 16 + lk;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) xn[s] = Xb[4 * s];
+    }
+    for (;;) {
       const int cj = __shfl(c, j);
       const unsigned int mj = __builtin_amdgcn_readfirstlane(__shfl((int)mk, j));
-      const Real* Xb = X + (size_t)(base + j) * 256 + lr * 16 + lk;
-      const Real* Ct = C + (size_t)slot[pb + cj] * (RB * W) + lk * W + lr;
-      Real xa[4], cb[4][NT];
+      Real xa[4];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) xa[s] = Xb[4 * s];
+      for (int s = 0; s < 4; ++s) xa[s] = xn[s];
+      // k-steps (4 columns of the X block) that hold a nonzero: the others add exact zeros,
+      // and their C rows are not read
+      unsigned int km = 0xFu;
+      if constexpr (sizeof(Real) == sizeof(double)) {
+        km = 0u;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          if (__ballot(xa[s] != Real(0))) km |= 1u << s;
+      }
+      const Real* Ct = C + (size_t)slot[pb + cj] * (RB * W) + lk * W + lr;
+      Real cb[4][NT];
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int n = 0; n < NT; ++n) cb[s][n] = ((mj >> n) & 1u) ? Ct[4 * s * W + n * 16] : Real(0);
+        for (int n = 0; n < NT; ++n)
+          cb[s][n] = (((mj >> n) & 1u) && ((km >> s) & 1u)) ? Ct[4 * s * W + n * 16] : Real(0);
+      int jn = -1;
+      if (m) {
+        jn = __ffsll((long long)m) - 1;
+        m &= m - 1ull;
+        const Real* Xb = X + (size_t)(base + jn) * 256 + lr * 16 + lk;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) xn[s] = Xb[4 * s];
+      }
       if constexpr (sizeof(Real) == sizeof(double)) {
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
           for (int n = 0; n < NT; ++n)
-            if ((mj >> n) & 1u) {
+            if (((mj >> n) & 1u) && ((km >> s) & 1u)) {
               acc[n] = Mfma<Real>::op(xa[s], cb[s][n], acc[n]);
               ++n_mfma;
             }
@@ -2000,6 +2027,8 @@ __global__ void __launch_bounds__(256) k_spmm_row(int G, int n_rb, int nchunk, c
           for (int n = 0; n < NT; ++n) acc[n] = Mfma<Real>::op(xa[s], cb[s][n], acc[n]);
         n_mfma += 4 * NT;
       }
+      if (jn < 0) break;
+      j = jn;
     }
   }
   Real* Yt = Y + (size_t)slotY[pb + r] * (RB * W);
