@@ -283,13 +283,24 @@ __global__ void __launch_bounds__(256) k_pair(int n_rb, int W, const int* __rest
 #pragma unroll
           for (int jj = 0; jj < NW; ++jj) b[s][jj] = (mb & (1u << jj)) ? Yt[ro + jj * 16] : 0.0;
         }
+        // a k-step (4 rows) of a slice that is all zero on either side adds exact zeros
+        unsigned int za = 0u, zb = 0u;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+#pragma unroll
+          for (int i = 0; i < MW; ++i)
+            if (__ballot(a[s][i] != 0.0)) za |= 1u << (s * MW + i);
+#pragma unroll
+          for (int jj = 0; jj < NW; ++jj)
+            if (__ballot(b[s][jj] != 0.0)) zb |= 1u << (s * NW + jj);
+        }
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
           for (int i = 0; i < MW; ++i)
 #pragma unroll
             for (int jj = 0; jj < NW; ++jj)
-              if ((ma & (1u << i)) && (mb & (1u << jj))) {
+              if (((za >> (s * MW + i)) & 1u) && ((zb >> (s * NW + jj)) & 1u)) {
                 acc[i][jj] = mfma64(a[s][i], b[s][jj], acc[i][jj]);
                 ++n_mfma;
               }
