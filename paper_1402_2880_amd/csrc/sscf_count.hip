@@ -15,7 +15,9 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
   return v;
 }
 
-// block of 256 threads: sum of v added to *out (one atomic per block)
+// block of 256 threads: sum of v added to *out (one atomic per block).  Every thread of the
+// block calls it; the closing barrier keeps a following call's writes to red from overtaking
+// thread 0's reads of this one.
 __device__ void block_add(unsigned long long v, unsigned long long* out) {
   __shared__ unsigned long long red[4];
   v = wave_sum_u64(v);
@@ -25,6 +27,7 @@ __device__ void block_add(unsigned long long v, unsigned long long* out) {
     const unsigned long long s = red[0] + red[1] + red[2] + red[3];
     if (s) atomicAdd(out, s);
   }
+  __syncthreads();
 }
 
 // Nonzeros of each AO row of X (16 x 16 blocks on the row-block pattern) into xrow (added;

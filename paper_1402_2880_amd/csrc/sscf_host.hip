@@ -387,7 +387,7 @@ struct sscf_ctx {
       HIPC(hipMemsetAsync(&sd->err, 0, sizeof(int), stream));
       launch_ortho_scale(v, v.G, self_pair, O, pnocc, pnvirt, occ_only, sc, sd, stream);
       launch_normalize_d(v, n_pairs, pg, ph, O, Dt, sc, pnocc, pnvirt, occ_only, sd, stream);
-      launch_scale_c(v, C[cur], listC[cur], cntC[cur], sc, stream);
+      launch_scale_c(v, C[cur], listC[cur], cntC[cur], cmask[cur], sc, stream);
       const Scalars h = read_scalars();
       if (h.err & 1) fail(SSCF_E_NOT_SPD, "C^T S C has a non-positive diagonal element");
       double eta;
@@ -432,7 +432,7 @@ struct sscf_ctx {
     launch_coulomb(v, scc, dq, part, Q, stream);
     launch_sum_coul(v, scc && !fock_full, dq, Q, sd, stream);
     product(fock_full ? Hfull : H0, false, true);   // support of C unchanged since the last dilation
-    launch_coldot(v, C[cur], listC[cur], cntC[cur], Y, actY, part, dvec, stream);
+    launch_coldot(v, C[cur], listC[cur], cntC[cur], cmask[cur], Y, actY, part, dvec, stream);
     launch_sum_band(v, dvec, pnocc, sd, stream);
   }
 
@@ -894,6 +894,16 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
     x->n_slots_y = (size_t)std::max<int64_t>(nsy, 1);
     x->slotY = x->upload(slotY.data(), slotY.size());
     v.slotY = x->slotY;
+    v.max_c = v.max_y = 1;
+    for (int g = 0; g < G; ++g) {
+      int nc = 0, ny = 0;
+      for (int r = 0; r < v.n_rb; ++r) {
+        nc += slot[(size_t)g * v.n_rb + r] >= 0;
+        ny += slotY[(size_t)g * v.n_rb + r] >= 0;
+      }
+      v.max_c = std::max(v.max_c, nc);
+      v.max_y = std::max(v.max_y, ny);
+    }
   }
   const size_t nslot = x->n_slots, nslot_y = x->n_slots_y;
   // one pool of C values (C[0] and C[1] are the same memory: see orthonormalize), two sets of
@@ -1071,7 +1081,7 @@ static void step(sscf_ctx* x, sscf_step_info* out) {
     launch_dilate(v, x->actC[x->cur], x->actY, s);
     launch_list(v, x->actY, x->listY, x->cntY, s);
     pi = x->pbegin(KC_SPMM);
-    launch_round_c32(v, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur], x->C32, s);
+    launch_round_c32(v, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur], x->cmask[x->cur], x->C32, s);
     launch_spmm32(v, x->H32, x->C32, x->actC[x->cur], x->cmask[x->cur], x->listY, x->cntY, x->Y32, x->ymask,
                   x->ctr(KC_SPMM), s);
     x->pend(pi);
@@ -1084,7 +1094,7 @@ static void step(sscf_ctx* x, sscf_step_info* out) {
     if (x->wc())
       x->count_pairs(KC_PAIR_F, x->n_blocks, x->jb_g, x->jb_h, x->C32, x->Y32, true, 0, v.OW, v.OW, v.W, 0,
                      x->fock_pairs());
-    launch_coldot32(v, x->C32, x->listC[x->cur], x->cntC[x->cur], x->Y32, x->actY, x->Fdiag, s);
+    launch_coldot32(v, x->C32, x->listC[x->cur], x->cntC[x->cur], x->cmask[x->cur], x->Y32, x->actY, x->Fdiag, s);
   } else {
     x->product(x->H, true);
     pi = x->pbegin(KC_PAIR_F);
@@ -1095,7 +1105,8 @@ static void step(sscf_ctx* x, sscf_step_info* out) {
     if (x->wc())
       x->count_pairs(KC_PAIR_F, x->n_blocks, x->jb_g, x->jb_h, x->C[x->cur], x->Y, false, 0, v.OW, v.OW, v.W, 0,
                      x->fock_pairs());
-    launch_coldot(v, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur], x->Y, x->actY, x->part, x->Fdiag, s);
+    launch_coldot(v, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur], x->cmask[x->cur], x->Y, x->actY, x->part,
+                  x->Fdiag, s);
   }
   HIPC(hipEventRecord(x->ev[2], s));
   // step V: selection of the rotations

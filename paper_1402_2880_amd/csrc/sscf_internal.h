@@ -80,6 +80,7 @@ struct View {
   // to a tile of C with a slot, so a product never falls outside it.
   const int* slot;
   const int* slotY;
+  int max_c, max_y;   // the most tiles with a slot in any one group (C, Y): bounds a panel's lists
   int* cap_err;
 };
 
@@ -101,16 +102,16 @@ void launch_pair(const View& v, int n_pairs, const int* perm, int maxc, const in
                  const uint8_t* actY, const unsigned int* ymask, int row_off, int MT, int col_off,
                  int NT, double* out, int ld, size_t out_stride, unsigned long long* ctr,
                  hipStream_t s);
-void launch_coldot(const View& v, const double* C, const int* listC, const int* cntC, const double* Y,
-                   const uint8_t* actY, double* part, double* out, hipStream_t s);
+void launch_coldot(const View& v, const double* C, const int* listC, const int* cntC, const unsigned int* cmask,
+                   const double* Y, const uint8_t* actY, double* part, double* out, hipStream_t s);
 void launch_ortho_scale(const View& v, int n_pairs_self, const int* self_pair, const double* O,
                         const int* pnocc, const int* pnvirt, int occ_only, double* sc,
                         Scalars* sd, hipStream_t s);
 void launch_normalize_d(const View& v, int n_pairs, const int* pg, const int* ph, double* O,
                         double* Dt, const double* sc, const int* pnocc, const int* pnvirt,
                         int occ_only, Scalars* sd, hipStream_t s);
-void launch_scale_c(const View& v, double* C, const int* listC, const int* cntC, const double* sc,
-                    hipStream_t s);
+void launch_scale_c(const View& v, double* C, const int* listC, const int* cntC, const unsigned int* cmask,
+                    const double* sc, hipStream_t s);
 void launch_mark_selected(const View& v, int n_pairs, const int* pg, const int* ph, const double* D,
                           const Scalars* sd, uint8_t* pair_sel, uint8_t* upd, uint8_t* rmask, int* nsel,
                           hipStream_t s);
@@ -183,8 +184,9 @@ void launch_pair32(const View& v, int n_pairs, const int* perm, int maxc, const 
                    const uint8_t* actY, const unsigned int* ymask, int row_off, int MT, int col_off,
                    int NT, double* out, int ld, size_t out_stride, unsigned long long* ctr,
                    hipStream_t s);
-void launch_round_c32(const View& v, const double* C, const int* list, const int* cnt, float* C32, hipStream_t s);
-void launch_coldot32(const View& v, const float* C, const int* listC, const int* cntC,
+void launch_round_c32(const View& v, const double* C, const int* list, const int* cnt, const unsigned int* cmask,
+                      float* C32, hipStream_t s);
+void launch_coldot32(const View& v, const float* C, const int* listC, const int* cntC, const unsigned int* cmask,
                      const float* Y, const uint8_t* actY, double* out, hipStream_t s);
 void launch_charges_rows(const View& v, const double* C, const uint8_t* actC, const double* Y,
                          const uint8_t* actY, const double* sc, const int* pnocc, double* rowq,

@@ -343,14 +343,15 @@ void launch_pair(const View& v, int n_pairs, const int* perm, int maxc, const in
 // the parts' sums are added in a fixed order by k_coldot_sum.
 
 __global__ void k_coldot(int n_rb, int W, const int* slot, const int* slotY, const double* C, const int* listC,
-                         const int* cntC, const double* Y, const uint8_t* actY, double* part) {
+                         const int* cntC, const unsigned int* cmask, const double* Y, const uint8_t* actY,
+                         double* part) {
   const int g = blockIdx.x, sp = blockIdx.y, c = threadIdx.x;
   if (c >= W) return;
   const size_t gb = (size_t)g * n_rb;
   double s = 0.0;
   for (int t = sp; t < cntC[g]; t += CD_SPLIT) {
     const int r = listC[gb + t];
-    if (!actY[gb + r]) continue;
+    if (!actY[gb + r] || !((cmask[gb + r] >> (c >> 4)) & 1u)) continue;   // a zero slice adds zeros
     const double* Ct = C + (size_t)slot[gb + r] * (RB * W) + c;
     const double* Yt = Y + (size_t)slotY[gb + r] * (RB * W) + c;
 #pragma unroll
@@ -365,10 +366,10 @@ __global__ void k_coldot_sum(size_t n, const double* part, double* out) {
   for (int sp = 0; sp < CD_SPLIT; ++sp) s += part[(size_t)sp * n + i];
   out[i] = s;
 }
-void launch_coldot(const View& v, const double* C, const int* listC, const int* cntC, const double* Y,
-                   const uint8_t* actY, double* part, double* out, hipStream_t s) {
+void launch_coldot(const View& v, const double* C, const int* listC, const int* cntC, const unsigned int* cmask,
+                   const double* Y, const uint8_t* actY, double* part, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_coldot, dim3(v.G, CD_SPLIT), dim3(v.W <= 64 ? 64 : (v.W <= 128 ? 128 : 256)), 0, s, v.n_rb,
-                     v.W, v.slot, v.slotY, C, listC, cntC, Y, actY, part);
+                     v.W, v.slot, v.slotY, C, listC, cntC, cmask, Y, actY, part);
   const size_t n = (size_t)v.G * v.W;
   hipLaunchKernelGGL(k_coldot_sum, dim3(nblk(n, 256)), dim3(256), 0, s, n, part, out);
 }
@@ -445,17 +446,28 @@ void launch_normalize_d(const View& v, int n_pairs, const int* pg, const int* ph
                        occ_only, sd);
 }
 
+// Workgroups per group of the kernels that stride over a group's listed tiles (the lists are
+// on the device, so the grid cannot be sized by their lengths)
+constexpr int TILE_STRIDE_WG = 64;
+
 __global__ void __launch_bounds__(256) k_scale_c(int n_rb, int W, const int* slot, double* C, const int* listC,
-                                                 const int* cntC, const double* sc) {
-  const int g = blockIdx.y, t = blockIdx.x;
-  if (t >= cntC[g]) return;
-  const size_t tile = (size_t)g * n_rb + listC[(size_t)g * n_rb + t];
-  double* Ct = C + (size_t)slot[tile] * (RB * W);
+                                                 const int* cntC, const unsigned int* cmask, const double* sc) {
+  const int g = blockIdx.y;
   const double* s = sc + (size_t)g * W;
-  for (int e = threadIdx.x; e < RB * W; e += 256) Ct[e] = Ct[e] / s[e % W];
+  for (int t = blockIdx.x; t < cntC[g]; t += gridDim.x) {
+    const size_t tile = (size_t)g * n_rb + listC[(size_t)g * n_rb + t];
+    double* Ct = C + (size_t)slot[tile] * (RB * W);
+    const unsigned int cm = cmask[tile];
+    for (int e = threadIdx.x; e < RB * W; e += 256) {
+      const int c = e % W;
+      if ((cm >> (c >> 4)) & 1u) Ct[e] = Ct[e] / s[c];     // a zero slice stays zero
+    }
+  }
 }
-void launch_scale_c(const View& v, double* C, const int* listC, const int* cntC, const double* sc, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_c, dim3(v.n_rb, v.G), dim3(256), 0, s, v.n_rb, v.W, v.slot, C, listC, cntC, sc);
+void launch_scale_c(const View& v, double* C, const int* listC, const int* cntC, const unsigned int* cmask,
+                    const double* sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_c, dim3(std::min(v.n_rb, TILE_STRIDE_WG), v.G), dim3(256), 0, s, v.n_rb, v.W, v.slot, C,
+                     listC, cntC, cmask, sc);
 }
 
 // Per pair: flag it when any |D| >= 1e-3 eta, flag the MOs that take part, and record for
@@ -649,7 +661,7 @@ __global__ void __launch_bounds__(256) k_pack_cols(int G, int n_rb, int nchunk, 
 
 void launch_tile_flags(const View& v, const double* C, const int* list, const int* cnt, uint8_t* act,
                        unsigned int* cmask, ulonglong2* colm, hipStream_t s) {
-  const int nchunk = (v.n_rb + 3) / 4;
+  const int nchunk = (v.max_c + 3) / 4;
   dim3 grid(xcd_grid(v.G, nchunk)), blk(256);
   switch (v.W / 16) {
 #define SSCF_TF(NT) case NT: hipLaunchKernelGGL(k_tile_flags<NT>, grid, blk, 0, s, v.G, v.n_rb, nchunk, v.slot, C, list, cnt, act, cmask, colm); break;
@@ -660,7 +672,7 @@ void launch_tile_flags(const View& v, const double* C, const int* list, const in
 
 void launch_pack_cols(const View& v, const double* C, const int* list, const int* cnt, int col_end, double* P,
                       uint8_t* cidx, uint8_t* ncol, hipStream_t s) {
-  const int nchunk = (v.n_rb + 3) / 4;
+  const int nchunk = (v.max_c + 3) / 4;
   dim3 grid(xcd_grid(v.G, nchunk)), blk(256);
   switch (v.W / 16) {
 #define SSCF_PK(NT) case NT: hipLaunchKernelGGL(k_pack_cols<NT>, grid, blk, 0, s, v.G, v.n_rb, nchunk, v.slot, v.slotY, C, list, cnt, col_end, P, cidx, ncol); break;
@@ -1780,7 +1792,7 @@ __global__ void __launch_bounds__(256) k_apply_occ(int G, int n_rb, int W, int n
 void launch_apply_occ(const View& v, const double* C, const uint8_t* actC, const int* gn_ptr, const int* gn,
                       const int* pair_of, const int* pg, const double* FA, const double* FB, const int* listZ,
                       const int* cntZ, double* Z, hipStream_t s) {
-  const int nchunk = (v.n_rb + 3) / 4;
+  const int nchunk = (v.max_y + 3) / 4;
   dim3 grid(xcd_grid(v.G, nchunk)), blk(256);
   switch (v.OW / 16) {
 #define SSCF_APO(NO) case NO: hipLaunchKernelGGL(k_apply_occ<NO>, grid, blk, 0, s, v.G, v.n_rb, v.W, nchunk, v.slot, v.slotY, C, actC, gn_ptr, gn, pair_of, pg, FA, FB, listZ, cntZ, Z); break;
@@ -1797,17 +1809,25 @@ void launch_apply_occ(const View& v, const double* C, const uint8_t* actC, const
 // step for the active tiles (k_round_c32), so every product reads half the bytes.
 // ---------------------------------------------------------------------------------------
 
+// (only the nonzero 16-column slices: the FP32 kernels read no other slice of C32)
 __global__ void __launch_bounds__(256) k_round_c32(int n_rb, int W, const int* __restrict__ slot,
                                                    const double* __restrict__ C,
                                                    const int* __restrict__ list, const int* __restrict__ cnt,
+                                                   const unsigned int* __restrict__ cmask,
                                                    float* __restrict__ C32) {
-  const int g = blockIdx.y, t = blockIdx.x;
-  if (t >= cnt[g]) return;
-  const size_t base = (size_t)slot[(size_t)g * n_rb + list[(size_t)g * n_rb + t]] * (size_t)(RB * W);
-  for (int e = threadIdx.x; e < RB * W; e += 256) C32[base + e] = (float)C[base + e];
+  const int g = blockIdx.y;
+  for (int t = blockIdx.x; t < cnt[g]; t += gridDim.x) {
+    const size_t tile = (size_t)g * n_rb + list[(size_t)g * n_rb + t];
+    const size_t base = (size_t)slot[tile] * (size_t)(RB * W);
+    const unsigned int cm = cmask[tile];
+    for (int e = threadIdx.x; e < RB * W; e += 256)
+      if ((cm >> ((e % W) >> 4)) & 1u) C32[base + e] = (float)C[base + e];
+  }
 }
-void launch_round_c32(const View& v, const double* C, const int* list, const int* cnt, float* C32, hipStream_t s) {
-  hipLaunchKernelGGL(k_round_c32, dim3(v.n_rb, v.G), dim3(256), 0, s, v.n_rb, v.W, v.slot, C, list, cnt, C32);
+void launch_round_c32(const View& v, const double* C, const int* list, const int* cnt, const unsigned int* cmask,
+                      float* C32, hipStream_t s) {
+  hipLaunchKernelGGL(k_round_c32, dim3(std::min(v.n_rb, TILE_STRIDE_WG), v.G), dim3(256), 0, s, v.n_rb, v.W, v.slot,
+                     C, list, cnt, cmask, C32);
 }
 
 template <int MW, int NW>
@@ -1915,14 +1935,15 @@ void launch_pair32(const View& v, int n_pairs, const int* perm, int maxc, const 
 }
 
 __global__ void k_coldot32(int n_rb, int W, const int* slot, const int* slotY, const float* C, const int* listC,
-                           const int* cntC, const float* Y, const uint8_t* actY, double* out) {
+                           const int* cntC, const unsigned int* cmask, const float* Y, const uint8_t* actY,
+                           double* out) {
   const int g = blockIdx.x, c = threadIdx.x;
   if (c >= W) return;
   const size_t gb = (size_t)g * n_rb;
   float s = 0.f;
   for (int t = 0; t < cntC[g]; ++t) {
     const int r = listC[gb + t];
-    if (!actY[gb + r]) continue;
+    if (!actY[gb + r] || !((cmask[gb + r] >> (c >> 4)) & 1u)) continue;   // a zero slice adds zeros
     const float* Ct = C + (size_t)slot[gb + r] * (RB * W) + c;
     const float* Yt = Y + (size_t)slotY[gb + r] * (RB * W) + c;
 #pragma unroll
@@ -1930,10 +1951,10 @@ __global__ void k_coldot32(int n_rb, int W, const int* slot, const int* slotY, c
   }
   out[(size_t)g * W + c] = (double)s;
 }
-void launch_coldot32(const View& v, const float* C, const int* listC, const int* cntC, const float* Y,
-                     const uint8_t* actY, double* out, hipStream_t s) {
+void launch_coldot32(const View& v, const float* C, const int* listC, const int* cntC, const unsigned int* cmask,
+                     const float* Y, const uint8_t* actY, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_coldot32, dim3(v.G), dim3(v.W <= 64 ? 64 : (v.W <= 128 ? 128 : 256)), 0, s, v.n_rb, v.W,
-                     v.slot, v.slotY, C, listC, cntC, Y, actY, out);
+                     v.slot, v.slotY, C, listC, cntC, cmask, Y, actY, out);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -2064,7 +2085,7 @@ template <typename Real>
 static void launch_spmm_row(const View& v, const Real* X, const Real* C, const uint8_t* actC,
                             const unsigned int* cmask, const int* listY, const int* cntY, Real* Y,
                             unsigned int* ymask, unsigned int smask, unsigned long long* ctr, hipStream_t s) {
-  const int nchunk = (v.n_rb + 3) / 4;
+  const int nchunk = (v.max_y + 3) / 4;
   dim3 grid(xcd_grid(v.G, nchunk)), blk(256);
   switch (v.W / 16) {
 #define SSCF_SPR(NT) case NT: hipLaunchKernelGGL((k_spmm_row<NT, Real>), grid, blk, 0, s, v.G, v.n_rb, nchunk, v.slot, v.slotY, v.xs_ptr, v.xs_col, X, C, actC, cmask, listY, cntY, Y, ymask, smask, ctr); break;

@@ -15,7 +15,7 @@ from typing import Dict, Optional
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsscf.so")
+LIB_PATH = os.environ.get("SSCF_LIB") or os.path.join(HERE, "libsscf.so")
 
 SSCF_OK = 0
 STATUS_CAPACITY = -6
@@ -166,16 +166,20 @@ def _torch_allocator(device):
     import torch
 
     live = {}
+    alloc, delete = torch.cuda.caching_allocator_alloc, torch.cuda.caching_allocator_delete
 
     def _alloc(_self, nbytes, stream):
-        ptr = torch.cuda.caching_allocator_alloc(int(nbytes), device)
+        ptr = alloc(int(nbytes), device)
         live[ptr] = nbytes
         return ptr
 
     def _free(_self, ptr, stream):
         if ptr in live:
             del live[ptr]
-            torch.cuda.caching_allocator_delete(ptr)
+            try:
+                delete(ptr)
+            except Exception:       # interpreter shutdown: torch is already torn down
+                pass
 
     return ALLOC_FN(_alloc), FREE_FN(_free)
 
