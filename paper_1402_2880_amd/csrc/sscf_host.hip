@@ -119,6 +119,7 @@ struct sscf_ctx {
   unsigned int* ymask = nullptr;
   int *listY = nullptr, *cntY = nullptr;
   uint8_t* act_tmp = nullptr;
+  int *listT = nullptr, *cntT = nullptr;   // per row block, the groups active in C there
   int *list_tmp = nullptr, *cnt_tmp = nullptr;
   int *pnocc = nullptr, *pnvirt = nullptr, *mo_of = nullptr;
   int *gn_ptr = nullptr, *gn = nullptr, *pair_of = nullptr, *pg = nullptr, *ph = nullptr, *self_pair = nullptr;
@@ -421,7 +422,8 @@ struct sscf_ctx {
 
   // Mulliken charges from C and Y = S C of the last orthonormalization pass
   void charges(int shift_prev) {
-    launch_charges_rows(v, C[cur], actC[cur], Y, actY, sc, pnocc, rowq, stream);
+    launch_list_t(v, actC[cur], listT, cntT, stream);
+    launch_charges_rows(v, C[cur], listT, cntT, Y, actY, sc, pnocc, rowq, stream);
     HIPC(hipMemsetAsync(&sd->dq_bits, 0, sizeof(unsigned long long), stream));
     launch_atom_charges(v, ao_off, rowq, q, q_prev, dq, sd, shift_prev, stream);
   }
@@ -467,8 +469,9 @@ struct sscf_ctx {
     launch_list(v, act_tmp, list_tmp, cnt_tmp, s);
     launch_apply_occ(v, C[cur], actC[cur], gn_ptr, gn, pair_of, pg, foo_a, foo_b, list_tmp, cnt_tmp, Y, s);
     // P = 2 C_occ C_occ^T and W = 2 C_occ Z^T on the pattern of S, then the layout of S_val
-    launch_density_blocks(v, C[cur], actC[cur], C[cur], actC[cur], false, pblk, s);
-    launch_density_blocks(v, C[cur], actC[cur], Y, act_tmp, true, wblk, s);
+    launch_list_t(v, actC[cur], listT, cntT, s);
+    launch_density_blocks(v, C[cur], listT, cntT, C[cur], actC[cur], false, pblk, s);
+    launch_density_blocks(v, C[cur], listT, cntT, Y, act_tmp, true, wblk, s);
     launch_grad_assemble(v, n_val, val_map, pblk, wblk, Q, scc && !fock_full, dX, dS, s);
     if (don) launch_grad_onsite(v, ao_off, xs_diag, pblk, don, s);
   }
@@ -927,6 +930,8 @@ static void build(sscf_ctx* x, const sscf_system_desc* d) {
   x->act_tmp = x->dalloc<uint8_t>(ntiles);
   x->list_tmp = x->dalloc<int>(ntiles);
   x->cnt_tmp = x->dalloc<int>(G);
+  x->listT = x->dalloc<int>(ntiles);
+  x->cntT = x->dalloc<int>(v.n_rb);
   x->pnocc = x->upload(nocc.data(), G);
   x->pnvirt = x->upload(nvirt.data(), G);
   x->mo_of = x->upload(x->h_mo_of.data(), x->h_mo_of.size());
@@ -1776,7 +1781,9 @@ sscf_status sscf_get_density(const sscf_ctx* cx, double* p_val, size_t n_val) {
   return guarded(x, [&] {
     if (!x->pblk) x->pblk = x->dalloc<double>((size_t)x->v.nbx * 256);
     if (!x->pval) x->pval = x->dalloc<double>(x->n_val);
-    launch_density_blocks(x->v, x->C[x->cur], x->actC[x->cur], x->C[x->cur], x->actC[x->cur], false, x->pblk, x->stream);
+    launch_list_t(x->v, x->actC[x->cur], x->listT, x->cntT, x->stream);
+    launch_density_blocks(x->v, x->C[x->cur], x->listT, x->cntT, x->C[x->cur], x->actC[x->cur], false, x->pblk,
+                          x->stream);
     launch_gather(x->val_map, x->n_val, x->pblk, x->pval, x->stream);
     HIPC(hipMemcpyAsync(p_val, x->pval, sizeof(double) * x->n_val, hipMemcpyDeviceToHost, x->stream));
     x->sync();

@@ -93,6 +93,8 @@ void launch_scatter_c0(const View& v, int nnz, const int64_t* colptr_expanded_co
                        uint8_t* act, unsigned int* cmask, int* cap_err, hipStream_t s);
 void launch_dilate(const View& v, const uint8_t* actC, uint8_t* actY, hipStream_t s);
 void launch_list(const View& v, const uint8_t* act, int* list, int* cnt, hipStream_t s);
+// per row block, the groups active there (ascending): listT[r G + k], k < cntT[r]
+void launch_list_t(const View& v, const uint8_t* act, int* listT, int* cntT, hipStream_t s);
 void launch_spmm(const View& v, const double* X, const double* C, const uint8_t* actC,
                  const unsigned int* cmask, const int* listY, const int* cntY, double* Y,
                  unsigned int* ymask, unsigned int smask, unsigned long long* ctr, hipStream_t s);
@@ -188,16 +190,15 @@ void launch_round_c32(const View& v, const double* C, const int* list, const int
                       float* C32, hipStream_t s);
 void launch_coldot32(const View& v, const float* C, const int* listC, const int* cntC, const unsigned int* cmask,
                      const float* Y, const uint8_t* actY, double* out, hipStream_t s);
-void launch_charges_rows(const View& v, const double* C, const uint8_t* actC, const double* Y,
-                         const uint8_t* actY, const double* sc, const int* pnocc, double* rowq,
-                         hipStream_t s);
+void launch_charges_rows(const View& v, const double* C, const int* listTC, const int* cntTC, const double* Y,
+                         const uint8_t* actY, const double* sc, const int* pnocc, double* rowq, hipStream_t s);
 void launch_atom_charges(const View& v, const int64_t* ao_off, const double* rowq, double* q,
                          double* q_prev, double* dq, Scalars* sd, int shift_prev, hipStream_t s);
 void launch_sum_band(const View& v, const double* d, const int* pnocc, Scalars* sd, hipStream_t s);
 void launch_sum_coul(const View& v, int scc, const double* dq, const double* Q, Scalars* sd,
                      hipStream_t s);
-// B_is_y: B lives in the pool of Y (slotY), else in that of C
-void launch_density_blocks(const View& v, const double* A, const uint8_t* actA, const double* B,
+// listTA/cntTA: launch_list_t of A's activity; B_is_y: B lives in the pool of Y (slotY), else in that of C
+void launch_density_blocks(const View& v, const double* A, const int* listTA, const int* cntTA, const double* B,
                            const uint8_t* actB, bool B_is_y, double* P, hipStream_t s);
 void launch_grad_assemble(const View& v, int64_t n_val, const int64_t* map, const double* P, const double* Wb,
                           const double* Q, int qterm, double* dX, double* dS, hipStream_t s);

@@ -181,6 +181,35 @@ void launch_list(const View& v, const uint8_t* act, int* list, int* cnt, hipStre
   hipLaunchKernelGGL(k_list, dim3(v.G), dim3(256), 0, s, v.n_rb, act, list, cnt);
 }
 
+// The transposed lists: for row block r, the groups g with act[g][r] set, ascending, in
+// listT[r G ...] with their number in cntT[r] (kernels that sum over the groups of a row block
+// visit only these, in the order of a loop over all groups)
+__global__ void __launch_bounds__(256) k_list_t(int G, int n_rb, const uint8_t* act, int* listT, int* cntT) {
+  const int r = blockIdx.x;
+  __shared__ int wsum[4];
+  int* L = listT + (size_t)r * G;
+  int base_out = 0;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int base = 0; base < G; base += 256) {
+    const int g = base + threadIdx.x;
+    const bool f = g < G && act[(size_t)g * n_rb + r];
+    const unsigned long long m = __ballot(f);
+    const int pre = __popcll(m & ((1ULL << lane) - 1ULL));
+    if (lane == 0) wsum[w] = __popcll(m);
+    __syncthreads();
+    int off = base_out;
+    for (int i = 0; i < w; ++i) off += wsum[i];
+    if (f) L[off + pre] = g;
+    const int tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+    base_out += tot;
+  }
+  if (threadIdx.x == 0) cntT[r] = base_out;
+}
+void launch_list_t(const View& v, const uint8_t* act, int* listT, int* cntT, hipStream_t s) {
+  hipLaunchKernelGGL(k_list_t, dim3(v.n_rb), dim3(256), 0, s, v.G, v.n_rb, act, listT, cntT);
+}
+
 // ---------------------------------------------------------------------------------------
 // Workgroups go round-robin over the 8 XCDs of the chip, each with its own L2: linear
 // workgroup id L runs on XCD L % 8.  Kernels that work group by group decode L so that all
@@ -1573,14 +1602,18 @@ void launch_givens_rb(const View& v, int n_rounds, const int* roff, const int4* 
 
 __global__ void __launch_bounds__(256) k_charges_rows(int G, int n_rb, int n_ao, int W, const int* slot,
                                                       const int* slotY, const double* C,
-                                                      const uint8_t* actC, const double* Y, const uint8_t* actY,
-                                                      const double* sc, const int* pnocc, double* rowq) {
+                                                      const int* listTC, const int* cntTC, const double* Y,
+                                                      const uint8_t* actY, const double* sc, const int* pnocc,
+                                                      double* rowq) {
   const int rb = blockIdx.x;
   const int k = threadIdx.x >> 4, l = threadIdx.x & 15;
   double acc = 0.0;
-  for (int g = 0; g < G; ++g) {
+  const int* LC = listTC + (size_t)rb * G;
+  const int nc = cntTC[rb];
+  for (int i = 0; i < nc; ++i) {                 // the groups active in C at rb, ascending
+    const int g = LC[i];
     const size_t tile = (size_t)g * n_rb + rb;
-    if (!actC[tile] || !actY[tile]) continue;
+    if (!actY[tile]) continue;
     const int no = pnocc[g];
     const double* Cr = C + ((size_t)slot[tile] * RB + k) * W;
     const double* Yr = Y + ((size_t)slotY[tile] * RB + k) * W;
@@ -1593,10 +1626,10 @@ __global__ void __launch_bounds__(256) k_charges_rows(int G, int n_rb, int n_ao,
   const int mu = rb * RB + k;
   if (l == 0 && mu < n_ao) rowq[mu] = 2.0 * acc;
 }
-void launch_charges_rows(const View& v, const double* C, const uint8_t* actC, const double* Y, const uint8_t* actY,
-                         const double* sc, const int* pnocc, double* rowq, hipStream_t s) {
-  hipLaunchKernelGGL(k_charges_rows, dim3(v.n_rb), dim3(256), 0, s, v.G, v.n_rb, v.n_ao, v.W, v.slot, v.slotY, C, actC, Y, actY,
-                     sc, pnocc, rowq);
+void launch_charges_rows(const View& v, const double* C, const int* listTC, const int* cntTC, const double* Y,
+                         const uint8_t* actY, const double* sc, const int* pnocc, double* rowq, hipStream_t s) {
+  hipLaunchKernelGGL(k_charges_rows, dim3(v.n_rb), dim3(256), 0, s, v.G, v.n_rb, v.n_ao, v.W, v.slot, v.slotY, C,
+                     listTC, cntTC, Y, actY, sc, pnocc, rowq);
 }
 
 __global__ void k_atom_charges(int n_atoms, const int64_t* ao_off, const double* rowq, const double* q0, double* q,
@@ -1674,16 +1707,20 @@ void launch_sum_coul(const View& v, int scc, const double* dq, const double* Q, 
 __global__ void __launch_bounds__(256) k_density_blocks(int nbx, int G, int n_rb, int W, int OW, const int* slot,
                                                         const int* slotB,
                                                         const int* xs_row,
-                                                        const int* xs_col, const double* A, const uint8_t* actA,
-                                                        const double* B, const uint8_t* actB, double* P) {
+                                                        const int* xs_col, const double* A, const int* listTA,
+                                                        const int* cntTA, const double* B, const uint8_t* actB,
+                                                        double* P) {
   const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (b >= nbx) return;
   const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
   const int r = xs_row[b], c = xs_col[b];
   d4 acc = d4{0.0, 0.0, 0.0, 0.0};
-  for (int g = 0; g < G; ++g) {
+  const int* LA = listTA + (size_t)r * G;
+  const int na = cntTA[r];
+  for (int k = 0; k < na; ++k) {                // the groups active in A at row block r, ascending
+    const int g = LA[k];
     const size_t tr = (size_t)g * n_rb + r, tc = (size_t)g * n_rb + c;
-    if (!actA[tr] || !actB[tc]) continue;
+    if (!actB[tc]) continue;
     const double* At = A + (size_t)slot[tr] * (RB * W);
     const double* Bt = B + (size_t)slotB[tc] * (RB * W);
     for (int s = 0; s < OW / 4; ++s) acc = mfma64(At[lr * W + 4 * s + lk], Bt[lr * W + 4 * s + lk], acc);
@@ -1693,10 +1730,10 @@ __global__ void __launch_bounds__(256) k_density_blocks(int nbx, int G, int n_rb
 }
 // 2 A_occ B_occ^T on the 16 x 16 blocks of the S pattern: the density P (A = B = C) or
 // W = 2 C_occ Z_occ^T (B = Z) of the energy gradient
-void launch_density_blocks(const View& v, const double* A, const uint8_t* actA, const double* B, const uint8_t* actB,
-                           bool B_is_y, double* P, hipStream_t s) {
+void launch_density_blocks(const View& v, const double* A, const int* listTA, const int* cntTA, const double* B,
+                           const uint8_t* actB, bool B_is_y, double* P, hipStream_t s) {
   hipLaunchKernelGGL(k_density_blocks, dim3((v.nbx + 3) / 4), dim3(256), 0, s, v.nbx, v.G, v.n_rb, v.W, v.OW,
-                     v.slot, B_is_y ? v.slotY : v.slot, v.xs_row, v.xs_col, A, actA, B, actB, P);
+                     v.slot, B_is_y ? v.slotY : v.slot, v.xs_row, v.xs_col, A, listTA, cntTA, B, actB, P);
 }
 
 // ---------------------------------------------------------------------------------------
