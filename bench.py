@@ -105,8 +105,8 @@ def cpu_baseline(system, budget_s: float, eps: float, e_conv: float, gpu_window:
                 cpu_model=cpu_model(), host_cpus=os.cpu_count(),
                 sample=f"oracle (FP64, OpenMP, {threads} threads) SCF steps 1..{len(times)} of the same "
                        f"{system.name} system from the initial guess (set-up not timed), {sum(times):.1f} s; "
-                       f"value = 1 / median s per step; the GPU window is {gpu_window}: the oracle needs tens "
-                       "of seconds per step here, so the bounded sample cannot reach it",
+                       f"value = 1 / median s per step; the GPU window is {gpu_window}: at {med:.1f} s per "
+                       "oracle step here, the bounded sample cannot reach it",
                 s_per_step=[round(x, 2) for x in times], median_s_per_step=round(med, 3),
                 one_thread=dict(workload="water512 seed 1 (1,536 atoms), SCF step 1",
                                 s_1_thread=round(one[1], 3), s_all_threads=round(one[threads], 3),
