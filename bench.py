@@ -42,7 +42,7 @@ CLASSES = ("spmm_tiles", "pair_overlap", "pair_fock", "ortho_update", "rotations
 # Measured HBM traffic per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a copy kernel);
 # reported only while the kernel source is the one the counters were taken from.
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic_water4096_fp64.json")
-GOLDEN = os.path.join(ROOT, "tests", "golden", "water4096_seed{}.json")
+GOLDEN = os.path.join(ROOT, "tests", "golden", "{}_seed{}.json")
 # The paper's own numbers for this path (context only: other hardware, no steps/s or GB/s printed)
 PAPER_CONTEXT = {
     "note": "the paper prints no SCF steps/s, GB/s or seconds per step for this path; shares of its "
@@ -173,8 +173,8 @@ def measured_traffic(kernel: str, config: str, precision: str, seed: int):
 
 
 def load_golden(config: str, seed: int, eps: float, e_conv: float):
-    path = GOLDEN.format(seed)
-    if config != "water4096" or not os.path.exists(path):
+    path = GOLDEN.format(config, seed)
+    if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("seed") != seed or rec.get("eps") != eps or rec.get("e_conv") != e_conv:

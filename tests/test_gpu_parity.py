@@ -173,16 +173,19 @@ def test_not_spd_is_reported():
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "water4096_seed1.json")
 
 
-@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden values not generated")
-@pytest.mark.parametrize("seed", [1, 2])
-def test_water4096_against_stored_oracle(seed):
-    """The 12,288-atom box (two geometries): set-up and every stored step (25 per geometry, the
-    benchmark's window included) against stored oracle values."""
-    rec = json.load(open(GOLDEN.replace("seed1", f"seed{seed}")))
-    assert rec["seed"] == seed
-    s = synth.make_config("water4096", seed)
-    print(f"[parity] water4096 n_atoms={s.n_atoms}", flush=True)
-    g = gpu(s, eps=rec["eps"], e_conv=rec["e_conv"])
+@pytest.mark.parametrize("config,seed", [("water4096", 1), ("water4096", 2), ("octane400", 1)])
+def test_against_stored_oracle(config, seed):
+    """The 12,288-atom water box (two geometries) and the 10,400-atom octane box: set-up and every
+    stored step (the benchmark's window included) against stored oracle values
+    (tests/golden/make_golden.py)."""
+    path = GOLDEN.replace("water4096_seed1", f"{config}_seed{seed}")
+    if not os.path.exists(path):
+        pytest.skip("golden values not generated")
+    rec = json.load(open(path))
+    assert rec["seed"] == seed and rec.get("config", "water4096") == config
+    s = synth.make_config(config, seed)
+    print(f"[parity] {config} n_atoms={s.n_atoms}", flush=True)
+    g = gpu(s, eps=rec["eps"], e_conv=rec["e_conv"], **rec.get("options", {}))
     sample = np.array(rec["charge_sample_atoms"])
     gi = g.init_info()
     assert abs(gi["energy"] - rec["init"]["energy"]) < E_TOL
@@ -190,7 +193,7 @@ def test_water4096_against_stored_oracle(seed):
     assert np.abs(g.charges()[sample] - np.array(rec["init"]["charges_sample"])).max() < Q_TOL
     for k, st in enumerate(rec["steps"]):
         gs = g.step()
-        print(f"[parity] water4096 step {k + 1} gpu {gs['energy']!r} oracle {st['energy']!r} "
+        print(f"[parity] {config} step {k + 1} gpu {gs['energy']!r} oracle {st['energy']!r} "
               f"ms {gs['ms_total']:.1f}", flush=True)
         assert abs(gs["energy"] - st["energy"]) < E_TOL
         assert gs["n_candidates"] == st["n_candidates"]
