@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 
 CLASSES = {"spmm_tiles": "product", "pair_overlap": "overlap", "pair_fock": "fock_blocks",
            "ortho_update": "combine", "rotations": "rotate"}
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "water4096_seed{}.json")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "{}_seed{}.json")
 
 
 def gpu(system, **kw):
@@ -77,24 +77,27 @@ def test_counts_off_by_default(water128):
     g.close()
 
 
-@pytest.mark.parametrize("seed", [1, 2])
-def test_work_counts_water4096(seed):
-    """The 12,288-atom box: every stored step's counts (oracle, tests/golden/make_golden.py)."""
-    path = GOLDEN.format(seed)
+@pytest.mark.parametrize("config,seed", [("water4096", 1), ("water4096", 2), ("octane400", 1)])
+def test_work_counts_stored(config, seed):
+    """The 12,288-atom water box and the 10,400-atom octane box: every stored step's counts
+    (oracle, tests/golden/make_golden.py)."""
+    path = GOLDEN.format(config, seed)
+    if not os.path.exists(path):
+        pytest.skip("no stored values")
     rec = json.load(open(path))
     steps = [st for st in rec["steps"] if "work" in st]
     if not steps:
         pytest.skip("stored values hold no work counts")
-    s = synth.make_config("water4096", seed)
-    print(f"[work] water4096 seed {seed}: {len(steps)} stored steps", flush=True)
-    g = gpu(s, eps=rec["eps"], e_conv=rec["e_conv"])
+    s = synth.make_config(config, seed)
+    print(f"[work] {config} seed {seed}: {len(steps)} stored steps", flush=True)
+    g = gpu(s, eps=rec["eps"], e_conv=rec["e_conv"], **rec.get("options", {}))
     for k, st in enumerate(steps):
         g.reset_kernel_stats()
         gs = g.step()
         ks = g.kernel_stats()
-        print(f"[work] water4096 step {k + 1}: combination {ks['ortho_update']['alg_flops']:.4e} flops "
+        print(f"[work] {config} step {k + 1}: combination {ks['ortho_update']['alg_flops']:.4e} flops "
               f"(oracle {st['work']['classes']['combine']['flops']:.4e}), nnz C {gs['nnz_c']} "
               f"(oracle {st['nnz_c']})", flush=True)
-        check_counts(ks, st["work"]["classes"], 1e-5, f"water4096 step {k + 1}")
+        check_counts(ks, st["work"]["classes"], 1e-5, f"{config} step {k + 1}")
         assert abs(gs["nnz_c"] - st["nnz_c"]) <= 1e-5 * st["nnz_c"]
     g.close()
