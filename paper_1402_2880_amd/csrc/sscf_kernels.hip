@@ -285,24 +285,29 @@ __global__ void __launch_bounds__(256) k_pair(int n_rb, int W, const int* __rest
     // the rows active in both panels, 64 at a time, with their slice masks, before any product
     for (int base = 0; base < cnt; base += 64) {
       const int t = base + lane;
-      int rr = 0;
+      int rr = 0, sc = 0, sy = 0;
       unsigned int mab = 0u;
       if (t < cnt) {
         rr = listC[gb + t];
         if (actY[hb + rr]) {
           const unsigned int ma = (cmask[gb + rr] >> sa) & mcm, mb = (ymask[hb + rr] >> sb) & ncm;
-          if (ma && mb) mab = ma | (mb << 16);
+          if (ma && mb) {
+            mab = ma | (mb << 16);
+            sc = slot[gb + rr];                // the common rows' slots in one round trip
+            sy = slotY[hb + rr];
+          }
         }
       }
       unsigned long long m = __ballot(mab != 0u);
       while (m) {
         const int j = __ffsll((long long)m) - 1;
         m &= m - 1ull;
-        const int r = __shfl(rr, j);
         const unsigned int mj = __builtin_amdgcn_readfirstlane(__shfl((int)mab, j));
         const unsigned int ma = mj & 0xffffu, mb = mj >> 16;
-        const double* Ct = C + (size_t)slot[gb + r] * (RB * W) + row_off + mt0 * 16 + lr;
-        const double* Yt = Y + (size_t)slotY[hb + r] * (RB * W) + col_off + nt0 * 16 + lr;
+        const size_t scj = (size_t)(unsigned int)__builtin_amdgcn_readfirstlane(__shfl(sc, j));
+        const size_t syj = (size_t)(unsigned int)__builtin_amdgcn_readfirstlane(__shfl(sy, j));
+        const double* Ct = C + scj * (RB * W) + row_off + mt0 * 16 + lr;
+        const double* Yt = Y + syj * (RB * W) + col_off + nt0 * 16 + lr;
         double a[4][MW], b[4][NW];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -762,24 +767,27 @@ __global__ void __launch_bounds__(256) k_ortho_update(int G, int n_rb, int nchun
   const int k_end = gn_ptr[g + 1];
   for (int kb = gn_ptr[g]; kb < k_end; kb += 64) {
     const int k = kb + lane;
-    int h = 0, nz = 0;
+    int h = 0, nz = 0, pk = 0, shk = 0;
     if (k < k_end) {
       h = gn[k];
       const size_t th = (size_t)h * n_rb + r;
-      if (pair_sel[pair_of[(size_t)g * G + h]] && actC[th]) nz = ncol[th];
+      pk = pair_of[(size_t)g * G + h];
+      if (pair_sel[pk] && actC[th]) {
+        nz = ncol[th];
+        shk = slotP[th];                     // every lane's pair and slot in one round trip
+      }
     }
     unsigned long long M = __ballot(nz != 0);
     while (M) {
       const int j = __ffsll((long long)M) - 1;
       M &= M - 1ull;
-      const int hc = __shfl(h, j);
+      const int hc = __builtin_amdgcn_readfirstlane(__shfl(h, j));
       const int nzj = __builtin_amdgcn_readfirstlane(__shfl(nz, j));
-      const int p = pair_of[(size_t)g * G + hc];
+      const int p = __builtin_amdgcn_readfirstlane(__shfl(pk, j));
       const bool tr = hc > g;
-      const size_t th = (size_t)hc * n_rb + r;
       const double* Dp = (tr ? Dt : D) + (size_t)p * W * W + lr;
       const uint8_t* rm = rmask + ((size_t)p * 2 + (tr ? 1 : 0)) * W;
-      const size_t sh = (size_t)slotP[th];
+      const size_t sh = (size_t)(unsigned int)__builtin_amdgcn_readfirstlane(__shfl(shk, j));
       const double* A = P + sh * (RB * W) + lr;
       // packed column k's index and slice mask live in lane k (k < 64) or lane k - 64
       const uint8_t* ci = cidx + sh * W;
@@ -2030,11 +2038,12 @@ __global__ void __launch_bounds__(256) k_spmm_row(int G, int n_rb, int nchunk, c
   unsigned int n_mfma = 0;
   for (int base = k0; base < k1; base += 64) {
     const int k = base + lane;
-    int c = 0;
+    int c = 0, sc = 0;
     unsigned int mk = 0u;
     if (k < k1) {
       c = xs_col[k];
       mk = actC[pb + c] ? (cmask[pb + c] & smask) : 0u;
+      if (mk) sc = slot[pb + c];               // the products' C slots in one round trip
     }
     unsigned long long m = __ballot(mk != 0u);
     if (!m) continue;
@@ -2049,8 +2058,8 @@ __global__ void __launch_bounds__(256) k_spmm_row(int G, int n_rb, int nchunk, c
       for (int s = 0; s < 4; ++s) xn[s] = Xb[4 * s];
     }
     for (;;) {
-      const int cj = __shfl(c, j);
       const unsigned int mj = __builtin_amdgcn_readfirstlane(__shfl((int)mk, j));
+      const size_t scj = (size_t)(unsigned int)__builtin_amdgcn_readfirstlane(__shfl(sc, j));
       Real xa[4];
 #pragma unroll
       for (int s = 0; s < 4; ++s) xa[s] = xn[s];
@@ -2063,7 +2072,7 @@ __global__ void __launch_bounds__(256) k_spmm_row(int G, int n_rb, int nchunk, c
         for (int s = 0; s < 4; ++s)
           if (__ballot(xa[s] != Real(0))) km |= 1u << s;
       }
-      const Real* Ct = C + (size_t)slot[pb + cj] * (RB * W) + lk * W + lr;
+      const Real* Ct = C + scj * (RB * W) + lk * W + lr;
       Real cb[4][NT];
 #pragma unroll
       for (int s = 0; s < 4; ++s)
