@@ -778,9 +778,21 @@ __global__ void __launch_bounds__(256) k_ortho_update(int G, int n_rb, int nchun
       }
     }
     unsigned long long M = __ballot(nz != 0);
-    while (M) {
-      const int j = __ffsll((long long)M) - 1;
+    // the next neighbour's packed column indices load while the current one multiplies
+    int jn = -1, col0n = 0, col1n = 0;
+    auto fetch_cols = [&]() {
+      jn = __ffsll((long long)M) - 1;
       M &= M - 1ull;
+      const int nzn = __builtin_amdgcn_readfirstlane(__shfl(nz, jn));
+      const size_t shn = (size_t)(unsigned int)__builtin_amdgcn_readfirstlane(__shfl(shk, jn));
+      const uint8_t* ci = cidx + shn * W;      // packed column k's index lives in lane k or k - 64
+      col0n = lane < nzn ? ci[lane] : 0;
+      col1n = (W > 64 && lane + 64 < nzn) ? ci[lane + 64] : 0;
+    };
+    if (M) fetch_cols();
+    while (jn >= 0) {
+      const int j = jn;
+      const int col0 = col0n, col1 = col1n;
       const int hc = __builtin_amdgcn_readfirstlane(__shfl(h, j));
       const int nzj = __builtin_amdgcn_readfirstlane(__shfl(nz, j));
       const int p = __builtin_amdgcn_readfirstlane(__shfl(pk, j));
@@ -789,12 +801,10 @@ __global__ void __launch_bounds__(256) k_ortho_update(int G, int n_rb, int nchun
       const uint8_t* rm = rmask + ((size_t)p * 2 + (tr ? 1 : 0)) * W;
       const size_t sh = (size_t)(unsigned int)__builtin_amdgcn_readfirstlane(__shfl(shk, j));
       const double* A = P + sh * (RB * W) + lr;
-      // packed column k's index and slice mask live in lane k (k < 64) or lane k - 64
-      const uint8_t* ci = cidx + sh * W;
-      const int col0 = lane < nzj ? ci[lane] : 0;
-      const int col1 = (W > 64 && lane + 64 < nzj) ? ci[lane + 64] : 0;
       int m0 = lane < nzj ? rm[col0] : 0;
       int m1 = (W > 64 && lane + 64 < nzj) ? rm[col1] : 0;
+      jn = -1;
+      if (M) fetch_cols();
       // OR over the four columns of each k-step (aligned groups of four lanes)
       m0 |= __shfl_xor(m0, 1);
       m0 |= __shfl_xor(m0, 2);
@@ -1444,21 +1454,31 @@ __global__ void __launch_bounds__(256) k_givens_rb(int G, int n_rb, int W, int O
       if (rel) list_l[off + __popcll(m & ((1ull << lane) - 1ull))] = mt;
       __syncthreads();
       const int nl = cnt_l[0];
+      // a wave's next block: its touched columns and tile slots load while this one is applied
+      int4 itn = make_int4(0, 0, 0, 0);
+      int tcl0n = 0, tcl1n = 0, sgin = -1, shin = -1;
+      auto fetch = [&](int en) {
+        itn = list_l[en];
+        const int* tcn = tcol + (size_t)itn.x * W;
+        tcl0n = (lane < itn.w) ? tcn[lane] : 0;
+        tcl1n = (lane + 64 < itn.w) ? tcn[lane + 64] : 0;
+        sgin = slot[(size_t)itn.y * n_rb + rb];
+        shin = slot[(size_t)itn.z * n_rb + rb];
+      };
+      if (wv < nl) fetch(wv);
       for (int e = wv; e < nl; e += nw) {
-        const int4 it = list_l[e];
+        const int4 it = itn;
+        const int tcl0 = tcl0n, tcl1 = tcl1n, sgi = sgin, shi = shin;
+        if (e + nw < nl) fetch(e + nw);
         const int b = it.x, g = it.y, h = it.z, T = it.w;
         const int nt_n = (T + 15) >> 4;
-        const int* tc = tcol + (size_t)b * W;
         const Real* Rb = R + (size_t)b * W * W;
         // a tile without a slot is all zero and stays so: its columns are never nonzero in
         // cm_l, so nothing is gathered from it; a nonzero written to it is a capacity error
-        const int sgi = slot[(size_t)g * n_rb + rb], shi = slot[(size_t)h * n_rb + rb];
         double* Cg = C + (size_t)(sgi < 0 ? 0 : sgi) * RB * W;
         double* Ch = C + (size_t)(shi < 0 ? 0 : shi) * RB * W;
         // touched columns (two per lane) and whether each is nonzero at rb; the nonzero ones'
         // positions, packed in order, form the K dimension
-        const int tcl0 = (lane < T) ? tc[lane] : 0;
-        const int tcl1 = (lane + 64 < T) ? tc[lane + 64] : 0;
         auto col_nz = [&](int col) {
           const int grp = col < OW ? g : h;
           return (cm_l[2 * grp + (col >> 6)] >> (col & 63)) & 1ull;
