@@ -1928,24 +1928,29 @@ __global__ void __launch_bounds__(256) k_pair32(int n_rb, int W, const int* __re
     // the rows active in both panels, 64 at a time, with their slice masks, before any product
     for (int base = 0; base < cnt; base += 64) {
       const int t = base + lane;
-      int rr = 0;
+      int rr = 0, sc = 0, sy = 0;
       unsigned int mab = 0u;
       if (t < cnt) {
         rr = listC[gb + t];
         if (actY[hb + rr]) {
           const unsigned int ma = (cmask[gb + rr] >> sa) & mcm, mb = (ymask[hb + rr] >> sb) & ncm;
-          if (ma && mb) mab = ma | (mb << 16);
+          if (ma && mb) {
+            mab = ma | (mb << 16);
+            sc = slot[gb + rr];                // the common rows' slots in one round trip
+            sy = slotY[hb + rr];
+          }
         }
       }
       unsigned long long m = __ballot(mab != 0u);
       while (m) {
         const int j = __ffsll((long long)m) - 1;
         m &= m - 1ull;
-        const int r = __shfl(rr, j);
         const unsigned int mj = __builtin_amdgcn_readfirstlane(__shfl((int)mab, j));
         const unsigned int ma = mj & 0xffffu, mb = mj >> 16;
-        const float* Ct = C + (size_t)slot[gb + r] * (RB * W) + row_off + mt0 * 16 + lr;
-        const float* Yt = Y + (size_t)slotY[hb + r] * (RB * W) + col_off + nt0 * 16 + lr;
+        const size_t scj = (size_t)(unsigned int)__builtin_amdgcn_readfirstlane(__shfl(sc, j));
+        const size_t syj = (size_t)(unsigned int)__builtin_amdgcn_readfirstlane(__shfl(sy, j));
+        const float* Ct = C + scj * (RB * W) + row_off + mt0 * 16 + lr;
+        const float* Yt = Y + syj * (RB * W) + col_off + nt0 * 16 + lr;
         float a[4][MW], b[4][NW];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -2084,14 +2089,11 @@ __global__ void __launch_bounds__(256) k_spmm_row(int G, int n_rb, int nchunk, c
 #pragma unroll
       for (int s = 0; s < 4; ++s) xa[s] = xn[s];
       // k-steps (4 columns of the X block) that hold a nonzero: the others add exact zeros,
-      // and their C rows are not read
-      unsigned int km = 0xFu;
-      if constexpr (sizeof(Real) == sizeof(double)) {
-        km = 0u;
+      // and their C rows are not read (FP32: their MFMAs still run, on zeros, see below)
+      unsigned int km = 0u;
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
-          if (__ballot(xa[s] != Real(0))) km |= 1u << s;
-      }
+      for (int s = 0; s < 4; ++s)
+        if (__ballot(xa[s] != Real(0))) km |= 1u << s;
       const Real* Ct = C + scj * (RB * W) + lk * W + lr;
       Real cb[4][NT];
 #pragma unroll
