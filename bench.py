@@ -78,14 +78,21 @@ def host_threads() -> int:
     return n
 
 
-def cpu_baseline(system, budget_s: float, eps: float, e_conv: float, gpu_window: str):
-    """The FP64 oracle on the host cores: set-up untimed, then SCF steps from the initial guess until
-    the budget; and one step of the 512-molecule box on one thread and on all threads (the thread
-    scaling of the oracle)."""
+def cpu_baseline(system, budget_s: float, eps: float, e_conv: float, first_step: int, gpu_window: str,
+                 reach_s: float = 90.0):
+    """The FP64 oracle on the host cores over the GPU's step window: set-up untimed, the steps
+    before the window run untimed (up to reach_s seconds), then steps timed until the budget; and
+    one step of the 512-molecule box on one thread and on all threads (the oracle's thread scaling)."""
     from oracle.oracle import Oracle
     from paper_1402_2880_amd import synth
     threads = host_threads()
     o = Oracle(system, eps=eps, e_conv=e_conv, n_threads=threads)
+    t0 = time.perf_counter()
+    done = 0
+    while done < first_step - 1 and time.perf_counter() - t0 < reach_s:
+        o.step()
+        done += 1
+    reached = time.perf_counter() - t0
     times = []
     while sum(times) < budget_s and len(times) < 25:
         t = time.perf_counter()
@@ -101,13 +108,15 @@ def cpu_baseline(system, budget_s: float, eps: float, e_conv: float, gpu_window:
         ob.step()
         one[th] = time.perf_counter() - t
         del ob
+    window = (f"SCF steps {done + 1}..{done + len(times)} of the same {system.name} system "
+              f"(set-up and steps 1..{done} run untimed first, {reached:.0f} s)")
+    same = done == first_step - 1
     return dict(value=round(1.0 / med, 5), unit="SCF steps/s", cores=threads, kind="oracle",
                 cpu_model=cpu_model(), host_cpus=os.cpu_count(),
-                sample=f"oracle (FP64, OpenMP, {threads} threads) SCF steps 1..{len(times)} of the same "
-                       f"{system.name} system from the initial guess (set-up not timed), {sum(times):.1f} s; "
-                       f"value = 1 / median s per step; the GPU window is {gpu_window}: at {med:.1f} s per "
-                       "oracle step here, the bounded sample cannot reach it",
-                s_per_step=[round(x, 2) for x in times], median_s_per_step=round(med, 3),
+                sample=f"oracle (FP64, OpenMP, {threads} threads), {window}, {sum(times):.1f} s timed; "
+                       f"value = 1 / median s per step; the GPU window is {gpu_window}"
+                       + ("" if same else " (the untimed run could not reach it within its time limit)"),
+                window_matches_gpu=same, s_per_step=[round(x, 2) for x in times], median_s_per_step=round(med, 3),
                 one_thread=dict(workload="water512 seed 1 (1,536 atoms), SCF step 1",
                                 s_1_thread=round(one[1], 3), s_all_threads=round(one[threads], 3),
                                 speedup=round(one[1] / one[threads], 2)))
@@ -387,7 +396,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle) ...")
-        cpu = cpu_baseline(system, args.cpu_budget, args.eps, args.e_conv, window)
+        cpu = cpu_baseline(system, args.cpu_budget, args.eps, args.e_conv, first, window)
         log(f"[bench] CPU baseline {cpu}")
     last = infos[-1]
     out = {
