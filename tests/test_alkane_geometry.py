@@ -126,3 +126,24 @@ def test_long_chain_oracle_reaches_dense_energy_non_scc():
         raise AssertionError("no convergence")
     err = o.energy() - dense_scf(s, scc=False)["energy"]
     assert 0.0 <= err < 2e-4
+
+
+def test_stale_angle_rotations_diverge_on_interacting_long_chains():
+    """The rotation scheme of section 3.5 (the step's top-K rotations with angles from the F of
+    the start of the step) raises the energy on boxes of interacting C83 chains, here four chains
+    (1,004 atoms) without the charge term: the energy falls for three steps, then rises with
+    max |F_ia| growing from step to step.  (It happens at eps = 1e-5 and 1e-7, with a cap of 2 or
+    10 N_occ, and in the oracle's literal mode as well; a lone chain, whose guess already spans its
+    own solution, stays put.)  The 100k-atom chain workload shows the same on the GPU."""
+    from oracle.oracle import Oracle
+    s = synth.alkane_segments_box(4, 83, 34.5, 1, seg=10)
+    o = Oracle(s, scc=False)
+    e, fov = [], []
+    for _ in range(9):
+        st = o.step()
+        e.append(st["energy"])
+        fov.append(st["max_abs_fov"])
+    k = int(np.argmin(e))
+    assert 1 <= k <= 5, e                                   # it first goes down
+    assert e[-1] > e[k] + 1e-2, (e[k], e[-1])               # then up, by far more than e_conv
+    assert fov[-1] > 5.0 * fov[k]                           # the coupling grows back
