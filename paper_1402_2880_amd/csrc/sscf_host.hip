@@ -359,7 +359,7 @@ struct sscf_ctx {
   // Y = X C; occ_only: only the occupied columns of every panel are formed
   void product(const double* X, bool dilate, bool occ_only = false) {
     if (dilate) {
-      launch_dilate(v, actC[cur], actY, stream);
+      launch_dilate(v, listC[cur], cntC[cur], actY, stream);
       launch_list(v, actY, listY, cntY, stream);
     }
     const unsigned int smask = occ_only ? (1u << (v.OW / 16)) - 1u : 0xffffffffu;
@@ -402,7 +402,7 @@ struct sscf_ctx {
       HIPC(hipMemsetAsync(upd, 0, (size_t)v.G * W, stream));
       if (wc()) launch_fill_i32(w_nsel, (size_t)v.G * W, 0, stream);
       launch_mark_selected(v, n_pairs, pg, ph, O, sd, pair_sel, upd, rmask, wc() ? w_nsel : nullptr, stream);
-      launch_update_support(v, actC[cur], gn_ptr, gn, pair_of, pair_sel, nullptr, act_tmp, stream);
+      launch_update_support(v, listC[cur], cntC[cur], n_pairs, pg, ph, pair_sel, nullptr, act_tmp, stream);
       launch_list(v, act_tmp, list_tmp, cnt_tmp, stream);
       launch_clear_flags(v, actC[nx], cmask[nx], listC[nx], cntC[nx], stream);
       if (wc()) count_update_begin(occ_only != 0);
@@ -465,7 +465,7 @@ struct sscf_ctx {
                 0, no, 0, no, foo_b, v.OW, fo, nullptr, s);
     // Z = C_occ F on the row blocks where a neighbouring group is active and that S links to an
     // active row block of the group (W needs no other; Z overwrites Y, in Y's pool)
-    launch_update_support(v, actC[cur], gn_ptr, gn, pair_of, pair_all, actY, act_tmp, s);
+    launch_update_support(v, listC[cur], cntC[cur], n_pairs, pg, ph, pair_all, actY, act_tmp, s);
     launch_list(v, act_tmp, list_tmp, cnt_tmp, s);
     launch_apply_occ(v, C[cur], actC[cur], gn_ptr, gn, pair_of, pg, foo_a, foo_b, list_tmp, cnt_tmp, Y, s);
     // P = 2 C_occ C_occ^T and W = 2 C_occ Z^T on the pattern of S, then the layout of S_val
@@ -1083,7 +1083,7 @@ static void step(sscf_ctx* x, sscf_step_info* out) {
   HIPC(hipEventRecord(x->ev[1], s));
   // C^T H C: occupied-virtual blocks and the diagonal (FP32 in the precision form)
   if (x->precision == SSCF_FP32_MIXED) {
-    launch_dilate(v, x->actC[x->cur], x->actY, s);
+    launch_dilate(v, x->listC[x->cur], x->cntC[x->cur], x->actY, s);
     launch_list(v, x->actY, x->listY, x->cntY, s);
     pi = x->pbegin(KC_SPMM);
     launch_round_c32(v, x->C[x->cur], x->listC[x->cur], x->cntC[x->cur], x->cmask[x->cur], x->C32, s);

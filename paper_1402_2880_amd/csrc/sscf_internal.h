@@ -91,7 +91,9 @@ void launch_fill_i32(int* p, size_t n, int v, hipStream_t s);
 void launch_scatter_c0(const View& v, int nnz, const int64_t* colptr_expanded_col, const int* row,
                        const double* val, const int* mo_panel, const int* mo_col, double* C,
                        uint8_t* act, unsigned int* cmask, int* cap_err, hipStream_t s);
-void launch_dilate(const View& v, const uint8_t* actC, uint8_t* actY, hipStream_t s);
+// actY = the row blocks that S links to a tile of the lists listC / cntC (the lists of the
+// current activity flags), scattered through the symmetric pattern of S
+void launch_dilate(const View& v, const int* listC, const int* cntC, uint8_t* actY, hipStream_t s);
 void launch_list(const View& v, const uint8_t* act, int* list, int* cnt, hipStream_t s);
 // per row block, the groups active there (ascending): listT[r G + k], k < cntT[r]
 void launch_list_t(const View& v, const uint8_t* act, int* listT, int* cntT, hipStream_t s);
@@ -120,8 +122,8 @@ void launch_mark_selected(const View& v, int n_pairs, const int* pg, const int* 
 // act_new = support of C after the combinations of the selected pairs.  With mask, only the tiles
 // where mask is set (no capacity test); without, a tile with no slot is marked 2 (a tile the
 // combination computes only to check that it stays zero).
-void launch_update_support(const View& v, const uint8_t* actC, const int* gn_ptr, const int* gn,
-                           const int* pair_of, const uint8_t* pair_sel, const uint8_t* mask, uint8_t* act_new,
+void launch_update_support(const View& v, const int* listC, const int* cntC, int n_pairs, const int* pg,
+                           const int* ph, const uint8_t* pair_sel, const uint8_t* mask, uint8_t* act_new,
                            hipStream_t s);
 void launch_clear_flags(const View& v, uint8_t* act, unsigned int* cmask, const int* list, const int* cnt,
                         hipStream_t s);

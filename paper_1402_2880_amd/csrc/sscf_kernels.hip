@@ -129,29 +129,74 @@ void launch_scatter_c0(const View& v, int nnz, const int64_t* col_of, const int*
 }
 
 // ---------------------------------------------------------------------------------------
+// Workgroups go round-robin over the 8 XCDs of the chip, each with its own L2: linear
+// workgroup id L runs on XCD L % 8.  Kernels that work group by group decode L so that all
+// workgroups of one MO group land on one XCD, in group-major order, and share its L2.
+// ---------------------------------------------------------------------------------------
+
+constexpr int N_XCD = 8;
+
+__device__ inline int xcd_group_chunk(int nchunk, int& chunk) {
+  const int L = (int)blockIdx.x, slot = L / N_XCD;
+  chunk = slot % nchunk;
+  return L % N_XCD + N_XCD * (slot / nchunk);
+}
+static inline unsigned int xcd_grid(int G, int nchunk) {
+  return (unsigned int)(N_XCD * ((G + N_XCD - 1) / N_XCD) * nchunk);
+}
+// Kernels with one wave per listed tile of a group walk the group's list four tiles (one
+// workgroup) at a time: workgroup c of the group takes the steps c, c + nchunk, c + 2 nchunk, ...
+// The lists live on the device, so the host sizes nchunk from their bound (max_tiles), capped
+// so that the launch has about TILE_LIST_WGS workgroups: a grid sized by the bound alone
+// would be mostly workgroups with nothing to do where the lists are much shorter than it.
+constexpr int TILE_LIST_WGS = 16384;
+static inline int tile_list_chunks(int G, int max_tiles) {
+  const int need = (max_tiles + 3) / 4;
+  const int groups = N_XCD * ((G + N_XCD - 1) / N_XCD);
+  const int want = (TILE_LIST_WGS + groups - 1) / groups;
+  return std::max(1, std::min(need, want));
+}
+// item of a list sorted by group, placed by the host on the XCD of its group (-1: padding)
+__device__ inline int xcd_item(const int* perm, int maxc) {
+  const int L = (int)blockIdx.x;
+  return perm[(L % N_XCD) * maxc + L / N_XCD];
+}
+
+// ---------------------------------------------------------------------------------------
 // supports: dilation of a panel's active row blocks through the pattern of S/H, and the
 // sorted lists of active row blocks
 // ---------------------------------------------------------------------------------------
 
-__global__ void k_dilate(int G, int n_rb, const int* xs_ptr, const int* xs_col, const int* slotY, const uint8_t* actC,
-                         uint8_t* actY, int* cap_err) {
-  const size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  if (idx >= (size_t)G * n_rb) return;
-  const int g = (int)(idx / n_rb), r = (int)(idx % n_rb);
-  const uint8_t* a = actC + (size_t)g * n_rb;
-  uint8_t any = 0;
-  for (int k = xs_ptr[r]; k < xs_ptr[r + 1]; ++k)
-    if (a[xs_col[k]]) { any = 1; break; }
-  if (any && slotY[idx] < 0) {                  // cannot happen while C keeps to its slots
-    note_capacity(cap_err, idx);
-    any = 0;
+// actY[g][r] = 1 where S links row block r to a row block k active in panel g.  The pattern
+// of S is symmetric, so the dilation is scattered from the active tiles: one wave per listed
+// tile (g, k), its lanes over the row blocks r of row k of the pattern (actY is cleared first).
+// A target without a slot is reported (it cannot happen while C keeps to its slots).
+__global__ void __launch_bounds__(256) k_dilate(int G, int n_rb, int nchunk, const int* __restrict__ xs_ptr,
+                                                const int* __restrict__ xs_col, const int* __restrict__ slotY,
+                                                const int* __restrict__ listC, const int* __restrict__ cntC,
+                                                uint8_t* __restrict__ actY, int* __restrict__ cap_err) {
+  int chunk;
+  const int g = xcd_group_chunk(nchunk, chunk);
+  if (g >= G) return;
+  const int lane = threadIdx.x & 63;
+  const size_t gb = (size_t)g * n_rb;
+  const int n_t = cntC[g];
+  for (int t = chunk * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); t < n_t; t += 4 * nchunk) {
+    const int k = listC[gb + t];
+    for (int e = xs_ptr[k] + lane; e < xs_ptr[k + 1]; e += 64) {
+      const size_t idx = gb + xs_col[e];
+      if (slotY[idx] < 0)
+        note_capacity(cap_err, idx);
+      else
+        actY[idx] = 1;
+    }
   }
-  actY[idx] = any;
 }
-void launch_dilate(const View& v, const uint8_t* actC, uint8_t* actY, hipStream_t s) {
-  const size_t n = (size_t)v.G * v.n_rb;
-  hipLaunchKernelGGL(k_dilate, dim3(nblk(n, 256)), dim3(256), 0, s, v.G, v.n_rb, v.xs_ptr, v.xs_col, v.slotY, actC,
-                     actY, v.cap_err);
+void launch_dilate(const View& v, const int* listC, const int* cntC, uint8_t* actY, hipStream_t s) {
+  launch_fill_u8(actY, (size_t)v.G * v.n_rb, 0, s);
+  const int nchunk = tile_list_chunks(v.G, v.max_c);
+  hipLaunchKernelGGL(k_dilate, dim3(xcd_grid(v.G, nchunk)), dim3(256), 0, s, v.G, v.n_rb, nchunk, v.xs_ptr, v.xs_col,
+                     v.slotY, listC, cntC, actY, v.cap_err);
 }
 
 __global__ void __launch_bounds__(256) k_list(int n_rb, const uint8_t* act, int* list, int* cnt) {
@@ -208,28 +253,6 @@ __global__ void __launch_bounds__(256) k_list_t(int G, int n_rb, const uint8_t* 
 }
 void launch_list_t(const View& v, const uint8_t* act, int* listT, int* cntT, hipStream_t s) {
   hipLaunchKernelGGL(k_list_t, dim3(v.n_rb), dim3(256), 0, s, v.G, v.n_rb, act, listT, cntT);
-}
-
-// ---------------------------------------------------------------------------------------
-// Workgroups go round-robin over the 8 XCDs of the chip, each with its own L2: linear
-// workgroup id L runs on XCD L % 8.  Kernels that work group by group decode L so that all
-// workgroups of one MO group land on one XCD, in group-major order, and share its L2.
-// ---------------------------------------------------------------------------------------
-
-constexpr int N_XCD = 8;
-
-__device__ inline int xcd_group_chunk(int nchunk, int& chunk) {
-  const int L = (int)blockIdx.x, slot = L / N_XCD;
-  chunk = slot % nchunk;
-  return L % N_XCD + N_XCD * (slot / nchunk);
-}
-static inline unsigned int xcd_grid(int G, int nchunk) {
-  return (unsigned int)(N_XCD * ((G + N_XCD - 1) / N_XCD) * nchunk);
-}
-// item of a list sorted by group, placed by the host on the XCD of its group (-1: padding)
-__device__ inline int xcd_item(const int* perm, int maxc) {
-  const int L = (int)blockIdx.x;
-  return perm[(L % N_XCD) * maxc + L / N_XCD];
 }
 
 // A load that may be known to give zero reads a lane's entry of an all-zero page instead:
@@ -553,30 +576,51 @@ void launch_mark_selected(const View& v, int n_pairs, const int* pg, const int* 
                        nsel);
 }
 
-__global__ void k_update_support(int G, int n_rb, const int* slot, const uint8_t* actC, const int* gn_ptr, const int* gn,
-                                 const int* pair_of, const uint8_t* pair_sel, const uint8_t* mask, uint8_t* act_new) {
-  const size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  if (idx >= (size_t)G * n_rb) return;
-  const int g = (int)(idx / n_rb), r = (int)(idx % n_rb);
-  uint8_t a = actC[idx];
-  if (mask && !mask[idx]) {
-    act_new[idx] = 0;
+// Output tiles of the combination: act_new[g][r] is set where C_g is active at r or where a
+// neighbour h with a selected pair is.  Scattered from the lists of active tiles (act_new is
+// cleared first): one wave per item, an item being a selected pair in one orientation (target
+// group, source group) or a group's own tiles; the lanes walk the source's list.  Without a
+// mask, a target tile with no slot gets 2: the combination there is computed and must come
+// out zero (its values are the neighbours' tails times D_sel, mostly below the cut).  With a
+// mask, only masked tiles are set (to 1).  Every write to a tile stores the same value.
+__global__ void __launch_bounds__(256) k_update_support(int G, int n_rb, int n_pairs, const int* __restrict__ slot,
+                                                        const int* __restrict__ listC, const int* __restrict__ cntC,
+                                                        const int* __restrict__ pg, const int* __restrict__ ph,
+                                                        const uint8_t* __restrict__ pair_sel,
+                                                        const uint8_t* __restrict__ mask,
+                                                        uint8_t* __restrict__ act_new) {
+  const int item = (int)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int tgt, src;
+  if (item < 2 * n_pairs) {
+    const int p = item >> 1;
+    if (!pair_sel[p]) return;
+    tgt = (item & 1) ? ph[p] : pg[p];
+    src = (item & 1) ? pg[p] : ph[p];
+    if ((item & 1) && tgt == src) return;      // a group's pair with itself, once
+  } else if (item < 2 * n_pairs + G) {
+    tgt = src = item - 2 * n_pairs;
+  } else {
     return;
   }
-  for (int k = gn_ptr[g]; k < gn_ptr[g + 1] && !a; ++k) {
-    const int h = gn[k];
-    if (pair_sel[pair_of[(size_t)g * G + h]] && actC[(size_t)h * n_rb + r]) a = 1;
+  const int lane = threadIdx.x & 63;
+  const size_t sb = (size_t)src * n_rb, tb = (size_t)tgt * n_rb;
+  const int n_t = cntC[src];
+  for (int t = lane; t < n_t; t += 64) {
+    const size_t idx = tb + listC[sb + t];
+    if (mask) {
+      if (mask[idx]) act_new[idx] = 1;
+    } else {
+      act_new[idx] = slot[idx] < 0 ? 2 : 1;
+    }
   }
-  // no slot: the combination there is computed and must come out zero (its values are the
-  // neighbours' tails times D_sel, mostly below the cut)
-  if (a && !mask && slot[idx] < 0) a = 2;
-  act_new[idx] = a;
 }
-void launch_update_support(const View& v, const uint8_t* actC, const int* gn_ptr, const int* gn, const int* pair_of,
-                           const uint8_t* pair_sel, const uint8_t* mask, uint8_t* act_new, hipStream_t s) {
-  const size_t n = (size_t)v.G * v.n_rb;
-  hipLaunchKernelGGL(k_update_support, dim3(nblk(n, 256)), dim3(256), 0, s, v.G, v.n_rb, v.slot, actC, gn_ptr, gn,
-                     pair_of, pair_sel, mask, act_new);
+void launch_update_support(const View& v, const int* listC, const int* cntC, int n_pairs, const int* pg,
+                           const int* ph, const uint8_t* pair_sel, const uint8_t* mask, uint8_t* act_new,
+                           hipStream_t s) {
+  launch_fill_u8(act_new, (size_t)v.G * v.n_rb, 0, s);
+  const int items = 2 * n_pairs + v.G;
+  hipLaunchKernelGGL(k_update_support, dim3((items + 3) / 4), dim3(256), 0, s, v.G, v.n_rb, n_pairs, v.slot, listC,
+                     cntC, pg, ph, pair_sel, mask, act_new);
 }
 
 // activity flags and slice masks of the listed tiles back to zero (the values are not touched)
@@ -635,23 +679,24 @@ __global__ void __launch_bounds__(256) k_tile_flags(int G, int n_rb, int nchunk,
   int chunk;
   const int g = xcd_group_chunk(nchunk, chunk);
   if (g >= G) return;
-  const int t = chunk * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (t >= cnt[g]) return;
-  const size_t tile = (size_t)g * n_rb + list[(size_t)g * n_rb + t];
-  double v0[RB], v1[RB];
-  bool nz0, nz1;
-  tile_columns<NT>(C + (size_t)slot[tile] * (RB * W), W, v0, v1, nz0, nz1);
-  const unsigned long long b0 = __ballot(nz0), b1 = __ballot(nz1);
-  unsigned int cm = 0u;
+  const int n_t = cnt[g];
+  for (int t = chunk * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); t < n_t; t += 4 * nchunk) {
+    const size_t tile = (size_t)g * n_rb + list[(size_t)g * n_rb + t];
+    double v0[RB], v1[RB];
+    bool nz0, nz1;
+    tile_columns<NT>(C + (size_t)slot[tile] * (RB * W), W, v0, v1, nz0, nz1);
+    const unsigned long long b0 = __ballot(nz0), b1 = __ballot(nz1);
+    unsigned int cm = 0u;
 #pragma unroll
-  for (int n = 0; n < NT; ++n) {
-    const unsigned long long b = n < 4 ? b0 : b1;
-    if ((b >> (16 * (n & 3))) & 0xffffull) cm |= 1u << n;
-  }
-  if ((threadIdx.x & 63) == 0) {
-    cmask[tile] = cm;
-    act[tile] = (uint8_t)(cm != 0u);
-    if (colm) colm[tile] = make_ulonglong2(b0, b1);
+    for (int n = 0; n < NT; ++n) {
+      const unsigned long long b = n < 4 ? b0 : b1;
+      if ((b >> (16 * (n & 3))) & 0xffffull) cm |= 1u << n;
+    }
+    if ((threadIdx.x & 63) == 0) {
+      cmask[tile] = cm;
+      act[tile] = (uint8_t)(cm != 0u);
+      if (colm) colm[tile] = make_ulonglong2(b0, b1);
+    }
   }
 }
 
@@ -665,37 +710,38 @@ __global__ void __launch_bounds__(256) k_pack_cols(int G, int n_rb, int nchunk, 
   int chunk;
   const int g = xcd_group_chunk(nchunk, chunk);
   if (g >= G) return;
-  const int t = chunk * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (t >= cnt[g]) return;
   const int lane = threadIdx.x & 63;
-  const size_t tile = (size_t)g * n_rb + list[(size_t)g * n_rb + t];
-  double v0[RB], v1[RB];
-  bool nz0, nz1;
-  tile_columns<NT>(C + (size_t)slot[tile] * (RB * W), col_end, v0, v1, nz0, nz1);
-  const unsigned long long b0 = __ballot(nz0), b1 = __ballot(nz1);
   const unsigned long long below = (1ull << lane) - 1ull;
-  const int c0 = __popcll(b0);
-  const size_t sp = (size_t)slotP[tile];
-  double* Pt = P + sp * (RB * W);
-  uint8_t* ct = cidx + sp * W;
-  if (nz0) {
-    const int k = __popcll(b0 & below);
+  const int n_t = cnt[g];
+  for (int t = chunk * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); t < n_t; t += 4 * nchunk) {
+    const size_t tile = (size_t)g * n_rb + list[(size_t)g * n_rb + t];
+    double v0[RB], v1[RB];
+    bool nz0, nz1;
+    tile_columns<NT>(C + (size_t)slot[tile] * (RB * W), col_end, v0, v1, nz0, nz1);
+    const unsigned long long b0 = __ballot(nz0), b1 = __ballot(nz1);
+    const int c0 = __popcll(b0);
+    const size_t sp = (size_t)slotP[tile];
+    double* Pt = P + sp * (RB * W);
+    uint8_t* ct = cidx + sp * W;
+    if (nz0) {
+      const int k = __popcll(b0 & below);
 #pragma unroll
-    for (int r = 0; r < RB; ++r) Pt[k * RB + r] = v0[r];
-    ct[k] = (uint8_t)lane;
-  }
-  if (nz1) {
-    const int k = c0 + __popcll(b1 & below);
+      for (int r = 0; r < RB; ++r) Pt[k * RB + r] = v0[r];
+      ct[k] = (uint8_t)lane;
+    }
+    if (nz1) {
+      const int k = c0 + __popcll(b1 & below);
 #pragma unroll
-    for (int r = 0; r < RB; ++r) Pt[k * RB + r] = v1[r];
-    ct[k] = (uint8_t)(lane + 64);
+      for (int r = 0; r < RB; ++r) Pt[k * RB + r] = v1[r];
+      ct[k] = (uint8_t)(lane + 64);
+    }
+    if (lane == 0) ncol[tile] = (uint8_t)(c0 + __popcll(b1));
   }
-  if (lane == 0) ncol[tile] = (uint8_t)(c0 + __popcll(b1));
 }
 
 void launch_tile_flags(const View& v, const double* C, const int* list, const int* cnt, uint8_t* act,
                        unsigned int* cmask, ulonglong2* colm, hipStream_t s) {
-  const int nchunk = (v.max_c + 3) / 4;
+  const int nchunk = tile_list_chunks(v.G, v.max_c);
   dim3 grid(xcd_grid(v.G, nchunk)), blk(256);
   switch (v.W / 16) {
 #define SSCF_TF(NT) case NT: hipLaunchKernelGGL(k_tile_flags<NT>, grid, blk, 0, s, v.G, v.n_rb, nchunk, v.slot, C, list, cnt, act, cmask, colm); break;
@@ -706,7 +752,7 @@ void launch_tile_flags(const View& v, const double* C, const int* list, const in
 
 void launch_pack_cols(const View& v, const double* C, const int* list, const int* cnt, int col_end, double* P,
                       uint8_t* cidx, uint8_t* ncol, hipStream_t s) {
-  const int nchunk = (v.max_c + 3) / 4;
+  const int nchunk = tile_list_chunks(v.G, v.max_c);
   dim3 grid(xcd_grid(v.G, nchunk)), blk(256);
   switch (v.W / 16) {
 #define SSCF_PK(NT) case NT: hipLaunchKernelGGL(k_pack_cols<NT>, grid, blk, 0, s, v.G, v.n_rb, nchunk, v.slot, v.slotY, C, list, cnt, col_end, P, cidx, ncol); break;
@@ -722,7 +768,8 @@ void launch_pack_cols(const View& v, const double* C, const int* list, const int
 //
 // Cn may be C itself (the update runs in place): the wave of tile (g, r) is the only one that
 // reads or writes C's tile (g, r); the other groups' tiles come from their packed copy.
-// One wave per output tile (g, r), no workgroup synchronization.  A ballot over g's
+// One wave per output tile (g, r) at a time, walking g's list of output tiles (see
+// tile_list_chunks), with no workgroup synchronization.  A ballot over g's
 // neighbours finds, 64 at a time, those h whose pair is selected and whose tile (h, r) has a
 // nonzero column.  Per such h only the tile's nonzero columns enter the product: they come
 // packed (k_pack_cols), four per k-step of the 16 x 16 x 4 matrix-core product, each as one
@@ -730,166 +777,169 @@ void launch_pack_cols(const View& v, const double* C, const int* list, const int
 // eta), and a 16-column slice of the output is skipped for a k-step when none of its four
 // rows holds a selected entry there (rmask).  Adding the skipped terms would add exact
 // zeros.  The sum runs over h in neighbour order and over the packed columns in increasing
-// column order, so the result does not depend on the launch.
+// column order, so the result does not depend on the launch.  Four waves per SIMD are asked
+// for: the walk over the list would otherwise keep more registers live and leave three.
 template <int NT>
-__global__ void __launch_bounds__(256) k_ortho_update(int G, int n_rb, int nchunk, const int* __restrict__ slot,
-                                                      const int* __restrict__ slotP, const double* C,
-                                                      const uint8_t* __restrict__ actC,
-                                                      const double* __restrict__ P, const uint8_t* __restrict__ cidx,
-                                                      const uint8_t* __restrict__ ncol,
-                                                      const int* __restrict__ gn_ptr, const int* __restrict__ gn,
-                                                      const int* __restrict__ pair_of,
-                                                      const uint8_t* __restrict__ pair_sel,
-                                                      const double* __restrict__ D, const double* __restrict__ Dt,
-                                                      const uint8_t* __restrict__ rmask,
-                                                      const Scalars* __restrict__ sd,
-                                                      const uint8_t* __restrict__ upd, double cut,
-                                                      const int* __restrict__ listN, const int* __restrict__ cntN,
-                                                      double* Cn, uint8_t* __restrict__ actN,
-                                                      unsigned int* __restrict__ cmaskN, int* __restrict__ cap_err,
-                                                      unsigned long long* ctr) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_ortho_update(int G, int n_rb, int nchunk, const int* __restrict__ slot,
+               const int* __restrict__ slotP, const double* C,
+               const uint8_t* __restrict__ actC,
+               const double* __restrict__ P, const uint8_t* __restrict__ cidx,
+               const uint8_t* __restrict__ ncol,
+               const int* __restrict__ gn_ptr, const int* __restrict__ gn,
+               const int* __restrict__ pair_of,
+               const uint8_t* __restrict__ pair_sel,
+               const double* __restrict__ D, const double* __restrict__ Dt,
+               const uint8_t* __restrict__ rmask,
+               const Scalars* __restrict__ sd,
+               const uint8_t* __restrict__ upd, double cut,
+               const int* __restrict__ listN, const int* __restrict__ cntN,
+               double* Cn, uint8_t* __restrict__ actN,
+               unsigned int* __restrict__ cmaskN, int* __restrict__ cap_err,
+               unsigned long long* ctr) {
   constexpr int W = NT * 16;
   constexpr int KB = 2;                       // k-steps whose loads go out together
   int chunk;
   const int g = xcd_group_chunk(nchunk, chunk);
   if (g >= G) return;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int t = chunk * 4 + wv;
-  if (t >= cntN[g]) return;
   const int lane = threadIdx.x & 63;
   const int lr = lane & 15, lk = lane >> 4;
-  const int r = listN[(size_t)g * n_rb + t];
   const double thr = 1e-3 * __longlong_as_double((long long)sd->eta_bits);
-  d4 acc[NT];
-#pragma unroll
-  for (int n = 0; n < NT; ++n) acc[n] = d4{0.0, 0.0, 0.0, 0.0};
-  unsigned int n_mfma = 0;
   const int k_end = gn_ptr[g + 1];
-  for (int kb = gn_ptr[g]; kb < k_end; kb += 64) {
-    const int k = kb + lane;
-    int h = 0, nz = 0, pk = 0, shk = 0;
-    if (k < k_end) {
-      h = gn[k];
-      const size_t th = (size_t)h * n_rb + r;
-      pk = pair_of[(size_t)g * G + h];
-      if (pair_sel[pk] && actC[th]) {
-        nz = ncol[th];
-        shk = slotP[th];                     // every lane's pair and slot in one round trip
-      }
-    }
-    unsigned long long M = __ballot(nz != 0);
-    // the next neighbour's packed column indices load while the current one multiplies
-    int jn = -1, col0n = 0, col1n = 0;
-    auto fetch_cols = [&]() {
-      jn = __ffsll((long long)M) - 1;
-      M &= M - 1ull;
-      const int nzn = __builtin_amdgcn_readfirstlane(__shfl(nz, jn));
-      const size_t shn = (size_t)(unsigned int)__builtin_amdgcn_readfirstlane(__shfl(shk, jn));
-      const uint8_t* ci = cidx + shn * W;      // packed column k's index lives in lane k or k - 64
-      col0n = lane < nzn ? ci[lane] : 0;
-      col1n = (W > 64 && lane + 64 < nzn) ? ci[lane + 64] : 0;
-    };
-    if (M) fetch_cols();
-    while (jn >= 0) {
-      const int j = jn;
-      const int col0 = col0n, col1 = col1n;
-      const int hc = __builtin_amdgcn_readfirstlane(__shfl(h, j));
-      const int nzj = __builtin_amdgcn_readfirstlane(__shfl(nz, j));
-      const int p = __builtin_amdgcn_readfirstlane(__shfl(pk, j));
-      const bool tr = hc > g;
-      const double* Dp = (tr ? Dt : D) + (size_t)p * W * W + lr;
-      const uint8_t* rm = rmask + ((size_t)p * 2 + (tr ? 1 : 0)) * W;
-      const size_t sh = (size_t)(unsigned int)__builtin_amdgcn_readfirstlane(__shfl(shk, j));
-      const double* A = P + sh * (RB * W) + lr;
-      int m0 = lane < nzj ? rm[col0] : 0;
-      int m1 = (W > 64 && lane + 64 < nzj) ? rm[col1] : 0;
-      jn = -1;
-      if (M) fetch_cols();
-      // OR over the four columns of each k-step (aligned groups of four lanes)
-      m0 |= __shfl_xor(m0, 1);
-      m0 |= __shfl_xor(m0, 2);
-      m1 |= __shfl_xor(m1, 1);
-      m1 |= __shfl_xor(m1, 2);
-      for (int s0 = 0; s0 < nzj; s0 += 4 * KB) {
-        double a[KB];
-        int col[KB];
-        unsigned int nm[KB];
+  const int n_t = cntN[g];
+  for (int t = chunk * 4 + wv; t < n_t; t += 4 * nchunk) {
+    const int r = listN[(size_t)g * n_rb + t];
+    d4 acc[NT];
 #pragma unroll
-        for (int u = 0; u < KB; ++u) {
-          const int q0 = s0 + 4 * u;           // first packed column of this k-step
-          const int kk = q0 + lk;
-          a[u] = kk < nzj ? A[kk * RB] : 0.0;
-          const int c0 = __shfl(col0, kk & 63), c1 = __shfl(col1, kk & 63);
-          col[u] = q0 < 64 ? c0 : c1;
-          unsigned int mm = 0u;
-          if (q0 < nzj) mm = (unsigned int)(q0 < 64 ? __builtin_amdgcn_readlane(m0, q0 & 63)
-                                                     : __builtin_amdgcn_readlane(m1, q0 & 63));
-          nm[u] = mm;
+    for (int n = 0; n < NT; ++n) acc[n] = d4{0.0, 0.0, 0.0, 0.0};
+    unsigned int n_mfma = 0;
+    for (int kb = gn_ptr[g]; kb < k_end; kb += 64) {
+      const int k = kb + lane;
+      int h = 0, nz = 0, pk = 0, shk = 0;
+      if (k < k_end) {
+        h = gn[k];
+        const size_t th = (size_t)h * n_rb + r;
+        pk = pair_of[(size_t)g * G + h];
+        if (pair_sel[pk] && actC[th]) {
+          nz = ncol[th];
+          shk = slotP[th];                     // every lane's pair and slot in one round trip
         }
-        double b[KB][NT];
+      }
+      unsigned long long M = __ballot(nz != 0);
+      // the next neighbour's packed column indices load while the current one multiplies
+      int jn = -1, col0n = 0, col1n = 0;
+      auto fetch_cols = [&]() {
+        jn = __ffsll((long long)M) - 1;
+        M &= M - 1ull;
+        const int nzn = __builtin_amdgcn_readfirstlane(__shfl(nz, jn));
+        const size_t shn = (size_t)(unsigned int)__builtin_amdgcn_readfirstlane(__shfl(shk, jn));
+        const uint8_t* ci = cidx + shn * W;      // packed column k's index lives in lane k or k - 64
+        col0n = lane < nzn ? ci[lane] : 0;
+        col1n = (W > 64 && lane + 64 < nzn) ? ci[lane + 64] : 0;
+      };
+      if (M) fetch_cols();
+      while (jn >= 0) {
+        const int j = jn;
+        const int col0 = col0n, col1 = col1n;
+        const int hc = __builtin_amdgcn_readfirstlane(__shfl(h, j));
+        const int nzj = __builtin_amdgcn_readfirstlane(__shfl(nz, j));
+        const int p = __builtin_amdgcn_readfirstlane(__shfl(pk, j));
+        const bool tr = hc > g;
+        const double* Dp = (tr ? Dt : D) + (size_t)p * W * W + lr;
+        const uint8_t* rm = rmask + ((size_t)p * 2 + (tr ? 1 : 0)) * W;
+        const size_t sh = (size_t)(unsigned int)__builtin_amdgcn_readfirstlane(__shfl(shk, j));
+        const double* A = P + sh * (RB * W) + lr;
+        int m0 = lane < nzj ? rm[col0] : 0;
+        int m1 = (W > 64 && lane + 64 < nzj) ? rm[col1] : 0;
+        jn = -1;
+        if (M) fetch_cols();
+        // OR over the four columns of each k-step (aligned groups of four lanes)
+        m0 |= __shfl_xor(m0, 1);
+        m0 |= __shfl_xor(m0, 2);
+        m1 |= __shfl_xor(m1, 1);
+        m1 |= __shfl_xor(m1, 2);
+        for (int s0 = 0; s0 < nzj; s0 += 4 * KB) {
+          double a[KB];
+          int col[KB];
+          unsigned int nm[KB];
 #pragma unroll
-        for (int u = 0; u < KB; ++u)
+          for (int u = 0; u < KB; ++u) {
+            const int q0 = s0 + 4 * u;           // first packed column of this k-step
+            const int kk = q0 + lk;
+            a[u] = kk < nzj ? A[kk * RB] : 0.0;
+            const int c0 = __shfl(col0, kk & 63), c1 = __shfl(col1, kk & 63);
+            col[u] = q0 < 64 ? c0 : c1;
+            unsigned int mm = 0u;
+            if (q0 < nzj) mm = (unsigned int)(q0 < 64 ? __builtin_amdgcn_readlane(m0, q0 & 63)
+                                                       : __builtin_amdgcn_readlane(m1, q0 & 63));
+            nm[u] = mm;
+          }
+          double b[KB][NT];
 #pragma unroll
-          for (int n = 0; n < NT; ++n) b[u][n] = ((nm[u] >> n) & 1u) ? Dp[(size_t)col[u] * W + n * 16] : 0.0;
+          for (int u = 0; u < KB; ++u)
 #pragma unroll
-        for (int u = 0; u < KB; ++u)
+            for (int n = 0; n < NT; ++n) b[u][n] = ((nm[u] >> n) & 1u) ? Dp[(size_t)col[u] * W + n * 16] : 0.0;
 #pragma unroll
-          for (int n = 0; n < NT; ++n)
-            if ((nm[u] >> n) & 1u) {
-              const double bv = (fabs(b[u][n]) >= thr) ? b[u][n] : 0.0;
-              acc[n] = mfma64(a[u], bv, acc[n]);
-              ++n_mfma;
-            }
+          for (int u = 0; u < KB; ++u)
+#pragma unroll
+            for (int n = 0; n < NT; ++n)
+              if ((nm[u] >> n) & 1u) {
+                const double bv = (fabs(b[u][n]) >= thr) ? b[u][n] : 0.0;
+                acc[n] = mfma64(a[u], bv, acc[n]);
+                ++n_mfma;
+              }
+        }
       }
     }
-  }
-  const size_t tile = (size_t)g * n_rb + r;
-  const int so_i = slot[tile];
-  if (so_i < 0) {
-    // a tile with no slot (listed with activity 2): C is zero there; the combination must
-    // leave it so after the cut, else C has outgrown its capacity
-    int bad = 0;
+    const size_t tile = (size_t)g * n_rb + r;
+    const int so_i = slot[tile];
+    if (so_i < 0) {
+      // a tile with no slot (listed with activity 2): C is zero there; the combination must
+      // leave it so after the cut, else C has outgrown its capacity
+      int bad = 0;
+#pragma unroll
+      for (int n = 0; n < NT; ++n) {
+        const bool u = upd[(size_t)g * W + n * 16 + lr] != 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double v = -0.5 * acc[n][q];
+          bad |= (u ? fabs(v) >= cut : v != 0.0);
+        }
+      }
+      if (__ballot(bad) && lane == 0) note_capacity(cap_err, tile);
+      if (lane == 0) {
+        actN[tile] = 0;
+        cmaskN[tile] = 0u;
+        if (ctr && n_mfma) atomicAdd(ctr, (unsigned long long)n_mfma);
+      }
+      continue;
+    }
+    const bool own = actC[tile] != 0;
+    const size_t so = (size_t)so_i;
+    const double* Cg = C + so * (RB * W);
+    double* Co = Cn + so * (RB * W);
+    unsigned int cm = 0;
 #pragma unroll
     for (int n = 0; n < NT; ++n) {
-      const bool u = upd[(size_t)g * W + n * 16 + lr] != 0;
+      const int jj = n * 16 + lr;
+      const bool u = upd[(size_t)g * W + jj] != 0;
+      int nz = 0;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const double v = -0.5 * acc[n][q];
-        bad |= (u ? fabs(v) >= cut : v != 0.0);
+        const int i = lk + 4 * q;
+        double v = (own ? Cg[i * W + jj] : 0.0) - 0.5 * acc[n][q];
+        if (u && fabs(v) < cut) v = 0.0;
+        Co[i * W + jj] = v;
+        nz |= (v != 0.0);
       }
+      if (__ballot(nz)) cm |= 1u << n;
     }
-    if (__ballot(bad) && lane == 0) note_capacity(cap_err, tile);
     if (lane == 0) {
-      actN[tile] = 0;
-      cmaskN[tile] = 0u;
+      actN[tile] = (uint8_t)(cm != 0u);
+      cmaskN[tile] = cm;
       if (ctr && n_mfma) atomicAdd(ctr, (unsigned long long)n_mfma);
     }
-    return;
-  }
-  const bool own = actC[tile] != 0;
-  const size_t so = (size_t)so_i;
-  const double* Cg = C + so * (RB * W);
-  double* Co = Cn + so * (RB * W);
-  unsigned int cm = 0;
-#pragma unroll
-  for (int n = 0; n < NT; ++n) {
-    const int jj = n * 16 + lr;
-    const bool u = upd[(size_t)g * W + jj] != 0;
-    int nz = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = lk + 4 * q;
-      double v = (own ? Cg[i * W + jj] : 0.0) - 0.5 * acc[n][q];
-      if (u && fabs(v) < cut) v = 0.0;
-      Co[i * W + jj] = v;
-      nz |= (v != 0.0);
-    }
-    if (__ballot(nz)) cm |= 1u << n;
-  }
-  if (lane == 0) {
-    actN[tile] = (uint8_t)(cm != 0u);
-    cmaskN[tile] = cm;
-    if (ctr && n_mfma) atomicAdd(ctr, (unsigned long long)n_mfma);
   }
 }
 
@@ -898,7 +948,7 @@ void launch_ortho_update(const View& v, const double* C, const uint8_t* actC, co
                          const uint8_t* pair_sel, const double* D, const double* Dt, const uint8_t* rmask,
                          const Scalars* sd, const uint8_t* upd, double cut, const int* listN, const int* cntN,
                          double* Cn, uint8_t* actN, unsigned int* cmaskN, unsigned long long* ctr, hipStream_t s) {
-  const int nchunk = (v.n_rb + 3) / 4;
+  const int nchunk = tile_list_chunks(v.G, v.n_rb);
   dim3 grid(xcd_grid(v.G, nchunk)), blk(256);
   switch (v.W / 16) {
 #define SSCF_UPD(NT) case NT: hipLaunchKernelGGL(k_ortho_update<NT>, grid, blk, 0, s, v.G, v.n_rb, nchunk, v.slot, v.slotY, C, actC, P, cidx, ncol, gn_ptr, gn, pair_of, pair_sel, D, Dt, rmask, sd, upd, cut, listN, cntN, Cn, actN, cmaskN, v.cap_err, ctr); break;
