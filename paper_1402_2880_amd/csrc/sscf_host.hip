@@ -409,7 +409,7 @@ struct sscf_ctx {
       // the combination reads the nonzero columns of C packed into Y (free until the next product)
       const int pu = pbegin(KC_UPDATE);
       launch_pack_cols(v, C[cur], listC[cur], cntC[cur], occ_only ? v.OW : v.W, Y, pcidx, pncol, stream);
-      launch_ortho_update(v, C[cur], actC[cur], Y, pcidx, pncol, gn_ptr, gn, pair_of, pair_sel, O, Dt, rmask, sd, upd,
+      launch_ortho_update(v, C[cur], actC[cur], cmask[cur], Y, pcidx, pncol, gn_ptr, gn, pair_of, pair_sel, O, Dt, rmask, sd, upd,
                           cut, list_tmp, cnt_tmp, C[nx], actC[nx], cmask[nx], ctr(KC_UPDATE), stream);
       pend(pu);
       rebuild_list(nx);

@@ -131,7 +131,8 @@ void launch_tile_flags(const View& v, const double* C, const int* list, const in
                        unsigned int* cmask, ulonglong2* colm, hipStream_t s);
 void launch_pack_cols(const View& v, const double* C, const int* list, const int* cnt, int col_end, double* P,
                       uint8_t* cidx, uint8_t* ncol, hipStream_t s);
-void launch_ortho_update(const View& v, const double* C, const uint8_t* actC, const double* P, const uint8_t* cidx,
+void launch_ortho_update(const View& v, const double* C, const uint8_t* actC, const unsigned int* cmaskC,
+                         const double* P, const uint8_t* cidx,
                          const uint8_t* ncol, const int* gn_ptr, const int* gn, const int* pair_of,
                          const uint8_t* pair_sel, const double* D, const double* Dt, const uint8_t* rmask,
                          const Scalars* sd, const uint8_t* upd, double cut, const int* listN, const int* cntN,

@@ -783,7 +783,7 @@ template <int NT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_ortho_update(int G, int n_rb, int nchunk, const int* __restrict__ slot,
                const int* __restrict__ slotP, const double* C,
-               const uint8_t* __restrict__ actC,
+               const uint8_t* __restrict__ actC, const unsigned int* __restrict__ cmaskC,
                const double* __restrict__ P, const uint8_t* __restrict__ cidx,
                const uint8_t* __restrict__ ncol,
                const int* __restrict__ gn_ptr, const int* __restrict__ gn,
@@ -915,7 +915,10 @@ k_ortho_update(int G, int n_rb, int nchunk, const int* __restrict__ slot,
       }
       continue;
     }
-    const bool own = actC[tile] != 0;
+    // a 16-column slice whose flag is clear holds zeros (C's pool starts zeroed, and every
+    // writer of C leaves the flags exact for the values it stores): it is not read, and it is
+    // not written when the combination adds nothing to it
+    const unsigned int cm_old = actC[tile] ? cmaskC[tile] : 0u;
     const size_t so = (size_t)so_i;
     const double* Cg = C + so * (RB * W);
     double* Co = Cn + so * (RB * W);
@@ -924,13 +927,16 @@ k_ortho_update(int G, int n_rb, int nchunk, const int* __restrict__ slot,
     for (int n = 0; n < NT; ++n) {
       const int jj = n * 16 + lr;
       const bool u = upd[(size_t)g * W + jj] != 0;
+      const bool was = (cm_old >> n) & 1u;
+      const bool hit = __ballot(acc[n][0] != 0.0 || acc[n][1] != 0.0 || acc[n][2] != 0.0 || acc[n][3] != 0.0) != 0ull;
+      const bool put = was || hit;
       int nz = 0;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i = lk + 4 * q;
-        double v = (own ? Cg[i * W + jj] : 0.0) - 0.5 * acc[n][q];
+        double v = (was ? Cg[i * W + jj] : 0.0) - 0.5 * acc[n][q];
         if (u && fabs(v) < cut) v = 0.0;
-        Co[i * W + jj] = v;
+        if (put) Co[i * W + jj] = v;
         nz |= (v != 0.0);
       }
       if (__ballot(nz)) cm |= 1u << n;
@@ -943,7 +949,8 @@ k_ortho_update(int G, int n_rb, int nchunk, const int* __restrict__ slot,
   }
 }
 
-void launch_ortho_update(const View& v, const double* C, const uint8_t* actC, const double* P, const uint8_t* cidx,
+void launch_ortho_update(const View& v, const double* C, const uint8_t* actC, const unsigned int* cmaskC,
+                         const double* P, const uint8_t* cidx,
                          const uint8_t* ncol, const int* gn_ptr, const int* gn, const int* pair_of,
                          const uint8_t* pair_sel, const double* D, const double* Dt, const uint8_t* rmask,
                          const Scalars* sd, const uint8_t* upd, double cut, const int* listN, const int* cntN,
@@ -951,7 +958,7 @@ void launch_ortho_update(const View& v, const double* C, const uint8_t* actC, co
   const int nchunk = tile_list_chunks(v.G, v.n_rb);
   dim3 grid(xcd_grid(v.G, nchunk)), blk(256);
   switch (v.W / 16) {
-#define SSCF_UPD(NT) case NT: hipLaunchKernelGGL(k_ortho_update<NT>, grid, blk, 0, s, v.G, v.n_rb, nchunk, v.slot, v.slotY, C, actC, P, cidx, ncol, gn_ptr, gn, pair_of, pair_sel, D, Dt, rmask, sd, upd, cut, listN, cntN, Cn, actN, cmaskN, v.cap_err, ctr); break;
+#define SSCF_UPD(NT) case NT: hipLaunchKernelGGL(k_ortho_update<NT>, grid, blk, 0, s, v.G, v.n_rb, nchunk, v.slot, v.slotY, C, actC, cmaskC, P, cidx, ncol, gn_ptr, gn, pair_of, pair_sel, D, Dt, rmask, sd, upd, cut, listN, cntN, Cn, actN, cmaskN, v.cap_err, ctr); break;
     SSCF_UPD(1) SSCF_UPD(2) SSCF_UPD(3) SSCF_UPD(4) SSCF_UPD(5) SSCF_UPD(6) SSCF_UPD(7) SSCF_UPD(8)
 #undef SSCF_UPD
   }
