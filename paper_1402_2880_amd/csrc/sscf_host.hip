@@ -467,11 +467,11 @@ struct sscf_ctx {
     // active row block of the group (W needs no other; Z overwrites Y, in Y's pool)
     launch_update_support(v, listC[cur], cntC[cur], n_pairs, pg, ph, pair_all, actY, act_tmp, s);
     launch_list(v, act_tmp, list_tmp, cnt_tmp, s);
-    launch_apply_occ(v, C[cur], actC[cur], gn_ptr, gn, pair_of, pg, foo_a, foo_b, list_tmp, cnt_tmp, Y, s);
+    launch_apply_occ(v, C[cur], actC[cur], cmask[cur], gn_ptr, gn, pair_of, pg, foo_a, foo_b, list_tmp, cnt_tmp, Y, s);
     // P = 2 C_occ C_occ^T and W = 2 C_occ Z^T on the pattern of S, then the layout of S_val
     launch_list_t(v, actC[cur], listT, cntT, s);
-    launch_density_blocks(v, C[cur], listT, cntT, C[cur], actC[cur], false, pblk, s);
-    launch_density_blocks(v, C[cur], listT, cntT, Y, act_tmp, true, wblk, s);
+    launch_density_blocks(v, C[cur], cmask[cur], listT, cntT, C[cur], actC[cur], cmask[cur], false, pblk, s);
+    launch_density_blocks(v, C[cur], cmask[cur], listT, cntT, Y, act_tmp, nullptr, true, wblk, s);
     launch_grad_assemble(v, n_val, val_map, pblk, wblk, Q, scc && !fock_full, dX, dS, s);
     if (don) launch_grad_onsite(v, ao_off, xs_diag, pblk, don, s);
   }
@@ -1782,8 +1782,8 @@ sscf_status sscf_get_density(const sscf_ctx* cx, double* p_val, size_t n_val) {
     if (!x->pblk) x->pblk = x->dalloc<double>((size_t)x->v.nbx * 256);
     if (!x->pval) x->pval = x->dalloc<double>(x->n_val);
     launch_list_t(x->v, x->actC[x->cur], x->listT, x->cntT, x->stream);
-    launch_density_blocks(x->v, x->C[x->cur], x->listT, x->cntT, x->C[x->cur], x->actC[x->cur], false, x->pblk,
-                          x->stream);
+    launch_density_blocks(x->v, x->C[x->cur], x->cmask[x->cur], x->listT, x->cntT, x->C[x->cur], x->actC[x->cur],
+                          x->cmask[x->cur], false, x->pblk, x->stream);
     launch_gather(x->val_map, x->n_val, x->pblk, x->pval, x->stream);
     HIPC(hipMemcpyAsync(p_val, x->pval, sizeof(double) * x->n_val, hipMemcpyDeviceToHost, x->stream));
     x->sync();

@@ -200,14 +200,18 @@ void launch_atom_charges(const View& v, const int64_t* ao_off, const double* row
 void launch_sum_band(const View& v, const double* d, const int* pnocc, Scalars* sd, hipStream_t s);
 void launch_sum_coul(const View& v, int scc, const double* dq, const double* Q, Scalars* sd,
                      hipStream_t s);
-// listTA/cntTA: launch_list_t of A's activity; B_is_y: B lives in the pool of Y (slotY), else in that of C
-void launch_density_blocks(const View& v, const double* A, const int* listTA, const int* cntTA, const double* B,
-                           const uint8_t* actB, bool B_is_y, double* P, hipStream_t s);
+// listTA/cntTA: launch_list_t of A's activity; cmA / cmB: the 16-column slice masks of A's and
+// B's tiles (cmB may be NULL: B's slices not tracked); B_is_y: B lives in the pool of Y (slotY),
+// else in that of C
+void launch_density_blocks(const View& v, const double* A, const unsigned int* cmA, const int* listTA,
+                           const int* cntTA, const double* B, const uint8_t* actB, const unsigned int* cmB,
+                           bool B_is_y, double* P, hipStream_t s);
 void launch_grad_assemble(const View& v, int64_t n_val, const int64_t* map, const double* P, const double* Wb,
                           const double* Q, int qterm, double* dX, double* dS, hipStream_t s);
 void launch_grad_onsite(const View& v, const int64_t* ao_off, const int* xs_diag, const double* P, double* out,
                         hipStream_t s);
-void launch_apply_occ(const View& v, const double* C, const uint8_t* actC, const int* gn_ptr, const int* gn,
+void launch_apply_occ(const View& v, const double* C, const uint8_t* actC, const unsigned int* cmask,
+                      const int* gn_ptr, const int* gn,
                       const int* pair_of, const int* pg, const double* FA, const double* FB, const int* listZ,
                       const int* cntZ, double* Z, hipStream_t s);
 // ---- work counting (sscf_count.hip) --------------------------------------------------------

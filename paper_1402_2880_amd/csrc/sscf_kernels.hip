@@ -1792,9 +1792,10 @@ void launch_sum_coul(const View& v, int scc, const double* dq, const double* Q, 
 __global__ void __launch_bounds__(256) k_density_blocks(int nbx, int G, int n_rb, int W, int OW, const int* slot,
                                                         const int* slotB,
                                                         const int* xs_row,
-                                                        const int* xs_col, const double* A, const int* listTA,
+                                                        const int* xs_col, const double* A,
+                                                        const unsigned int* cmA, const int* listTA,
                                                         const int* cntTA, const double* B, const uint8_t* actB,
-                                                        double* P) {
+                                                        const unsigned int* cmB, double* P) {
   const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (b >= nbx) return;
   const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
@@ -1802,23 +1803,40 @@ __global__ void __launch_bounds__(256) k_density_blocks(int nbx, int G, int n_rb
   d4 acc = d4{0.0, 0.0, 0.0, 0.0};
   const int* LA = listTA + (size_t)r * G;
   const int na = cntTA[r];
+  const unsigned int occ = (1u << (OW / 16)) - 1u;
   for (int k = 0; k < na; ++k) {                // the groups active in A at row block r, ascending
     const int g = LA[k];
     const size_t tr = (size_t)g * n_rb + r, tc = (size_t)g * n_rb + c;
     if (!actB[tc]) continue;
-    const double* At = A + (size_t)slot[tr] * (RB * W);
-    const double* Bt = B + (size_t)slotB[tc] * (RB * W);
-    for (int s = 0; s < OW / 4; ++s) acc = mfma64(At[lr * W + 4 * s + lk], Bt[lr * W + 4 * s + lk], acc);
+    // occupied 16-column slices nonzero on both sides (cmB NULL: B's slices are not tracked);
+    // a 4-column k-step that is zero in every lane on either side adds exact zeros
+    const unsigned int m = cmA[tr] & (cmB ? cmB[tc] : 0xffffffffu) & occ;
+    if (!m) continue;
+    const double* At = A + (size_t)slot[tr] * (RB * W) + lr * W + lk;
+    const double* Bt = B + (size_t)slotB[tc] * (RB * W) + lr * W + lk;
+    for (int sl = 0; sl < OW / 16; ++sl) {
+      if (!((m >> sl) & 1u)) continue;
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = At[16 * sl + 4 * u];
+        b[u] = Bt[16 * sl + 4 * u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (__ballot(a[u] != 0.0) && __ballot(b[u] != 0.0)) acc = mfma64(a[u], b[u], acc);
+    }
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) P[(size_t)b * 256 + (lk + 4 * q) * 16 + lr] = 2.0 * acc[q];
 }
 // 2 A_occ B_occ^T on the 16 x 16 blocks of the S pattern: the density P (A = B = C) or
 // W = 2 C_occ Z_occ^T (B = Z) of the energy gradient
-void launch_density_blocks(const View& v, const double* A, const int* listTA, const int* cntTA, const double* B,
-                           const uint8_t* actB, bool B_is_y, double* P, hipStream_t s) {
+void launch_density_blocks(const View& v, const double* A, const unsigned int* cmA, const int* listTA,
+                           const int* cntTA, const double* B, const uint8_t* actB, const unsigned int* cmB,
+                           bool B_is_y, double* P, hipStream_t s) {
   hipLaunchKernelGGL(k_density_blocks, dim3((v.nbx + 3) / 4), dim3(256), 0, s, v.nbx, v.G, v.n_rb, v.W, v.OW,
-                     v.slot, B_is_y ? v.slotY : v.slot, v.xs_row, v.xs_col, A, listTA, cntTA, B, actB, P);
+                     v.slot, B_is_y ? v.slotY : v.slot, v.xs_row, v.xs_col, A, cmA, listTA, cntTA, B, actB, cmB, P);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1873,7 +1891,8 @@ void launch_grad_onsite(const View& v, const int64_t* ao_off, const int* xs_diag
 template <int NO>
 __global__ void __launch_bounds__(256) k_apply_occ(int G, int n_rb, int W, int nchunk, const int* __restrict__ slot,
                                                    const int* __restrict__ slotZ, const double* __restrict__ C,
-                                                   const uint8_t* __restrict__ actC, const int* __restrict__ gn_ptr,
+                                                   const uint8_t* __restrict__ actC,
+                                                   const unsigned int* __restrict__ cmask, const int* __restrict__ gn_ptr,
                                                    const int* __restrict__ gn, const int* __restrict__ pair_of,
                                                    const int* __restrict__ pg, const double* __restrict__ FA,
                                                    const double* __restrict__ FB, const int* __restrict__ listZ,
@@ -1894,14 +1913,28 @@ __global__ void __launch_bounds__(256) k_apply_occ(int G, int n_rb, int W, int n
     const int h = gn[k];
     const size_t th = (size_t)h * n_rb + r;
     if (!actC[th]) continue;
+    // the occupied 16-column slices of C_h(r) that hold a nonzero; a 4-column k-step that is
+    // zero in every lane adds exact zeros and is skipped
+    const unsigned int m = cmask[th] & ((1u << NO) - 1u);
+    if (!m) continue;
     const int p = pair_of[(size_t)g * G + h];
     const double* Fp = ((pg[p] == h) ? FA : FB) + (size_t)p * OW * OW + lr;
     const double* Ch = C + (size_t)slot[th] * (RB * W) + lr * W + lk;
-#pragma unroll 4
-    for (int s = 0; s < OW / 4; ++s) {
-      const double a = Ch[4 * s];
+    for (int sl = 0; sl < NO; ++sl) {
+      if (!((m >> sl) & 1u)) continue;
+      double a[4], f[4][NO];
 #pragma unroll
-      for (int n = 0; n < NO; ++n) acc[n] = mfma64(a, Fp[(4 * s + lk) * OW + n * 16], acc[n]);
+      for (int u = 0; u < 4; ++u) {
+        const int s = 4 * sl + u;
+        a[u] = Ch[4 * s];
+#pragma unroll
+        for (int n = 0; n < NO; ++n) f[u][n] = Fp[(4 * s + lk) * OW + n * 16];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (__ballot(a[u] != 0.0))
+#pragma unroll
+          for (int n = 0; n < NO; ++n) acc[n] = mfma64(a[u], f[u][n], acc[n]);
     }
   }
   double* Zt = Z + (size_t)slotZ[(size_t)g * n_rb + r] * (RB * W);
@@ -1911,13 +1944,14 @@ __global__ void __launch_bounds__(256) k_apply_occ(int G, int n_rb, int W, int n
     for (int q = 0; q < 4; ++q) Zt[(lk + 4 * q) * W + n * 16 + lr] = acc[n][q];
 }
 
-void launch_apply_occ(const View& v, const double* C, const uint8_t* actC, const int* gn_ptr, const int* gn,
+void launch_apply_occ(const View& v, const double* C, const uint8_t* actC, const unsigned int* cmask,
+                      const int* gn_ptr, const int* gn,
                       const int* pair_of, const int* pg, const double* FA, const double* FB, const int* listZ,
                       const int* cntZ, double* Z, hipStream_t s) {
   const int nchunk = (v.max_y + 3) / 4;
   dim3 grid(xcd_grid(v.G, nchunk)), blk(256);
   switch (v.OW / 16) {
-#define SSCF_APO(NO) case NO: hipLaunchKernelGGL(k_apply_occ<NO>, grid, blk, 0, s, v.G, v.n_rb, v.W, nchunk, v.slot, v.slotY, C, actC, gn_ptr, gn, pair_of, pg, FA, FB, listZ, cntZ, Z); break;
+#define SSCF_APO(NO) case NO: hipLaunchKernelGGL(k_apply_occ<NO>, grid, blk, 0, s, v.G, v.n_rb, v.W, nchunk, v.slot, v.slotY, C, actC, cmask, gn_ptr, gn, pair_of, pg, FA, FB, listZ, cntZ, Z); break;
     SSCF_APO(1) SSCF_APO(2) SSCF_APO(3) SSCF_APO(4) SSCF_APO(5) SSCF_APO(6) SSCF_APO(7) SSCF_APO(8)
 #undef SSCF_APO
     default: break;
