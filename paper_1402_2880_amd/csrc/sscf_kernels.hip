@@ -397,24 +397,57 @@ void launch_pair(const View& v, int n_pairs, const int* perm, int maxc, const in
 
 // per-column dot products d[g][c] = sum_r sum_k C[g][r][k][c] Y[g][r][k][c]
 // The active row blocks of panel g are split into CD_SPLIT strided parts, one workgroup each;
-// the parts' sums are added in a fixed order by k_coldot_sum.
+// the parts' sums are added in a fixed order by k_coldot_sum.  The workgroup first reads the
+// slots and slice masks of up to blockDim.x of its tiles into LDS, one tile per thread, so
+// that the walk over them waits on the tiles' values only.
 
-__global__ void k_coldot(int n_rb, int W, const int* slot, const int* slotY, const double* C, const int* listC,
-                         const int* cntC, const unsigned int* cmask, const double* Y, const uint8_t* actY,
-                         double* part) {
-  const int g = blockIdx.x, sp = blockIdx.y, c = threadIdx.x;
-  if (c >= W) return;
-  const size_t gb = (size_t)g * n_rb;
-  double s = 0.0;
-  for (int t = sp; t < cntC[g]; t += CD_SPLIT) {
-    const int r = listC[gb + t];
-    if (!actY[gb + r] || !((cmask[gb + r] >> (c >> 4)) & 1u)) continue;   // a zero slice adds zeros
-    const double* Ct = C + (size_t)slot[gb + r] * (RB * W) + c;
-    const double* Yt = Y + (size_t)slotY[gb + r] * (RB * W) + c;
-#pragma unroll
-    for (int k = 0; k < RB; ++k) s += Ct[k * W] * Yt[k * W];
+// slots and slice mask of the tiles t0 + stride i (i < n) of panel g, thread i -> LDS entry i
+// (mask 0: the tile is skipped); returns the number staged.  Every thread of the block calls it.
+__device__ inline int stage_tiles(size_t gb, const int* listC, int t0, int stride, int n, const int* slot,
+                                  const int* slotY, const unsigned int* cmask, const uint8_t* actY, int* s_so,
+                                  int* s_sy, unsigned int* s_cm) {
+  const int i = threadIdx.x;
+  unsigned int cm = 0u;
+  int so = 0, sy = 0;
+  if (i < n) {
+    const int r = listC[gb + t0 + stride * i];
+    if (actY[gb + r]) {
+      cm = cmask[gb + r];
+      so = slot[gb + r];
+      sy = slotY[gb + r];
+    }
   }
-  part[((size_t)sp * gridDim.x + g) * W + c] = s;
+  s_cm[i] = cm;
+  s_so[i] = so;
+  s_sy[i] = sy;
+  __syncthreads();
+  return n < (int)blockDim.x ? n : (int)blockDim.x;
+}
+
+__global__ void __launch_bounds__(256) k_coldot(int n_rb, int W, const int* slot, const int* slotY, const double* C,
+                                                const int* listC, const int* cntC, const unsigned int* cmask,
+                                                const double* Y, const uint8_t* actY, double* part) {
+  __shared__ int s_so[256], s_sy[256];
+  __shared__ unsigned int s_cm[256];
+  const int g = blockIdx.x, sp = blockIdx.y, c = threadIdx.x;
+  const size_t gb = (size_t)g * n_rb;
+  const int cnt = cntC[g];
+  const int mine = cnt > sp ? (cnt - sp + CD_SPLIT - 1) / CD_SPLIT : 0;   // tiles sp, sp + CD_SPLIT, ...
+  double s = 0.0;
+  for (int i0 = 0; i0 < mine; i0 += blockDim.x) {
+    const int nb = stage_tiles(gb, listC, sp + CD_SPLIT * i0, CD_SPLIT, mine - i0, slot, slotY, cmask, actY, s_so,
+                               s_sy, s_cm);
+    if (c < W)
+      for (int j = 0; j < nb; ++j) {
+        if (!((s_cm[j] >> (c >> 4)) & 1u)) continue;   // a zero slice adds zeros
+        const double* Ct = C + (size_t)s_so[j] * (RB * W) + c;
+        const double* Yt = Y + (size_t)s_sy[j] * (RB * W) + c;
+#pragma unroll
+        for (int k = 0; k < RB; ++k) s += Ct[k * W] * Yt[k * W];
+      }
+    __syncthreads();
+  }
+  if (c < W) part[((size_t)sp * gridDim.x + g) * W + c] = s;
 }
 __global__ void k_coldot_sum(size_t n, const double* part, double* out) {
   const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
@@ -509,16 +542,38 @@ constexpr int TILE_STRIDE_WG = 64;
 
 __global__ void __launch_bounds__(256) k_scale_c(int n_rb, int W, const int* slot, double* C, const int* listC,
                                                  const int* cntC, const unsigned int* cmask, const double* sc) {
+  __shared__ int s_so[256];
+  __shared__ unsigned int s_cm[256];
   const int g = blockIdx.y;
   const double* s = sc + (size_t)g * W;
-  for (int t = blockIdx.x; t < cntC[g]; t += gridDim.x) {
-    const size_t tile = (size_t)g * n_rb + listC[(size_t)g * n_rb + t];
-    double* Ct = C + (size_t)slot[tile] * (RB * W);
-    const unsigned int cm = cmask[tile];
-    for (int e = threadIdx.x; e < RB * W; e += 256) {
-      const int c = e % W;
-      if ((cm >> (c >> 4)) & 1u) Ct[e] = Ct[e] / s[c];     // a zero slice stays zero
+  const size_t gb = (size_t)g * n_rb;
+  const int cnt = cntC[g];
+  const int mine = cnt > (int)blockIdx.x ? (cnt - (int)blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
+  for (int i0 = 0; i0 < mine; i0 += 256) {
+    // the slots and slice masks of 256 of this workgroup's tiles, one per thread
+    {
+      const int i = i0 + (int)threadIdx.x;
+      int so = 0;
+      unsigned int cm = 0u;
+      if (i < mine) {
+        const size_t tile = gb + listC[gb + blockIdx.x + (size_t)gridDim.x * i];
+        so = slot[tile];
+        cm = cmask[tile];
+      }
+      s_so[threadIdx.x] = so;
+      s_cm[threadIdx.x] = cm;
     }
+    __syncthreads();
+    const int nb = mine - i0 < 256 ? mine - i0 : 256;
+    for (int j = 0; j < nb; ++j) {
+      double* Ct = C + (size_t)s_so[j] * (RB * W);
+      const unsigned int cm = s_cm[j];
+      for (int e = threadIdx.x; e < RB * W; e += 256) {
+        const int c = e % W;
+        if ((cm >> (c >> 4)) & 1u) Ct[e] = Ct[e] / s[c];     // a zero slice stays zero
+      }
+    }
+    __syncthreads();
   }
 }
 void launch_scale_c(const View& v, double* C, const int* listC, const int* cntC, const unsigned int* cmask,
@@ -1690,23 +1745,45 @@ __global__ void __launch_bounds__(256) k_charges_rows(int G, int n_rb, int n_ao,
                                                       const int* listTC, const int* cntTC, const double* Y,
                                                       const uint8_t* actY, const double* sc, const int* pnocc,
                                                       double* rowq) {
+  __shared__ int s_g[256], s_so[256], s_sy[256], s_no[256];
   const int rb = blockIdx.x;
   const int k = threadIdx.x >> 4, l = threadIdx.x & 15;
   double acc = 0.0;
   const int* LC = listTC + (size_t)rb * G;
   const int nc = cntTC[rb];
-  for (int i = 0; i < nc; ++i) {                 // the groups active in C at rb, ascending
-    const int g = LC[i];
-    const size_t tile = (size_t)g * n_rb + rb;
-    if (!actY[tile]) continue;
-    const int no = pnocc[g];
-    const double* Cr = C + ((size_t)slot[tile] * RB + k) * W;
-    const double* Yr = Y + ((size_t)slotY[tile] * RB + k) * W;
-    const double* s = sc + (size_t)g * W;
-    double part = 0.0;
-    for (int c = l; c < no; c += 16) part += Cr[c] * Yr[c] / s[c];
-    for (int o = 8; o > 0; o >>= 1) part += __shfl_xor(part, o, 16);
-    acc += part;
+  for (int i0 = 0; i0 < nc; i0 += 256) {         // the groups active in C at rb, ascending
+    // their slots and occupied counts, 256 at a time, one group per thread (no = 0: skipped)
+    {
+      const int i = i0 + (int)threadIdx.x;
+      int g = 0, so = 0, sy = 0, no = 0;
+      if (i < nc) {
+        g = LC[i];
+        const size_t tile = (size_t)g * n_rb + rb;
+        if (actY[tile]) {
+          so = slot[tile];
+          sy = slotY[tile];
+          no = pnocc[g];
+        }
+      }
+      s_g[threadIdx.x] = g;
+      s_so[threadIdx.x] = so;
+      s_sy[threadIdx.x] = sy;
+      s_no[threadIdx.x] = no;
+    }
+    __syncthreads();
+    const int nb = nc - i0 < 256 ? nc - i0 : 256;
+    for (int j = 0; j < nb; ++j) {
+      const int no = s_no[j];
+      if (!no) continue;
+      const double* Cr = C + ((size_t)s_so[j] * RB + k) * W;
+      const double* Yr = Y + ((size_t)s_sy[j] * RB + k) * W;
+      const double* s = sc + (size_t)s_g[j] * W;
+      double part = 0.0;
+      for (int c = l; c < no; c += 16) part += Cr[c] * Yr[c] / s[c];
+      for (int o = 8; o > 0; o >>= 1) part += __shfl_xor(part, o, 16);
+      acc += part;
+    }
+    __syncthreads();
   }
   const int mu = rb * RB + k;
   if (l == 0 && mu < n_ao) rowq[mu] = 2.0 * acc;
@@ -2095,22 +2172,28 @@ void launch_pair32(const View& v, int n_pairs, const int* perm, int maxc, const 
     hipLaunchKernelGGL((k_pair32<4, 4>), grid, blk, 0, s, v.n_rb, v.W, v.slot, v.slotY, perm, maxc, pg, ph, C, listC, cntC, cmask, Y, actY, ymask, row_off, MT, col_off, NT, out, ld, out_stride, ctr);
 }
 
-__global__ void k_coldot32(int n_rb, int W, const int* slot, const int* slotY, const float* C, const int* listC,
-                           const int* cntC, const unsigned int* cmask, const float* Y, const uint8_t* actY,
-                           double* out) {
+__global__ void __launch_bounds__(256) k_coldot32(int n_rb, int W, const int* slot, const int* slotY, const float* C,
+                                                  const int* listC, const int* cntC, const unsigned int* cmask,
+                                                  const float* Y, const uint8_t* actY, double* out) {
+  __shared__ int s_so[256], s_sy[256];
+  __shared__ unsigned int s_cm[256];
   const int g = blockIdx.x, c = threadIdx.x;
-  if (c >= W) return;
   const size_t gb = (size_t)g * n_rb;
+  const int cnt = cntC[g];
   float s = 0.f;
-  for (int t = 0; t < cntC[g]; ++t) {
-    const int r = listC[gb + t];
-    if (!actY[gb + r] || !((cmask[gb + r] >> (c >> 4)) & 1u)) continue;   // a zero slice adds zeros
-    const float* Ct = C + (size_t)slot[gb + r] * (RB * W) + c;
-    const float* Yt = Y + (size_t)slotY[gb + r] * (RB * W) + c;
+  for (int i0 = 0; i0 < cnt; i0 += blockDim.x) {
+    const int nb = stage_tiles(gb, listC, i0, 1, cnt - i0, slot, slotY, cmask, actY, s_so, s_sy, s_cm);
+    if (c < W)
+      for (int j = 0; j < nb; ++j) {
+        if (!((s_cm[j] >> (c >> 4)) & 1u)) continue;   // a zero slice adds zeros
+        const float* Ct = C + (size_t)s_so[j] * (RB * W) + c;
+        const float* Yt = Y + (size_t)s_sy[j] * (RB * W) + c;
 #pragma unroll
-    for (int k = 0; k < RB; ++k) s += Ct[k * W] * Yt[k * W];
+        for (int k = 0; k < RB; ++k) s += Ct[k * W] * Yt[k * W];
+      }
+    __syncthreads();
   }
-  out[(size_t)g * W + c] = (double)s;
+  if (c < W) out[(size_t)g * W + c] = (double)s;
 }
 void launch_coldot32(const View& v, const float* C, const int* listC, const int* cntC, const unsigned int* cmask,
                      const float* Y, const uint8_t* actY, double* out, hipStream_t s) {
