@@ -3,13 +3,15 @@
   python -m paper_1402_2880_amd.prof_summary kernels <stats.csv> <title> <command> > summary.md
   python -m paper_1402_2880_amd.prof_summary traffic <fetch.csv> <write.csv> <copy_mib> <title> <out.json>
                                                      <fetch command> <write command>
+  python -m paper_1402_2880_amd.prof_summary l2 <tcc.csv> <title> <command> > summary.md
 
 `kernels` turns a `--kernel-trace --stats` kernel_stats.csv into a table (calls, total, share,
 average, min, max).  `traffic` takes two `--pmc` runs (FETCH_SIZE, WRITE_SIZE; counter_collection.csv)
 of a program that first copied copy_mib MiB three times (bench.py --copy-calibration), scales each
 counter by what it reads for those copies (a copy reads and writes copy_mib MiB), and writes per
 kernel the mean HBM bytes per dispatch as JSON and Markdown; the JSON records the SHA-256 of the
-kernel source so that a reader can tell whether the kernels have changed since."""
+kernel source so that a reader can tell whether the kernels have changed since.  `l2` takes one
+`--pmc TCC_HIT_sum TCC_MISS_sum` run and tabulates the L2 hits, misses and hit rate per dispatch."""
 from __future__ import annotations
 
 import csv
@@ -119,9 +121,29 @@ def traffic(fetch_csv: str, write_csv: str, copy_mib: float, title: str, out_jso
     open(os.path.splitext(out_json)[0] + ".md", "w").write("\n".join(md) + "\n")
 
 
+def l2_table(tcc_csv: str, title: str, command: str) -> str:
+    hits, miss = per_dispatch(tcc_csv, "TCC_HIT_sum"), per_dispatch(tcc_csv, "TCC_MISS_sum")
+    per = defaultdict(lambda: [0, 0.0, 0.0])
+    for d, (name, h) in hits.items():
+        if d in miss:
+            per[name][0] += 1
+            per[name][1] += h
+            per[name][2] += miss[d][1]
+    rows = sorted(per.items(), key=lambda kv: -(kv[1][1] + kv[1][2]) / kv[1][0])[:12]
+    out = [f"# L2 (TCC) hits and misses per dispatch: {title}", "", "One rocprofv3 counter run (REPO = repository "
+           "root on the GPU box):", "", f"    {command}", "", f"Kernel sources sha256 `{source_sha256()}`.", "",
+           "Means over the dispatches of the run; a miss goes to the fabric (MALL or HBM).", "",
+           "| kernel | dispatches | hits | misses | hit rate |", "|---|---|---|---|---|"]
+    for name, (n, h, m) in rows:
+        out.append(f"| `{name}` | {n} | {h / n:,.0f} | {m / n:,.0f} | {h / max(h + m, 1.0):.3f} |")
+    return "\n".join(out) + "\n"
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "kernels":
         sys.stdout.write(kernels_table(sys.argv[2], sys.argv[3], sys.argv[4]))
+    elif sys.argv[1] == "l2":
+        sys.stdout.write(l2_table(sys.argv[2], sys.argv[3], sys.argv[4]))
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], float(sys.argv[4]), sys.argv[5], sys.argv[6], sys.argv[7], sys.argv[8])
     else:
