@@ -437,14 +437,36 @@ __global__ void __launch_bounds__(256) k_coldot(int n_rb, int W, const int* slot
   for (int i0 = 0; i0 < mine; i0 += blockDim.x) {
     const int nb = stage_tiles(gb, listC, sp + CD_SPLIT * i0, CD_SPLIT, mine - i0, slot, slotY, cmask, actY, s_so,
                                s_sy, s_cm);
-    if (c < W)
-      for (int j = 0; j < nb; ++j) {
-        if (!((s_cm[j] >> (c >> 4)) & 1u)) continue;   // a zero slice adds zeros
+    if (c < W) {
+      // two tiles' loads go out together; a zero slice is not read and adds exact zeros, and
+      // the terms are added in the same order as one tile at a time
+      int j = 0;
+      for (; j + 1 < nb; j += 2) {
+        const bool on0 = (s_cm[j] >> (c >> 4)) & 1u, on1 = (s_cm[j + 1] >> (c >> 4)) & 1u;
+        const double* C0 = C + (size_t)s_so[j] * (RB * W) + c;
+        const double* Y0 = Y + (size_t)s_sy[j] * (RB * W) + c;
+        const double* C1 = C + (size_t)s_so[j + 1] * (RB * W) + c;
+        const double* Y1 = Y + (size_t)s_sy[j + 1] * (RB * W) + c;
+        double c0[RB], y0[RB], c1[RB], y1[RB];
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+          c0[k] = on0 ? C0[k * W] : 0.0;
+          y0[k] = on0 ? Y0[k * W] : 0.0;
+          c1[k] = on1 ? C1[k * W] : 0.0;
+          y1[k] = on1 ? Y1[k * W] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < RB; ++k) s += c0[k] * y0[k];
+#pragma unroll
+        for (int k = 0; k < RB; ++k) s += c1[k] * y1[k];
+      }
+      if (j < nb && ((s_cm[j] >> (c >> 4)) & 1u)) {
         const double* Ct = C + (size_t)s_so[j] * (RB * W) + c;
         const double* Yt = Y + (size_t)s_sy[j] * (RB * W) + c;
 #pragma unroll
         for (int k = 0; k < RB; ++k) s += Ct[k * W] * Yt[k * W];
       }
+    }
     __syncthreads();
   }
   if (c < W) part[((size_t)sp * gridDim.x + g) * W + c] = s;
