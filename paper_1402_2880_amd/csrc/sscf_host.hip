@@ -388,14 +388,19 @@ struct sscf_ctx {
       HIPC(hipMemsetAsync(&sd->err, 0, sizeof(int), stream));
       launch_ortho_scale(v, v.G, self_pair, O, pnocc, pnvirt, occ_only, sc, sd, stream);
       launch_normalize_d(v, n_pairs, pg, ph, O, Dt, sc, pnocc, pnvirt, occ_only, sd, stream);
-      launch_scale_c(v, C[cur], listC[cur], cntC[cur], cmask[cur], sc, stream);
       const Scalars h = read_scalars();
       if (h.err & 1) fail(SSCF_E_NOT_SPD, "C^T S C has a non-positive diagonal element");
       double eta;
       std::memcpy(&eta, &h.eta_bits, sizeof(double));
       *eta_out = eta;
-      if (eta < tol) { *converged = 1; break; }
-      if (sweeps >= max_sweeps) break;
+      // C's columns are divided by their norms sc: here when the loop ends, else by the packing
+      // and the combination as they read C
+      const bool last = eta < tol || sweeps >= max_sweeps;
+      if (last) {
+        launch_scale_c(v, C[cur], listC[cur], cntC[cur], cmask[cur], sc, stream);
+        if (eta < tol) *converged = 1;
+        break;
+      }
       // pair combinations C <- C - 1/2 C D_sel, in place: the combination reads the other
       // groups' tiles from their packed copy, and only the activity flags are double-buffered
       const int nx = 1 - cur;
@@ -408,9 +413,9 @@ struct sscf_ctx {
       if (wc()) count_update_begin(occ_only != 0);
       // the combination reads the nonzero columns of C packed into Y (free until the next product)
       const int pu = pbegin(KC_UPDATE);
-      launch_pack_cols(v, C[cur], listC[cur], cntC[cur], occ_only ? v.OW : v.W, Y, pcidx, pncol, stream);
+      launch_pack_cols(v, C[cur], listC[cur], cntC[cur], occ_only ? v.OW : v.W, sc, Y, pcidx, pncol, stream);
       launch_ortho_update(v, C[cur], actC[cur], cmask[cur], Y, pcidx, pncol, gn_ptr, gn, pair_of, pair_sel, O, Dt, rmask, sd, upd,
-                          cut, list_tmp, cnt_tmp, C[nx], actC[nx], cmask[nx], ctr(KC_UPDATE), stream);
+                          sc, cut, list_tmp, cnt_tmp, C[nx], actC[nx], cmask[nx], ctr(KC_UPDATE), stream);
       pend(pu);
       rebuild_list(nx);
       if (wc()) count_update_end(nx, occ_only != 0);

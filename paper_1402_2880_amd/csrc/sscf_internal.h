@@ -129,14 +129,16 @@ void launch_clear_flags(const View& v, uint8_t* act, unsigned int* cmask, const 
                         hipStream_t s);
 void launch_tile_flags(const View& v, const double* C, const int* list, const int* cnt, uint8_t* act,
                        unsigned int* cmask, ulonglong2* colm, hipStream_t s);
-void launch_pack_cols(const View& v, const double* C, const int* list, const int* cnt, int col_end, double* P,
-                      uint8_t* cidx, uint8_t* ncol, hipStream_t s);
+// sc: the sweep's column norms; the packed columns are C's divided by them
+void launch_pack_cols(const View& v, const double* C, const int* list, const int* cnt, int col_end,
+                      const double* sc, double* P, uint8_t* cidx, uint8_t* ncol, hipStream_t s);
 void launch_ortho_update(const View& v, const double* C, const uint8_t* actC, const unsigned int* cmaskC,
                          const double* P, const uint8_t* cidx,
                          const uint8_t* ncol, const int* gn_ptr, const int* gn, const int* pair_of,
                          const uint8_t* pair_sel, const double* D, const double* Dt, const uint8_t* rmask,
-                         const Scalars* sd, const uint8_t* upd, double cut, const int* listN, const int* cntN,
-                         double* Cn, uint8_t* actN, unsigned int* cmaskN, unsigned long long* ctr, hipStream_t s);
+                         const Scalars* sd, const uint8_t* upd, const double* sc, double cut, const int* listN,
+                         const int* cntN, double* Cn, uint8_t* actN, unsigned int* cmaskN, unsigned long long* ctr,
+                         hipStream_t s);
 void launch_coulomb(const View& v, int scc, const double* dq, double* part, double* Q, hipStream_t s);
 void launch_fock(const View& v, const double* S, const double* H0, const double* Hfull,
                  const double* Q, double eps, double* H, float* H32, hipStream_t s);

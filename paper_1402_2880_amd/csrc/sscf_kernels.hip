@@ -781,7 +781,8 @@ template <int NT>
 __global__ void __launch_bounds__(256) k_pack_cols(int G, int n_rb, int nchunk, const int* __restrict__ slot,
                                                    const int* __restrict__ slotP, const double* __restrict__ C,
                                                    const int* __restrict__ list, const int* __restrict__ cnt,
-                                                   int col_end, double* __restrict__ P, uint8_t* __restrict__ cidx,
+                                                   int col_end, const double* __restrict__ sc,
+                                                   double* __restrict__ P, uint8_t* __restrict__ cidx,
                                                    uint8_t* __restrict__ ncol) {
   constexpr int W = NT * 16;
   int chunk;
@@ -789,6 +790,10 @@ __global__ void __launch_bounds__(256) k_pack_cols(int G, int n_rb, int nchunk, 
   if (g >= G) return;
   const int lane = threadIdx.x & 63;
   const unsigned long long below = (1ull << lane) - 1ull;
+  // the columns' norms of the sweep (1 for a column out of its scope): P holds C's columns
+  // divided by them, as k_scale_c would have left them
+  const double s0 = lane < W ? sc[(size_t)g * W + lane] : 1.0;
+  const double s1 = lane + 64 < W ? sc[(size_t)g * W + lane + 64] : 1.0;
   const int n_t = cnt[g];
   for (int t = chunk * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); t < n_t; t += 4 * nchunk) {
     const size_t tile = (size_t)g * n_rb + list[(size_t)g * n_rb + t];
@@ -803,13 +808,13 @@ __global__ void __launch_bounds__(256) k_pack_cols(int G, int n_rb, int nchunk, 
     if (nz0) {
       const int k = __popcll(b0 & below);
 #pragma unroll
-      for (int r = 0; r < RB; ++r) Pt[k * RB + r] = v0[r];
+      for (int r = 0; r < RB; ++r) Pt[k * RB + r] = v0[r] / s0;
       ct[k] = (uint8_t)lane;
     }
     if (nz1) {
       const int k = c0 + __popcll(b1 & below);
 #pragma unroll
-      for (int r = 0; r < RB; ++r) Pt[k * RB + r] = v1[r];
+      for (int r = 0; r < RB; ++r) Pt[k * RB + r] = v1[r] / s1;
       ct[k] = (uint8_t)(lane + 64);
     }
     if (lane == 0) ncol[tile] = (uint8_t)(c0 + __popcll(b1));
@@ -827,19 +832,21 @@ void launch_tile_flags(const View& v, const double* C, const int* list, const in
   }
 }
 
-void launch_pack_cols(const View& v, const double* C, const int* list, const int* cnt, int col_end, double* P,
-                      uint8_t* cidx, uint8_t* ncol, hipStream_t s) {
+void launch_pack_cols(const View& v, const double* C, const int* list, const int* cnt, int col_end,
+                      const double* sc, double* P, uint8_t* cidx, uint8_t* ncol, hipStream_t s) {
   const int nchunk = tile_list_chunks(v.G, v.max_c);
   dim3 grid(xcd_grid(v.G, nchunk)), blk(256);
   switch (v.W / 16) {
-#define SSCF_PK(NT) case NT: hipLaunchKernelGGL(k_pack_cols<NT>, grid, blk, 0, s, v.G, v.n_rb, nchunk, v.slot, v.slotY, C, list, cnt, col_end, P, cidx, ncol); break;
+#define SSCF_PK(NT) case NT: hipLaunchKernelGGL(k_pack_cols<NT>, grid, blk, 0, s, v.G, v.n_rb, nchunk, v.slot, v.slotY, C, list, cnt, col_end, sc, P, cidx, ncol); break;
     SSCF_PK(1) SSCF_PK(2) SSCF_PK(3) SSCF_PK(4) SSCF_PK(5) SSCF_PK(6) SSCF_PK(7) SSCF_PK(8)
 #undef SSCF_PK
   }
 }
 
 // Cn[g][r] = C[g][r] - 1/2 sum_{h ~ g} C[h][r] D_sel(h, g), then |v| < cut -> 0 in the
-// columns that took part in a combination.  D is stored per unordered pair (a <= b) with
+// columns that took part in a combination.  C enters divided by the sweep's column norms sc
+// (the normalization of section 3.4, applied here and in the packing rather than in a pass of
+// its own; the last sweep of a loop, which combines nothing, runs k_scale_c instead).  D is stored per unordered pair (a <= b) with
 // rows = MOs of a, columns = MOs of b; Dt holds the transposes, so D_sel(h, g) (rows = MOs
 // of h) is read row-contiguously in both orientations.
 //
@@ -869,7 +876,7 @@ k_ortho_update(int G, int n_rb, int nchunk, const int* __restrict__ slot,
                const double* __restrict__ D, const double* __restrict__ Dt,
                const uint8_t* __restrict__ rmask,
                const Scalars* __restrict__ sd,
-               const uint8_t* __restrict__ upd, double cut,
+               const uint8_t* __restrict__ upd, const double* __restrict__ sc, double cut,
                const int* __restrict__ listN, const int* __restrict__ cntN,
                double* Cn, uint8_t* __restrict__ actN,
                unsigned int* __restrict__ cmaskN, int* __restrict__ cap_err,
@@ -1005,13 +1012,14 @@ k_ortho_update(int G, int n_rb, int nchunk, const int* __restrict__ slot,
       const int jj = n * 16 + lr;
       const bool u = upd[(size_t)g * W + jj] != 0;
       const bool was = (cm_old >> n) & 1u;
+      const double sg = was ? sc[(size_t)g * W + jj] : 1.0;
       const bool hit = __ballot(acc[n][0] != 0.0 || acc[n][1] != 0.0 || acc[n][2] != 0.0 || acc[n][3] != 0.0) != 0ull;
       const bool put = was || hit;
       int nz = 0;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i = lk + 4 * q;
-        double v = (was ? Cg[i * W + jj] : 0.0) - 0.5 * acc[n][q];
+        double v = (was ? Cg[i * W + jj] / sg : 0.0) - 0.5 * acc[n][q];
         if (u && fabs(v) < cut) v = 0.0;
         if (put) Co[i * W + jj] = v;
         nz |= (v != 0.0);
@@ -1030,12 +1038,13 @@ void launch_ortho_update(const View& v, const double* C, const uint8_t* actC, co
                          const double* P, const uint8_t* cidx,
                          const uint8_t* ncol, const int* gn_ptr, const int* gn, const int* pair_of,
                          const uint8_t* pair_sel, const double* D, const double* Dt, const uint8_t* rmask,
-                         const Scalars* sd, const uint8_t* upd, double cut, const int* listN, const int* cntN,
+                         const Scalars* sd, const uint8_t* upd, const double* sc, double cut, const int* listN,
+                         const int* cntN,
                          double* Cn, uint8_t* actN, unsigned int* cmaskN, unsigned long long* ctr, hipStream_t s) {
   const int nchunk = tile_list_chunks(v.G, v.n_rb);
   dim3 grid(xcd_grid(v.G, nchunk)), blk(256);
   switch (v.W / 16) {
-#define SSCF_UPD(NT) case NT: hipLaunchKernelGGL(k_ortho_update<NT>, grid, blk, 0, s, v.G, v.n_rb, nchunk, v.slot, v.slotY, C, actC, cmaskC, P, cidx, ncol, gn_ptr, gn, pair_of, pair_sel, D, Dt, rmask, sd, upd, cut, listN, cntN, Cn, actN, cmaskN, v.cap_err, ctr); break;
+#define SSCF_UPD(NT) case NT: hipLaunchKernelGGL(k_ortho_update<NT>, grid, blk, 0, s, v.G, v.n_rb, nchunk, v.slot, v.slotY, C, actC, cmaskC, P, cidx, ncol, gn_ptr, gn, pair_of, pair_sel, D, Dt, rmask, sd, upd, sc, cut, listN, cntN, Cn, actN, cmaskN, v.cap_err, ctr); break;
     SSCF_UPD(1) SSCF_UPD(2) SSCF_UPD(3) SSCF_UPD(4) SSCF_UPD(5) SSCF_UPD(6) SSCF_UPD(7) SSCF_UPD(8)
 #undef SSCF_UPD
   }
